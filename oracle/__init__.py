@@ -1,0 +1,150 @@
+"""CPU oracle for the multiway joins -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s CPU-baseline
+leg may import this package.  The product library never calls it, and the
+two share no code: the oracle's C file (``oracle.c``) is compiled here with
+gcc, on its own.
+
+Contents
+  * the join counts (plain nested-loop joins in C, Sec. 3 / Sec. 5):
+      ``linear3_count``, ``triangle3_count``, ``join2_size``,
+      ``triangle3_count_masked``, ``linear3_count_sampled``
+  * ``cost_model``: the paper's analytic cost formulas (Sec. 4.2, 5.2, 6.3,
+    6.5 footnote, App. A), in float64
+  * ``mlp_ref``: a float64 reference of the learned planner's network
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, OVERFLOW, KEY_RANGE, NOMEM = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (in place)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-Wextra", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def bind(lib):
+    """Declare the C signatures on a loaded oracle library."""
+    u32p = ctypes.c_void_p
+    i64, u64 = ctypes.c_int64, ctypes.c_uint64
+    lib.orc_linear3_count.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                      u32p, i64, u64, ctypes.c_uint32, u32p]
+    lib.orc_join2_size.argtypes = [u32p, u32p, i64, u64, u32p, i64, u64, u32p]
+    lib.orc_triangle3_count.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                        u32p, u32p, i64, u64, u32p, u32p]
+    lib.orc_triangle3_count_masked.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                               u32p, u32p, u32p, i64, u64, u32p, u32p]
+    lib.orc_linear3_count_sampled.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                              u32p, i64, u64, u32p, u64, u32p]
+    for f in ("orc_linear3_count", "orc_join2_size", "orc_triangle3_count",
+              "orc_triangle3_count_masked", "orc_linear3_count_sampled"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _rel(x):
+    """[n, 2] array of 32-bit values -> (uint32 contiguous array, col0, col1, stride, n)."""
+    a = np.ascontiguousarray(np.asarray(x)).view(np.uint32).reshape(-1, 2)
+    a = np.ascontiguousarray(a)
+    p = a.ctypes.data
+    return a, ctypes.c_void_p(p), ctypes.c_void_p(p + 4), 2, a.shape[0]
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(st, what):
+    if st == KEY_RANGE:
+        raise OracleError(f"{what}: an A value is outside [0, a_domain)")
+    if st == NOMEM:
+        raise MemoryError(what)
+    if st == OVERFLOW:
+        raise OverflowError(f"{what}: a count does not fit 64 bits")
+
+
+def linear3_count(R, S, T, a_domain: int) -> np.ndarray:
+    """uint64[a_domain]: out[a] = #{(r,s,t): r.a=a, r.b=s.b, s.c=t.c}."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, _t1, ts, nt = _rel(T)
+    out = np.zeros(max(int(a_domain), 1), dtype=np.uint64)
+    st = lib.orc_linear3_count(r0, r1, rs, nr, s0, s1, ss, ns, t0, ts, nt,
+                               ctypes.c_uint32(a_domain), out.ctypes.data)
+    _check(st, "linear3_count")
+    return out[:a_domain]
+
+
+def linear3_count_sampled(R, S, T, alist) -> np.ndarray:
+    """Counts for the A values in ``alist`` only (returned in sorted order of
+    the unique values: ``np.unique(alist)``)."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, _t1, ts, nt = _rel(T)
+    al = np.unique(np.asarray(alist).view(np.uint32) if np.asarray(alist).dtype.itemsize == 4
+                   else np.asarray(alist, dtype=np.uint32))
+    al = np.ascontiguousarray(al.astype(np.uint32))
+    out = np.zeros(max(al.size, 1), dtype=np.uint64)
+    st = lib.orc_linear3_count_sampled(r0, r1, rs, nr, s0, s1, ss, ns, t0, ts, nt,
+                                       al.ctypes.data, al.size, out.ctypes.data)
+    _check(st, "linear3_count_sampled")
+    return al, out[:al.size]
+
+
+def join2_size(R, S) -> int:
+    """|R(AB) join S(BC)| on B."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    out = np.zeros(1, dtype=np.uint64)
+    st = lib.orc_join2_size(r0, r1, rs, nr, s0, ss, ns, out.ctypes.data)
+    _check(st, "join2_size")
+    return int(out[0])
+
+
+def triangle3_count(R, S, T, smask=None) -> int:
+    """#{(r,s,t): r.b=s.b, s.c=t.c, t.a=r.a} (optionally over the S tuples
+    whose mask byte is non-zero)."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, t1, ts, nt = _rel(T)
+    lo = np.zeros(1, dtype=np.uint64)
+    hi = np.zeros(1, dtype=np.uint64)
+    if smask is None:
+        st = lib.orc_triangle3_count(r0, r1, rs, nr, s0, s1, ss, ns, t0, t1, ts, nt,
+                                     lo.ctypes.data, hi.ctypes.data)
+    else:
+        m = np.ascontiguousarray(np.asarray(smask, dtype=np.uint8))
+        assert m.size == ns
+        st = lib.orc_triangle3_count_masked(r0, r1, rs, nr, s0, s1, ss, ns, m.ctypes.data,
+                                            t0, t1, ts, nt, lo.ctypes.data, hi.ctypes.data)
+    if st == NOMEM:
+        raise MemoryError("triangle3_count")
+    return int(lo[0]) + (int(hi[0]) << 64)

@@ -1,0 +1,267 @@
+/*
+ * Plain single-threaded CPU oracle for the three-way joins.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or constant with the
+ * HIP library.
+ *
+ * What it computes is the plain relational definition (Sec. 3 and Sec. 5 of
+ * the paper: R(AB) join S(BC) join T(CD), resp. T(CA); bags, no duplicate
+ * elimination, Example 1's footnote; the result is aggregated by COUNT rather
+ * than materialised, Sec. 6).  Every loop below is a nested-loop join whose
+ * inner loops are restricted, through a sorted copy and binary search, to
+ * the tuples that satisfy the join predicate.  Sorting and searching only
+ * select tuples; they change no count.
+ *
+ * Keys are 32-bit patterns compared for equality.  Sums are carried in
+ * unsigned 128-bit integers; a result that does not fit 64 bits is flagged.
+ *
+ * Relations are passed as two column pointers and an element stride
+ * (stride 2 with col1 == col0 + 1 is a row-major [n, 2] array).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+enum { ORC_OK = 0, ORC_OVERFLOW = 1, ORC_KEY_RANGE = 2, ORC_NOMEM = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* small helpers: pairs (key, val) sorted by key then val                    */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint32_t key, val; } pair_t;
+
+static int cmp_pair(const void* x, const void* y) {
+    const pair_t* p = (const pair_t*)x;
+    const pair_t* q = (const pair_t*)y;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    if (p->val != q->val) return p->val < q->val ? -1 : 1;
+    return 0;
+}
+
+static int cmp_u32(const void* x, const void* y) {
+    uint32_t p = *(const uint32_t*)x, q = *(const uint32_t*)y;
+    return p < q ? -1 : (p > q ? 1 : 0);
+}
+
+/* copy a relation into pairs with key = column kcol, val = the other one */
+static pair_t* load_pairs(const uint32_t* c0, const uint32_t* c1, int64_t stride,
+                          uint64_t n, int kcol) {
+    pair_t* p = (pair_t*)malloc((n ? n : 1) * sizeof(pair_t));
+    if (!p) return NULL;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t x = c0[i * stride], y = c1[i * stride];
+        p[i].key = kcol == 0 ? x : y;
+        p[i].val = kcol == 0 ? y : x;
+    }
+    qsort(p, n, sizeof(pair_t), cmp_pair);
+    return p;
+}
+
+/* first index in p[lo, hi) whose key is >= k */
+static uint64_t lower_key(const pair_t* p, uint64_t lo, uint64_t hi, uint32_t k) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].key < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+/* first index in p[lo, hi) whose key is > k */
+static uint64_t upper_key(const pair_t* p, uint64_t lo, uint64_t hi, uint32_t k) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].key <= k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+/* first index in p[lo, hi) (all with one key, vals sorted) with val >= v */
+static uint64_t lower_val(const pair_t* p, uint64_t lo, uint64_t hi, uint32_t v) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].val < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+static uint64_t upper_val(const pair_t* p, uint64_t lo, uint64_t hi, uint32_t v) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].val <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+static uint64_t lower_u32(const uint32_t* a, uint64_t n, uint32_t k) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+static uint64_t upper_u32(const uint32_t* a, uint64_t n, uint32_t k) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] <= k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear join, per-A count (Sec. 3 problem statement, Example 1's query).   */
+/*   out[a] = #{ (r, s, t) : r.a = a, r.b = s.b, s.c = t.c }                 */
+/* T's D column never takes part in a predicate, so for each s the inner     */
+/* loop over t contributes the number of t with t.c = s.c.                   */
+/* Returns ORC_KEY_RANGE if some r.a >= a_domain (out untouched), else       */
+/* ORC_OVERFLOW if some out[a] needs more than 64 bits, else ORC_OK.         */
+/* ------------------------------------------------------------------------ */
+int orc_linear3_count(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                      const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                      const uint32_t* t0, int64_t tstride, uint64_t nt,
+                      uint32_t a_domain, uint64_t* out) {
+    for (uint64_t i = 0; i < nr; ++i)
+        if (r0[i * rstride] >= a_domain) return ORC_KEY_RANGE;
+
+    /* T's C column, sorted */
+    uint32_t* tc = (uint32_t*)malloc((nt ? nt : 1) * sizeof(uint32_t));
+    /* S as (b, c) sorted by b */
+    pair_t* s = load_pairs(s0, s1, sstride, ns, 0);
+    u128* acc = (u128*)calloc(a_domain ? a_domain : 1, sizeof(u128));
+    if (!tc || !s || !acc) { free(tc); free(s); free(acc); return ORC_NOMEM; }
+    for (uint64_t i = 0; i < nt; ++i) tc[i] = t0[i * tstride];
+    qsort(tc, nt, sizeof(uint32_t), cmp_u32);
+
+    for (uint64_t i = 0; i < nr; ++i) {
+        uint32_t a = r0[i * rstride], b = r1[i * rstride];
+        uint64_t lo = lower_key(s, 0, ns, b), hi = upper_key(s, lo, ns, b);
+        for (uint64_t j = lo; j < hi; ++j) {            /* s with s.b = r.b */
+            uint32_t c = s[j].val;
+            uint64_t nmatch = upper_u32(tc, nt, c) - lower_u32(tc, nt, c);  /* t with t.c = s.c */
+            acc[a] += nmatch;
+        }
+    }
+    int status = ORC_OK;
+    for (uint32_t a = 0; a < a_domain; ++a) {
+        if (acc[a] >> 64) status = ORC_OVERFLOW;
+        out[a] = (uint64_t)acc[a];
+    }
+    free(tc); free(s); free(acc);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Size of the binary intermediate R(AB) join S(BC) on B (Sec. 6.3, the      */
+/* first join of the cascade): #{ (r, s) : r.b = s.b }.                      */
+/* ------------------------------------------------------------------------ */
+int orc_join2_size(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                   const uint32_t* s0, int64_t sstride, uint64_t ns, uint64_t* out) {
+    (void)r0;
+    uint32_t* sb = (uint32_t*)malloc((ns ? ns : 1) * sizeof(uint32_t));
+    if (!sb) return ORC_NOMEM;
+    for (uint64_t i = 0; i < ns; ++i) sb[i] = s0[i * sstride];
+    qsort(sb, ns, sizeof(uint32_t), cmp_u32);
+    u128 total = 0;
+    for (uint64_t i = 0; i < nr; ++i) {
+        uint32_t b = r1[i * rstride];
+        total += upper_u32(sb, ns, b) - lower_u32(sb, ns, b);
+    }
+    free(sb);
+    *out = (uint64_t)total;
+    return (total >> 64) ? ORC_OVERFLOW : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cyclic join R(AB) join S(BC) join T(CA), total count (Sec. 5).            */
+/*   total = #{ (r, s, t) : r.b = s.b, s.c = t.c, t.a = r.a }                */
+/* For each s the pairs (r, t) it joins with are those whose A values are    */
+/* equal, with r from R's tuples of B = s.b and t from T's tuples of         */
+/* C = s.c; the loop walks the shorter of the two lists and counts, for      */
+/* each of its tuples, the tuples of the other list with the same A.         */
+/* ------------------------------------------------------------------------ */
+int orc_triangle3_count(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                        const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                        const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
+                        uint64_t* out_lo, uint64_t* out_hi) {
+    pair_t* R = load_pairs(r0, r1, rstride, nr, 1);   /* key b, val a */
+    pair_t* T = load_pairs(t0, t1, tstride, nt, 0);   /* key c, val a */
+    if (!R || !T) { free(R); free(T); return ORC_NOMEM; }
+    u128 total = 0;
+    for (uint64_t i = 0; i < ns; ++i) {
+        uint32_t b = s0[i * sstride], c = s1[i * sstride];
+        uint64_t rlo = lower_key(R, 0, nr, b), rhi = upper_key(R, rlo, nr, b);
+        uint64_t tlo = lower_key(T, 0, nt, c), thi = upper_key(T, tlo, nt, c);
+        const pair_t* short_list = R; uint64_t slo = rlo, shi = rhi;
+        const pair_t* long_list = T;  uint64_t llo = tlo, lhi = thi;
+        if (rhi - rlo > thi - tlo) {
+            short_list = T; slo = tlo; shi = thi;
+            long_list = R;  llo = rlo; lhi = rhi;
+        }
+        for (uint64_t j = slo; j < shi; ++j) {
+            uint32_t a = short_list[j].val;
+            uint64_t lo = lower_val(long_list, llo, lhi, a);
+            uint64_t hi = upper_val(long_list, lo, lhi, a);
+            total += hi - lo;
+        }
+    }
+    free(R); free(T);
+    *out_lo = (uint64_t)total;
+    *out_hi = (uint64_t)(total >> 64);
+    return (total >> 64) ? ORC_OVERFLOW : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cyclic join restricted to a subset of S given by a 0/1 mask: used to      */
+/* check a large join on a sample of S (the total is a sum over S tuples).   */
+/* ------------------------------------------------------------------------ */
+int orc_triangle3_count_masked(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                               const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                               const uint8_t* smask,
+                               const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
+                               uint64_t* out_lo, uint64_t* out_hi) {
+    uint64_t m = 0;
+    for (uint64_t i = 0; i < ns; ++i) m += smask[i] != 0;
+    uint32_t* sb = (uint32_t*)malloc((m ? m : 1) * 2 * sizeof(uint32_t));
+    if (!sb) return ORC_NOMEM;
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < ns; ++i)
+        if (smask[i]) { sb[2 * k] = s0[i * sstride]; sb[2 * k + 1] = s1[i * sstride]; ++k; }
+    int st = orc_triangle3_count(r0, r1, rstride, nr, sb, sb + 1, 2, m, t0, t1, tstride, nt,
+                                 out_lo, out_hi);
+    free(sb);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linear join restricted to the R tuples whose A value is in a sorted list  */
+/* of sampled A values: out[i] = count for a = alist[i].  Used to check the  */
+/* full-size per-A counts on a sample of A values.                           */
+/* ------------------------------------------------------------------------ */
+int orc_linear3_count_sampled(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                              const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                              const uint32_t* t0, int64_t tstride, uint64_t nt,
+                              const uint32_t* alist, uint64_t na, uint64_t* out) {
+    uint32_t* tc = (uint32_t*)malloc((nt ? nt : 1) * sizeof(uint32_t));
+    pair_t* s = load_pairs(s0, s1, sstride, ns, 0);
+    u128* acc = (u128*)calloc(na ? na : 1, sizeof(u128));
+    if (!tc || !s || !acc) { free(tc); free(s); free(acc); return ORC_NOMEM; }
+    for (uint64_t i = 0; i < nt; ++i) tc[i] = t0[i * tstride];
+    qsort(tc, nt, sizeof(uint32_t), cmp_u32);
+    for (uint64_t i = 0; i < nr; ++i) {
+        uint32_t a = r0[i * rstride], b = r1[i * rstride];
+        uint64_t ia = lower_u32(alist, na, a);
+        if (ia == na || alist[ia] != a) continue;
+        uint64_t lo = lower_key(s, 0, ns, b), hi = upper_key(s, lo, ns, b);
+        for (uint64_t j = lo; j < hi; ++j) {
+            uint32_t c = s[j].val;
+            acc[ia] += upper_u32(tc, nt, c) - lower_u32(tc, nt, c);
+        }
+    }
+    int status = ORC_OK;
+    for (uint64_t i = 0; i < na; ++i) {
+        if (acc[i] >> 64) status = ORC_OVERFLOW;
+        out[i] = (uint64_t)acc[i];
+    }
+    free(tc); free(s); free(acc);
+    return status;
+}
