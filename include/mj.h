@@ -1,0 +1,151 @@
+/*
+ * mj.h -- C ABI of libmj, the MI355X (gfx950) multiway hash-join library.
+ *
+ * The operations follow the relational statement of Olukotun, Prabhakar,
+ * Singhal, Ullman, Zhang, "Efficient Multiway Hash Join on Reconfigurable
+ * Hardware" (arXiv 1905.13376):
+ *   - linear three-way join  R(A,B) |x| S(B,C) |x| T(C,D)      (Sec. 3, Sec. 4)
+ *   - cyclic three-way join  R(A,B) |x| S(B,C) |x| T(C,A)      (Sec. 5)
+ *   - the cascade of two binary hash joins, materialising I = R |x| S (Sec. 6.3)
+ * Relations are bags: duplicate tuples count with their multiplicity
+ * (Example 1's footnote).  The final result is aggregated by COUNT instead
+ * of being materialised (Sec. 6, introduction and Sec. 6.3.1).
+ *
+ * Conventions shared by every entry point
+ *   - Keys are 32-bit values compared by bit pattern (int32 or uint32).
+ *   - A relation is given by two device column pointers and an element
+ *     stride: tuple i is (col0[i*stride], col1[i*stride]).  A row-major
+ *     [n, 2] array is col0 = base, col1 = base + 1, stride = 2.
+ *   - Every pointer passed to a count call is DEVICE memory owned by the
+ *     caller; the library allocates no device memory and keeps no pointer
+ *     after a call returns.  The caller supplies a workspace of at least
+ *     mj_plan_t.workspace_bytes bytes (256-byte aligned).
+ *   - Count calls are asynchronous on the given HIP stream (a hipStream_t
+ *     passed as void*; NULL = the default stream); results are valid after
+ *     the stream synchronises.  Calls on one context from one host thread
+ *     per stream are safe; overlapping calls that share a workspace race.
+ *   - Every function returns an mj_status; on an error no kernel has been
+ *     launched and outputs are untouched.  No C++ exception crosses the ABI.
+ *   - n = 0 is valid and yields zero counts.
+ */
+#ifndef MJ_H
+#define MJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MJ_OK = 0,
+    MJ_ERR_INVALID_ARG = -1,   /* NULL pointer, stride < 1, n >= 2^32, bad plan field */
+    MJ_ERR_KEY_RANGE = -2,     /* some A value >= a_domain (found by mj_plan)         */
+    MJ_ERR_WORKSPACE = -3,     /* workspace smaller than the plan requires            */
+    MJ_ERR_PLAN_MISMATCH = -4, /* plan made for other relation sizes or another kind  */
+    MJ_ERR_HIP = -5,           /* a HIP runtime call failed                           */
+    MJ_ERR_OVERFLOW = -6,      /* a count can exceed 2^64 (host bound)                */
+    MJ_ERR_UNSUPPORTED = -7
+} mj_status;
+
+typedef struct mj_ctx mj_ctx;
+
+/* A relation: two key columns on the device. */
+typedef struct {
+    const uint32_t* col0;
+    const uint32_t* col1;
+    uint64_t n;        /* number of tuples, < 2^32 */
+    int64_t stride;    /* elements between consecutive tuples, >= 1 */
+} mj_rel;
+
+typedef enum { MJ_LINEAR = 0, MJ_TRIANGLE = 1 } mj_kind;
+typedef enum { MJ_ALGO_3WAY = 0, MJ_ALGO_CASCADE = 1 } mj_algo;
+typedef enum {
+    MJ_PLANNER_ANALYTIC = 0,   /* cost model with measured device constants        */
+    MJ_PLANNER_LEARNED = 1,    /* MLP on degree sketches; analytic fallback         */
+    MJ_PLANNER_FIXED = 2       /* keep the bucket fields the caller filled in       */
+} mj_planner;
+
+/* Execution plan.  The hyper-parameters are the paper's bucket counts
+ * (Sec. 3.1: a hash function's name stands for its number of buckets):
+ *   linear:   nb = H*h buckets on B, nc = g buckets on C (Sec. 4)
+ *   cyclic:   share = buckets on each of A, B, C (Sec. 5, equal shares)
+ * All bucket counts are powers of two, given by their log2.             */
+typedef struct {
+    int32_t kind;              /* mj_kind                                   */
+    int32_t algo;              /* mj_algo chosen                            */
+    uint32_t log2_nb;          /* linear: buckets on B                      */
+    uint32_t log2_nc;          /* linear: buckets on C                      */
+    uint32_t log2_share;       /* cyclic: buckets per attribute             */
+    uint32_t seed;             /* hash seed                                 */
+    uint64_t n_r, n_s, n_t;    /* sizes the plan was made for               */
+    uint32_t a_domain;         /* linear: length of the per-A output        */
+    uint32_t flags;            /* reserved, 0                               */
+    uint64_t join2_size;       /* |R |x| S| on B, exact when known, else 0  */
+    uint64_t workspace_bytes;  /* bytes the count call needs                */
+    double est_ms_3way;        /* planner's time estimates (0 = not known)  */
+    double est_ms_cascade;
+} mj_plan_t;
+
+/* Context: binds the library to a device (the current one if device < 0). */
+int mj_ctx_create(int device, mj_ctx** out);
+int mj_ctx_destroy(mj_ctx* ctx);
+
+/* Per-kernel timing.  With profiling on, every kernel a call launches is
+ * bracketed by HIP events recorded on the call's stream.  mj_ctx_profile_read
+ * waits for those events and returns, per kernel name (32-byte slots in
+ * `names`), the summed milliseconds and the number of launches since the
+ * last read; it returns the number of entries written (or a negative status). */
+int mj_ctx_profile(mj_ctx* ctx, int enable);
+int mj_ctx_profile_read(mj_ctx* ctx, int max_entries, char* names, double* total_ms,
+                        int64_t* launches);
+
+/* Human-readable name of a status code (static string). */
+const char* mj_status_str(int status);
+
+/* Plan a join (synchronous on `stream`: it may launch statistics kernels
+ * over the inputs and waits for them).  Fills *plan (host memory).  With
+ * MJ_PLANNER_FIXED the caller's log2_nb / log2_nc / log2_share / seed / algo
+ * are kept and only the sizes and workspace are filled in.  For the linear
+ * kind it checks that every A value is < a_domain (MJ_ERR_KEY_RANGE).
+ * Sec. 4.2 and Sec. 5.2 give the costs the analytic planner compares. */
+int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+            uint32_t a_domain, int planner, mj_plan_t* plan, void* stream);
+
+/* Linear three-way join with per-A count (Sec. 4, Algorithm 1; Example 1):
+ *   count_per_a[a] = #{ (r,s,t) in R x S x T : r.a = a, r.b = s.b, s.c = t.c }
+ * for a in [0, a_domain); T's second column (D) takes no part.
+ * count_per_a: device uint64[a_domain], fully overwritten.             */
+int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                     uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan,
+                     void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* Cyclic three-way join, total count (Sec. 5):
+ *   total[0] = #{ (r,s,t) : r.b = s.b, s.c = t.c, t.a = r.a }
+ * With R = S = T = the symmetric edge relation of a simple graph this is
+ * trace(A^3) = 6 x (number of triangles).  total: device uint64[1].      */
+int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                       uint64_t* total, const mj_plan_t* plan,
+                       void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* Cascade of binary hash joins (Sec. 6.3): I(A,C) = R |x| S on B is
+ * materialised in the workspace (in chunks when it does not fit), then
+ * I |x| T is counted.  Same outputs as mj_linear3_count (kind MJ_LINEAR,
+ * out = uint64[a_domain]) or mj_triangle3_count (kind MJ_TRIANGLE,
+ * out = uint64[1]).                                                      */
+int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                      uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
+                      void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* Exact |R |x| S| on B = sum_b deg_R(b) * deg_S(b) (the cascade's
+ * intermediate size, Sec. 6.3), computed on the device.  Synchronous;
+ * *out is host memory.  Needs a workspace of mj_join2_size_workspace()
+ * bytes.                                                                 */
+uint64_t mj_join2_size_workspace(uint64_t n_r, uint64_t n_s);
+int mj_join2_size(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, uint64_t* out,
+                  void* workspace, uint64_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MJ_H */

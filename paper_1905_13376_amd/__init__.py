@@ -1,0 +1,7 @@
+"""MI355X-native multiway hash joins (arXiv 1905.13376): linear and cyclic
+three-way joins and the binary cascade, behind the C ABI of ``libmj.so``.
+
+Importing the package loads the HIP library; it fails loudly when the
+library is missing (there is no CPU path)."""
+from ._lib import (ALGO_3WAY, ALGO_CASCADE, LINEAR, TRIANGLE, Context, MJError,  # noqa: F401
+                   Plan, Rel, as_u64, rel, status_str, LIB_PATH)

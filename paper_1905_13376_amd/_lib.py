@@ -1,0 +1,226 @@
+"""ctypes binding of libmj (include/mj.h).
+
+Argument marshalling only: every step of every join runs in the HIP
+library.  PyTorch provides device memory and streams.  If ``libmj.so`` has
+not been built this module raises on import -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmj.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmj.so not found at {LIB_PATH}; build it with "
+                      "`python -m paper_1905_13376_amd.build` (no CPU fallback exists)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MJ_OK = 0
+STATUS = {0: "MJ_OK", -1: "MJ_ERR_INVALID_ARG", -2: "MJ_ERR_KEY_RANGE", -3: "MJ_ERR_WORKSPACE",
+          -4: "MJ_ERR_PLAN_MISMATCH", -5: "MJ_ERR_HIP", -6: "MJ_ERR_OVERFLOW",
+          -7: "MJ_ERR_UNSUPPORTED"}
+LINEAR, TRIANGLE = 0, 1
+ALGO_3WAY, ALGO_CASCADE = 0, 1
+PLANNERS = {"analytic": 0, "learned": 1, "fixed": 2}
+
+
+class MJError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)}")
+
+
+class Rel(ctypes.Structure):
+    _fields_ = [("col0", ctypes.c_void_p), ("col1", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("stride", ctypes.c_int64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("log2_nb", ctypes.c_uint32), ("log2_nc", ctypes.c_uint32),
+                ("log2_share", ctypes.c_uint32), ("seed", ctypes.c_uint32),
+                ("n_r", ctypes.c_uint64), ("n_s", ctypes.c_uint64), ("n_t", ctypes.c_uint64),
+                ("a_domain", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("join2_size", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("est_ms_3way", ctypes.c_double), ("est_ms_cascade", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+    def copy(self):
+        p = Plan()
+        ctypes.pointer(p)[0] = self
+        return p
+
+
+_vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_RP = ctypes.POINTER(Rel)
+_PP = ctypes.POINTER(Plan)
+
+_SIGS = {
+    "mj_ctx_create": ([_i32, ctypes.POINTER(_vp)], _i32),
+    "mj_ctx_destroy": ([_vp], _i32),
+    "mj_status_str": ([_i32], ctypes.c_char_p),
+    "mj_plan": ([_vp, _i32, _RP, _RP, _RP, _u32, _i32, _PP, _vp], _i32),
+    "mj_linear3_count": ([_vp, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
+    "mj_triangle3_count": ([_vp, _RP, _RP, _RP, _vp, _PP, _vp, _u64, _vp], _i32),
+    "mj_cascade2_count": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
+    "mj_join2_size_workspace": ([_u64, _u64], _u64),
+    "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
+    "mj_ctx_profile": ([_vp, _i32], _i32),
+    "mj_ctx_profile_read": ([_vp, _i32, _vp, _vp, _vp], _i32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def status_str(code: int) -> str:
+    return _lib.mj_status_str(code).decode()
+
+
+def _check(st, what):
+    if st != MJ_OK:
+        raise MJError(st, what)
+
+
+def rel(t: torch.Tensor) -> Rel:
+    """A relation from an ``[n, 2]`` 32-bit tensor (any element strides)."""
+    if t.dim() != 2 or t.shape[1] != 2 or t.element_size() != 4:
+        raise ValueError("a relation is an [n, 2] tensor of 32-bit keys")
+    if t.is_cuda is False and t.numel() > 0:
+        raise ValueError("relations must be on the GPU")
+    base = t.data_ptr()
+    return Rel(base, base + 4 * t.stride(1), t.shape[0], t.stride(0))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One libmj context bound to a device."""
+
+    def __init__(self, device: int | None = None):
+        h = ctypes.c_void_p()
+        _check(_lib.mj_ctx_create(-1 if device is None else int(device), ctypes.byref(h)),
+               "mj_ctx_create")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            _lib.mj_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- profiling
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch with HIP events on its stream."""
+        _check(_lib.mj_ctx_profile(self._h, 1 if enable else 0), "mj_ctx_profile")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last read (waits for
+        the recorded events)."""
+        import numpy as np
+        cap = 64
+        names = ctypes.create_string_buffer(32 * cap)
+        ms = np.zeros(cap, dtype=np.float64)
+        cnt = np.zeros(cap, dtype=np.int64)
+        k = _lib.mj_ctx_profile_read(self._h, cap, names, ms.ctypes.data, cnt.ctypes.data)
+        if k < 0:
+            raise MJError(k, "mj_ctx_profile_read")
+        raw = names.raw
+        out = {}
+        for i in range(k):
+            nm = raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(cnt[i]))
+        return out
+
+    # ---------------------------------------------------------------- helpers
+    def workspace(self, nbytes: int, device) -> torch.Tensor:
+        """A cached workspace tensor of at least ``nbytes`` bytes."""
+        nbytes = max(int(nbytes), 256)
+        if self._ws is None or self._ws.numel() < nbytes or self._ws.device != device:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def plan(self, kind, R, S, T, a_domain=0, planner="analytic", fixed: Plan | None = None,
+             stream=None) -> Plan:
+        p = fixed.copy() if fixed is not None else Plan()
+        r, s, t = rel(R), rel(S), rel(T)
+        _check(_lib.mj_plan(self._h, kind, r, s, t, a_domain, PLANNERS[planner],
+                            ctypes.byref(p), _stream_ptr(stream)), "mj_plan")
+        return p
+
+    def linear3_count(self, R, S, T, a_domain, plan: Plan | None = None, out=None,
+                      workspace=None, stream=None) -> torch.Tensor:
+        """uint64 per-A counts (returned as an int64 tensor holding the bits)."""
+        if plan is None:
+            plan = self.plan(LINEAR, R, S, T, a_domain, stream=stream)
+        if out is None:
+            out = torch.empty(max(a_domain, 1), dtype=torch.int64, device=R.device)
+        ws = workspace if workspace is not None else self.workspace(plan.workspace_bytes, R.device)
+        _check(_lib.mj_linear3_count(self._h, rel(R), rel(S), rel(T), a_domain,
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream_ptr(stream)), "mj_linear3_count")
+        return out[:a_domain]
+
+    def triangle3_count(self, R, S, T, plan: Plan | None = None, out=None, workspace=None,
+                        stream=None) -> torch.Tensor:
+        if plan is None:
+            plan = self.plan(TRIANGLE, R, S, T, stream=stream)
+        if out is None:
+            out = torch.empty(1, dtype=torch.int64, device=R.device)
+        ws = workspace if workspace is not None else self.workspace(plan.workspace_bytes, R.device)
+        _check(_lib.mj_triangle3_count(self._h, rel(R), rel(S), rel(T),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_ptr(stream)), "mj_triangle3_count")
+        return out
+
+    def cascade2_count(self, kind, R, S, T, a_domain=0, plan: Plan | None = None, out=None,
+                       workspace=None, stream=None) -> torch.Tensor:
+        if plan is None:
+            plan = self.plan(kind, R, S, T, a_domain, stream=stream)
+        n_out = max(a_domain, 1) if kind == LINEAR else 1
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.int64, device=R.device)
+        ws = workspace if workspace is not None else self.workspace(plan.workspace_bytes, R.device)
+        _check(_lib.mj_cascade2_count(self._h, kind, rel(R), rel(S), rel(T), a_domain,
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_ptr(stream)), "mj_cascade2_count")
+        return out[:a_domain] if kind == LINEAR else out
+
+    def join2_size(self, R, S, stream=None) -> int:
+        need = _lib.mj_join2_size_workspace(R.shape[0], S.shape[0])
+        ws = self.workspace(need, R.device)
+        out = ctypes.c_uint64()
+        _check(_lib.mj_join2_size(self._h, rel(R), rel(S), ctypes.byref(out),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _stream_ptr(stream)), "mj_join2_size")
+        return out.value
+
+
+def as_u64(t: torch.Tensor):
+    """Host numpy uint64 view of a device int64 tensor holding uint64 bits."""
+    return t.detach().cpu().numpy().view("uint64")

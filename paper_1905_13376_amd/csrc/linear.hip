@@ -1,0 +1,266 @@
+// Linear three-way join R(A,B) |x| S(B,C) |x| T(C,D) with per-A COUNT
+// (Sec. 4, Algorithm 1 and its steps 1-4; Example 1).
+//
+// Mapping onto MI355X:
+//  * the "chip" of the paper is the whole GPU and a "PMU" is one CU's LDS;
+//    R is not split at the top level (H = 1) as long as the b-buckets of R
+//    and S fit the LDS of the workgroups that own them (h = nb buckets);
+//  * T is partitioned by g(C) (nc buckets).  Each bucket T_j is reduced once
+//    to a table of C -> multiplicity (its D column takes no part in a COUNT)
+//    and that compact table is what every workgroup "receives" when the paper
+//    broadcasts T_j to all PMUs: the tables stay L2/MALL resident and every
+//    cell reads them in place (k_dbuild);
+//  * a cell is one b-bucket: its workgroup keeps, in LDS, the per-B state
+//    W[b] = sum over s(b,c) in S_i of mult_T(c) for all of S_i -- the
+//    per-R_i-tuple state of Sec. 4.1's footnote -- and then streams R_i,
+//    adding W[r.b] to count[r.a] (k_linear_cell).  When the distinct B values
+//    of a bucket do not fit the LDS table the bucket is split again by
+//    another hash of B (the paper's sub-partitions), recursively.
+#include "mj_kernels.h"
+
+namespace mj {
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out) {
+    uint32_t m = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        m = max(m, ld_col(col, i, stride));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor(m, off, WAVE));
+    if (lane_id() == 0) atomicMax(out, m);
+}
+
+__device__ __forceinline__ uint32_t next_pow2_u32(uint32_t x) {
+    return x <= 1 ? 1u : 1u << (32 - __clz(x - 1));
+}
+
+// Insert `key` with count increment into a global open-addressing region
+// (claim with CAS on the key word, then add to the count word).
+__device__ __forceinline__ void gtab_add(uint2* base, uint32_t mask, uint32_t key,
+                                         uint32_t inc, uint32_t slot_seed) {
+    uint32_t s = slot_hash(key, slot_seed) & mask;
+    uint32_t* kw = reinterpret_cast<uint32_t*>(base);
+    while (true) {
+        uint32_t old = atomicCAS(&kw[2 * s], EMPTY_KEY, key);
+        if (old == EMPTY_KEY || old == key) {
+            atomicAdd(&kw[2 * s + 1], inc);
+            return;
+        }
+        s = (s + 1u) & mask;
+    }
+}
+
+// ------------------------------------------------ multiplicity tables (D)
+__global__ void __launch_bounds__(DB_THREADS)
+k_dbuild(DBuildArgs A) {
+    __shared__ uint32_t tkeys[DB_CAP];
+    __shared__ uint32_t tvals[DB_CAP];
+    __shared__ uint32_t s_special, s_distinct, s_over, s_log2;
+    __shared__ unsigned long long s_base;
+    const uint32_t j = blockIdx.x;
+    const uint32_t beg = A.starts[j], end = A.starts[j + 1];
+    const uint32_t n = end - beg;
+    const uint32_t mask = DB_CAP - 1;
+
+    for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
+    if (threadIdx.x == 0) { s_special = 0; s_distinct = 0; s_over = 0; }
+    __syncthreads();
+
+    for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+        if (*(volatile uint32_t*)&s_over) break;
+        const uint32_t k = A.keys[i];
+        if (k == EMPTY_KEY) { atomicAdd(&s_special, 1u); continue; }
+        uint32_t s = slot_hash(k, A.slot_seed) & mask;
+        for (uint32_t step = 0;; ++step) {
+            uint32_t cur = tkeys[s];
+            if (cur == k) { atomicAdd(&tvals[s], 1u); break; }
+            if (cur == EMPTY_KEY || step >= DB_CAP) {
+                // no new key is claimed after the overflow flag (the bucket is
+                // rebuilt in global memory), so the LDS table never fills
+                if (*(volatile uint32_t*)&s_over || step >= DB_CAP) { s_over = 1; break; }
+                uint32_t old = atomicCAS(&tkeys[s], EMPTY_KEY, k);
+                if (old == EMPTY_KEY) {
+                    if (atomicAdd(&s_distinct, 1u) + 1 >= DB_LIMIT) s_over = 1;
+                    atomicAdd(&tvals[s], 1u);
+                    break;
+                }
+                if (old == k) { atomicAdd(&tvals[s], 1u); break; }
+            }
+            s = (s + 1u) & mask;
+        }
+    }
+    __syncthreads();
+    const bool spill = s_over != 0;
+    if (threadIdx.x == 0) {
+        const uint32_t want = spill ? (n > (1u << 30) ? (1u << 31) : 2u * n) : 2u * s_distinct;
+        uint32_t cap = max(DB_MIN_CAP, next_pow2_u32(want));
+        unsigned long long base = atomicAdd(A.pool_cursor, (unsigned long long)cap);
+        if (base + cap > A.pool_cap) {       // cannot happen with a planned workspace
+            atomicExch(A.err, 1u);
+            base = 0;                        // the pool's first DB_MIN_CAP slots stay empty
+            cap = DB_MIN_CAP;
+        }
+        s_base = base;
+        s_log2 = 31 - __clz(cap);
+        if (spill) s_special = 0;            // recounted below
+    }
+    __syncthreads();
+    const unsigned long long base = s_base;
+    const uint32_t cap = 1u << s_log2;
+    uint2* region = A.pool + base;
+    if (base != 0) {
+        for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) region[s] = make_uint2(EMPTY_KEY, 0u);
+        __threadfence();
+        __syncthreads();
+        if (!spill) {
+            for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) {
+                uint32_t k = tkeys[s];
+                if (k != EMPTY_KEY) gtab_add(region, cap - 1, k, tvals[s], A.slot_seed);
+            }
+        } else {
+            for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+                const uint32_t k = A.keys[i];
+                if (k == EMPTY_KEY) atomicAdd(&s_special, 1u);
+                else gtab_add(region, cap - 1, k, 1u, A.slot_seed);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DirEntry e;
+        e.offset = base;
+        e.log2cap = s_log2;
+        e.special = s_special;
+        A.dir[j] = e;
+    }
+}
+
+// --------------------------------------------------------------- probe-sum
+__global__ void k_probe_sum(ProbeSumArgs A) {
+    unsigned long long acc = 0;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t k = ld_col(A.col, i, A.stride);
+        acc += dtab_lookup(A.dir, A.pool, k, A.bkt_seed, A.bkt_bits, A.slot_seed);
+    }
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(A.total, acc);
+}
+
+// ------------------------------------------------------------ linear cells
+__device__ __forceinline__ uint32_t pass_of(uint32_t b, uint32_t seed, uint32_t level) {
+    return top_bits(mix32(b, seed ^ 0x3C6EF372u), level);
+}
+
+__global__ void __launch_bounds__(CELL_THREADS)
+k_linear_cell(LinearCellArgs A) {
+    __shared__ uint32_t wkeys[CELL_CAP];
+    __shared__ unsigned long long wvals[CELL_CAP];
+    __shared__ unsigned long long w_special;
+    __shared__ uint32_t s_distinct, s_over;
+    __shared__ uint32_t st_level[64], st_pass[64];
+    __shared__ int s_sp;
+
+    const uint32_t i = blockIdx.x;
+    const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
+    const uint32_t r0 = A.rstarts[i], r1 = A.rstarts[i + 1];
+    if (s0 == s1 || r0 == r1) return;      // nothing can match in this cell
+    const uint32_t mask = CELL_CAP - 1;
+    const int nthr = blockDim.x;
+
+    if (threadIdx.x == 0) { s_sp = 1; st_level[0] = 0; st_pass[0] = 0; }
+    __syncthreads();
+    while (s_sp > 0) {
+        const uint32_t level = st_level[s_sp - 1];
+        const uint32_t pass = st_pass[s_sp - 1];
+        for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) { wkeys[s] = EMPTY_KEY; wvals[s] = 0; }
+        if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; --s_sp; }
+        __syncthreads();
+
+        // phase 1: W[b] += mult_T(c) over the S tuples of this (sub-)bucket
+        for (uint32_t q = s0 + threadIdx.x; q < s1; q += 4 * nthr) {
+            if (*(volatile uint32_t*)&s_over) break;
+            uint2 sv[4];
+            uint32_t w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                uint32_t idx = q + u * nthr;
+                sv[u] = idx < s1 ? A.S[idx] : make_uint2(0u, 0u);
+                bool live = idx < s1 && (level == 0 || pass_of(sv[u].x, A.w_seed, level) == pass);
+                w[u] = live ? dtab_lookup(A.ddir, A.dpool, sv[u].y, A.c_seed, A.c_bits, A.slot_seed) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (w[u] == 0) continue;
+                const uint32_t b = sv[u].x;
+                if (b == EMPTY_KEY) { atomicAdd(&w_special, (unsigned long long)w[u]); continue; }
+                uint32_t s = slot_hash(b, A.w_seed) & mask;
+                for (uint32_t step = 0;; ++step) {
+                    uint32_t cur = wkeys[s];
+                    if (cur == b) { atomicAdd(&wvals[s], (unsigned long long)w[u]); break; }
+                    if (cur == EMPTY_KEY || step >= CELL_CAP) {
+                        // a new key: once the pass has overflowed no new slot is
+                        // claimed (the pass is redone split), so the table can
+                        // never fill up and every probe finds an empty slot
+                        if (*(volatile uint32_t*)&s_over || step >= CELL_CAP) { s_over = 1; break; }
+                        uint32_t old = atomicCAS(&wkeys[s], EMPTY_KEY, b);
+                        if (old == EMPTY_KEY || old == b) {
+                            if (old == EMPTY_KEY && atomicAdd(&s_distinct, 1u) + 1 >= CELL_LIMIT) s_over = 1;
+                            atomicAdd(&wvals[s], (unsigned long long)w[u]);
+                            break;
+                        }
+                    }
+                    s = (s + 1u) & mask;
+                }
+            }
+        }
+        __syncthreads();
+        if (s_over) {
+            // too many distinct B values: split this pass in two by one more hash bit
+            if (threadIdx.x == 0) {
+                st_level[s_sp] = level + 1; st_pass[s_sp] = 2 * pass + 1; ++s_sp;
+                st_level[s_sp] = level + 1; st_pass[s_sp] = 2 * pass;     ++s_sp;
+            }
+            __syncthreads();
+            continue;
+        }
+        // phase 2: count[r.a] += W[r.b] over the R tuples of this (sub-)bucket
+        for (uint32_t q = r0 + threadIdx.x; q < r1; q += nthr) {
+            const uint2 rv = A.R[q];
+            const uint32_t b = rv.y;
+            if (level && pass_of(b, A.w_seed, level) != pass) continue;
+            unsigned long long w = 0;
+            if (b == EMPTY_KEY) {
+                w = w_special;
+            } else {
+                uint32_t s = slot_hash(b, A.w_seed) & mask;
+                while (true) {
+                    uint32_t cur = wkeys[s];
+                    if (cur == b) { w = wvals[s]; break; }
+                    if (cur == EMPTY_KEY) break;
+                    s = (s + 1u) & mask;
+                }
+            }
+            if (w) {
+                if (rv.x < A.a_domain) atomicAdd(&A.count[rv.x], w);
+                else atomicExch(A.err, 1u);     // key outside [0, a_domain): reported, not written
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace mj

@@ -1,0 +1,62 @@
+// Device-side building blocks shared by the libmj kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mj {
+
+constexpr int WAVE = 64;
+constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;   // LDS/global table sentinel; the real
+                                              // key 0xFFFFFFFF is kept in a side slot
+
+// 32-bit finaliser of MurmurHash3 applied to key ^ seed: a bijection of the
+// 32-bit keys, so distinct keys never collide in the full hash value.  The
+// paper asks only for "robust" hash functions (Sec. 4); bucket numbers are
+// the top bits (radix digits of the hash), table slots the low bits.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t k, uint32_t seed) {
+    uint32_t h = k ^ seed;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// Bucket from the top `bits` bits of a hash (bits may be 0: one bucket).
+__host__ __device__ __forceinline__ uint32_t top_bits(uint32_t h, uint32_t bits) {
+    return bits == 0 ? 0u : (h >> (32u - bits));
+}
+
+// Second, independent hash for table slots inside a bucket.
+__host__ __device__ __forceinline__ uint32_t slot_hash(uint32_t k, uint32_t seed) {
+    return mix32(k, seed ^ 0x68E31DA4u);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Wave-wide sum of a 64-bit value (DPP/permute based reduction via shuffles).
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Read tuple component from a strided column.
+__device__ __forceinline__ uint32_t ld_col(const uint32_t* __restrict__ col, uint64_t i,
+                                           int64_t stride) {
+    return __builtin_nontemporal_load(col + i * (uint64_t)stride);
+}
+
+__device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long* p,
+                                                             unsigned long long v) {
+    return atomicAdd(p, v);
+}
+
+}  // namespace mj

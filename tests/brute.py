@@ -54,14 +54,21 @@ def _dense_ids(*cols):
 
 
 def linear_closed_total(R, S, T):
-    """Sum over (b, c) in S of deg_R(b) * deg_T(c) (python ints)."""
+    """Sum over (b, c) in S of deg_R(b) * deg_T(c), with degrees from
+    np.unique counts (exact while the total stays below 2^63)."""
     R, S, T = as_u32(R), as_u32(S), as_u32(T)
+
+    def deg_of(keys, cnts, q):
+        i = np.searchsorted(keys, q)
+        i = np.minimum(i, max(len(keys) - 1, 0))
+        hit = (keys[i] == q) if len(keys) else np.zeros(len(q), bool)
+        return np.where(hit, cnts[i] if len(keys) else 0, 0).astype(np.int64)
+
     rb, rcnt = np.unique(R[:, 1], return_counts=True)
     tc, tcnt = np.unique(T[:, 0], return_counts=True)
-    degR = dict(zip(rb.tolist(), rcnt.tolist()))
-    degT = dict(zip(tc.tolist(), tcnt.tolist()))
-    sb, sc = S[:, 0].tolist(), S[:, 1].tolist()
-    return sum(degR.get(b, 0) * degT.get(c, 0) for b, c in zip(sb, sc))
+    dR = deg_of(rb, rcnt, S[:, 0])
+    dT = deg_of(tc, tcnt, S[:, 1])
+    return int((dR * dT).sum())
 
 
 def linear_closed_per_a(R, S, T, a_domain):

@@ -1,0 +1,174 @@
+"""GPU parity of the linear three-way join (Sec. 4) against the oracle:
+bit-exact uint64 per-A counts."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import brute
+from tests.gpu_util import banner, dev, fixed_plan
+from workloads import generators as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1905_13376_amd as mj
+    return mj
+
+
+@pytest.fixture(scope="module")
+def ctx(mj):
+    c = mj.Context()
+    yield c
+    c.close()
+
+
+def run_linear(mj, ctx, R, S, T, a_domain, plan=None):
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    out = ctx.linear3_count(Rd, Sd, Td, a_domain, plan=plan)
+    return mj.as_u64(out)
+
+
+def test_linear_small_uniform(mj, ctx):
+    banner("linear 65,536 uniform tuples over [0,4096)")
+    F = G.linear_small()
+    got = run_linear(mj, ctx, F, F, F, 4096)
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 4096))
+
+
+@pytest.mark.parametrize("nb,nc,seed", [(0, 0, 1), (1, 3, 7), (5, 2, 99), (12, 12, 3), (7, 9, 0xFFFFFFFF)])
+def test_linear_bucket_sweep_invariant(mj, ctx, nb, nc, seed):
+    banner(f"linear bucket sweep nb=2^{nb} nc=2^{nc} seed={seed}")
+    F = G.linear_small()[:20000]
+    Fd = dev(F)
+    p = fixed_plan(mj, ctx, mj.LINEAR, Fd, Fd, Fd, 4096, log2_nb=nb, log2_nc=nc, seed=seed)
+    got = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 4096, plan=p))
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 4096))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_linear_random_bags_distinct_relations(mj, ctx, seed):
+    banner(f"linear random bags seed={seed}")
+    rng = np.random.default_rng(seed)
+    dom = [3, 50, 1000, 70000, 5, 300][seed]
+    nr, ns, nt = (int(x) for x in rng.integers(1, 30000, size=3))
+    R = rng.integers(0, dom, size=(nr, 2)).astype(np.uint32)
+    S = rng.integers(0, dom, size=(ns, 2)).astype(np.uint32)
+    T = rng.integers(0, dom, size=(nt, 2)).astype(np.uint32)
+    # high-bit and sentinel-valued join keys must behave like any other key
+    special = np.array([0xFFFFFFFF, 0x80000000, 0xFFFFFFFE], dtype=np.uint32)
+    for X, col in ((R, 1), (S, 0), (S, 1), (T, 0)):
+        m = rng.random(X.shape[0]) < 0.05
+        X[m, col] = special[rng.integers(0, 3, size=m.sum())]
+    a_dom = dom
+    got = run_linear(mj, ctx, R, S, T, a_dom)
+    np.testing.assert_array_equal(got, oracle.linear3_count(R, S, T, a_dom))
+
+
+def test_linear_overflowing_tables(mj, ctx):
+    """One bucket with far more distinct B and C values than an LDS table
+    holds: exercises the split passes of the cells and the spilled
+    multiplicity tables."""
+    banner("linear single-bucket overflow paths")
+    rng = np.random.default_rng(5)
+    n = 60000
+    R = np.stack([rng.integers(0, 512, n), rng.integers(0, 40000, n)], 1).astype(np.uint32)
+    S = np.stack([rng.integers(0, 40000, n), rng.integers(0, 30000, n)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, 30000, n), rng.integers(0, 9, n)], 1).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    p = fixed_plan(mj, ctx, mj.LINEAR, Rd, Sd, Td, 512, log2_nb=0, log2_nc=0, seed=11)
+    got = mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 512, plan=p))
+    np.testing.assert_array_equal(got, oracle.linear3_count(R, S, T, 512))
+
+
+def test_linear_empty_and_tiny(mj, ctx):
+    banner("linear empty / one-tuple relations")
+    e = np.zeros((0, 2), dtype=np.uint32)
+    one = np.array([[1, 2]], dtype=np.uint32)
+    S1 = np.array([[2, 3]] * 5, dtype=np.uint32)
+    T1 = np.array([[3, 0]] * 7, dtype=np.uint32)
+    np.testing.assert_array_equal(run_linear(mj, ctx, one, S1, T1, 4),
+                                  np.array([0, 35, 0, 0], dtype=np.uint64))
+    for R, S, T in ((e, S1, T1), (one, e, T1), (one, S1, e)):
+        Rd, Sd, Td = dev(R), dev(S), dev(T)
+        got = mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 4))
+        assert not got.any()
+
+
+def test_linear_column_layouts(mj, ctx):
+    """Separate column tensors (stride 1) and a strided view give the same
+    counts as the packed [n, 2] layout."""
+    import torch
+    banner("linear column layouts")
+    F = G.linear_small()[:30000]
+    want = oracle.linear3_count(F, F, F, 4096)
+    Fd = dev(F)
+    soa = torch.stack([Fd[:, 0].contiguous(), Fd[:, 1].contiguous()], 0)  # [2, n]
+    R = soa.t()                                  # strides (1, n)
+    got = mj.as_u64(ctx.linear3_count(R, R, R, 4096))
+    np.testing.assert_array_equal(got, want)
+    wide = torch.zeros((F.shape[0], 5), dtype=torch.int32, device="cuda")
+    wide[:, 1] = Fd[:, 0]
+    wide[:, 3] = Fd[:, 1]
+    V = wide[:, 1:4:2]                           # strides (5, 2)
+    got = mj.as_u64(ctx.linear3_count(V, V, V, 4096))
+    np.testing.assert_array_equal(got, want)
+
+
+def test_linear_powerlaw_scaled(mj, ctx):
+    banner("linear power-law 2^20 edges over 2^16 vertices")
+    F = G.linear_powerlaw(seed=2001, n_vertices=1 << 16, m=1 << 20)
+    got = run_linear(mj, ctx, F, F, F, 1 << 16)
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 1 << 16))
+
+
+def test_linear_powerlaw_full_sampled(mj, ctx):
+    """Full-size power-law input (2^24 edges, 2^20 vertices), in the plan
+    the benchmark uses: the sum equals the closed form, and sampled A values
+    equal the oracle's per-A counts."""
+    banner("linear power-law full size 2^24 edges")
+    F = G.linear_powerlaw()
+    Fd = dev(F)
+    got = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 1 << 20))
+    assert int(got.sum(dtype=np.uint64)) == brute.linear_closed_total(F, F, F)
+    rng = np.random.default_rng(0)
+    hubs = np.argsort(np.bincount(F[:, 0], minlength=1 << 20))[-8:]
+    sample = np.concatenate([rng.integers(0, 1 << 20, 200), hubs]).astype(np.uint32)
+    al, want = oracle.linear3_count_sampled(F, F, F, sample)
+    np.testing.assert_array_equal(got[al], want)
+
+
+def test_join2_size(mj, ctx):
+    banner("join2 size")
+    F = G.linear_powerlaw(seed=3, n_vertices=1 << 14, m=1 << 18)
+    Fd = dev(F)
+    assert ctx.join2_size(Fd, Fd) == oracle.join2_size(F, F)
+    rng = np.random.default_rng(1)
+    R = rng.integers(0, 100, size=(5000, 2)).astype(np.uint32)
+    S = rng.integers(0, 100, size=(7000, 2)).astype(np.uint32)
+    assert ctx.join2_size(dev(R), dev(S)) == oracle.join2_size(R, S)
+
+
+def test_linear_key_range_rejected(mj, ctx):
+    banner("linear key range error")
+    F = np.array([[7, 1], [2, 3]], dtype=np.uint32)
+    Fd = dev(F)
+    with pytest.raises(mj.MJError) as e:
+        ctx.plan(mj.LINEAR, Fd, Fd, Fd, 5)
+    assert "KEY_RANGE" in str(e.value)
+
+
+def test_linear_workspace_and_plan_errors(mj, ctx):
+    banner("linear workspace / plan mismatch errors")
+    import torch
+    F = G.linear_small()[:1000]
+    Fd = dev(F)
+    p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, 4096)
+    small = torch.empty(128, dtype=torch.uint8, device="cuda")
+    with pytest.raises(mj.MJError) as e:
+        ctx.linear3_count(Fd, Fd, Fd, 4096, plan=p, workspace=small)
+    assert "WORKSPACE" in str(e.value)
+    with pytest.raises(mj.MJError) as e:
+        ctx.linear3_count(Fd[:999], Fd, Fd, 4096, plan=p)
+    assert "PLAN_MISMATCH" in str(e.value)
