@@ -21,19 +21,19 @@ using namespace mj;
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 struct Prof {
     bool on = false;
-    struct Rec { const char* name; hipEvent_t a, b; };
+    struct Rec { std::string name; hipEvent_t a, b; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> free_ev;
     std::map<std::string, std::pair<double, long>> total;   // ms, launches
     hipEvent_t ev() {
         if (!free_ev.empty()) { hipEvent_t e = free_ev.back(); free_ev.pop_back(); return e; }
-        hipEvent_t e; hipEventCreate(&e); return e;
+        hipEvent_t e = nullptr; (void)hipEventCreate(&e); return e;
     }
     void collect() {
         for (auto& r : pending) {
-            hipEventSynchronize(r.b);
+            (void)hipEventSynchronize(r.b);
             float ms = 0.f;
-            hipEventElapsedTime(&ms, r.a, r.b);
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
             auto& t = total[r.name];
             t.first += ms; t.second += 1;
             free_ev.push_back(r.a); free_ev.push_back(r.b);
@@ -42,7 +42,7 @@ struct Prof {
     }
     ~Prof() {
         collect();
-        for (auto e : free_ev) hipEventDestroy(e);
+        for (auto e : free_ev) (void)hipEventDestroy(e);
     }
 };
 
@@ -51,15 +51,16 @@ struct Prof {
     do {                                                                           \
         hipEvent_t ea_ = nullptr, eb_ = nullptr;                                   \
         if ((prof) && (prof)->on) { ea_ = (prof)->ev(); eb_ = (prof)->ev();        \
-                                    hipEventRecord(ea_, st); }                     \
+                                    (void)hipEventRecord(ea_, st); }               \
         hipLaunchKernelGGL(kern, grid, block, smem, st, __VA_ARGS__);              \
         hipError_t le_ = hipGetLastError();                                        \
         if (le_ != hipSuccess) {                                                   \
-            std::fprintf(stderr, "libmj: launch of %s failed: %s\n", name,        \
-                         hipGetErrorString(le_));                                  \
+            std::fprintf(stderr, "libmj: launch of %s failed: %s\n",              \
+                         std::string(name).c_str(), hipGetErrorString(le_));       \
             return MJ_ERR_HIP;                                                     \
         }                                                                          \
-        if (ea_) { hipEventRecord(eb_, st); (prof)->pending.push_back({name, ea_, eb_}); } \
+        if (ea_) { (void)hipEventRecord(eb_, st);                                  \
+                   (prof)->pending.push_back({std::string(name), ea_, eb_}); }     \
     } while (0)
 
 // ------------------------------------------------------------------ context
@@ -148,9 +149,9 @@ struct Bump {
 };
 
 struct TableLayout {                 // bucketed multiplicity tables of one column
+    uint32_t* hist;
     uint32_t* counts;
     uint32_t* starts;
-    uint32_t* cursor;
     uint32_t* keys;                  // the partitioned column
     DirEntry* dir;
     uint2* pool;
@@ -159,15 +160,17 @@ struct TableLayout {                 // bucketed multiplicity tables of one colu
     uint64_t pool_slots;
 };
 
+uint32_t ntiles_of(uint64_t n) { return (uint32_t)((n + PART_TILE - 1) / PART_TILE); }
+
 uint64_t pool_slots_for(uint64_t n, uint32_t nbkt) {
     return 4 * n + uint64_t(DB_MIN_CAP) * nbkt + DB_MIN_CAP;
 }
 
 void take_table(Bump& B, TableLayout& L, uint64_t n, uint32_t bits) {
     const uint32_t nb = 1u << bits;
+    L.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(n));
     L.counts = B.take<uint32_t>(nb);
     L.starts = B.take<uint32_t>(nb + 1);
-    L.cursor = B.take<uint32_t>(nb);
     L.keys = B.take<uint32_t>(std::max<uint64_t>(n, 1));
     L.dir = B.take<DirEntry>(nb);
     L.pool_slots = pool_slots_for(n, nb);
@@ -176,11 +179,23 @@ void take_table(Bump& B, TableLayout& L, uint64_t n, uint32_t bits) {
     L.err = B.take<uint32_t>(1);
 }
 
+struct RelPart {                     // one relation partitioned into 2^bits buckets
+    uint32_t* hist;
+    uint32_t* counts;
+    uint32_t* starts;
+    uint2* pairs;
+};
+
+void take_part(Bump& B, RelPart& P, uint64_t n, uint32_t bits) {
+    const uint32_t nb = 1u << bits;
+    P.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(n));
+    P.counts = B.take<uint32_t>(nb);
+    P.starts = B.take<uint32_t>(nb + 1);
+    P.pairs = B.take<uint2>(std::max<uint64_t>(n, 1));
+}
+
 struct LinearLayout {
-    uint2* Rp;
-    uint32_t* rcounts; uint32_t* rstarts; uint32_t* rcursor;
-    uint2* Sp;
-    uint32_t* scounts; uint32_t* sstarts; uint32_t* scursor;
+    RelPart R, S;
     TableLayout T;
     size_t bytes;
 };
@@ -188,17 +203,47 @@ struct LinearLayout {
 LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
     Bump B(ws);
     LinearLayout L;
-    const uint32_t nb = 1u << p.log2_nb;
-    L.Rp = B.take<uint2>(std::max<uint64_t>(p.n_r, 1));
-    L.rcounts = B.take<uint32_t>(nb);
-    L.rstarts = B.take<uint32_t>(nb + 1);
-    L.rcursor = B.take<uint32_t>(nb);
-    L.Sp = B.take<uint2>(std::max<uint64_t>(p.n_s, 1));
-    L.scounts = B.take<uint32_t>(nb);
-    L.sstarts = B.take<uint32_t>(nb + 1);
-    L.scursor = B.take<uint32_t>(nb);
+    take_part(B, L.R, p.n_r, p.log2_nb);
+    take_part(B, L.S, p.n_s, p.log2_nb);
     take_table(B, L.T, p.n_t, p.log2_nc);
     L.bytes = B.off + 256;
+    return L;
+}
+
+struct CascadeLayout {
+    RelPart R, S;
+    TableLayout T;
+    uint32_t* Rgrp;
+    uint32_t* ecnt;
+    uint32_t* elist;
+    unsigned long long* eoff;
+    unsigned long long* partial;
+    uint2* I;
+    uint64_t i_cap;               // pairs of I that fit the workspace
+    size_t base_bytes;            // everything but I
+};
+
+constexpr uint64_t CAS_DEFAULT_I_CAP = uint64_t(1) << 28;   // 2 GiB of (a, c) pairs
+
+CascadeLayout cascade_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
+    Bump B(ws);
+    CascadeLayout L;
+    take_part(B, L.R, p.n_r, p.log2_nb);
+    take_part(B, L.S, p.n_s, p.log2_nb);
+    take_table(B, L.T, p.n_t, p.log2_nc);
+    L.Rgrp = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+    L.ecnt = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.elist = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.eoff = B.take<unsigned long long>(p.n_s + 1);
+    const uint64_t nblk = (p.n_s + SCAN_TILE - 1) / SCAN_TILE;
+    L.partial = B.take<unsigned long long>(nblk + 1);
+    L.I = B.take<uint2>(0);
+    L.base_bytes = B.off + 256;
+    if (ws) {
+        L.i_cap = ws_bytes > L.base_bytes ? (ws_bytes - L.base_bytes) / sizeof(uint2) : 0;
+    } else {
+        L.i_cap = std::max<uint64_t>(1, std::min<uint64_t>(p.join2_size, CAS_DEFAULT_I_CAP));
+    }
     return L;
 }
 
@@ -212,42 +257,72 @@ uint32_t grid_for(uint64_t n, int threads, uint32_t cap = 65535) {
     return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, cap));
 }
 
+PartJob make_job(const mj_rel& r, uint32_t* hist, uint32_t* counts, uint32_t* starts,
+                 int key0, uint32_t seed0, uint32_t bits0, int key1, uint32_t seed1, uint32_t bits1) {
+    PartJob J{};
+    J.col0 = r.col0; J.col1 = r.col1; J.stride = r.stride; J.n = r.n;
+    J.packed = (r.stride == 2 && r.col1 == r.col0 + 1 &&
+                (reinterpret_cast<uintptr_t>(r.col0) & 15) == 0) ? 1u : 0u;
+    J.key0_col = key0; J.seed0 = seed0; J.bits0 = bits0;
+    J.key1_col = key1; J.seed1 = seed1; J.bits1 = bits1;
+    J.hist = hist; J.counts = counts; J.starts = starts;
+    J.ntiles = ntiles_of(r.n);
+    return J;
+}
+
+// Partition up to MJ_PART_MAX_JOBS relations (four launches in all).
+int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st) {
+    uint32_t tiles = 0, rows = 0, maxbits = 0;
+    for (int q = 0; q < P.njobs; ++q) {
+        P.job[q].tile_begin = tiles;
+        tiles += P.job[q].ntiles;
+        const uint32_t bits = P.job[q].bits0 + P.job[q].bits1;
+        rows += 1u << bits;
+        maxbits = std::max(maxbits, bits);
+    }
+    const std::string t(tag);
+    if (tiles)
+        MJ_LAUNCH(prof, t + ":k_part_hist", k_part_hist, dim3(tiles), dim3(PART_THREADS),
+                  (size_t(1) << maxbits) * 4, st, P);
+    MJ_LAUNCH(prof, t + ":k_part_rowscan", k_part_rowscan, dim3(rows), dim3(PART_THREADS),
+              PART_SCAN_CHUNK * 4, st, P);
+    MJ_LAUNCH(prof, t + ":k_part_scan", k_part_scan, dim3(P.njobs), dim3(PART_THREADS),
+              (size_t(1) << maxbits) * 4, st, P);
+    if (tiles)
+        MJ_LAUNCH(prof, t + ":k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_THREADS),
+                  part_scatter_smem(maxbits), st, P);
+    return MJ_OK;
+}
+
 // Partition T.c (or any single column) by bucket and build its tables.
 int launch_tables(Prof* prof, const TableLayout& L, const mj_rel& rel, int col, uint32_t bits,
                   uint32_t bseed, uint32_t sseed, hipStream_t st) {
     const uint32_t nb = 1u << bits;
-    MJ_LAUNCH(prof, "tab:k_fill_u32", k_fill_u32, dim3(grid_for(nb, 256)), dim3(256), 0, st, L.counts, (uint64_t)nb, 0u);
     MJ_LAUNCH(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.pool),
                        (uint64_t)(2 * DB_MIN_CAP), EMPTY_KEY);
-    // pool[0..DB_MIN_CAP) keys EMPTY, counts EMPTY too: counts are never read for
-    // an empty key.  cursor = DB_MIN_CAP; err = 0.
+    // pool[0..DB_MIN_CAP) stays empty (keys EMPTY); cursor = DB_MIN_CAP; err = 0
     MJ_LAUNCH(prof, "tab:k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, st, L.pool_cursor, (uint64_t)1,
                        (unsigned long long)DB_MIN_CAP);
     MJ_LAUNCH(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, L.err, (uint64_t)1, 0u);
 
     PartLaunch P{};
     P.njobs = 1;
-    PartJob& J = P.job[0];
-    J.col0 = rel.col0; J.col1 = rel.col1; J.stride = rel.stride; J.n = rel.n;
-    J.key0_col = col; J.key1_col = 0; J.seed0 = bseed; J.bits0 = bits; J.seed1 = 0; J.bits1 = 0;
-    J.counts = L.counts; J.starts = L.starts; J.cursor = L.cursor;
-    J.out_pair = nullptr; J.out_single = L.keys; J.single_col = col;
-    J.tile_begin = 0;
-    J.ntiles = (uint32_t)((rel.n + PART_TILE - 1) / PART_TILE);
-    if (J.ntiles) {
-        MJ_LAUNCH(prof, "tab:k_part_hist", k_part_hist, dim3(J.ntiles), dim3(PART_THREADS), nb * 4, st, P);
-    }
-    MJ_LAUNCH(prof, "tab:k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), nb * 4, st, P);
-    if (J.ntiles) {
-        MJ_LAUNCH(prof, "tab:k_part_scatter", k_part_scatter, dim3(J.ntiles), dim3(PART_THREADS),
-                           part_scatter_smem(bits), st, P);
-    }
+    P.job[0] = make_job(rel, L.hist, L.counts, L.starts, col, bseed, bits, 0, 0, 0);
+    P.job[0].out_single = L.keys;
+    P.job[0].single_col = col;
+    int st2 = launch_partition(prof, "tab", P, st);
+    if (st2) return st2;
     DBuildArgs D;
     D.keys = L.keys; D.starts = L.starts; D.nbkt = nb; D.slot_seed = sseed;
     D.dir = L.dir; D.pool = L.pool; D.pool_cursor = L.pool_cursor; D.pool_cap = L.pool_slots;
     D.err = L.err;
     MJ_LAUNCH(prof, "tab:k_dbuild", k_dbuild, dim3(nb), dim3(DB_THREADS), 0, st, D);
     return MJ_OK;
+}
+
+int cascade_triangle(mj_ctx*, const mj_rel*, const mj_rel*, const mj_rel*, uint64_t*,
+                     const mj_plan_t&, void*, uint64_t, void*) {
+    return MJ_ERR_UNSUPPORTED;
 }
 
 }  // namespace
@@ -284,9 +359,10 @@ int mj_ctx_create(int device, mj_ctx** out) {
     if (e != hipSuccess) { delete c; return MJ_ERR_HIP; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_scatter),
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)part_scatter_smem(PART_MAX_BITS));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_scatter),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)part_scatter_smem(PART_MAX_BITS));
+    (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
     e = hipMalloc(&c->stats, 4096);
     if (e != hipSuccess) { delete c; return MJ_ERR_HIP; }
     c->stats_bytes = 4096;
@@ -452,30 +528,18 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     // T: partition by g(C) and reduce each bucket to C -> multiplicity
     st = launch_tables(&ctx->prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
     if (st) return st;
-    // R and S: partition by the bucket of B (one launch for both)
-    MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(grid_for(nb, 256)), dim3(256), 0, s, L.rcounts, (uint64_t)nb, 0u);
-    MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(grid_for(nb, 256)), dim3(256), 0, s, L.scounts, (uint64_t)nb, 0u);
+    // R and S: partition by the bucket of B (one group of launches for both)
     PartLaunch P{};
     P.njobs = 2;
-    PartJob& JR = P.job[0];
-    JR.col0 = R->col0; JR.col1 = R->col1; JR.stride = R->stride; JR.n = R->n;
-    JR.key0_col = 1; JR.seed0 = seed_b(p); JR.bits0 = p.log2_nb;
-    JR.counts = L.rcounts; JR.starts = L.rstarts; JR.cursor = L.rcursor;
-    JR.out_pair = L.Rp; JR.tile_begin = 0;
-    JR.ntiles = (uint32_t)((R->n + PART_TILE - 1) / PART_TILE);
-    PartJob& JS = P.job[1];
-    JS.col0 = S->col0; JS.col1 = S->col1; JS.stride = S->stride; JS.n = S->n;
-    JS.key0_col = 0; JS.seed0 = seed_b(p); JS.bits0 = p.log2_nb;
-    JS.counts = L.scounts; JS.starts = L.sstarts; JS.cursor = L.scursor;
-    JS.out_pair = L.Sp; JS.tile_begin = JR.ntiles;
-    JS.ntiles = (uint32_t)((S->n + PART_TILE - 1) / PART_TILE);
-    const uint32_t tiles = JR.ntiles + JS.ntiles;
-    MJ_LAUNCH(&ctx->prof, "rs:k_part_hist", k_part_hist, dim3(tiles), dim3(PART_THREADS), nb * 4, s, P);
-    MJ_LAUNCH(&ctx->prof, "rs:k_part_scan", k_part_scan, dim3(2), dim3(PART_THREADS), nb * 4, s, P);
-    MJ_LAUNCH(&ctx->prof, "rs:k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_THREADS), part_scatter_smem(p.log2_nb), s, P);
+    P.job[0] = make_job(*R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[0].out_pair = L.R.pairs;
+    P.job[1] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[1].out_pair = L.S.pairs;
+    st = launch_partition(&ctx->prof, "rs", P, s);
+    if (st) return st;
     // cells: one workgroup per b-bucket
     LinearCellArgs C;
-    C.R = L.Rp; C.rstarts = L.rstarts; C.S = L.Sp; C.sstarts = L.sstarts;
+    C.R = L.R.pairs; C.rstarts = L.R.starts; C.S = L.S.pairs; C.sstarts = L.S.starts;
     C.ddir = L.T.dir; C.dpool = L.T.pool;
     C.c_seed = seed_c(p); C.c_bits = p.log2_nc; C.slot_seed = seed_slot(p);
     C.w_seed = seed_w(p);
@@ -491,9 +555,71 @@ int mj_triangle3_count(mj_ctx*, const mj_rel*, const mj_rel*, const mj_rel*, uin
     return MJ_ERR_UNSUPPORTED;
 }
 
-int mj_cascade2_count(mj_ctx*, int, const mj_rel*, const mj_rel*, const mj_rel*, uint32_t,
-                      uint64_t*, const mj_plan_t*, void*, uint64_t, void*) {
-    return MJ_ERR_UNSUPPORTED;
+int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                      uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
+                      void* ws, uint64_t ws_bytes, void* stream) {
+    if (!ctx || !plan || !out) return MJ_ERR_INVALID_ARG;
+    int st;
+    if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
+    if (kind != MJ_LINEAR && kind != MJ_TRIANGLE) return MJ_ERR_INVALID_ARG;
+    const mj_plan_t& p = *plan;
+    if (p.kind != kind || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n ||
+        (kind == MJ_LINEAR && p.a_domain != a_domain))
+        return MJ_ERR_PLAN_MISMATCH;
+    if (kind == MJ_TRIANGLE) return cascade_triangle(ctx, R, S, T, out, p, ws, ws_bytes, stream);
+    if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
+    if (!ws) return MJ_ERR_WORKSPACE;
+    CascadeLayout L = cascade_layout(ws, p, ws_bytes);
+    if (ws_bytes < L.base_bytes || (p.join2_size && L.i_cap == 0)) return MJ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(out);
+
+    if (a_domain)
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+                  count, (uint64_t)a_domain, 0ull);
+    if (R->n == 0 || S->n == 0 || T->n == 0 || p.join2_size == 0) return MJ_OK;
+
+    // join 2's build side: T partitioned by C, one multiplicity table per bucket
+    st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
+    if (st) return st;
+    // join 1: R and S partitioned by B
+    const uint32_t nb = 1u << p.log2_nb;
+    PartLaunch P{};
+    P.njobs = 2;
+    P.job[0] = make_job(*R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[0].out_pair = L.R.pairs;
+    P.job[1] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[1].out_pair = L.S.pairs;
+    st = launch_partition(prof, "rs", P, s);
+    if (st) return st;
+    CasIndexArgs X;
+    X.R = L.R.pairs; X.rstarts = L.R.starts; X.S = L.S.pairs; X.sstarts = L.S.starts;
+    X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
+    MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
+    const uint32_t nblk = (uint32_t)((S->n + SCAN_TILE - 1) / SCAN_TILE);
+    MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s,
+              L.ecnt, (uint64_t)S->n, L.partial);
+    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s,
+              L.partial, nblk);
+    MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s,
+              L.ecnt, (uint64_t)S->n, L.partial, L.eoff);
+    // the intermediate, chunk by chunk: materialise, then join with T
+    const uint64_t total = p.join2_size;
+    for (uint64_t lo = 0; lo < total; lo += L.i_cap) {
+        const uint64_t hi = std::min<uint64_t>(total, lo + L.i_cap);
+        CasExpandArgs E;
+        E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.S.pairs; E.ns = S->n;
+        E.lo = lo; E.hi = hi; E.I = L.I;
+        MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
+                  dim3(EXP_THREADS), 0, s, E);
+        CasProbeArgs Q;
+        Q.I = L.I; Q.n = hi - lo; Q.ddir = L.T.dir; Q.dpool = L.T.pool;
+        Q.c_seed = seed_c(p); Q.c_bits = p.log2_nc; Q.slot_seed = seed_slot(p);
+        Q.count = count; Q.a_domain = a_domain; Q.err = L.T.err;
+        MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
+    }
+    return MJ_OK;
 }
 
 }  // extern "C"
@@ -509,8 +635,12 @@ uint32_t join2_bits(uint64_t n) {
 
 int plan_workspace(mj_plan_t& p) {
     if (p.kind == MJ_LINEAR) {
-        size_t lin = linear_layout(nullptr, p).bytes;
-        p.workspace_bytes = lin;
+        const size_t lin = linear_layout(nullptr, p).bytes;
+        const CascadeLayout C = cascade_layout(nullptr, p, 0);
+        const size_t cas = C.base_bytes + C.i_cap * sizeof(uint2) + 256;
+        // enough for whichever algorithm the plan picked, and for the other
+        // one when the caller runs both on the same plan
+        p.workspace_bytes = std::max(lin, cas);
     } else {
         p.workspace_bytes = 256;
     }
@@ -524,8 +654,11 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu) {
     if (kind == MJ_LINEAR) {
         // b-buckets: about 2048 S tuples per cell; c-buckets: about 4096 T
         // tuples per multiplicity table
-        p.log2_nb = std::min<uint32_t>(PART_MAX_BITS, ceil_log2((p.n_s + 2047) / 2048));
-        p.log2_nc = std::min<uint32_t>(PART_MAX_BITS, ceil_log2((p.n_t + 4095) / 4096));
+        // b-buckets: about 32K S tuples per cell (enough cells to fill the
+        // chip, few enough for long partition runs); c-buckets: about 32K T
+        // tuples per multiplicity table
+        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 32767) / 32768));
+        p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
     } else {
         p.log2_share = 3;
     }

@@ -182,26 +182,32 @@ k_linear_cell(LinearCellArgs A) {
     const int nthr = blockDim.x;
 
     if (threadIdx.x == 0) { s_sp = 1; st_level[0] = 0; st_pass[0] = 0; }
-    __syncthreads();
-    while (s_sp > 0) {
-        const uint32_t level = st_level[s_sp - 1];
-        const uint32_t pass = st_pass[s_sp - 1];
+    while (true) {
+        // every wave reads the top of the pass stack before thread 0 pops it
+        __syncthreads();
+        const int sp = s_sp;
+        if (sp == 0) break;
+        const uint32_t level = st_level[sp - 1];
+        const uint32_t pass = st_pass[sp - 1];
         for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) { wkeys[s] = EMPTY_KEY; wvals[s] = 0; }
-        if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; --s_sp; }
+        __syncthreads();
+        if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; s_sp = sp - 1; }
         __syncthreads();
 
         // phase 1: W[b] += mult_T(c) over the S tuples of this (sub-)bucket
         for (uint32_t q = s0 + threadIdx.x; q < s1; q += 4 * nthr) {
             if (*(volatile uint32_t*)&s_over) break;
             uint2 sv[4];
-            uint32_t w[4];
+            uint32_t w[4], cc[4];
+            bool live[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 uint32_t idx = q + u * nthr;
                 sv[u] = idx < s1 ? A.S[idx] : make_uint2(0u, 0u);
-                bool live = idx < s1 && (level == 0 || pass_of(sv[u].x, A.w_seed, level) == pass);
-                w[u] = live ? dtab_lookup(A.ddir, A.dpool, sv[u].y, A.c_seed, A.c_bits, A.slot_seed) : 0u;
+                live[u] = idx < s1 && (level == 0 || pass_of(sv[u].x, A.w_seed, level) == pass);
+                cc[u] = sv[u].y;
             }
+            dtab_lookup4(A.ddir, A.dpool, cc, live, A.c_seed, A.c_bits, A.slot_seed, w);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (w[u] == 0) continue;
@@ -229,12 +235,13 @@ k_linear_cell(LinearCellArgs A) {
         }
         __syncthreads();
         if (s_over) {
-            // too many distinct B values: split this pass in two by one more hash bit
+            // too many distinct B values: split this pass in two by one more
+            // hash bit (the barrier at the loop head orders the push)
             if (threadIdx.x == 0) {
-                st_level[s_sp] = level + 1; st_pass[s_sp] = 2 * pass + 1; ++s_sp;
-                st_level[s_sp] = level + 1; st_pass[s_sp] = 2 * pass;     ++s_sp;
+                st_level[sp - 1] = level + 1; st_pass[sp - 1] = 2 * pass + 1;
+                st_level[sp] = level + 1;     st_pass[sp] = 2 * pass;
+                s_sp = sp + 1;
             }
-            __syncthreads();
             continue;
         }
         // phase 2: count[r.a] += W[r.b] over the R tuples of this (sub-)bucket
@@ -259,7 +266,6 @@ k_linear_cell(LinearCellArgs A) {
                 else atomicExch(A.err, 1u);     // key outside [0, a_domain): reported, not written
             }
         }
-        __syncthreads();
     }
 }
 

@@ -5,6 +5,9 @@
 
 namespace mj {
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int WAVE = 64;
 constexpr uint32_t EMPTY_KEY = 0xFFFFFFFFu;   // LDS/global table sentinel; the real
                                               // key 0xFFFFFFFF is kept in a side slot
@@ -25,7 +28,7 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t k, uint32_t seed) {
 
 // Bucket from the top `bits` bits of a hash (bits may be 0: one bucket).
 __host__ __device__ __forceinline__ uint32_t top_bits(uint32_t h, uint32_t bits) {
-    return bits == 0 ? 0u : (h >> (32u - bits));
+    return bits == 0 ? 0u : (bits >= 32 ? h : (h >> (32u - bits)));
 }
 
 // Second, independent hash for table slots inside a bucket.
@@ -57,6 +60,38 @@ __device__ __forceinline__ uint32_t ld_col(const uint32_t* __restrict__ col, uin
 __device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long* p,
                                                              unsigned long long v) {
     return atomicAdd(p, v);
+}
+
+// Block-wide exclusive scan of lds[0..n), in place; returns the total.
+// All threads of the block must call it.
+__device__ inline uint32_t block_exclusive_scan(uint32_t* lds, uint32_t n, uint32_t* wave_tmp) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint32_t b = min(n, t * per), e = min(n, b + per);
+    uint32_t s = 0;
+    for (uint32_t i = b; i < e; ++i) s += lds[i];
+    uint32_t v = s;
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        uint32_t y = __shfl_up(v, off, WAVE);
+        if (lane >= off) v += y;
+    }
+    const int w = t / WAVE, nw = blockDim.x / WAVE;
+    if (lane == WAVE - 1) wave_tmp[w] = v;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int q = 0; q < nw; ++q) { uint32_t x = wave_tmp[q]; wave_tmp[q] = run; run += x; }
+        wave_tmp[nw] = run;
+    }
+    __syncthreads();
+    uint32_t excl = v - s + wave_tmp[w];
+    for (uint32_t i = b; i < e; ++i) { uint32_t x = lds[i]; lds[i] = excl; excl += x; }
+    __syncthreads();
+    uint32_t total = wave_tmp[nw];
+    __syncthreads();
+    return total;
 }
 
 }  // namespace mj

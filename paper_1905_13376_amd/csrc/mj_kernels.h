@@ -5,8 +5,21 @@
 namespace mj {
 
 // ---------------------------------------------------------------- partition
-constexpr int PART_THREADS = 256;
-constexpr int PART_TILE = 4096;          // tuples per block
+#ifndef MJ_PART_THREADS
+#define MJ_PART_THREADS 512
+#endif
+#ifndef MJ_PART_TILE
+#define MJ_PART_TILE 8192
+#endif
+#ifndef MJ_DB_THREADS
+#define MJ_DB_THREADS 512
+#endif
+#ifndef MJ_CELL_THREADS
+#define MJ_CELL_THREADS 512
+#endif
+constexpr int PART_THREADS = MJ_PART_THREADS;
+constexpr int PART_TILE = MJ_PART_TILE;  // tuples per block (<= 2^16)
+constexpr int PART_SCAN_CHUNK = 4096;    // row-scan chunk (LDS entries)
 constexpr int MJ_PART_MAX_JOBS = 4;
 constexpr uint32_t PART_MAX_BITS = 12;   // at most 4096 buckets per pass
 
@@ -15,15 +28,16 @@ struct PartJob {
     const uint32_t* col1;
     int64_t stride;
     uint64_t n;
+    uint32_t packed;     // stride 2, col1 == col0 + 1, 16-byte aligned: 16-byte loads
     uint32_t key0_col;   // column (0/1) hashed for the first digit
     uint32_t key1_col;   // column hashed for the second digit (bits1 > 0)
     uint32_t seed0, bits0;
     uint32_t seed1, bits1;
-    uint32_t* counts;    // [nb] zeroed before the hist pass
-    uint32_t* starts;    // [nb + 1]
-    uint32_t* cursor;    // [nb]
+    uint32_t* hist;      // [nb][ntiles] per-tile counts, then run offsets
+    uint32_t* counts;    // [nb] bucket sizes
+    uint32_t* starts;    // [nb + 1] bucket starts
     uint2* out_pair;     // both columns as (col0, col1), or
-    uint32_t* out_single;// one column (single_col) when out_pair == nullptr
+    uint32_t* out_single;// one column (single_col, also the bucketed column)
     uint32_t single_col;
     uint32_t tile_begin; // first block of this job in the grid
     uint32_t ntiles;
@@ -35,6 +49,7 @@ struct PartLaunch {
 };
 
 __global__ void k_part_hist(PartLaunch L);
+__global__ void k_part_rowscan(PartLaunch L);
 __global__ void k_part_scan(PartLaunch L);
 __global__ void k_part_scatter(PartLaunch L);
 size_t part_scatter_smem(uint32_t max_bits);
@@ -48,9 +63,12 @@ struct DirEntry {
     uint32_t special;            // multiplicity of key 0xFFFFFFFF in this bucket
 };
 
-constexpr int DB_THREADS = 256;
+constexpr int DB_THREADS = MJ_DB_THREADS;
 constexpr uint32_t DB_CAP = 8192;                  // LDS slots per build
-constexpr uint32_t DB_LIMIT = DB_CAP - DB_CAP / 8; // distinct keys before spilling
+// distinct keys before spilling; after the flag each thread claims at most
+// one more slot, so the table keeps at least one empty slot
+constexpr uint32_t DB_LIMIT = DB_CAP - (DB_CAP / 8 > DB_THREADS ? DB_CAP / 8 : DB_THREADS) - 1;
+static_assert(DB_LIMIT + DB_THREADS < DB_CAP, "LDS table slack");
 constexpr uint32_t DB_MIN_CAP = 16;
 
 struct DBuildArgs {
@@ -85,10 +103,47 @@ __device__ __forceinline__ uint32_t dtab_lookup(const DirEntry* __restrict__ dir
     }
 }
 
+// Four independent lookups: the directory loads, then the first slot loads
+// are issued together so that four table reads are in flight per lane;
+// only keys that collide walk further.
+__device__ __forceinline__ void dtab_lookup4(const DirEntry* __restrict__ dir,
+                                             const uint2* __restrict__ pool,
+                                             const uint32_t (&key)[4], const bool (&live)[4],
+                                             uint32_t bkt_seed, uint32_t bkt_bits,
+                                             uint32_t slot_seed, uint32_t (&out)[4]) {
+    DirEntry e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (live[u]) e[u] = dir[top_bits(mix32(key[u], bkt_seed), bkt_bits)];
+    uint32_t s[4];
+    uint2 kv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (live[u] && key[u] != EMPTY_KEY) {
+            s[u] = slot_hash(key[u], slot_seed) & ((1u << e[u].log2cap) - 1u);
+            kv[u] = pool[e[u].offset + s[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (!live[u]) { out[u] = 0u; continue; }
+        if (key[u] == EMPTY_KEY) { out[u] = e[u].special; continue; }
+        const uint32_t mask = (1u << e[u].log2cap) - 1u;
+        uint2 v = kv[u];
+        uint32_t t = s[u];
+        while (v.x != key[u] && v.x != EMPTY_KEY) {
+            t = (t + 1u) & mask;
+            v = pool[e[u].offset + t];
+        }
+        out[u] = v.x == key[u] ? v.y : 0u;
+    }
+}
+
 // --------------------------------------------------------- linear cells
-constexpr int CELL_THREADS = 256;
+constexpr int CELL_THREADS = MJ_CELL_THREADS;
 constexpr uint32_t CELL_CAP = 4096;                      // W-table slots (LDS)
-constexpr uint32_t CELL_LIMIT = CELL_CAP - CELL_CAP / 8;
+constexpr uint32_t CELL_LIMIT = CELL_CAP - (CELL_CAP / 8 > CELL_THREADS ? CELL_CAP / 8 : CELL_THREADS) - 1;
+static_assert(CELL_LIMIT + CELL_THREADS < CELL_CAP, "LDS table slack");
 
 struct LinearCellArgs {
     const uint2* R;              // partitioned (a, b) by bucket of b
@@ -116,6 +171,56 @@ struct ProbeSumArgs {
     unsigned long long* total;
 };
 __global__ void k_probe_sum(ProbeSumArgs A);
+
+// ------------------------------------------------------------- cascade
+constexpr int CAS_THREADS = 512;
+constexpr uint32_t CAS_CAP = 4096;
+constexpr uint32_t CAS_LIMIT = CAS_CAP - (CAS_CAP / 8 > CAS_THREADS ? CAS_CAP / 8 : CAS_THREADS) - 1;
+static_assert(CAS_LIMIT + CAS_THREADS < CAS_CAP, "LDS table slack");
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_TILE = 4096;
+constexpr int EXP_THREADS = 256;
+constexpr int EXP_TILE = 4096;
+
+struct CasIndexArgs {
+    const uint2* R;              // partitioned (a, b) by bucket of b
+    const uint32_t* rstarts;
+    const uint2* S;              // partitioned (b, c) by bucket of b
+    const uint32_t* sstarts;
+    uint32_t* Rgrp;              // A values of R grouped by B inside each bucket
+    uint32_t* ecnt;              // per S tuple: |{r : r.b = s.b}|
+    uint32_t* elist;             // per S tuple: start of its list in Rgrp
+    uint32_t seed;
+};
+__global__ void k_cas_index(CasIndexArgs A);
+
+struct CasExpandArgs {
+    const unsigned long long* eoff;   // [ns + 1] exclusive scan of ecnt
+    const uint32_t* elist;
+    const uint32_t* Rgrp;
+    const uint2* S;
+    uint64_t ns;
+    unsigned long long lo, hi;        // chunk of I positions
+    uint2* I;                         // [hi - lo]
+};
+__global__ void k_cas_expand(CasExpandArgs A);
+
+struct CasProbeArgs {
+    const uint2* I;
+    uint64_t n;
+    const DirEntry* ddir;
+    const uint2* dpool;
+    uint32_t c_seed, c_bits, slot_seed;
+    unsigned long long* count;
+    uint32_t a_domain;
+    uint32_t* err;
+};
+__global__ void k_cas_probe(CasProbeArgs A);
+
+__global__ void k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial);
+__global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
+__global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
+                             unsigned long long* out);
 
 // max of a column (key-range check)
 __global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out);

@@ -2,16 +2,22 @@
 // radix digits of robust hashes of their join columns; the paper leaves the
 // partitioner's implementation open).
 //
-// Two passes over each relation, both coalesced:
-//   k_part_hist    : per-tile LDS histogram of bucket ids -> global bucket counts
-//   k_part_scan    : exclusive scan of the bucket counts -> bucket starts, cursors
-//   k_part_scatter : per tile, tuples are placed in LDS grouped by bucket
-//                    (local rank from LDS atomics), one global atomic per
-//                    bucket reserves the tile's run, then the staged tile is
-//                    written out linearly, so consecutive lanes store
-//                    consecutive addresses inside each bucket run.
-// Order inside a bucket is not specified (the joins are order-insensitive).
-// Up to MJ_PART_MAX_JOBS relations are partitioned by one launch.
+// Three launches per group of relations, none with a global atomic:
+//   k_part_hist    : per tile, an LDS histogram of bucket ids, stored as
+//                    column `tile` of a bucket-major matrix hist[d][tile]
+//   k_part_rowscan : per bucket, the exclusive prefix of its row over tiles
+//                    (in place) and the row total
+//   k_part_scan    : per relation, the exclusive prefix of the bucket totals
+//                    (bucket starts)
+//   k_part_scatter : per tile, tuples are grouped by bucket in LDS (local
+//                    rank by LDS atomics), then the staged tile is written
+//                    out linearly: lane p stores element p of the tile's
+//                    bucket-sorted order at starts[d] + hist[d][tile] + rank,
+//                    so consecutive lanes store consecutive addresses inside
+//                    every (tile, bucket) run.
+// Tiles hold PART_TILE tuples; with at most 2^PART_MAX_BITS buckets a
+// (tile, bucket) run averages >= 8 tuples.  Packed [n, 2] inputs are read
+// with 16-byte loads.  Order inside a bucket is not specified.
 #include "mj_kernels.h"
 
 namespace mj {
@@ -34,6 +40,42 @@ __device__ __forceinline__ int find_job(const PartLaunch& L, uint32_t blk) {
     return j;
 }
 
+// Load the tile's tuples into registers: item k of thread t is tuple
+// beg + t*2 + (k&1) + (k>>1)*2*blockDim for packed inputs (two tuples per
+// 16-byte load), beg + t + k*blockDim otherwise.
+template <int ITEMS>
+__device__ __forceinline__ void load_tile(const PartJob& J, uint64_t beg, uint32_t cnt,
+                                          uint32_t (&x0)[ITEMS], uint32_t (&x1)[ITEMS],
+                                          uint32_t (&idx)[ITEMS]) {
+    const uint32_t t = threadIdx.x, B = blockDim.x;
+    if (J.packed) {
+        const u32x4* src = reinterpret_cast<const u32x4*>(J.col0 + 2 * beg);
+#pragma unroll
+        for (int k = 0; k < ITEMS; k += 2) {
+            const uint32_t i = 2 * t + (k >> 1) * 2 * B;   // first of two tuples
+            idx[k] = i;
+            idx[k + 1] = i + 1;
+            if (i + 1 < cnt) {
+                u32x4 v = __builtin_nontemporal_load(src + (i >> 1));
+                x0[k] = v.x; x1[k] = v.y; x0[k + 1] = v.z; x1[k + 1] = v.w;
+            } else if (i < cnt) {
+                x0[k] = J.col0[2 * (beg + i)];
+                x1[k] = J.col0[2 * (beg + i) + 1];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t i = t + k * B;
+            idx[k] = i;
+            if (i < cnt) {
+                x0[k] = ld_col(J.col0, beg + i, J.stride);
+                x1[k] = ld_col(J.col1, beg + i, J.stride);
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(PART_THREADS)
 k_part_hist(PartLaunch L) {
     extern __shared__ uint32_t lhist[];
@@ -42,56 +84,52 @@ k_part_hist(PartLaunch L) {
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lhist[d] = 0;
     __syncthreads();
-    const uint64_t tile = blockIdx.x - J.tile_begin;
-    const uint64_t beg = tile * PART_TILE;
-    const uint64_t end = min<uint64_t>(beg + PART_TILE, J.n);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        uint32_t x0 = ld_col(J.col0, i, J.stride);
-        uint32_t x1 = ld_col(J.col1, i, J.stride);
-        atomicAdd(&lhist[part_bucket(J, x0, x1)], 1u);
-    }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
-        uint32_t c = lhist[d];
-        if (c) atomicAdd(&J.counts[d], c);
-    }
-}
-
-// Block-wide exclusive scan of lds[0..n) (n <= PART_THREADS * 32), in place;
-// returns the total.  All threads of the block must call it.
-__device__ uint32_t block_exclusive_scan(uint32_t* lds, uint32_t n, uint32_t* wave_tmp) {
-    const uint32_t t = threadIdx.x;
-    const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-    const uint32_t b = min(n, t * per), e = min(n, b + per);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += lds[i];
-    // inclusive scan of s over the block
-    uint32_t v = s;
-    const int lane = lane_id();
+    const uint32_t tile = blockIdx.x - J.tile_begin;
+    const uint64_t beg = uint64_t(tile) * PART_TILE;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(PART_TILE, J.n - beg);
+    constexpr int ITEMS = PART_TILE / PART_THREADS;
+    uint32_t x0[ITEMS], x1[ITEMS], idx[ITEMS];
+    load_tile<ITEMS>(J, beg, cnt, x0, x1, idx);
 #pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        uint32_t y = __shfl_up(v, off, WAVE);
-        if (lane >= off) v += y;
-    }
-    const int w = t / WAVE, nw = blockDim.x / WAVE;
-    if (lane == WAVE - 1) wave_tmp[w] = v;
+    for (int k = 0; k < ITEMS; ++k)
+        if (idx[k] < cnt) atomicAdd(&lhist[part_bucket(J, x0[k], x1[k])], 1u);
     __syncthreads();
-    if (t == 0) {
-        uint32_t run = 0;
-        for (int q = 0; q < nw; ++q) { uint32_t x = wave_tmp[q]; wave_tmp[q] = run; run += x; }
-        wave_tmp[nw] = run;
-    }
-    __syncthreads();
-    uint32_t excl = v - s + wave_tmp[w];
-    for (uint32_t i = b; i < e; ++i) { uint32_t x = lds[i]; lds[i] = excl; excl += x; }
-    __syncthreads();
-    uint32_t total = wave_tmp[nw];
-    __syncthreads();
-    return total;
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x)
+        J.hist[uint64_t(d) * J.ntiles + tile] = lhist[d];
 }
 
-// One block per job: starts[d] = exclusive prefix of counts, starts[nb] = n,
-// cursor[d] = starts[d].
+// grid = sum over jobs of nb; block = one bucket row of one job.
+__global__ void __launch_bounds__(PART_THREADS)
+k_part_rowscan(PartLaunch L) {
+    __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
+    __shared__ uint32_t carry;
+    int jid = 0;
+    uint32_t row = blockIdx.x;
+    for (int q = 0; q < L.njobs; ++q) {
+        const uint32_t nbq = 1u << (L.job[q].bits0 + L.job[q].bits1);
+        if (row < nbq) { jid = q; break; }
+        row -= nbq;
+    }
+    const PartJob& J = L.job[jid];
+    uint32_t* h = J.hist + uint64_t(row) * J.ntiles;
+    extern __shared__ uint32_t chunk[];           // PART_SCAN_CHUNK entries
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < J.ntiles; c0 += PART_SCAN_CHUNK) {
+        const uint32_t m = min<uint32_t>(PART_SCAN_CHUNK, J.ntiles - c0);
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) chunk[i] = h[c0 + i];
+        __syncthreads();
+        const uint32_t tot = block_exclusive_scan(chunk, m, wave_tmp);
+        const uint32_t base = carry;
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) h[c0 + i] = chunk[i] + base;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = base + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) J.counts[row] = carry;
+}
+
+// One block per job: starts[d] = exclusive prefix of counts, starts[nb] = n.
 __global__ void __launch_bounds__(PART_THREADS)
 k_part_scan(PartLaunch L) {
     extern __shared__ uint32_t lds[];
@@ -101,10 +139,7 @@ k_part_scan(PartLaunch L) {
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = J.counts[d];
     __syncthreads();
     uint32_t total = block_exclusive_scan(lds, nb, wave_tmp);
-    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
-        J.starts[d] = lds[d];
-        J.cursor[d] = lds[d];
-    }
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) J.starts[d] = lds[d];
     if (threadIdx.x == 0) J.starts[nb] = total;
 }
 
@@ -117,71 +152,66 @@ k_part_scatter(PartLaunch L) {
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
     uint32_t* lcount = smem;                 // [nb]  counts, then local starts
     uint32_t* gbase = smem + nb;             // [nb]  global run start per bucket
-    uint2* stage = reinterpret_cast<uint2*>(smem + 2 * nb);          // [PART_TILE]
-    uint16_t* stage_d = reinterpret_cast<uint16_t*>(stage + PART_TILE);  // [PART_TILE]
+    uint32_t* stage = smem + 2 * nb;         // [PART_TILE] (x2 words for pairs)
 
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lcount[d] = 0;
     __syncthreads();
-    const uint64_t tile = blockIdx.x - J.tile_begin;
-    const uint64_t beg = tile * PART_TILE;
+    const uint32_t tile = blockIdx.x - J.tile_begin;
+    const uint64_t beg = uint64_t(tile) * PART_TILE;
     const uint32_t cnt = (uint32_t)min<uint64_t>(PART_TILE, J.n - beg);
 
     constexpr int ITEMS = PART_TILE / PART_THREADS;
-    uint32_t x0[ITEMS], x1[ITEMS], dd[ITEMS], rk[ITEMS];
+    uint32_t x0[ITEMS], x1[ITEMS], idx[ITEMS], rk[ITEMS];
+    load_tile<ITEMS>(J, beg, cnt, x0, x1, idx);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        uint32_t i = threadIdx.x + k * PART_THREADS;
-        if (i < cnt) {
-            x0[k] = ld_col(J.col0, beg + i, J.stride);
-            x1[k] = ld_col(J.col1, beg + i, J.stride);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        uint32_t i = threadIdx.x + k * PART_THREADS;
-        if (i < cnt) {
-            dd[k] = part_bucket(J, x0[k], x1[k]);
-            rk[k] = atomicAdd(&lcount[dd[k]], 1u);
+        if (idx[k] < cnt) {
+            const uint32_t d = part_bucket(J, x0[k], x1[k]);
+            rk[k] = (d << 16) | atomicAdd(&lcount[d], 1u);   // PART_TILE <= 2^16
         }
     }
     __syncthreads();
-    // reserve this tile's run in every non-empty bucket, then turn counts
-    // into local starts
-    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
-        uint32_t c = lcount[d];
-        gbase[d] = c ? atomicAdd(&J.cursor[d], c) : 0u;
-    }
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x)
+        gbase[d] = J.starts[d] + J.hist[uint64_t(d) * J.ntiles + tile];
     block_exclusive_scan(lcount, nb, wave_tmp);
+    const bool pair = J.out_pair != nullptr;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        uint32_t i = threadIdx.x + k * PART_THREADS;
-        if (i < cnt) {
-            uint32_t p = lcount[dd[k]] + rk[k];
-            stage[p] = make_uint2(x0[k], x1[k]);
-            stage_d[p] = (uint16_t)dd[k];
+        if (idx[k] < cnt) {
+            const uint32_t d = rk[k] >> 16;
+            const uint32_t p = lcount[d] + (rk[k] & 0xFFFFu);
+            if (pair) {
+                reinterpret_cast<uint2*>(stage)[p] = make_uint2(x0[k], x1[k]);
+            } else {
+                stage[p] = J.single_col ? x1[k] : x0[k];
+            }
         }
     }
     __syncthreads();
-    if (J.out_pair) {
-        uint2* out = J.out_pair;
+    // write out in bucket-sorted order; the bucket of element p is recomputed
+    // from its key (a binary search over lcount would cost as much)
+    if (pair) {
+        const uint2* st = reinterpret_cast<const uint2*>(stage);
         for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
-            uint32_t d = stage_d[p];
-            out[gbase[d] + (p - lcount[d])] = stage[p];
+            const uint2 v = st[p];
+            const uint32_t d = part_bucket(J, v.x, v.y);
+            u32x2 w; w.x = v.x; w.y = v.y;
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(J.out_pair) + gbase[d] + (p - lcount[d]));
         }
     } else {
-        uint32_t* out = J.out_single;
-        const bool second = J.single_col != 0;
+        // single-column payloads are only used with a one-column bucket id
+        // computed from that same column
         for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
-            uint32_t d = stage_d[p];
-            uint2 v = stage[p];
-            out[gbase[d] + (p - lcount[d])] = second ? v.y : v.x;
+            const uint32_t v = stage[p];
+            const uint32_t d = top_bits(mix32(v, J.seed0), J.bits0);
+            __builtin_nontemporal_store(v, J.out_single + gbase[d] + (p - lcount[d]));
         }
     }
 }
 
 size_t part_scatter_smem(uint32_t max_bits) {
     size_t nb = size_t(1) << max_bits;
-    return nb * 8 + size_t(PART_TILE) * 10;
+    return nb * 8 + size_t(PART_TILE) * 8;
 }
 
 }  // namespace mj

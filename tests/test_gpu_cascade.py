@@ -1,0 +1,128 @@
+"""GPU parity of the binary cascade (Sec. 6.3): materialised I = R |x| S,
+then I |x| T counted per A.  Bit-exact against the oracle, and equal to the
+three-way join on the same inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import brute
+from tests.gpu_util import banner, dev, fixed_plan
+from workloads import generators as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mj():
+    import paper_1905_13376_amd as mj
+    return mj
+
+
+@pytest.fixture(scope="module")
+def ctx(mj):
+    c = mj.Context()
+    yield c
+    c.close()
+
+
+def cascade(mj, ctx, R, S, T, a_domain, plan=None, workspace=None):
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    out = ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, a_domain, plan=plan, workspace=workspace)
+    return mj.as_u64(out)
+
+
+def test_cascade_linear_small(mj, ctx):
+    banner("cascade linear 65,536 uniform tuples")
+    F = G.linear_small()
+    Fd = dev(F)
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, 4096))
+    want = oracle.linear3_count(F, F, F, 4096)
+    np.testing.assert_array_equal(got, want)
+    three = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 4096))
+    np.testing.assert_array_equal(got, three)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_cascade_random_bags(mj, ctx, seed):
+    banner(f"cascade random bags seed={seed}")
+    rng = np.random.default_rng(40 + seed)
+    dom = [4, 60, 900, 50000, 7][seed]
+    R = rng.integers(0, dom, size=(int(rng.integers(1, 20000)), 2)).astype(np.uint32)
+    S = rng.integers(0, dom, size=(int(rng.integers(1, 20000)), 2)).astype(np.uint32)
+    T = rng.integers(0, dom, size=(int(rng.integers(1, 20000)), 2)).astype(np.uint32)
+    special = np.array([0xFFFFFFFF, 0x80000000], dtype=np.uint32)
+    for X, col in ((R, 1), (S, 0), (S, 1), (T, 0)):
+        m = rng.random(X.shape[0]) < 0.05
+        X[m, col] = special[rng.integers(0, 2, size=m.sum())]
+    np.testing.assert_array_equal(cascade(mj, ctx, R, S, T, dom), oracle.linear3_count(R, S, T, dom))
+
+
+def test_cascade_many_chunks(mj, ctx):
+    """A workspace that holds only a slice of I: the intermediate is made and
+    consumed in many chunks."""
+    import torch
+    banner("cascade chunked intermediate")
+    F = G.linear_powerlaw(seed=77, n_vertices=1 << 12, m=1 << 16)
+    Fd = dev(F)
+    p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, 1 << 12)
+    assert p.join2_size == oracle.join2_size(F, F)
+    full = p.workspace_bytes
+    # room for ~1/7 of the intermediate
+    need = full - 8 * min(p.join2_size, 1 << 28) + 8 * (p.join2_size // 7 + 3)
+    ws = torch.empty(int(need), dtype=torch.uint8, device="cuda")
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, 1 << 12, plan=p, workspace=ws))
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 1 << 12))
+
+
+def test_cascade_single_bucket_overflow(mj, ctx):
+    banner("cascade single-bucket split passes")
+    rng = np.random.default_rng(9)
+    n = 40000
+    R = np.stack([rng.integers(0, 300, n), rng.integers(0, 30000, n)], 1).astype(np.uint32)
+    S = np.stack([rng.integers(0, 30000, n), rng.integers(0, 20000, n)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, 20000, n), rng.integers(0, 5, n)], 1).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    p = fixed_plan(mj, ctx, mj.LINEAR, Rd, Sd, Td, 300, log2_nb=0, log2_nc=0, seed=5, algo=1)
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 300, plan=p))
+    np.testing.assert_array_equal(got, oracle.linear3_count(R, S, T, 300))
+
+
+def test_cascade_hub_keys(mj, ctx):
+    """A few B values joined with thousands of tuples on both sides (one
+    list expands over many workgroups)."""
+    banner("cascade hub keys")
+    rng = np.random.default_rng(3)
+    R = np.stack([rng.integers(0, 1000, 30000), rng.integers(0, 4, 30000)], 1).astype(np.uint32)
+    S = np.stack([rng.integers(0, 4, 20000), rng.integers(0, 100, 20000)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, 100, 5000), rng.integers(0, 100, 5000)], 1).astype(np.uint32)
+    np.testing.assert_array_equal(cascade(mj, ctx, R, S, T, 1000), oracle.linear3_count(R, S, T, 1000))
+
+
+def test_cascade_empty(mj, ctx):
+    banner("cascade empty inputs")
+    e = np.zeros((0, 2), dtype=np.uint32)
+    F = G.linear_small()[:500]
+    for R, S, T in ((e, F, F), (F, e, F), (F, F, e)):
+        assert not cascade(mj, ctx, R, S, T, 4096).any()
+
+
+def test_cascade_powerlaw_scaled_equals_3way(mj, ctx):
+    banner("cascade power-law 2^20 edges")
+    F = G.linear_powerlaw(seed=2001, n_vertices=1 << 16, m=1 << 20)
+    Fd = dev(F)
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, 1 << 16))
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 1 << 16))
+
+
+def test_cascade_powerlaw_full(mj, ctx):
+    """Full size (2^24 edges): |I| = 2.7e8 pairs materialised; equals the
+    three-way join element by element and the closed-form total."""
+    banner("cascade power-law full size")
+    F = G.linear_powerlaw()
+    Fd = dev(F)
+    A = 1 << 20
+    p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, A)
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, A, plan=p))
+    three = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, A, plan=p))
+    np.testing.assert_array_equal(got, three)
+    assert int(got.sum(dtype=np.uint64)) == brute.linear_closed_total(F, F, F)
