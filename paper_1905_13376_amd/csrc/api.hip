@@ -320,6 +320,148 @@ int launch_tables(Prof* prof, const TableLayout& L, const mj_rel& rel, int col, 
     return MJ_OK;
 }
 
+struct RunBuf {
+    uint32_t* run_key;
+    uint32_t* run_start;
+    uint32_t* dir;
+    uint32_t bits;
+    unsigned long long* nruns;
+};
+
+struct TriLayout {
+    unsigned long long* Rk;
+    unsigned long long* Sk;
+    unsigned long long* Tk;
+    unsigned long long* tmp;          // radix double buffer
+    uint32_t* rs_hist;
+    uint32_t* rs_counts;
+    uint32_t* rs_starts;
+    uint32_t* flags;
+    unsigned long long* ridx;
+    unsigned long long* partial;
+    RunBuf R, S, T;
+    uint32_t* light;
+    uint32_t* ctr;                    // nlight, light_next, nheavy_groups, heavy_next
+    uint32_t* heavy_group;
+    uint32_t* heavy_items;
+    unsigned long long* heavy_off;
+    uint32_t n_heavy_cap;
+    size_t bytes;
+};
+
+uint32_t dir_bits(uint64_t n) { return std::min<uint32_t>(24, std::max<uint32_t>(1, ceil_log2(n))); }
+
+void take_runs(Bump& B, RunBuf& X, uint64_t n, bool with_dir) {
+    X.run_key = B.take<uint32_t>(std::max<uint64_t>(n, 1));
+    X.run_start = B.take<uint32_t>(n + 1);
+    X.bits = dir_bits(n);
+    X.dir = with_dir ? B.take<uint32_t>((uint64_t(1) << X.bits) + 1) : nullptr;
+    X.nruns = B.take<unsigned long long>(1);
+}
+
+TriLayout tri_layout(void* ws, const mj_plan_t& p) {
+    Bump B(ws);
+    TriLayout L;
+    const uint64_t nmax = std::max<uint64_t>({p.n_r, p.n_s, p.n_t, 1});
+    L.Rk = B.take<unsigned long long>(std::max<uint64_t>(p.n_r, 1));
+    L.Sk = B.take<unsigned long long>(std::max<uint64_t>(p.n_s, 1));
+    L.Tk = B.take<unsigned long long>(std::max<uint64_t>(p.n_t, 1));
+    L.tmp = B.take<unsigned long long>(nmax);
+    const uint64_t ntiles = (nmax + RS_TILE - 1) / RS_TILE;
+    L.rs_hist = B.take<uint32_t>(256 * ntiles);
+    L.rs_counts = B.take<uint32_t>(256);
+    L.rs_starts = B.take<uint32_t>(257);
+    L.flags = B.take<uint32_t>(nmax);
+    L.ridx = B.take<unsigned long long>(nmax + 1);
+    L.partial = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
+    take_runs(B, L.R, p.n_r, true);
+    take_runs(B, L.S, p.n_s, false);
+    take_runs(B, L.T, p.n_t, true);
+    L.light = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.ctr = B.take<uint32_t>(4);
+    L.n_heavy_cap = (uint32_t)(p.n_r / (TRI_LIGHT_X + 1) + p.n_s / (TRI_LIGHT_S + 1) + 2);
+    L.heavy_group = B.take<uint32_t>(L.n_heavy_cap);
+    L.heavy_items = B.take<uint32_t>(L.n_heavy_cap);
+    L.heavy_off = B.take<unsigned long long>(L.n_heavy_cap + 1);
+    L.bytes = B.off + 256;
+    return L;
+}
+
+int launch_scan_u32(Prof* prof, const uint32_t* in, uint64_t n, unsigned long long* partial,
+                    unsigned long long* out, hipStream_t s) {
+    const uint32_t nblk = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
+    if (nblk == 0) {
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+        return MJ_OK;
+    }
+    MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
+    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, nblk);
+    MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    return MJ_OK;
+}
+
+// Sort n 64-bit keys in place (8 stable passes of 8 bits; tmp is the other buffer).
+int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* tmp, uint64_t n,
+                      uint32_t* hist, uint32_t* counts, uint32_t* starts, hipStream_t s) {
+    if (n <= 1) return MJ_OK;
+    const uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
+    unsigned long long* src = keys;
+    unsigned long long* dst = tmp;
+    for (uint32_t pass = 0; pass < 8; ++pass) {
+        RsArgs A;
+        A.in = src; A.out = dst; A.n = n; A.shift = 8 * pass; A.ntiles = ntiles;
+        A.hist = hist; A.starts = starts;
+        MJ_LAUNCH(prof, "k_rs_hist", k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
+        PartLaunch P{};
+        P.njobs = 1;
+        P.job[0].hist = hist; P.job[0].ntiles = ntiles; P.job[0].counts = counts;
+        P.job[0].starts = starts; P.job[0].bits0 = 8; P.job[0].bits1 = 0;
+        MJ_LAUNCH(prof, "k_part_rowscan", k_part_rowscan, dim3(256), dim3(PART_THREADS),
+                  PART_SCAN_CHUNK * 4, s, P);
+        MJ_LAUNCH(prof, "k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), 256 * 4, s, P);
+        MJ_LAUNCH(prof, "k_rs_scatter", k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
+        std::swap(src, dst);
+    }
+    return MJ_OK;            // eight passes: the result is back in `keys`
+}
+
+int launch_runs(Prof* prof, const TriLayout& L, const unsigned long long* keys, uint64_t n,
+                const RunBuf& X, hipStream_t s) {
+    if (n == 0) {
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, X.nruns, (uint64_t)1, 0ull);
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, X.run_start, (uint64_t)1, 0u);
+    } else {
+        MJ_LAUNCH(prof, "k_run_flags", k_run_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
+                  keys, n, L.flags);
+        int st = launch_scan_u32(prof, L.flags, n, L.partial, L.ridx, s);
+        if (st) return st;
+        MJ_LAUNCH(prof, "k_run_compact", k_run_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
+                  keys, n, L.flags, L.ridx, X.run_key, X.run_start, X.nruns);
+    }
+    if (X.dir)
+        MJ_LAUNCH(prof, "k_run_dir", k_run_dir, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, s,
+                  X.run_key, X.nruns, X.bits, X.dir);
+    return MJ_OK;
+}
+
+RunIndex run_index(const RunBuf& X) {
+    RunIndex I;
+    I.run_key = X.run_key; I.run_start = X.run_start; I.dir = X.dir; I.bits = X.bits;
+    I.nruns = X.nruns;
+    return I;
+}
+
+int tri_keys(Prof* prof, const mj_rel& r, int key_col, unsigned long long* out, uint32_t seed,
+             hipStream_t s) {
+    if (r.n == 0) return MJ_OK;
+    TriKeyArgs K;
+    K.key_col = key_col ? r.col1 : r.col0;
+    K.val_col = key_col ? r.col0 : r.col1;
+    K.stride = r.stride; K.n = r.n; K.seed = seed; K.out = out;
+    MJ_LAUNCH(prof, "k_tri_keys", k_tri_keys, dim3(grid_for(r.n, 256, 16384)), dim3(256), 0, s, K);
+    return MJ_OK;
+}
+
 int cascade_triangle(mj_ctx*, const mj_rel*, const mj_rel*, const mj_rel*, uint64_t*,
                      const mj_plan_t&, void*, uint64_t, void*) {
     return MJ_ERR_UNSUPPORTED;
@@ -550,9 +692,57 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     return MJ_OK;
 }
 
-int mj_triangle3_count(mj_ctx*, const mj_rel*, const mj_rel*, const mj_rel*, uint64_t*,
-                       const mj_plan_t*, void*, uint64_t, void*) {
-    return MJ_ERR_UNSUPPORTED;
+int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                       uint64_t* total, const mj_plan_t* plan, void* ws, uint64_t ws_bytes,
+                       void* stream) {
+    if (!ctx || !plan || !total) return MJ_ERR_INVALID_ARG;
+    int st;
+    if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
+    const mj_plan_t& p = *plan;
+    if (p.kind != MJ_TRIANGLE || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n)
+        return MJ_ERR_PLAN_MISMATCH;
+    if (p.log2_share > 16) return MJ_ERR_INVALID_ARG;
+    TriLayout L = tri_layout(nullptr, p);
+    if (ws_bytes < L.bytes || !ws) return MJ_ERR_WORKSPACE;
+    L = tri_layout(ws, p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(total);
+    MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+    if (R->n == 0 || S->n == 0 || T->n == 0) return MJ_OK;
+    const uint32_t seed = p.seed;
+    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)), T -> (m(c), m(a)); sorted
+    if ((st = tri_keys(prof, *R, 1, L.Rk, seed, s))) return st;
+    if ((st = tri_keys(prof, *S, 0, L.Sk, seed, s))) return st;
+    if ((st = tri_keys(prof, *T, 0, L.Tk, seed, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Rk, L.tmp, R->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    // lists of R per B, of T per C; groups of S per B
+    if ((st = launch_runs(prof, L, L.Rk, R->n, L.R, s))) return st;
+    if ((st = launch_runs(prof, L, L.Tk, T->n, L.T, s))) return st;
+    if ((st = launch_runs(prof, L, L.Sk, S->n, L.S, s))) return st;
+    // work queues
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.ctr, (uint64_t)4, 0u);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(L.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
+              L.heavy_items, (uint64_t)L.n_heavy_cap, 0u);
+    const uint32_t share = 1u << p.log2_share;
+    TriClassifyArgs C;
+    C.R = run_index(L.R); C.S = run_index(L.S); C.share = share;
+    C.nlight = L.ctr + 0; C.light = L.light;
+    C.nheavy_groups = L.ctr + 2; C.heavy_group = L.heavy_group; C.heavy_items = L.heavy_items;
+    MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, C);
+    if ((st = launch_scan_u32(prof, L.heavy_items, L.n_heavy_cap, L.partial, L.heavy_off, s))) return st;
+    TriJoinArgs J;
+    J.R = run_index(L.R); J.S = run_index(L.S); J.T = run_index(L.T);
+    J.Rk = L.Rk; J.Sk = L.Sk; J.Tk = L.Tk;
+    J.nlight = L.ctr + 0; J.light = L.light; J.light_next = L.ctr + 1;
+    J.heavy_group = L.heavy_group; J.heavy_off = L.heavy_off; J.n_heavy_cap = L.n_heavy_cap;
+    J.heavy_next = L.ctr + 3; J.share = share; J.total = out;
+    const uint32_t persistent = (uint32_t)ctx->num_cu * 8;
+    MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
+    MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_THREADS), 0, s, J);
+    return MJ_OK;
 }
 
 int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
@@ -642,7 +832,7 @@ int plan_workspace(mj_plan_t& p) {
         // one when the caller runs both on the same plan
         p.workspace_bytes = std::max(lin, cas);
     } else {
-        p.workspace_bytes = 256;
+        p.workspace_bytes = tri_layout(nullptr, p).bytes;
     }
     return MJ_OK;
 }

@@ -222,6 +222,86 @@ __global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
 __global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
                              unsigned long long* out);
 
+// ------------------------------------------------------------- radix sort
+constexpr int RS_THREADS = 256;
+constexpr int RS_TILE = 4096;
+struct RsArgs {
+    const unsigned long long* in;
+    unsigned long long* out;
+    uint64_t n;
+    uint32_t shift;              // digit = (key >> shift) & 255
+    uint32_t ntiles;
+    uint32_t* hist;              // [256][ntiles]
+    const uint32_t* starts;      // [257] digit starts
+};
+__global__ void k_rs_hist(RsArgs A);
+__global__ void k_rs_scatter(RsArgs A);
+
+// --------------------------------------------------------------- triangle
+constexpr int TRI_THREADS = 256;
+constexpr uint32_t TRI_LIGHT_X = 512;      // R list length handled by one wave
+constexpr uint32_t TRI_LIGHT_CAP = 1024;   // its LDS table (load <= 1/2)
+constexpr uint32_t TRI_LIGHT_S = 4096;     // S group size handled by one wave
+constexpr uint32_t TRI_HEAVY_X = 4096;     // R slice handled by one workgroup
+constexpr uint32_t TRI_HEAVY_CAP = 8192;
+constexpr uint32_t TRI_HEAVY_S = 512;      // S tuples per heavy item
+
+struct RunIndex {                          // runs of equal high words of sorted keys
+    const uint32_t* run_key;               // [nruns]
+    const uint32_t* run_start;             // [nruns + 1]
+    const uint32_t* dir;                   // [2^bits + 1] first run with prefix >= p
+    uint32_t bits;
+    const unsigned long long* nruns;
+};
+
+struct TriKeyArgs {
+    const uint32_t* key_col;
+    const uint32_t* val_col;
+    int64_t stride;
+    uint64_t n;
+    uint32_t seed;
+    unsigned long long* out;
+};
+
+struct TriHeavyItem { uint32_t r0, r1, s0, s1; };
+
+struct TriClassifyArgs {
+    RunIndex R, S;
+    uint32_t share;
+    uint32_t* nlight;
+    uint32_t* light;
+    uint32_t* nheavy_groups;
+    uint32_t* heavy_group;
+    uint32_t* heavy_items;
+};
+
+struct TriJoinArgs {
+    RunIndex R, S, T;
+    const unsigned long long* Rk;
+    const unsigned long long* Sk;
+    const unsigned long long* Tk;
+    const uint32_t* nlight;
+    const uint32_t* light;
+    uint32_t* light_next;
+    const uint32_t* heavy_group;
+    const unsigned long long* heavy_off;
+    uint32_t n_heavy_cap;
+    uint32_t* heavy_next;
+    uint32_t share;
+    unsigned long long* total;
+};
+
+__global__ void k_tri_keys(TriKeyArgs A);
+__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags);
+__global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,
+                              const unsigned long long* ridx, uint32_t* run_key,
+                              uint32_t* run_start, unsigned long long* nruns);
+__global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nruns_p,
+                          uint32_t bits, uint32_t* dir);
+__global__ void k_tri_classify(TriClassifyArgs A);
+__global__ void k_tri_light(TriJoinArgs A);
+__global__ void k_tri_heavy(TriJoinArgs A);
+
 // max of a column (key-range check)
 __global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out);
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v);

@@ -1,0 +1,304 @@
+// Cyclic three-way join R(A,B) |x| S(B,C) |x| T(C,A), total count (Sec. 5).
+//
+// Every relation is turned into 64-bit keys of mixed 32-bit values and
+// sorted (radix.hip):  R -> (m(b), m(a)),  T -> (m(c), m(a)),  S -> (m(b), m(c)).
+// m is a bijection of the 32-bit keys, so equal mixed values mean equal keys
+// and every join predicate can be evaluated on mixed values.  After sorting,
+// R's tuples with one B value form a contiguous list ordered by m(a), and so
+// do T's tuples with one C value; S's tuples with one B value form a group.
+//
+// The paper keeps a partition R' of R on chip and streams S' and T' past it
+// (Sec. 5.1).  Here the unit kept on chip is R's list for one B value:
+//   * k_tri_light : one wave per S group whose R list has at most TRI_LIGHT_X
+//                   tuples; the wave loads that list into its LDS table
+//                   (A -> multiplicity) and, for every s(b,c) of the group,
+//                   streams T's list of c past it (or, when T's list is much
+//                   longer, searches T's sorted list for each R tuple);
+//   * k_tri_heavy : R lists of hub B values are cut into slices of at most
+//                   TRI_HEAVY_X tuples by ranges of m(a) -- the share on A --
+//                   and the groups' S tuples into ranges; one workgroup per
+//                   (slice, S range) loads the slice into LDS and streams the
+//                   part of each T list that falls into the slice's A range.
+// Work items come from device queues filled by k_tri_classify.  Each wave
+// sums its counts in registers and adds them to the total once.
+#include "mj_kernels.h"
+
+namespace mj {
+
+// --------------------------------------------------------------- key forms
+__global__ void k_tri_keys(TriKeyArgs A) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t hi = ld_col(A.key_col, i, A.stride);
+        const uint32_t lo = ld_col(A.val_col, i, A.stride);
+        A.out[i] = ((unsigned long long)mix32(hi, A.seed) << 32) | mix32(lo, A.seed);
+    }
+}
+
+// ------------------------------------------------------- runs of equal keys
+__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        flags[i] = (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ? 1u : 0u;
+}
+
+// run r starts at element i for every head i (ridx = exclusive scan of flags)
+__global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,
+                              const unsigned long long* ridx, uint32_t* run_key,
+                              uint32_t* run_start, unsigned long long* nruns) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (flags[i]) {
+            const uint64_t r = ridx[i];
+            run_key[r] = (uint32_t)(keys[i] >> 32);
+            run_start[r] = (uint32_t)i;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        run_start[ridx[n]] = (uint32_t)n;
+        *nruns = ridx[n];
+    }
+}
+
+// dir[p] = first run whose key prefix (top `bits` bits) is >= p, p in [0, 2^bits]
+__global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nruns_p,
+                          uint32_t bits, uint32_t* dir) {
+    const uint64_t nruns = *nruns_p;
+    const uint64_t np = uint64_t(1) << bits;
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= nruns;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t lo = r == 0 ? 0 : uint64_t(top_bits(run_key[r - 1], bits)) + 1;
+        const uint64_t hi = r == nruns ? np : uint64_t(top_bits(run_key[r], bits));
+        for (uint64_t p = lo; p <= hi; ++p) dir[p] = (uint32_t)r;
+    }
+}
+
+__device__ __forceinline__ bool run_lookup(const RunIndex& X, uint32_t key, uint32_t& start,
+                                           uint32_t& len) {
+    const uint32_t p = top_bits(key, X.bits);
+    uint32_t r = X.dir[p];
+    const uint32_t rend = X.dir[p + 1];
+    for (; r < rend; ++r) {
+        const uint32_t k = X.run_key[r];
+        if (k == key) {
+            start = X.run_start[r];
+            len = X.run_start[r + 1] - start;
+            return true;
+        }
+        if (k > key) break;
+    }
+    return false;
+}
+
+// --------------------------------------------------------------- classify
+// Light: R list of b short and S group small -> one wave.  Heavy: otherwise
+// -> (slice of R's list) x (range of the S group) workgroup items, counted
+// per group here and enumerated through a scan of the counts.
+__device__ __forceinline__ void heavy_shape(uint32_t x, uint32_t gn, uint32_t share,
+                                            uint32_t& nsl, uint32_t& nsr) {
+    nsl = (x + TRI_HEAVY_X - 1) / TRI_HEAVY_X;
+    nsl = max(nsl, min(share, (x + 63) / 64));
+    nsr = (gn + TRI_HEAVY_S - 1) / TRI_HEAVY_S;
+}
+
+__global__ void k_tri_classify(TriClassifyArgs A) {
+    const uint64_t ng = *A.S.nruns;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ng;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t rs, x;
+        if (!run_lookup(A.R, A.S.run_key[g], rs, x)) continue;
+        const uint32_t gn = A.S.run_start[g + 1] - A.S.run_start[g];
+        if (x <= TRI_LIGHT_X && gn <= TRI_LIGHT_S) {
+            const uint32_t q = atomicAdd(A.nlight, 1u);
+            A.light[q] = (uint32_t)g;
+        } else {
+            uint32_t nsl, nsr;
+            heavy_shape(x, gn, A.share, nsl, nsr);
+            const uint32_t h = atomicAdd(A.nheavy_groups, 1u);
+            A.heavy_group[h] = (uint32_t)g;
+            A.heavy_items[h] = nsl * nsr;
+        }
+    }
+}
+
+// ------------------------------------------------------------ LDS A-tables
+// open addressing on m(a); value = multiplicity; m(a) = 0xFFFFFFFF in `spec`
+__device__ __forceinline__ void atab_add(uint32_t* keys, uint32_t* vals, uint32_t mask,
+                                         uint32_t* spec, uint32_t a) {
+    if (a == EMPTY_KEY) { atomicAdd(spec, 1u); return; }
+    uint32_t s = a & mask;                    // m(a) is already a hash
+    while (true) {
+        const uint32_t cur = keys[s];
+        if (cur == a) { atomicAdd(&vals[s], 1u); return; }
+        if (cur == EMPTY_KEY) {
+            const uint32_t old = atomicCAS(&keys[s], EMPTY_KEY, a);
+            if (old == EMPTY_KEY || old == a) { atomicAdd(&vals[s], 1u); return; }
+        }
+        s = (s + 1u) & mask;
+    }
+}
+
+__device__ __forceinline__ uint32_t atab_get(const uint32_t* keys, const uint32_t* vals,
+                                             uint32_t mask, uint32_t spec, uint32_t a) {
+    if (a == EMPTY_KEY) return spec;
+    uint32_t s = a & mask;
+    while (true) {
+        const uint32_t cur = keys[s];
+        if (cur == a) return vals[s];
+        if (cur == EMPTY_KEY) return 0u;
+        s = (s + 1u) & mask;
+    }
+}
+
+// number of entries of sorted low words keys[lo, hi) equal to a
+__device__ __forceinline__ uint32_t count_low(const unsigned long long* keys, uint32_t lo,
+                                              uint32_t hi, uint32_t a) {
+    uint32_t l = lo, h = hi;
+    while (l < h) { uint32_t m = (l + h) >> 1; if ((uint32_t)keys[m] < a) l = m + 1; else h = m; }
+    uint32_t l2 = l, h2 = hi;
+    while (l2 < h2) { uint32_t m = (l2 + h2) >> 1; if ((uint32_t)keys[m] <= a) l2 = m + 1; else h2 = m; }
+    return l2 - l;
+}
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------- light groups
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tri_light(TriJoinArgs A) {
+    constexpr int NW = TRI_THREADS / WAVE;
+    __shared__ uint32_t tkeys[NW][TRI_LIGHT_CAP];
+    __shared__ uint32_t tvals[NW][TRI_LIGHT_CAP];
+    __shared__ uint32_t tused[NW][TRI_LIGHT_X];
+    __shared__ uint32_t tnused[NW];
+    __shared__ uint32_t tspec[NW];
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    uint32_t* keys = tkeys[w];
+    uint32_t* vals = tvals[w];
+    uint32_t* used = tused[w];
+    const uint32_t mask = TRI_LIGHT_CAP - 1;
+    for (uint32_t s = lane; s < TRI_LIGHT_CAP; s += WAVE) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+    if (lane == 0) { tspec[w] = 0; tnused[w] = 0; }
+    wave_fence();
+    const uint32_t nitems = *A.nlight;
+    unsigned long long acc = 0;
+    while (true) {
+        uint32_t it = 0;
+        if (lane == 0) it = atomicAdd(A.light_next, 1u);
+        it = __shfl(it, 0, WAVE);
+        if (it >= nitems) break;
+        const uint32_t g = A.light[it];
+        const uint32_t mb = A.S.run_key[g];
+        const uint32_t gs = A.S.run_start[g], ge = A.S.run_start[g + 1];
+        uint32_t rs = 0, x = 0;
+        run_lookup(A.R, mb, rs, x);
+        // the R list of b -> the wave's LDS table (slots claimed are recorded)
+        for (uint32_t q = lane; q < x; q += WAVE) {
+            const uint32_t a = (uint32_t)A.Rk[rs + q];
+            if (a == EMPTY_KEY) { atomicAdd(&tspec[w], 1u); continue; }
+            uint32_t s = a & mask;
+            while (true) {
+                const uint32_t cur = keys[s];
+                if (cur == a) { atomicAdd(&vals[s], 1u); break; }
+                if (cur == EMPTY_KEY) {
+                    const uint32_t old = atomicCAS(&keys[s], EMPTY_KEY, a);
+                    if (old == EMPTY_KEY) { used[atomicAdd(&tnused[w], 1u)] = s; atomicAdd(&vals[s], 1u); break; }
+                    if (old == a) { atomicAdd(&vals[s], 1u); break; }
+                }
+                s = (s + 1u) & mask;
+            }
+        }
+        wave_fence();
+        const uint32_t spec = tspec[w];
+        for (uint32_t si = gs + lane; si < ge; si += WAVE) {
+            const uint32_t mc = (uint32_t)A.Sk[si];
+            uint32_t ts, y;
+            if (!run_lookup(A.T, mc, ts, y)) continue;
+            if (y <= 4 * x) {
+                for (uint32_t t = ts; t < ts + y; ++t)
+                    acc += atab_get(keys, vals, mask, spec, (uint32_t)A.Tk[t]);
+            } else {
+                for (uint32_t q = rs; q < rs + x; ++q)
+                    acc += count_low(A.Tk, ts, ts + y, (uint32_t)A.Rk[q]);
+            }
+        }
+        wave_fence();
+        const uint32_t nu = tnused[w];
+        for (uint32_t q = lane; q < nu; q += WAVE) { const uint32_t s = used[q]; keys[s] = EMPTY_KEY; vals[s] = 0; }
+        wave_fence();
+        if (lane == 0) { tspec[w] = 0; tnused[w] = 0; }
+        wave_fence();
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0 && acc) atomicAdd(A.total, acc);
+}
+
+// ------------------------------------------------------------- heavy groups
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tri_heavy(TriJoinArgs A) {
+    __shared__ uint32_t keys[TRI_HEAVY_CAP];
+    __shared__ uint32_t vals[TRI_HEAVY_CAP];
+    __shared__ uint32_t spec;
+    __shared__ uint32_t s_item;
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    constexpr int NW = TRI_THREADS / WAVE;
+    const uint32_t mask = TRI_HEAVY_CAP - 1;
+    const uint32_t nitems = (uint32_t)A.heavy_off[A.n_heavy_cap];
+    unsigned long long acc = 0;
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) { s_item = atomicAdd(A.heavy_next, 1u); spec = 0; }
+        for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+        __syncthreads();
+        const uint32_t it = s_item;
+        if (it >= nitems) break;
+        // item -> (heavy group, slice of R's list, range of S tuples)
+        uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
+        while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (A.heavy_off[m] <= it) lo = m; else hi = m; }
+        const uint32_t g = A.heavy_group[lo];
+        const uint32_t local = (uint32_t)(it - A.heavy_off[lo]);
+        uint32_t rs = 0, x = 0;
+        run_lookup(A.R, A.S.run_key[g], rs, x);
+        const uint32_t gs = A.S.run_start[g], gn = A.S.run_start[g + 1] - gs;
+        uint32_t nsl, nsr;
+        heavy_shape(x, gn, A.share, nsl, nsr);
+        const uint32_t sa = local / nsr, sb = local % nsr;
+        TriHeavyItem H;
+        H.r0 = rs + (uint32_t)((uint64_t)x * sa / nsl);
+        H.r1 = rs + (uint32_t)((uint64_t)x * (sa + 1) / nsl);
+        H.s0 = gs + sb * TRI_HEAVY_S;
+        H.s1 = min(gs + gn, H.s0 + TRI_HEAVY_S);
+        if (H.r0 == H.r1) continue;
+        for (uint32_t q = H.r0 + threadIdx.x; q < H.r1; q += blockDim.x)
+            atab_add(keys, vals, mask, &spec, (uint32_t)A.Rk[q]);
+        __syncthreads();
+        const uint32_t sp = spec;
+        const uint32_t alo = (uint32_t)A.Rk[H.r0], ahi = (uint32_t)A.Rk[H.r1 - 1];
+        const uint32_t xs = H.r1 - H.r0;
+        // each wave takes S tuples of the range; its lanes share one T list
+        for (uint32_t si = H.s0 + w; si < H.s1; si += NW) {
+            const uint32_t mc = (uint32_t)A.Sk[si];
+            uint32_t ts, y;
+            if (!run_lookup(A.T, mc, ts, y)) continue;
+            // the part of T's list (sorted by m(a)) inside [alo, ahi]
+            uint32_t l = ts, h = ts + y;
+            while (l < h) { uint32_t m = (l + h) >> 1; if ((uint32_t)A.Tk[m] < alo) l = m + 1; else h = m; }
+            uint32_t l2 = l, h2 = ts + y;
+            while (l2 < h2) { uint32_t m = (l2 + h2) >> 1; if ((uint32_t)A.Tk[m] <= ahi) l2 = m + 1; else h2 = m; }
+            const uint32_t ysub = l2 - l;
+            if (ysub <= 4 * xs) {
+                for (uint32_t t = l + lane; t < l2; t += WAVE)
+                    acc += atab_get(keys, vals, mask, sp, (uint32_t)A.Tk[t]);
+            } else {
+                for (uint32_t q = H.r0 + lane; q < H.r1; q += WAVE)
+                    acc += count_low(A.Tk, l, l2, (uint32_t)A.Rk[q]);
+            }
+        }
+    }
+    acc = wave_sum_u64(acc);
+    if (lane == 0 && acc) atomicAdd(A.total, acc);
+}
+
+}  // namespace mj
