@@ -42,6 +42,22 @@ def kernel_bytes(name, n_r, n_s, n_t, distinct_t):
     return table.get(name)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["traffic_bytes"] if h.hexdigest() == rec["sha256"] else None
+
+
 def cpu_baseline(F, a_domain):
     """The oracle (single-threaded C) on a bounded sample: R = every 16th
     tuple of F, S = T = F."""
@@ -63,6 +79,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (to scale HBM byte counters)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time only the main workload (no cascade / cyclic / small runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -82,6 +102,14 @@ def main():
     Fd = torch.from_numpy(F).to("cuda")
     torch.cuda.synchronize()
 
+    if args.calib_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = mj.Context()
     t0 = time.perf_counter()
     plan = ctx.plan(mj.LINEAR, Fd, Fd, Fd, a_domain)
@@ -129,7 +157,8 @@ def main():
     if nbytes:
         ach = nbytes / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom),
                 "algorithmic_bytes": nbytes, "avg_launch_us": round(avg_ms * 1e3, 2)}
     result = {
         "metric": "join input tuples/s (linear 3-way, per-A count)",
@@ -152,10 +181,89 @@ def main():
                    "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kern.items()}},
         "roofline": roof,
     }
+    if not args.no_extra:
+        result["paths"] = extra_paths(mj, ctx, F, Fd, a_domain, plan, ms)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(F, a_domain)
     print(json.dumps(result), flush=True)
+
+
+def time_call(fn, steps, warmup=1):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
+    """The other paths of the method, each on its own workload."""
+    import numpy as np
+    import torch
+    from workloads import generators as G
+    out = {}
+    n = F.shape[0]
+    # cascade of binary joins on the same power-law input (Sec. 6.3)
+    log("cascade on the power-law graph")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(a_domain, dtype=torch.int64, device="cuda")
+    ms_c = time_call(lambda: ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, a_domain, plan=plan,
+                                                out=cnt, workspace=ws), 3)
+    out["cascade_linear"] = {"ms": round(ms_c, 3), "tuples_per_s": 3 * n / (ms_c * 1e-3),
+                             "intermediate_pairs": plan.join2_size,
+                             "speedup_3way_over_cascade": round(ms_c / ms_3way, 2)}
+    del ws
+    # small uniform linear workload (65,536 tuples, keys in [0, 4096))
+    Fs = G.linear_small()
+    Fsd = torch.from_numpy(Fs.view(np.int32)).to("cuda")
+    ps = ctx.plan(mj.LINEAR, Fsd, Fsd, Fsd, 4096)
+    ws = torch.empty(ps.workspace_bytes, dtype=torch.uint8, device="cuda")
+    cs = torch.empty(4096, dtype=torch.int64, device="cuda")
+    ms_s = time_call(lambda: ctx.linear3_count(Fsd, Fsd, Fsd, 4096, plan=ps, out=cs, workspace=ws), 20, 3)
+    ms_sc = time_call(lambda: ctx.cascade2_count(mj.LINEAR, Fsd, Fsd, Fsd, 4096, plan=ps, out=cs,
+                                                 workspace=ws), 20, 3)
+    out["linear_small"] = {"ms_3way": round(ms_s, 4), "ms_cascade": round(ms_sc, 4),
+                           "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3)}
+    del ws
+    # cyclic join on the R-MAT scale-22 graph, shares 8 / 16 / 32 (Sec. 5)
+    log("generating R-MAT scale 22 (2^26 undirected edges)")
+    E = G.triangle_rmat()
+    Ed = torch.from_numpy(E).to("cuda")
+    golden = None
+    gp = os.path.join(ROOT, "tests", "golden", "triangle_rmat22.json")
+    if os.path.exists(gp):
+        golden = json.load(open(gp))["total"]
+    tri = {}
+    tot = torch.empty(1, dtype=torch.int64, device="cuda")
+    for share in (3, 4, 5):
+        p = mj.Plan()
+        p.log2_share = share
+        p.seed = 0x1B873593
+        pt = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed, 0, planner="fixed", fixed=p)
+        ws = torch.empty(pt.workspace_bytes, dtype=torch.uint8, device="cuda")
+        ctx.profile(True)
+        ctx.profile_read()
+        ms_t = time_call(lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=pt, out=tot, workspace=ws), 2)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        got = int(mj.as_u64(tot)[0])
+        tri[f"share_{1 << share}"] = {
+            "ms": round(ms_t, 2), "tuples_per_s": 3 * E.shape[0] / (ms_t * 1e-3),
+            "total": got, "triangles": got // 6,
+            "matches_oracle_total": (got == golden) if golden is not None else None,
+            "kernels_ms": {k: round(v[0] / max(v[1], 1) * v[1] / 3, 3)
+                           for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]}}
+        log(f"cyclic share {1 << share}: {ms_t:.1f} ms total {got}")
+        del ws
+    out["triangle_rmat22"] = tri
+    return out
 
 
 if __name__ == "__main__":
