@@ -137,6 +137,39 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
                       uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
                       void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* Autotuner: times candidate plans of this join on the device (HIP events
+ * on `stream`; synchronous) and keeps the fastest: for the linear kind
+ * both algorithms and B / C bucket counts 2^8..2^10, for the cyclic kind
+ * the shares 8, 16, 32 (and the cascade when the planner rated it within a
+ * factor of 4).  `plan` must come from mj_plan for these relations; it is
+ * overwritten with the winner.  Results are cached in the context per size
+ * class (log2 of the three sizes and of the intermediate), so a second
+ * call on a join of the same class costs no runs.  The workspace must hold
+ * the largest candidate (mj_plan's workspace_bytes covers all of them).
+ * Counts written to `out` (uint64[a_domain] or uint64[1]) by the runs are
+ * those of the final plan.  *tuned_ms receives the winner's time.       */
+int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                uint32_t a_domain, uint64_t* out, mj_plan_t* plan, void* workspace,
+                uint64_t workspace_bytes, double* tuned_ms, void* stream);
+
+/* The paper's analytic cost formulas as the planner evaluates them (for
+ * inspection and testing): tuples read onto the chip by the linear join
+ * (Sec. 4.2), moved by the cascade (Example 3), the break-even capacity of
+ * Example 3, the cyclic cost and its optimum (Sec. 5.2), the uniform-key
+ * size of a binary join (Sec. 6.3) and the branch probability of App. A.
+ * args as listed per formula; *out receives the value.                   */
+typedef enum {
+    MJ_COST_LINEAR_TUPLES = 0,     /* R, S, T, M          */
+    MJ_COST_CASCADE_TUPLES = 1,    /* I                   */
+    MJ_COST_LINEAR_BREAK_EVEN_M = 2, /* R, S, T, I        */
+    MJ_COST_CYCLIC_TUPLES = 3,     /* R, S, T, M, H       */
+    MJ_COST_CYCLIC_OPTIMAL_H = 4,  /* R, S, T, M          */
+    MJ_COST_CYCLIC_MIN = 5,        /* R, S, T, M          */
+    MJ_COST_JOIN2_UNIFORM = 6,     /* R, S, d             */
+    MJ_COST_BRANCH_HIT = 7         /* g3, d               */
+} mj_cost_formula;
+int mj_cost_model(int which, const double* args, int nargs, double* out);
+
 /* Exact |R |x| S| on B = sum_b deg_R(b) * deg_S(b) (the cascade's
  * intermediate size, Sec. 6.3), computed on the device.  Synchronous;
  * *out is host memory.  Needs a workspace of mj_join2_size_workspace()

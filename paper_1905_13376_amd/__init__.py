@@ -4,4 +4,4 @@ three-way joins and the binary cascade, behind the C ABI of ``libmj.so``.
 Importing the package loads the HIP library; it fails loudly when the
 library is missing (there is no CPU path)."""
 from ._lib import (ALGO_3WAY, ALGO_CASCADE, LINEAR, TRIANGLE, Context, MJError,  # noqa: F401
-                   Plan, Rel, as_u64, rel, status_str, LIB_PATH)
+                   Plan, Rel, as_u64, cost_model, rel, status_str, LIB_PATH)

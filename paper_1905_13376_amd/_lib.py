@@ -73,12 +73,28 @@ _SIGS = {
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
     "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
     "mj_ctx_profile": ([_vp, _i32], _i32),
+    "mj_autotune": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64,
+                     ctypes.POINTER(ctypes.c_double), _vp], _i32),
+    "mj_cost_model": ([_i32, ctypes.POINTER(ctypes.c_double), _i32,
+                       ctypes.POINTER(ctypes.c_double)], _i32),
     "mj_ctx_profile_read": ([_vp, _i32, _vp, _vp, _vp], _i32),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
+
+
+COST = {"linear_tuples": 0, "cascade_tuples": 1, "linear_break_even_M": 2, "cyclic_tuples": 3,
+        "cyclic_optimal_H": 4, "cyclic_min": 5, "join2_uniform": 6, "branch_hit": 7}
+
+
+def cost_model(name: str, *args) -> float:
+    """Evaluate one of the planner's analytic cost formulas (no GPU needed)."""
+    arr = (ctypes.c_double * max(len(args), 1))(*[float(a) for a in args])
+    out = ctypes.c_double()
+    _check(_lib.mj_cost_model(COST[name], arr, len(args), ctypes.byref(out)), "mj_cost_model")
+    return out.value
 
 
 def exported_symbols():
@@ -210,6 +226,25 @@ class Context:
                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                       _stream_ptr(stream)), "mj_cascade2_count")
         return out[:a_domain] if kind == LINEAR else out
+
+    def autotune(self, kind, R, S, T, a_domain=0, plan: Plan | None = None, out=None,
+                 workspace=None, stream=None):
+        """Time candidate plans on the device, keep the fastest (cached per
+        size class).  Returns (plan, ms, counts)."""
+        if plan is None:
+            plan = self.plan(kind, R, S, T, a_domain, stream=stream)
+        else:
+            plan = plan.copy()
+        n_out = max(a_domain, 1) if kind == LINEAR else 1
+        if out is None:
+            out = torch.empty(n_out, dtype=torch.int64, device=R.device)
+        ws = workspace if workspace is not None else self.workspace(plan.workspace_bytes, R.device)
+        ms = ctypes.c_double()
+        _check(_lib.mj_autotune(self._h, kind, rel(R), rel(S), rel(T), a_domain,
+                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(ms),
+                                _stream_ptr(stream)), "mj_autotune")
+        return plan, ms.value, (out[:a_domain] if kind == LINEAR else out)
 
     def join2_size(self, R, S, stream=None) -> int:
         need = _lib.mj_join2_size_workspace(R.shape[0], S.shape[0])

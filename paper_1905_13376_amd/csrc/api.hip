@@ -11,6 +11,7 @@
 #include "mj.h"
 #include "mj_kernels.h"
 #include "mj_host.h"
+#include "mj_plan_model.h"
 
 #include <map>
 #include <string>
@@ -74,6 +75,8 @@ struct mj_ctx {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     Prof prof;
+    DeviceModel model = default_model();
+    std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
 };
 
 namespace {
@@ -462,9 +465,100 @@ int tri_keys(Prof* prof, const mj_rel& r, int key_col, unsigned long long* out, 
     return MJ_OK;
 }
 
-int cascade_triangle(mj_ctx*, const mj_rel*, const mj_rel*, const mj_rel*, uint64_t*,
-                     const mj_plan_t&, void*, uint64_t, void*) {
-    return MJ_ERR_UNSUPPORTED;
+struct CasTriLayout {
+    RelPart R, S;
+    uint32_t* Rgrp;
+    uint32_t* ecnt;
+    uint32_t* elist;
+    unsigned long long* eoff;
+    unsigned long long* partial;
+    unsigned long long* Tk;
+    unsigned long long* tmp;
+    uint32_t* rs_hist;
+    uint32_t* rs_counts;
+    uint32_t* rs_starts;
+    uint32_t* flags;
+    unsigned long long* ridx;
+    RunBuf Trun;
+    uint2* I;
+    uint64_t i_cap;
+    size_t base_bytes;
+};
+
+CasTriLayout cas_tri_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
+    Bump B(ws);
+    CasTriLayout L;
+    take_part(B, L.R, p.n_r, p.log2_nb);
+    take_part(B, L.S, p.n_s, p.log2_nb);
+    L.Rgrp = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+    L.ecnt = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.elist = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.eoff = B.take<unsigned long long>(p.n_s + 1);
+    const uint64_t nmax = std::max<uint64_t>({p.n_s, p.n_t, 1});
+    L.partial = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
+    L.Tk = B.take<unsigned long long>(std::max<uint64_t>(p.n_t, 1));
+    L.tmp = B.take<unsigned long long>(std::max<uint64_t>(p.n_t, 1));
+    L.rs_hist = B.take<uint32_t>(256 * ((std::max<uint64_t>(p.n_t, 1) + RS_TILE - 1) / RS_TILE));
+    L.rs_counts = B.take<uint32_t>(256);
+    L.rs_starts = B.take<uint32_t>(257);
+    L.flags = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
+    L.ridx = B.take<unsigned long long>(p.n_t + 1);
+    take_runs(B, L.Trun, p.n_t, true);
+    L.I = B.take<uint2>(0);
+    L.base_bytes = B.off + 256;
+    if (ws) {
+        L.i_cap = ws_bytes > L.base_bytes ? (ws_bytes - L.base_bytes) / sizeof(uint2) : 0;
+    } else {
+        L.i_cap = std::max<uint64_t>(1, std::min<uint64_t>(p.join2_size, CAS_DEFAULT_I_CAP));
+    }
+    return L;
+}
+
+int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, uint64_t* out,
+                     const mj_plan_t& p, void* ws, uint64_t ws_bytes, void* stream) {
+    if (p.log2_nb > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
+    if (!ws) return MJ_ERR_WORKSPACE;
+    CasTriLayout L = cas_tri_layout(ws, p, ws_bytes);
+    if (ws_bytes < L.base_bytes || (p.join2_size && L.i_cap == 0)) return MJ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    unsigned long long* total = reinterpret_cast<unsigned long long*>(out);
+    MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0ull);
+    if (R->n == 0 || S->n == 0 || T->n == 0 || p.join2_size == 0) return MJ_OK;
+    // join 2's side: T as sorted (m(c), m(a)) keys with its lists per C
+    int st = tri_keys(prof, *T, 0, L.Tk, p.seed, s);
+    if (st) return st;
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    TriLayout TL{};                    // launch_runs only uses flags / ridx / partial
+    TL.flags = L.flags; TL.ridx = L.ridx; TL.partial = L.partial;
+    if ((st = launch_runs(prof, TL, L.Tk, T->n, L.Trun, s))) return st;
+    // join 1: as in the linear cascade
+    const uint32_t nb = 1u << p.log2_nb;
+    PartLaunch P{};
+    P.njobs = 2;
+    P.job[0] = make_job(*R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[0].out_pair = L.R.pairs;
+    P.job[1] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[1].out_pair = L.S.pairs;
+    if ((st = launch_partition(prof, "rs", P, s))) return st;
+    CasIndexArgs X;
+    X.R = L.R.pairs; X.rstarts = L.R.starts; X.S = L.S.pairs; X.sstarts = L.S.starts;
+    X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
+    MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
+    if ((st = launch_scan_u32(prof, L.ecnt, S->n, L.partial, L.eoff, s))) return st;
+    const uint64_t totI = p.join2_size;
+    for (uint64_t lo = 0; lo < totI; lo += L.i_cap) {
+        const uint64_t hi = std::min<uint64_t>(totI, lo + L.i_cap);
+        CasExpandArgs E;
+        E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.S.pairs; E.ns = S->n;
+        E.lo = lo; E.hi = hi; E.I = L.I;
+        MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
+                  dim3(EXP_THREADS), 0, s, E);
+        CasProbeTriArgs Q;
+        Q.I = L.I; Q.n = hi - lo; Q.T = run_index(L.Trun); Q.Tk = L.Tk; Q.seed = p.seed; Q.total = total;
+        MJ_LAUNCH(prof, "k_cas_probe_tri", k_cas_probe_tri, dim3(grid_for(hi - lo, 256, 16384)), dim3(256), 0, s, Q);
+    }
+    return MJ_OK;
 }
 
 }  // namespace
@@ -630,7 +724,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         p.join2_size = I;
     }
     if (planner != MJ_PLANNER_FIXED) {
-        st = analytic_plan(kind, p, ctx->num_cu);
+        st = analytic_plan(kind, p, ctx->num_cu, ctx->model);
         if (st) return st;
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
@@ -812,6 +906,90 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     return MJ_OK;
 }
 
+static int run_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                    uint32_t a_domain, uint64_t* out, const mj_plan_t& p, void* ws,
+                    uint64_t ws_bytes, void* stream) {
+    if (p.algo == MJ_ALGO_CASCADE)
+        return mj_cascade2_count(ctx, kind, R, S, T, a_domain, out, &p, ws, ws_bytes, stream);
+    if (kind == MJ_LINEAR)
+        return mj_linear3_count(ctx, R, S, T, a_domain, out, &p, ws, ws_bytes, stream);
+    return mj_triangle3_count(ctx, R, S, T, out, &p, ws, ws_bytes, stream);
+}
+
+int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                uint32_t a_domain, uint64_t* out, mj_plan_t* plan, void* ws,
+                uint64_t ws_bytes, double* tuned_ms, void* stream) {
+    if (!ctx || !plan || !out) return MJ_ERR_INVALID_ARG;
+    if (plan->kind != kind) return MJ_ERR_PLAN_MISMATCH;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char key[128];
+    std::snprintf(key, sizeof key, "%d:%u:%u:%u:%u", kind, ceil_log2(plan->n_r + 1),
+                  ceil_log2(plan->n_s + 1), ceil_log2(plan->n_t + 1),
+                  ceil_log2(plan->join2_size + 1));
+    auto hit = ctx->tuned.find(key);
+    if (hit != ctx->tuned.end()) {
+        const mj_plan_t& c = hit->second;
+        plan->algo = c.algo; plan->log2_nb = c.log2_nb; plan->log2_nc = c.log2_nc;
+        plan->log2_share = c.log2_share; plan->seed = c.seed;
+        int st = plan_workspace(*plan);
+        if (st) return st;
+        if (tuned_ms) *tuned_ms = c.est_ms_3way;
+        return run_plan(ctx, kind, R, S, T, a_domain, out, *plan, ws, ws_bytes, stream);
+    }
+    std::vector<mj_plan_t> cand;
+    mj_plan_t base = *plan;
+    if (kind == MJ_LINEAR) {
+        for (uint32_t nb = 8; nb <= 10; ++nb)
+            for (uint32_t nc = 8; nc <= 10; ++nc) {
+                mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; c.log2_nb = nb; c.log2_nc = nc;
+                cand.push_back(c);
+            }
+        for (uint32_t nb = 8; nb <= 10; ++nb) {
+            mj_plan_t c = base; c.algo = MJ_ALGO_CASCADE; c.log2_nb = nb; c.log2_nc = 9;
+            cand.push_back(c);
+        }
+    } else {
+        for (uint32_t k = 3; k <= 5; ++k) {
+            mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; c.log2_share = k; cand.push_back(c);
+        }
+        if (base.est_ms_cascade < 4.0 * base.est_ms_3way) {
+            mj_plan_t c = base; c.algo = MJ_ALGO_CASCADE; cand.push_back(c);
+        }
+    }
+    hipEvent_t e0, e1;
+    MJ_HIP(hipEventCreate(&e0));
+    MJ_HIP(hipEventCreate(&e1));
+    double best = INFINITY;
+    mj_plan_t best_p = base;
+    const int reps = kind == MJ_LINEAR ? 2 : 1;
+    for (mj_plan_t c : cand) {
+        int st = plan_workspace(c);
+        if (st) return st;
+        if (c.workspace_bytes > ws_bytes) continue;
+        if (kind == MJ_LINEAR && (st = run_plan(ctx, kind, R, S, T, a_domain, out, c, ws, ws_bytes, stream)))
+            return st;
+        MJ_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r)
+            if ((st = run_plan(ctx, kind, R, S, T, a_domain, out, c, ws, ws_bytes, stream))) return st;
+        MJ_HIP(hipEventRecord(e1, s));
+        MJ_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        MJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double t = ms / reps;
+        if (t < best) { best = t; best_p = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!std::isfinite(best)) return MJ_ERR_WORKSPACE;
+    *plan = best_p;
+    mj_plan_t rec = best_p;
+    rec.est_ms_3way = best;
+    ctx->tuned[key] = rec;
+    if (tuned_ms) *tuned_ms = best;
+    // leave the winner's counts in `out`
+    return run_plan(ctx, kind, R, S, T, a_domain, out, best_p, ws, ws_bytes, stream);
+}
+
 }  // extern "C"
 
 // ============================================================== planning
@@ -825,32 +1003,22 @@ uint32_t join2_bits(uint64_t n) {
 
 int plan_workspace(mj_plan_t& p) {
     if (p.kind == MJ_LINEAR) {
-        const size_t lin = linear_layout(nullptr, p).bytes;
-        const CascadeLayout C = cascade_layout(nullptr, p, 0);
-        const size_t cas = C.base_bytes + C.i_cap * sizeof(uint2) + 256;
-        // enough for whichever algorithm the plan picked, and for the other
-        // one when the caller runs both on the same plan
-        p.workspace_bytes = std::max(lin, cas);
+        // enough for whichever algorithm the plan picked, for the other one
+        // when the caller runs both on the same plan, and for every bucket
+        // count the autotuner tries (up to 2^10)
+        size_t need = 0;
+        for (int wide = 0; wide < 2; ++wide) {
+            mj_plan_t q = p;
+            if (wide) { q.log2_nb = std::max<uint32_t>(q.log2_nb, 10); q.log2_nc = std::max<uint32_t>(q.log2_nc, 10); }
+            const size_t lin = linear_layout(nullptr, q).bytes;
+            const CascadeLayout C = cascade_layout(nullptr, q, 0);
+            need = std::max({need, lin, C.base_bytes + C.i_cap * sizeof(uint2) + 256});
+        }
+        p.workspace_bytes = need;
     } else {
-        p.workspace_bytes = tri_layout(nullptr, p).bytes;
-    }
-    return MJ_OK;
-}
-
-int analytic_plan(int kind, mj_plan_t& p, int num_cu) {
-    (void)num_cu;
-    p.seed = 0x1B873593u;
-    p.algo = MJ_ALGO_3WAY;
-    if (kind == MJ_LINEAR) {
-        // b-buckets: about 2048 S tuples per cell; c-buckets: about 4096 T
-        // tuples per multiplicity table
-        // b-buckets: about 32K S tuples per cell (enough cells to fill the
-        // chip, few enough for long partition runs); c-buckets: about 32K T
-        // tuples per multiplicity table
-        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 32767) / 32768));
-        p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
-    } else {
-        p.log2_share = 3;
+        const CasTriLayout C = cas_tri_layout(nullptr, p, 0);
+        p.workspace_bytes = std::max<size_t>(tri_layout(nullptr, p).bytes,
+                                             C.base_bytes + C.i_cap * sizeof(uint2) + 256);
     }
     return MJ_OK;
 }

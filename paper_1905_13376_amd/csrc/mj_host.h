@@ -10,6 +10,5 @@ int check_rel(const mj_rel* r);
 uint32_t ceil_log2(uint64_t x);
 uint32_t join2_bits(uint64_t n);
 int plan_workspace(mj_plan_t& p);
-int analytic_plan(int kind, mj_plan_t& p, int num_cu);
 
 }  // namespace mj

@@ -217,6 +217,7 @@ struct CasProbeArgs {
 };
 __global__ void k_cas_probe(CasProbeArgs A);
 
+
 __global__ void k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial);
 __global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
 __global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
@@ -291,6 +292,15 @@ struct TriJoinArgs {
     unsigned long long* total;
 };
 
+struct CasProbeTriArgs {
+    const uint2* I;                   // (a, c) pairs of R |x| S
+    uint64_t n;
+    RunIndex T;                       // T's lists per m(c), sorted by m(a)
+    const unsigned long long* Tk;
+    uint32_t seed;
+    unsigned long long* total;
+};
+__global__ void k_cas_probe_tri(CasProbeTriArgs A);
 __global__ void k_tri_keys(TriKeyArgs A);
 __global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags);
 __global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,

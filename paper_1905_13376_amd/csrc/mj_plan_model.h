@@ -1,0 +1,35 @@
+// Planner internals of libmj: device time model and cost formulas.
+#pragma once
+#include <stdint.h>
+
+#include "mj.h"
+
+namespace mj {
+
+struct DeviceModel {
+    double stream_gbs;
+    double probe_ps;
+    double atomic_ps;
+    double launch_us;
+    double lds_ps;
+    double list_ps;
+};
+
+DeviceModel default_model();
+int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m);
+
+double cost_linear_tuples(double R, double S, double T, double M);
+double cost_cascade_tuples(double I);
+double linear_break_even_M(double R, double S, double T, double I);
+double cost_cyclic_tuples(double R, double S, double T, double M, double H);
+double cyclic_optimal_H(double R, double S, double T, double M);
+double cost_cyclic_min(double R, double S, double T, double M);
+double join2_uniform_estimate(double R, double S, double d);
+double branch_hit_probability(double g3, double d);
+
+double model_linear_3way_ms(const DeviceModel& m, double R, double S, double T);
+double model_linear_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
+double model_cyclic_ms(const DeviceModel& m, double R, double S, double T, double I, double share);
+double model_cyclic_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
+
+}  // namespace mj

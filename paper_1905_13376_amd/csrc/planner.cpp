@@ -1,0 +1,168 @@
+// Analytic planner of libmj: the paper's cost formulas (tuples read onto the
+// chip) and an MI355X time model built on them, used to choose between the
+// three-way join and the cascade and to pick bucket counts and shares.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "mj.h"
+#include "mj_host.h"
+#include "mj_plan_model.h"
+
+namespace mj {
+
+// ---------------------------------------------------------- paper formulas
+// Sec. 4.2: R and S are read once, T once per partition of R (|R|/M of them).
+double cost_linear_tuples(double R, double S, double T, double M) { return R + S + R * T / M; }
+
+// Example 3: the cascade writes its intermediate and reads it back.
+double cost_cascade_tuples(double I) { return 2.0 * I; }
+
+// Example 3 solved for M: the smallest on-chip capacity for which the
+// three-way join reads fewer tuples than the cascade moves.
+double linear_break_even_M(double R, double S, double T, double I) {
+    const double room = 2.0 * I - R - S;
+    return room <= 0.0 ? INFINITY : R * T / room;
+}
+
+// Sec. 5.2: |R| + H|S| + G|T| with G H = |R| / M.
+double cost_cyclic_tuples(double R, double S, double T, double M, double H) {
+    return R + H * S + (R / (M * H)) * T;
+}
+double cyclic_optimal_H(double R, double S, double T, double M) { return std::sqrt(R * T / (M * S)); }
+double cost_cyclic_min(double R, double S, double T, double M) {
+    return R + 2.0 * std::sqrt(R * S * T / M);
+}
+
+// Sec. 6.3: |R join S| under uniform keys with d distinct values.
+double join2_uniform_estimate(double R, double S, double d) { return R * S / d; }
+
+// App. A: branch hit probability of the S.C = T.C test with g3 buckets.
+double branch_hit_probability(double g3, double d) { return g3 / d; }
+
+// ----------------------------------------------------------- time model
+// Device constants, calibrated on MI355X with the benchmark workloads:
+//   stream_gbs  bandwidth the partition/scan kernels reach (GB/s)
+//   probe_ps    amortised cost of one random table probe (ps)
+//   atomic_ps   amortised cost of one random 64-bit global atomic (ps)
+//   launch_us   fixed cost per kernel launch (us)
+//   lds_ps      amortised cost of one LDS probe in the cyclic join (ps)
+//   list_ps     amortised cost of one streamed list element (ps)
+DeviceModel default_model() {
+    DeviceModel m;
+    m.stream_gbs = 1900.0;
+    m.probe_ps = 21.0;
+    m.atomic_ps = 24.0;
+    m.launch_us = 6.0;
+    m.lds_ps = 8.0;
+    m.list_ps = 30.0;
+    return m;
+}
+
+// Linear three-way join: partitions (R, S: 16 B/tuple each pass incl. the
+// histogram read; T: 12 B), T's tables, one table probe per S tuple, one
+// LDS probe + one count atomic per R tuple, about 20 launches.
+double model_linear_3way_ms(const DeviceModel& m, double R, double S, double T) {
+    const double bytes = 24.0 * (R + S) + 16.0 * T + 16.0 * (R + S);
+    const double t = bytes / (m.stream_gbs * 1e9) + (S * m.probe_ps + R * m.atomic_ps) * 1e-12 +
+                     20.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
+// Cascade: the same partitions, R grouped by B, the scan over S, the
+// intermediate written and read (8 B each way per pair), one table probe
+// and one count atomic per pair.
+double model_linear_cascade_ms(const DeviceModel& m, double R, double S, double T, double I) {
+    const double bytes = 24.0 * (R + S) + 16.0 * T + 12.0 * R + 20.0 * S + 16.0 * I;
+    const double t = bytes / (m.stream_gbs * 1e9) + I * (m.probe_ps + m.atomic_ps) * 1e-12 +
+                     26.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
+// Cyclic join: three sorts (8 passes of 24 B/tuple), the run indexes, and
+// the intersection work, bounded by the wedges the cascade would
+// materialise (I); `share` slices hub lists and adds a list search per
+// slice and S tuple of hub groups (taken as a fraction of S).
+double model_cyclic_ms(const DeviceModel& m, double R, double S, double T, double I,
+                       double share) {
+    const double bytes = 8.0 * 24.0 * (R + S + T) + 40.0 * (R + S + T);
+    const double inter = std::min(I, 64.0 * std::sqrt(I) * std::sqrt(std::max(1.0, S)));
+    const double t = bytes / (m.stream_gbs * 1e9) + inter * m.list_ps * 1e-12 +
+                     share * 0.05 * S * 20.0 * m.probe_ps * 1e-12 + 90.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
+// Cyclic cascade: the wedges are materialised and each is checked against T.
+double model_cyclic_cascade_ms(const DeviceModel& m, double R, double S, double T, double I) {
+    const double bytes = 8.0 * 24.0 * T + 24.0 * (R + S) + 16.0 * I;
+    const double t = bytes / (m.stream_gbs * 1e9) + I * 3.0 * m.probe_ps * 1e-12 +
+                     40.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
+int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
+    (void)num_cu;
+    p.seed = 0x1B873593u;
+    const double R = (double)p.n_r, S = (double)p.n_s, T = (double)p.n_t;
+    const double I = (double)p.join2_size;
+    if (kind == MJ_LINEAR) {
+        // b-buckets: about 32K S tuples per cell; c-buckets: about 32K T
+        // tuples per multiplicity table (at most 2^10 of either)
+        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 32767) / 32768));
+        p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
+        p.est_ms_3way = model_linear_3way_ms(m, R, S, T);
+        p.est_ms_cascade = model_linear_cascade_ms(m, R, S, T, I);
+    } else {
+        // share on A: the candidate of {8, 16, 32} the time model prefers
+        double best = INFINITY;
+        uint32_t best_k = 3;
+        for (uint32_t k = 3; k <= 5; ++k) {
+            const double t = model_cyclic_ms(m, R, S, T, I, double(1u << k));
+            if (t < best) { best = t; best_k = k; }
+        }
+        p.log2_share = best_k;
+        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 32767) / 32768));
+        p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
+        p.est_ms_3way = best;
+        p.est_ms_cascade = model_cyclic_cascade_ms(m, R, S, T, I);
+    }
+    p.algo = p.est_ms_cascade < p.est_ms_3way ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
+    return MJ_OK;
+}
+
+}  // namespace mj
+
+// ------------------------------------------------------------- C ABI
+extern "C" int mj_cost_model(int which, const double* args, int nargs, double* out) {
+    using namespace mj;
+    if (!args || !out) return MJ_ERR_INVALID_ARG;
+    auto need = [&](int k) { return nargs >= k; };
+    switch (which) {
+        case MJ_COST_LINEAR_TUPLES:
+            if (!need(4)) return MJ_ERR_INVALID_ARG;
+            *out = cost_linear_tuples(args[0], args[1], args[2], args[3]); return MJ_OK;
+        case MJ_COST_CASCADE_TUPLES:
+            if (!need(1)) return MJ_ERR_INVALID_ARG;
+            *out = cost_cascade_tuples(args[0]); return MJ_OK;
+        case MJ_COST_LINEAR_BREAK_EVEN_M:
+            if (!need(4)) return MJ_ERR_INVALID_ARG;
+            *out = linear_break_even_M(args[0], args[1], args[2], args[3]); return MJ_OK;
+        case MJ_COST_CYCLIC_TUPLES:
+            if (!need(5)) return MJ_ERR_INVALID_ARG;
+            *out = cost_cyclic_tuples(args[0], args[1], args[2], args[3], args[4]); return MJ_OK;
+        case MJ_COST_CYCLIC_OPTIMAL_H:
+            if (!need(4)) return MJ_ERR_INVALID_ARG;
+            *out = cyclic_optimal_H(args[0], args[1], args[2], args[3]); return MJ_OK;
+        case MJ_COST_CYCLIC_MIN:
+            if (!need(4)) return MJ_ERR_INVALID_ARG;
+            *out = cost_cyclic_min(args[0], args[1], args[2], args[3]); return MJ_OK;
+        case MJ_COST_JOIN2_UNIFORM:
+            if (!need(3)) return MJ_ERR_INVALID_ARG;
+            *out = join2_uniform_estimate(args[0], args[1], args[2]); return MJ_OK;
+        case MJ_COST_BRANCH_HIT:
+            if (!need(2)) return MJ_ERR_INVALID_ARG;
+            *out = branch_hit_probability(args[0], args[1]); return MJ_OK;
+        default:
+            return MJ_ERR_INVALID_ARG;
+    }
+}

@@ -301,4 +301,21 @@ k_tri_heavy(TriJoinArgs A) {
     if (lane == 0 && acc) atomicAdd(A.total, acc);
 }
 
+// ----------------------------------------------- cascade, cyclic second join
+// For every (a, c) of I = R |x| S: the multiplicity of (c, a) in T, found in
+// T's sorted list of m(c) by binary search on m(a).
+__global__ void __launch_bounds__(256)
+k_cas_probe_tri(CasProbeTriArgs A) {
+    unsigned long long acc = 0;
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < A.n;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint2 iv = A.I[q];
+        uint32_t ts, y;
+        if (!run_lookup(A.T, mix32(iv.y, A.seed), ts, y)) continue;
+        acc += count_low(A.Tk, ts, ts + y, mix32(iv.x, A.seed));
+    }
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(A.total, acc);
+}
+
 }  // namespace mj
