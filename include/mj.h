@@ -137,6 +137,30 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
                       uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
                       void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* A batch of independent joins (many joins of uneven size).  Every item
+ * carries its relations, its output (uint64[a_domain] or uint64[1], device)
+ * and a plan from mj_plan (or the autotuner).  The preparation of every join
+ * (partitions, multiplicity tables, sorts, work queues) is launched join by
+ * join; then the cells of ALL linear joins run in one launch, and the groups
+ * of ALL cyclic joins in two persistent launches that pull work items from
+ * device queues (so the many small joins share the chip instead of each
+ * paying its own tail).  Items planned as cascades run their own path.
+ * Nothing is synchronised with the host, so the whole call can be captured
+ * in a HIP graph and replayed; the device argument tables are copied from
+ * pinned buffers the context keeps until mj_ctx_destroy.  Workspace: at
+ * least mj_batch_workspace() bytes; each join gets its own slice.        */
+typedef struct {
+    int32_t kind;
+    uint32_t a_domain;
+    mj_rel R, S, T;
+    uint64_t* out;
+    mj_plan_t plan;
+} mj_batch_item;
+
+uint64_t mj_batch_workspace(const mj_batch_item* items, int n);
+int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* workspace,
+                   uint64_t workspace_bytes, void* stream);
+
 /* Autotuner: times candidate plans of this join on the device (HIP events
  * on `stream`; synchronous) and keeps the fastest: for the linear kind
  * both algorithms and B / C bucket counts 2^8..2^10, for the cyclic kind

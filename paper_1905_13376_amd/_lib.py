@@ -58,6 +58,11 @@ class Plan(ctypes.Structure):
         return p
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a_domain", ctypes.c_uint32),
+                ("R", Rel), ("S", Rel), ("T", Rel), ("out", ctypes.c_void_p), ("plan", Plan)]
+
+
 _vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
 _RP = ctypes.POINTER(Rel)
 _PP = ctypes.POINTER(Plan)
@@ -73,6 +78,8 @@ _SIGS = {
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
     "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
     "mj_ctx_profile": ([_vp, _i32], _i32),
+    "mj_batch_workspace": ([ctypes.POINTER(BatchItem), _i32], _u64),
+    "mj_batch_count": ([_vp, ctypes.POINTER(BatchItem), _i32, _vp, _u64, _vp], _i32),
     "mj_autotune": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64,
                      ctypes.POINTER(ctypes.c_double), _vp], _i32),
     "mj_cost_model": ([_i32, ctypes.POINTER(ctypes.c_double), _i32,
@@ -246,6 +253,27 @@ class Context:
                                 _stream_ptr(stream)), "mj_autotune")
         return plan, ms.value, (out[:a_domain] if kind == LINEAR else out)
 
+    def batch(self, joins, stream=None, plans=None):
+        """Prepare a batch: `joins` is a list of (kind, R, S, T, a_domain).
+        Returns a Batch whose run() launches mj_batch_count and whose
+        `outs` hold the per-join uint64 results."""
+        items = (BatchItem * len(joins))()
+        outs = []
+        for i, (kind, R, S, T, a_domain) in enumerate(joins):
+            p = plans[i] if plans is not None else self.plan(kind, R, S, T, a_domain, stream=stream)
+            n_out = max(a_domain, 1) if kind == LINEAR else 1
+            o = torch.empty(n_out, dtype=torch.int64, device=R.device)
+            outs.append(o[:a_domain] if kind == LINEAR else o)
+            items[i].kind = kind
+            items[i].a_domain = a_domain
+            items[i].R, items[i].S, items[i].T = rel(R), rel(S), rel(T)
+            items[i].out = o.data_ptr()
+            items[i].plan = p
+        nbytes = _lib.mj_batch_workspace(items, len(joins))
+        device = joins[0][1].device if joins else "cuda"
+        ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return Batch(self, items, len(joins), ws, outs, [j[1:4] for j in joins])
+
     def join2_size(self, R, S, stream=None) -> int:
         need = _lib.mj_join2_size_workspace(R.shape[0], S.shape[0])
         ws = self.workspace(need, R.device)
@@ -254,6 +282,20 @@ class Context:
                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                   _stream_ptr(stream)), "mj_join2_size")
         return out.value
+
+
+class Batch:
+    """A prepared batch of joins (see Context.batch)."""
+
+    def __init__(self, ctx, items, n, ws, outs, keep):
+        self.ctx, self.items, self.n, self.ws, self.outs = ctx, items, n, ws, outs
+        self._keep = keep          # the relations must outlive the batch
+
+    def run(self, stream=None):
+        _check(_lib.mj_batch_count(self.ctx._h, self.items, self.n,
+                                   ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                   _stream_ptr(stream)), "mj_batch_count")
+        return self.outs
 
 
 def as_u64(t: torch.Tensor):

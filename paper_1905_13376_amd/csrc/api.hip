@@ -77,6 +77,7 @@ struct mj_ctx {
     Prof prof;
     DeviceModel model = default_model();
     std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
+    std::vector<void*> pinned;                  // batch argument tables (kept alive)
 };
 
 namespace {
@@ -514,6 +515,44 @@ CasTriLayout cas_tri_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
     return L;
 }
 
+int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const mj_rel& T,
+                const mj_plan_t& p, const TriLayout& L, unsigned long long* out, hipStream_t s) {
+    (void)num_cu; (void)out;
+    int st;
+    const uint32_t seed = p.seed;
+    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)), T -> (m(c), m(a)); sorted
+    if ((st = tri_keys(prof, R, 1, L.Rk, seed, s))) return st;
+    if ((st = tri_keys(prof, S, 0, L.Sk, seed, s))) return st;
+    if ((st = tri_keys(prof, T, 0, L.Tk, seed, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Rk, L.tmp, R.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    // lists of R per B, of T per C; groups of S per B
+    if ((st = launch_runs(prof, L, L.Rk, R.n, L.R, s))) return st;
+    if ((st = launch_runs(prof, L, L.Tk, T.n, L.T, s))) return st;
+    if ((st = launch_runs(prof, L, L.Sk, S.n, L.S, s))) return st;
+    // work queues
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.ctr, (uint64_t)4, 0u);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(L.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
+              L.heavy_items, (uint64_t)L.n_heavy_cap, 0u);
+    TriClassifyArgs C;
+    C.R = run_index(L.R); C.S = run_index(L.S); C.share = 1u << p.log2_share;
+    C.nlight = L.ctr + 0; C.light = L.light;
+    C.nheavy_groups = L.ctr + 2; C.heavy_group = L.heavy_group; C.heavy_items = L.heavy_items;
+    MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S.n, 256, 16384)), dim3(256), 0, s, C);
+    return launch_scan_u32(prof, L.heavy_items, L.n_heavy_cap, L.partial, L.heavy_off, s);
+}
+
+TriJoinArgs tri_join_args(const TriLayout& L, const mj_plan_t& p, unsigned long long* out) {
+    TriJoinArgs J;
+    J.R = run_index(L.R); J.S = run_index(L.S); J.T = run_index(L.T);
+    J.Rk = L.Rk; J.Sk = L.Sk; J.Tk = L.Tk;
+    J.nlight = L.ctr + 0; J.light = L.light; J.light_next = L.ctr + 1;
+    J.heavy_group = L.heavy_group; J.heavy_off = L.heavy_off; J.n_heavy_cap = L.n_heavy_cap;
+    J.heavy_next = L.ctr + 3; J.share = 1u << p.log2_share; J.total = out;
+    return J;
+}
+
 int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, uint64_t* out,
                      const mj_plan_t& p, void* ws, uint64_t ws_bytes, void* stream) {
     if (p.log2_nb > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
@@ -611,6 +650,7 @@ int mj_ctx_destroy(mj_ctx* ctx) {
     hipDeviceSynchronize();
     if (ctx->stats) hipFree(ctx->stats);
     if (ctx->scratch) hipFree(ctx->scratch);
+    for (void* h : ctx->pinned) (void)hipHostFree(h);
     delete ctx;
     return MJ_OK;
 }
@@ -804,35 +844,8 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
     unsigned long long* out = reinterpret_cast<unsigned long long*>(total);
     MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0) return MJ_OK;
-    const uint32_t seed = p.seed;
-    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)), T -> (m(c), m(a)); sorted
-    if ((st = tri_keys(prof, *R, 1, L.Rk, seed, s))) return st;
-    if ((st = tri_keys(prof, *S, 0, L.Sk, seed, s))) return st;
-    if ((st = tri_keys(prof, *T, 0, L.Tk, seed, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Rk, L.tmp, R->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    // lists of R per B, of T per C; groups of S per B
-    if ((st = launch_runs(prof, L, L.Rk, R->n, L.R, s))) return st;
-    if ((st = launch_runs(prof, L, L.Tk, T->n, L.T, s))) return st;
-    if ((st = launch_runs(prof, L, L.Sk, S->n, L.S, s))) return st;
-    // work queues
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.ctr, (uint64_t)4, 0u);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(L.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
-              L.heavy_items, (uint64_t)L.n_heavy_cap, 0u);
-    const uint32_t share = 1u << p.log2_share;
-    TriClassifyArgs C;
-    C.R = run_index(L.R); C.S = run_index(L.S); C.share = share;
-    C.nlight = L.ctr + 0; C.light = L.light;
-    C.nheavy_groups = L.ctr + 2; C.heavy_group = L.heavy_group; C.heavy_items = L.heavy_items;
-    MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, C);
-    if ((st = launch_scan_u32(prof, L.heavy_items, L.n_heavy_cap, L.partial, L.heavy_off, s))) return st;
-    TriJoinArgs J;
-    J.R = run_index(L.R); J.S = run_index(L.S); J.T = run_index(L.T);
-    J.Rk = L.Rk; J.Sk = L.Sk; J.Tk = L.Tk;
-    J.nlight = L.ctr + 0; J.light = L.light; J.light_next = L.ctr + 1;
-    J.heavy_group = L.heavy_group; J.heavy_off = L.heavy_off; J.n_heavy_cap = L.n_heavy_cap;
-    J.heavy_next = L.ctr + 3; J.share = share; J.total = out;
+    if ((st = tri_prepare(prof, ctx->num_cu, *R, *S, *T, p, L, out, s))) return st;
+    TriJoinArgs J = tri_join_args(L, p, out);
     const uint32_t persistent = (uint32_t)ctx->num_cu * 8;
     MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
     MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_THREADS), 0, s, J);
@@ -902,6 +915,132 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         Q.c_seed = seed_c(p); Q.c_bits = p.log2_nc; Q.slot_seed = seed_slot(p);
         Q.count = count; Q.a_domain = a_domain; Q.err = L.T.err;
         MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
+    }
+    return MJ_OK;
+}
+
+// ------------------------------------------------------------------ batch
+static size_t batch_item_bytes(const mj_batch_item& it) {
+    if (it.plan.algo == MJ_ALGO_CASCADE) return it.plan.workspace_bytes;
+    if (it.kind == MJ_LINEAR) return linear_layout(nullptr, it.plan).bytes;
+    return tri_layout(nullptr, it.plan).bytes;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+uint64_t mj_batch_workspace(const mj_batch_item* items, int n) {
+    if (!items || n < 0) return 0;
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) off += align256(batch_item_bytes(items[i]));
+    const size_t nn = (size_t)n;
+    off += align256(nn * sizeof(LinearCellArgs)) + align256((nn + 1) * 4) +
+           align256(nn * sizeof(TriJoinArgs)) + 2 * align256((nn + 1) * 8) + align256(16);
+    return off + 256;
+}
+
+int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uint64_t ws_bytes,
+                   void* stream) {
+    if (!ctx || (!items && n) || n < 0) return MJ_ERR_INVALID_ARG;
+    if (n == 0) return MJ_OK;
+    if (!ws || ws_bytes < mj_batch_workspace(items, n)) return MJ_ERR_WORKSPACE;
+    // validation first: nothing is launched unless every item is valid
+    for (int i = 0; i < n; ++i) {
+        const mj_batch_item& it = items[i];
+        int st;
+        if ((st = check_rel(&it.R)) || (st = check_rel(&it.S)) || (st = check_rel(&it.T))) return st;
+        if (!it.out) return MJ_ERR_INVALID_ARG;
+        const mj_plan_t& p = it.plan;
+        if (p.kind != it.kind || p.n_r != it.R.n || p.n_s != it.S.n || p.n_t != it.T.n ||
+            (it.kind == MJ_LINEAR && p.a_domain != it.a_domain))
+            return MJ_ERR_PLAN_MISMATCH;
+        if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 16)
+            return MJ_ERR_INVALID_ARG;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    char* base = static_cast<char*>(ws);
+    size_t off = 0;
+    std::vector<LinearCellArgs> lin;
+    std::vector<uint32_t> cell_base(1, 0);
+    std::vector<TriJoinArgs> tri;
+    for (int i = 0; i < n; ++i) {
+        const mj_batch_item& it = items[i];
+        const mj_plan_t& p = it.plan;
+        void* wsi = base + off;
+        const size_t bytes = batch_item_bytes(it);
+        off += align256(bytes);
+        int st;
+        if (p.algo == MJ_ALGO_CASCADE) {
+            st = mj_cascade2_count(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, &p, wsi,
+                                   bytes, stream);
+            if (st) return st;
+            continue;
+        }
+        if (it.kind == MJ_LINEAR) {
+            LinearLayout L = linear_layout(wsi, p);
+            unsigned long long* count = reinterpret_cast<unsigned long long*>(it.out);
+            if (it.a_domain)
+                MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(it.a_domain, 256, 4096)), dim3(256), 0, s,
+                          count, (uint64_t)it.a_domain, 0ull);
+            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) continue;
+            if ((st = launch_tables(prof, L.T, it.T, 0, p.log2_nc, seed_c(p), seed_slot(p), s))) return st;
+            PartLaunch P{};
+            P.njobs = 2;
+            P.job[0] = make_job(it.R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+            P.job[0].out_pair = L.R.pairs;
+            P.job[1] = make_job(it.S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+            P.job[1].out_pair = L.S.pairs;
+            if ((st = launch_partition(prof, "rs", P, s))) return st;
+            LinearCellArgs C;
+            C.R = L.R.pairs; C.rstarts = L.R.starts; C.S = L.S.pairs; C.sstarts = L.S.starts;
+            C.ddir = L.T.dir; C.dpool = L.T.pool;
+            C.c_seed = seed_c(p); C.c_bits = p.log2_nc; C.slot_seed = seed_slot(p); C.w_seed = seed_w(p);
+            C.count = count; C.a_domain = it.a_domain; C.err = L.T.err;
+            lin.push_back(C);
+            cell_base.push_back(cell_base.back() + (1u << p.log2_nb));
+        } else {
+            TriLayout L = tri_layout(wsi, p);
+            unsigned long long* out = reinterpret_cast<unsigned long long*>(it.out);
+            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) continue;
+            if ((st = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, s))) return st;
+            tri.push_back(tri_join_args(L, p, out));
+        }
+    }
+    // device argument tables, staged through a pinned buffer kept by the context
+    const size_t nl = lin.size(), nt = tri.size();
+    const size_t a_lin = align256(nl * sizeof(LinearCellArgs)), a_cb = align256((nl + 1) * 4);
+    const size_t a_tri = align256(nt * sizeof(TriJoinArgs));
+    const size_t stage = a_lin + a_cb + a_tri;
+    char* host = nullptr;
+    MJ_HIP(hipHostMalloc(reinterpret_cast<void**>(&host), std::max<size_t>(stage, 256)));
+    ctx->pinned.push_back(host);
+    if (nl) std::memcpy(host, lin.data(), nl * sizeof(LinearCellArgs));
+    std::memcpy(host + a_lin, cell_base.data(), (nl + 1) * 4);
+    if (nt) std::memcpy(host + a_lin + a_cb, tri.data(), nt * sizeof(TriJoinArgs));
+    char* dev = base + off;
+    MJ_HIP(hipMemcpyAsync(dev, host, stage, hipMemcpyHostToDevice, s));
+    if (nl) {
+        LinearBatchArgs B;
+        B.joins = reinterpret_cast<const LinearCellArgs*>(dev);
+        B.cell_base = reinterpret_cast<const uint32_t*>(dev + a_lin);
+        B.njoins = (uint32_t)nl;
+        MJ_LAUNCH(prof, "k_linear_cell_batch", k_linear_cell_batch, dim3(cell_base.back()),
+                  dim3(CELL_THREADS), 0, s, B);
+    }
+    if (nt) {
+        char* q = dev + stage;
+        TriBatchArgs B;
+        B.joins = reinterpret_cast<const TriJoinArgs*>(dev + a_lin + a_cb);
+        B.njoins = (uint32_t)nt;
+        B.light_base = reinterpret_cast<unsigned long long*>(q);
+        B.heavy_base = reinterpret_cast<unsigned long long*>(q + align256((nt + 1) * 8));
+        B.next = reinterpret_cast<unsigned long long*>(q + 2 * align256((nt + 1) * 8));
+        MJ_LAUNCH(prof, "k_tri_batch_prefix", k_tri_batch_prefix, dim3(1), dim3(64), 0, s, B);
+        MJ_LAUNCH(prof, "k_tri_light_batch", k_tri_light_batch, dim3((uint32_t)ctx->num_cu * 8),
+                  dim3(TRI_THREADS), 0, s, B);
+        MJ_LAUNCH(prof, "k_tri_heavy_batch", k_tri_heavy_batch, dim3((uint32_t)ctx->num_cu * 2),
+                  dim3(TRI_THREADS), 0, s, B);
     }
     return MJ_OK;
 }

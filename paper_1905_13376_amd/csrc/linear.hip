@@ -165,8 +165,7 @@ __device__ __forceinline__ uint32_t pass_of(uint32_t b, uint32_t seed, uint32_t 
     return top_bits(mix32(b, seed ^ 0x3C6EF372u), level);
 }
 
-__global__ void __launch_bounds__(CELL_THREADS)
-k_linear_cell(LinearCellArgs A) {
+__device__ void linear_cell_run(const LinearCellArgs& A, uint32_t i) {
     __shared__ uint32_t wkeys[CELL_CAP];
     __shared__ unsigned long long wvals[CELL_CAP];
     __shared__ unsigned long long w_special;
@@ -174,7 +173,6 @@ k_linear_cell(LinearCellArgs A) {
     __shared__ uint32_t st_level[64], st_pass[64];
     __shared__ int s_sp;
 
-    const uint32_t i = blockIdx.x;
     const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
     const uint32_t r0 = A.rstarts[i], r1 = A.rstarts[i + 1];
     if (s0 == s1 || r0 == r1) return;      // nothing can match in this cell
@@ -267,6 +265,21 @@ k_linear_cell(LinearCellArgs A) {
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(CELL_THREADS)
+k_linear_cell(LinearCellArgs A) {
+    linear_cell_run(A, blockIdx.x);
+}
+
+// All cells of all linear joins of a batch in one launch: block b is cell
+// b - cell_base[j] of the join j with cell_base[j] <= b < cell_base[j + 1].
+__global__ void __launch_bounds__(CELL_THREADS)
+k_linear_cell_batch(LinearBatchArgs B) {
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = B.njoins;
+    while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (B.cell_base[m] <= b) lo = m; else hi = m; }
+    linear_cell_run(B.joins[lo], b - B.cell_base[lo]);
 }
 
 }  // namespace mj

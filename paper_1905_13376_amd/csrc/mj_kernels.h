@@ -301,6 +301,24 @@ struct CasProbeTriArgs {
     unsigned long long* total;
 };
 __global__ void k_cas_probe_tri(CasProbeTriArgs A);
+struct TriBatchArgs {
+    const TriJoinArgs* joins;            // [njoins] on the device
+    uint32_t njoins;
+    unsigned long long* light_base;      // [njoins + 1]
+    unsigned long long* heavy_base;      // [njoins + 1]
+    unsigned long long* next;            // [2] work counters
+};
+__global__ void k_tri_light_batch(TriBatchArgs B);
+__global__ void k_tri_heavy_batch(TriBatchArgs B);
+__global__ void k_tri_batch_prefix(TriBatchArgs B);
+
+struct LinearBatchArgs {
+    const LinearCellArgs* joins;         // [njoins] on the device
+    const uint32_t* cell_base;           // [njoins + 1] first cell of each join
+    uint32_t njoins;
+};
+__global__ void k_linear_cell_batch(LinearBatchArgs B);
+
 __global__ void k_tri_keys(TriKeyArgs A);
 __global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags);
 __global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,

@@ -166,22 +166,78 @@ __device__ __forceinline__ void wave_fence() {
 }
 
 // ------------------------------------------------------------- light groups
+// One wave, one S group: R's list of b into the wave's LDS table, then every
+// s(b,c) of the group streams T's list of c past it.  Returns the lane's sum.
+struct WaveTable {
+    uint32_t* keys;
+    uint32_t* vals;
+    uint32_t* used;
+    uint32_t* nused;
+    uint32_t* spec;
+};
+
+__device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, const WaveTable& W) {
+    const int lane = lane_id();
+    const uint32_t mask = TRI_LIGHT_CAP - 1;
+    const uint32_t mb = A.S.run_key[g];
+    const uint32_t gs = A.S.run_start[g], ge = A.S.run_start[g + 1];
+    uint32_t rs = 0, x = 0;
+    run_lookup(A.R, mb, rs, x);
+    for (uint32_t q = lane; q < x; q += WAVE) {
+        const uint32_t a = (uint32_t)A.Rk[rs + q];
+        if (a == EMPTY_KEY) { atomicAdd(W.spec, 1u); continue; }
+        uint32_t s = a & mask;
+        while (true) {
+            const uint32_t cur = W.keys[s];
+            if (cur == a) { atomicAdd(&W.vals[s], 1u); break; }
+            if (cur == EMPTY_KEY) {
+                const uint32_t old = atomicCAS(&W.keys[s], EMPTY_KEY, a);
+                if (old == EMPTY_KEY) { W.used[atomicAdd(W.nused, 1u)] = s; atomicAdd(&W.vals[s], 1u); break; }
+                if (old == a) { atomicAdd(&W.vals[s], 1u); break; }
+            }
+            s = (s + 1u) & mask;
+        }
+    }
+    wave_fence();
+    const uint32_t spec = *W.spec;
+    unsigned long long acc = 0;
+    for (uint32_t si = gs + lane; si < ge; si += WAVE) {
+        const uint32_t mc = (uint32_t)A.Sk[si];
+        uint32_t ts, y;
+        if (!run_lookup(A.T, mc, ts, y)) continue;
+        if (y <= 4 * x) {
+            for (uint32_t t = ts; t < ts + y; ++t)
+                acc += atab_get(W.keys, W.vals, mask, spec, (uint32_t)A.Tk[t]);
+        } else {
+            for (uint32_t q = rs; q < rs + x; ++q)
+                acc += count_low(A.Tk, ts, ts + y, (uint32_t)A.Rk[q]);
+        }
+    }
+    wave_fence();
+    const uint32_t nu = *W.nused;
+    for (uint32_t q = lane; q < nu; q += WAVE) { const uint32_t s = W.used[q]; W.keys[s] = EMPTY_KEY; W.vals[s] = 0; }
+    wave_fence();
+    if (lane == 0) { *W.spec = 0; *W.nused = 0; }
+    wave_fence();
+    return acc;
+}
+
+#define TRI_LIGHT_SETUP                                                              \
+    constexpr int NW = TRI_THREADS / WAVE;                                           \
+    __shared__ uint32_t tkeys[NW][TRI_LIGHT_CAP];                                    \
+    __shared__ uint32_t tvals[NW][TRI_LIGHT_CAP];                                    \
+    __shared__ uint32_t tused[NW][TRI_LIGHT_X];                                      \
+    __shared__ uint32_t tnused[NW];                                                  \
+    __shared__ uint32_t tspec[NW];                                                   \
+    const int w = threadIdx.x / WAVE, lane = lane_id();                              \
+    WaveTable W{tkeys[w], tvals[w], tused[w], &tnused[w], &tspec[w]};                \
+    for (uint32_t s = lane; s < TRI_LIGHT_CAP; s += WAVE) { W.keys[s] = EMPTY_KEY; W.vals[s] = 0; } \
+    if (lane == 0) { *W.spec = 0; *W.nused = 0; }                                    \
+    wave_fence();
+
 __global__ void __launch_bounds__(TRI_THREADS)
 k_tri_light(TriJoinArgs A) {
-    constexpr int NW = TRI_THREADS / WAVE;
-    __shared__ uint32_t tkeys[NW][TRI_LIGHT_CAP];
-    __shared__ uint32_t tvals[NW][TRI_LIGHT_CAP];
-    __shared__ uint32_t tused[NW][TRI_LIGHT_X];
-    __shared__ uint32_t tnused[NW];
-    __shared__ uint32_t tspec[NW];
-    const int w = threadIdx.x / WAVE, lane = lane_id();
-    uint32_t* keys = tkeys[w];
-    uint32_t* vals = tvals[w];
-    uint32_t* used = tused[w];
-    const uint32_t mask = TRI_LIGHT_CAP - 1;
-    for (uint32_t s = lane; s < TRI_LIGHT_CAP; s += WAVE) { keys[s] = EMPTY_KEY; vals[s] = 0; }
-    if (lane == 0) { tspec[w] = 0; tnused[w] = 0; }
-    wave_fence();
+    TRI_LIGHT_SETUP
     const uint32_t nitems = *A.nlight;
     unsigned long long acc = 0;
     while (true) {
@@ -189,116 +245,162 @@ k_tri_light(TriJoinArgs A) {
         if (lane == 0) it = atomicAdd(A.light_next, 1u);
         it = __shfl(it, 0, WAVE);
         if (it >= nitems) break;
-        const uint32_t g = A.light[it];
-        const uint32_t mb = A.S.run_key[g];
-        const uint32_t gs = A.S.run_start[g], ge = A.S.run_start[g + 1];
-        uint32_t rs = 0, x = 0;
-        run_lookup(A.R, mb, rs, x);
-        // the R list of b -> the wave's LDS table (slots claimed are recorded)
-        for (uint32_t q = lane; q < x; q += WAVE) {
-            const uint32_t a = (uint32_t)A.Rk[rs + q];
-            if (a == EMPTY_KEY) { atomicAdd(&tspec[w], 1u); continue; }
-            uint32_t s = a & mask;
-            while (true) {
-                const uint32_t cur = keys[s];
-                if (cur == a) { atomicAdd(&vals[s], 1u); break; }
-                if (cur == EMPTY_KEY) {
-                    const uint32_t old = atomicCAS(&keys[s], EMPTY_KEY, a);
-                    if (old == EMPTY_KEY) { used[atomicAdd(&tnused[w], 1u)] = s; atomicAdd(&vals[s], 1u); break; }
-                    if (old == a) { atomicAdd(&vals[s], 1u); break; }
-                }
-                s = (s + 1u) & mask;
-            }
-        }
-        wave_fence();
-        const uint32_t spec = tspec[w];
-        for (uint32_t si = gs + lane; si < ge; si += WAVE) {
-            const uint32_t mc = (uint32_t)A.Sk[si];
-            uint32_t ts, y;
-            if (!run_lookup(A.T, mc, ts, y)) continue;
-            if (y <= 4 * x) {
-                for (uint32_t t = ts; t < ts + y; ++t)
-                    acc += atab_get(keys, vals, mask, spec, (uint32_t)A.Tk[t]);
-            } else {
-                for (uint32_t q = rs; q < rs + x; ++q)
-                    acc += count_low(A.Tk, ts, ts + y, (uint32_t)A.Rk[q]);
-            }
-        }
-        wave_fence();
-        const uint32_t nu = tnused[w];
-        for (uint32_t q = lane; q < nu; q += WAVE) { const uint32_t s = used[q]; keys[s] = EMPTY_KEY; vals[s] = 0; }
-        wave_fence();
-        if (lane == 0) { tspec[w] = 0; tnused[w] = 0; }
-        wave_fence();
+        acc += tri_light_group(A, A.light[it], W);
     }
     acc = wave_sum_u64(acc);
     if (lane == 0 && acc) atomicAdd(A.total, acc);
 }
 
 // ------------------------------------------------------------- heavy groups
-__global__ void __launch_bounds__(TRI_THREADS)
-k_tri_heavy(TriJoinArgs A) {
-    __shared__ uint32_t keys[TRI_HEAVY_CAP];
-    __shared__ uint32_t vals[TRI_HEAVY_CAP];
-    __shared__ uint32_t spec;
-    __shared__ uint32_t s_item;
+// One workgroup, one item: a slice of a hub's R list into LDS, then the
+// item's S tuples, one wave per S tuple, stream the slice's A range of T's list.
+struct BlockTable {
+    uint32_t* keys;
+    uint32_t* vals;
+    uint32_t* spec;
+};
+
+__device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, const BlockTable& B) {
     const int w = threadIdx.x / WAVE, lane = lane_id();
     constexpr int NW = TRI_THREADS / WAVE;
     const uint32_t mask = TRI_HEAVY_CAP - 1;
+    // item -> (heavy group, slice of R's list, range of S tuples)
+    uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
+    while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (A.heavy_off[m] <= it) lo = m; else hi = m; }
+    const uint32_t g = A.heavy_group[lo];
+    const uint32_t local = (uint32_t)(it - A.heavy_off[lo]);
+    uint32_t rs = 0, x = 0;
+    run_lookup(A.R, A.S.run_key[g], rs, x);
+    const uint32_t gs = A.S.run_start[g], gn = A.S.run_start[g + 1] - gs;
+    uint32_t nsl, nsr;
+    heavy_shape(x, gn, A.share, nsl, nsr);
+    const uint32_t sa = local / nsr, sb = local % nsr;
+    TriHeavyItem H;
+    H.r0 = rs + (uint32_t)((uint64_t)x * sa / nsl);
+    H.r1 = rs + (uint32_t)((uint64_t)x * (sa + 1) / nsl);
+    H.s0 = gs + sb * TRI_HEAVY_S;
+    H.s1 = min(gs + gn, H.s0 + TRI_HEAVY_S);
+    unsigned long long acc = 0;
+    if (H.r0 == H.r1) return 0;                       // uniform across the block
+    for (uint32_t q = H.r0 + threadIdx.x; q < H.r1; q += blockDim.x)
+        atab_add(B.keys, B.vals, mask, B.spec, (uint32_t)A.Rk[q]);
+    __syncthreads();
+    const uint32_t sp = *B.spec;
+    const uint32_t alo = (uint32_t)A.Rk[H.r0], ahi = (uint32_t)A.Rk[H.r1 - 1];
+    const uint32_t xs = H.r1 - H.r0;
+    for (uint32_t si = H.s0 + w; si < H.s1; si += NW) {
+        const uint32_t mc = (uint32_t)A.Sk[si];
+        uint32_t ts, y;
+        if (!run_lookup(A.T, mc, ts, y)) continue;
+        // the part of T's list (sorted by m(a)) inside [alo, ahi]
+        uint32_t l = ts, h = ts + y;
+        while (l < h) { uint32_t m = (l + h) >> 1; if ((uint32_t)A.Tk[m] < alo) l = m + 1; else h = m; }
+        uint32_t l2 = l, h2 = ts + y;
+        while (l2 < h2) { uint32_t m = (l2 + h2) >> 1; if ((uint32_t)A.Tk[m] <= ahi) l2 = m + 1; else h2 = m; }
+        const uint32_t ysub = l2 - l;
+        if (ysub <= 4 * xs) {
+            for (uint32_t t = l + lane; t < l2; t += WAVE)
+                acc += atab_get(B.keys, B.vals, mask, sp, (uint32_t)A.Tk[t]);
+        } else {
+            for (uint32_t q = H.r0 + lane; q < H.r1; q += WAVE)
+                acc += count_low(A.Tk, l, l2, (uint32_t)A.Rk[q]);
+        }
+    }
+    return acc;
+}
+
+#define TRI_HEAVY_SETUP                                                   \
+    __shared__ uint32_t hkeys[TRI_HEAVY_CAP];                             \
+    __shared__ uint32_t hvals[TRI_HEAVY_CAP];                             \
+    __shared__ uint32_t hspec;                                            \
+    __shared__ uint32_t s_item;                                           \
+    BlockTable B{hkeys, hvals, &hspec};                                   \
+    const int lane = lane_id();
+
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tri_heavy(TriJoinArgs A) {
+    TRI_HEAVY_SETUP
     const uint32_t nitems = (uint32_t)A.heavy_off[A.n_heavy_cap];
     unsigned long long acc = 0;
     while (true) {
         __syncthreads();
-        if (threadIdx.x == 0) { s_item = atomicAdd(A.heavy_next, 1u); spec = 0; }
-        for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { keys[s] = EMPTY_KEY; vals[s] = 0; }
+        if (threadIdx.x == 0) { s_item = atomicAdd(A.heavy_next, 1u); hspec = 0; }
+        for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { hkeys[s] = EMPTY_KEY; hvals[s] = 0; }
         __syncthreads();
         const uint32_t it = s_item;
         if (it >= nitems) break;
-        // item -> (heavy group, slice of R's list, range of S tuples)
-        uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
-        while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (A.heavy_off[m] <= it) lo = m; else hi = m; }
-        const uint32_t g = A.heavy_group[lo];
-        const uint32_t local = (uint32_t)(it - A.heavy_off[lo]);
-        uint32_t rs = 0, x = 0;
-        run_lookup(A.R, A.S.run_key[g], rs, x);
-        const uint32_t gs = A.S.run_start[g], gn = A.S.run_start[g + 1] - gs;
-        uint32_t nsl, nsr;
-        heavy_shape(x, gn, A.share, nsl, nsr);
-        const uint32_t sa = local / nsr, sb = local % nsr;
-        TriHeavyItem H;
-        H.r0 = rs + (uint32_t)((uint64_t)x * sa / nsl);
-        H.r1 = rs + (uint32_t)((uint64_t)x * (sa + 1) / nsl);
-        H.s0 = gs + sb * TRI_HEAVY_S;
-        H.s1 = min(gs + gn, H.s0 + TRI_HEAVY_S);
-        if (H.r0 == H.r1) continue;
-        for (uint32_t q = H.r0 + threadIdx.x; q < H.r1; q += blockDim.x)
-            atab_add(keys, vals, mask, &spec, (uint32_t)A.Rk[q]);
-        __syncthreads();
-        const uint32_t sp = spec;
-        const uint32_t alo = (uint32_t)A.Rk[H.r0], ahi = (uint32_t)A.Rk[H.r1 - 1];
-        const uint32_t xs = H.r1 - H.r0;
-        // each wave takes S tuples of the range; its lanes share one T list
-        for (uint32_t si = H.s0 + w; si < H.s1; si += NW) {
-            const uint32_t mc = (uint32_t)A.Sk[si];
-            uint32_t ts, y;
-            if (!run_lookup(A.T, mc, ts, y)) continue;
-            // the part of T's list (sorted by m(a)) inside [alo, ahi]
-            uint32_t l = ts, h = ts + y;
-            while (l < h) { uint32_t m = (l + h) >> 1; if ((uint32_t)A.Tk[m] < alo) l = m + 1; else h = m; }
-            uint32_t l2 = l, h2 = ts + y;
-            while (l2 < h2) { uint32_t m = (l2 + h2) >> 1; if ((uint32_t)A.Tk[m] <= ahi) l2 = m + 1; else h2 = m; }
-            const uint32_t ysub = l2 - l;
-            if (ysub <= 4 * xs) {
-                for (uint32_t t = l + lane; t < l2; t += WAVE)
-                    acc += atab_get(keys, vals, mask, sp, (uint32_t)A.Tk[t]);
-            } else {
-                for (uint32_t q = H.r0 + lane; q < H.r1; q += WAVE)
-                    acc += count_low(A.Tk, l, l2, (uint32_t)A.Rk[q]);
-            }
-        }
+        acc += tri_heavy_item(A, it, B);
     }
     acc = wave_sum_u64(acc);
     if (lane == 0 && acc) atomicAdd(A.total, acc);
+}
+
+// ------------------------------------------------------------- batches
+// Every cyclic join of a batch prepared its own queues; one persistent
+// launch serves all of them.  Global item k -> (join j, local item) through
+// the exclusive prefix of the per-join item counts.
+__device__ __forceinline__ uint32_t batch_join_of(const unsigned long long* base, uint32_t njoins,
+                                                  unsigned long long k) {
+    uint32_t lo = 0, hi = njoins;                     // last j with base[j] <= k
+    while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (base[m] <= k) lo = m; else hi = m; }
+    return lo;
+}
+
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tri_light_batch(TriBatchArgs Bt) {
+    TRI_LIGHT_SETUP
+    const unsigned long long nitems = Bt.light_base[Bt.njoins];
+    while (true) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(Bt.next, 1ull);
+        it = __shfl(it, 0, WAVE);
+        if (it >= nitems) break;
+        const uint32_t j = batch_join_of(Bt.light_base, Bt.njoins, it);
+        const TriJoinArgs& A = Bt.joins[j];
+        unsigned long long acc = tri_light_group(A, A.light[it - Bt.light_base[j]], W);
+        acc = wave_sum_u64(acc);
+        if (lane == 0 && acc) atomicAdd(A.total, acc);
+    }
+}
+
+__global__ void __launch_bounds__(TRI_THREADS)
+k_tri_heavy_batch(TriBatchArgs Bt) {
+    TRI_HEAVY_SETUP
+    __shared__ unsigned long long s_bitem;
+    __shared__ unsigned long long s_sum;
+    const unsigned long long nitems = Bt.heavy_base[Bt.njoins];
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) { s_bitem = atomicAdd(Bt.next + 1, 1ull); hspec = 0; s_sum = 0; }
+        for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { hkeys[s] = EMPTY_KEY; hvals[s] = 0; }
+        __syncthreads();
+        const unsigned long long it = s_bitem;
+        if (it >= nitems) break;
+        const uint32_t j = batch_join_of(Bt.heavy_base, Bt.njoins, it);
+        const TriJoinArgs& A = Bt.joins[j];
+        unsigned long long acc = tri_heavy_item(A, (uint32_t)(it - Bt.heavy_base[j]), B);
+        acc = wave_sum_u64(acc);
+        if (lane == 0 && acc) atomicAdd(&s_sum, acc);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_sum) atomicAdd(A.total, s_sum);
+    }
+    (void)s_item;
+}
+
+// per-join item counts of a batch -> exclusive prefixes (one block)
+__global__ void k_tri_batch_prefix(TriBatchArgs Bt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long l = 0, h = 0;
+    for (uint32_t j = 0; j < Bt.njoins; ++j) {
+        Bt.light_base[j] = l;
+        Bt.heavy_base[j] = h;
+        l += *Bt.joins[j].nlight;
+        h += Bt.joins[j].heavy_off[Bt.joins[j].n_heavy_cap];
+    }
+    Bt.light_base[Bt.njoins] = l;
+    Bt.heavy_base[Bt.njoins] = h;
+    Bt.next[0] = 0;
+    Bt.next[1] = 0;
 }
 
 // ----------------------------------------------- cascade, cyclic second join

@@ -107,3 +107,20 @@ def test_triangle_relabel_invariant(mj, ctx):
     lab = np.random.default_rng(3).permutation(5000).astype(np.int32)
     assert tri(mj, ctx, E, E, E) == tri(mj, ctx, lab[E], lab[E], lab[E]) == \
         oracle.triangle3_count(E, E, E)
+
+
+def test_triangle_rmat22_full_golden(mj, ctx):
+    """Full-size R-MAT scale 22 (2^27 directed tuples) in the plan the
+    benchmark uses, against the total the oracle wrote
+    (tests/golden/make_triangle_golden.py)."""
+    import json
+    import os
+    banner("triangle R-MAT scale 22 against the stored oracle total")
+    path = os.path.join(os.path.dirname(__file__), "golden", "triangle_rmat22.json")
+    gold = json.load(open(path))
+    E = G.triangle_rmat()
+    assert E.shape[0] == gold["directed_tuples"]
+    Ed = dev(E)
+    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, log2_share=3, seed=0x1B873593)
+    got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
+    assert got == gold["total"] and got % 6 == 0
