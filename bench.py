@@ -263,7 +263,62 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
         log(f"cyclic share {1 << share}: {ms_t:.1f} ms total {got}")
         del ws
     out["triangle_rmat22"] = tri
+    del Ed, E
+    out["batch_512"] = batch_path(mj, ctx)
     return out
+
+
+def batch_path(mj, ctx):
+    """512 independent joins of uneven size (half linear, half cyclic; edge
+    counts log-uniform in [10^3, 10^6]; uniform or Zipf(1.1) degrees): one
+    mj_batch_count call, its HIP-graph replay, and the same joins one call
+    each for comparison."""
+    import numpy as np
+    import torch
+    from workloads import generators as G
+    log("generating the batch of 512 joins")
+    inst = G.batch_instances()
+    joins, keep = [], []
+    for x in inst:
+        Fd = torch.from_numpy(np.ascontiguousarray(x["F"]).view(np.int32)).to("cuda")
+        keep.append(Fd)
+        if x["kind"] == "linear":
+            joins.append((mj.LINEAR, Fd, Fd, Fd, x["n"]))
+        else:
+            joins.append((mj.TRIANGLE, Fd, Fd, Fd, 0))
+    tuples = 3 * sum(int(k.shape[0]) for k in keep)
+    t0 = time.perf_counter()
+    plans = [ctx.plan(k, R, S, T, a) for (k, R, S, T, a) in joins]
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    b = ctx.batch(joins, plans=plans)
+    ms_batch = time_call(lambda: b.run(), 3)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    b.run()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        b.run(stream=s)
+    ms_graph = time_call(lambda: g.replay(), 3)
+    outs_b = [mj.as_u64(o).copy() for o in b.outs]
+
+    # one call per join (same plans), for comparison
+    ws = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device="cuda")
+    outs = [torch.empty(max(a, 1), dtype=torch.int64, device="cuda") for (_, _, _, _, a) in joins]
+
+    def seq():
+        for (k, R, S, T, a), p, o in zip(joins, plans, outs):
+            if k == mj.LINEAR:
+                ctx.linear3_count(R, S, T, a, plan=p, out=o, workspace=ws)
+            else:
+                ctx.triangle3_count(R, S, T, plan=p, out=o, workspace=ws)
+    ms_seq = time_call(seq, 2)
+    same = all(np.array_equal(mj.as_u64(o)[:max(a, 1) if k == mj.LINEAR else 1][:len(ob)], ob)
+               for (k, _, _, _, a), o, ob in zip(joins, outs, outs_b))
+    log(f"batch of 512: {ms_batch:.2f} ms (graph {ms_graph:.2f} ms), one call per join {ms_seq:.2f} ms")
+    return {"joins": len(joins), "input_tuples": tuples, "ms_batch": round(ms_batch, 3),
+            "ms_graph_replay": round(ms_graph, 3), "ms_one_call_per_join": round(ms_seq, 3),
+            "tuples_per_s_batch": tuples / (ms_graph * 1e-3), "plan_ms_total": round(plan_ms, 1),
+            "batch_equals_per_join_calls": bool(same)}
 
 
 if __name__ == "__main__":

@@ -85,6 +85,8 @@ typedef struct {
     uint64_t workspace_bytes;  /* bytes the count call needs                */
     double est_ms_3way;        /* planner's time estimates (0 = not known)  */
     double est_ms_cascade;
+    double pred_log2_join2;    /* learned planner: predicted log2(1 + |R |x| S|) */
+    double pred_log2_out;      /* learned planner: predicted log2(1 + |output|)  */
 } mj_plan_t;
 
 /* Context: binds the library to a device (the current one if device < 0). */
@@ -193,6 +195,53 @@ typedef enum {
     MJ_COST_BRANCH_HIT = 7         /* g3, d               */
 } mj_cost_formula;
 int mj_cost_model(int which, const double* args, int nargs, double* out);
+
+/* ---------------------------------------------------------------------
+ * Learned planner (not from the paper; its choices never change a count).
+ * A join is summarised by a degree sketch of MJ_SKETCH_DIM features: for
+ * R's B column, S's B column and T's C column a 32-bin histogram of
+ * floor(log2 deg(v)) over their distinct values v (each bin given as
+ * log2(1 + keys in the bin) / 32), then log2(1 + |R|), (1 + |S|), (1 + |T|)
+ * over 32, then the kind.  A network MJ_SKETCH_DIM -> 64 -> 64 -> 7 with
+ * GELU maps it to: predicted log2(1 + |R |x| S|), log2(1 + |output|),
+ * logits of (three-way, cascade) and of the share (8, 16, 32).
+ * Weights are BF16 (W1, W2, W3), biases and arithmetic FP32.
+ * The parameter buffer is device memory of mj_mlp_param_bytes() bytes:
+ *   float master[P], grad[P], adam_m[P], adam_v[P]; uint16 bf16_weights[]
+ * with P = 64*100 + 64 + 64*64 + 64 + 7*64 + 7 parameters in the order
+ * W1 (row-major [64][100]), b1, W2 ([64][64]), b2, W3 ([7][64]), b3.
+ * All calls are asynchronous on `stream` and launch kernels only.       */
+#define MJ_SKETCH_DIM 100
+#define MJ_MLP_HIDDEN 64
+#define MJ_MLP_OUT 7
+uint64_t mj_mlp_param_bytes(void);
+/* BF16 copies from the FP32 masters; gradients cleared. */
+int mj_mlp_sync(mj_ctx* ctx, void* params, void* stream);
+/* Y[B][7] = network(X[B][100]) (device fp32 arrays). */
+int mj_mlp_forward(mj_ctx* ctx, const void* params, const float* X, uint32_t B, float* Y,
+                   void* stream);
+/* Forward, loss and backward of a batch: the gradients are ADDED to the
+ * grad block of `params`; *loss (device fp32) is increased by the batch's
+ * mean loss: squared error of heads 0-1 against targets[B][2], softmax
+ * cross entropy of heads 2-3 against plan_label[B] (0 = three-way,
+ * 1 = cascade) and of heads 4-6 against share_label[B] (0, 1, 2 for
+ * 8, 16, 32; -1 = no share term).  Workspace: mj_mlp_workspace(B).     */
+uint64_t mj_mlp_workspace(uint32_t B);
+int mj_mlp_grads(mj_ctx* ctx, void* params, const float* X, uint32_t B, const float* targets,
+                 const int32_t* plan_label, const int32_t* share_label, float* loss,
+                 void* workspace, uint64_t workspace_bytes, void* stream);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay) at
+ * step number `step` (>= 1); refreshes the BF16 copies, clears gradients. */
+int mj_mlp_adamw(mj_ctx* ctx, void* params, float lr, float weight_decay, uint32_t step,
+                 void* stream);
+/* The degree sketch of a join (features: device fp32[MJ_SKETCH_DIM]). */
+uint64_t mj_sketch_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t);
+int mj_sketch(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+              float* features, void* workspace, uint64_t workspace_bytes, void* stream);
+/* Network used by mj_plan with MJ_PLANNER_LEARNED (NULL: the analytic
+ * planner is used instead).  The buffer stays owned by the caller and must
+ * live while plans are made. */
+int mj_ctx_set_planner(mj_ctx* ctx, const void* params);
 
 /* Exact |R |x| S| on B = sum_b deg_R(b) * deg_S(b) (the cascade's
  * intermediate size, Sec. 6.3), computed on the device.  Synchronous;

@@ -47,7 +47,8 @@ class Plan(ctypes.Structure):
                 ("n_r", ctypes.c_uint64), ("n_s", ctypes.c_uint64), ("n_t", ctypes.c_uint64),
                 ("a_domain", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("join2_size", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
-                ("est_ms_3way", ctypes.c_double), ("est_ms_cascade", ctypes.c_double)]
+                ("est_ms_3way", ctypes.c_double), ("est_ms_cascade", ctypes.c_double),
+                ("pred_log2_join2", ctypes.c_double), ("pred_log2_out", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -78,6 +79,15 @@ _SIGS = {
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
     "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
     "mj_ctx_profile": ([_vp, _i32], _i32),
+    "mj_mlp_param_bytes": ([], _u64),
+    "mj_mlp_workspace": ([_u32], _u64),
+    "mj_mlp_sync": ([_vp, _vp, _vp], _i32),
+    "mj_mlp_forward": ([_vp, _vp, _vp, _u32, _vp, _vp], _i32),
+    "mj_mlp_grads": ([_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp, _u64, _vp], _i32),
+    "mj_mlp_adamw": ([_vp, _vp, ctypes.c_float, ctypes.c_float, _u32, _vp], _i32),
+    "mj_sketch_workspace": ([_u64, _u64, _u64], _u64),
+    "mj_sketch": ([_vp, _i32, _RP, _RP, _RP, _vp, _vp, _u64, _vp], _i32),
+    "mj_ctx_set_planner": ([_vp, _vp], _i32),
     "mj_batch_workspace": ([ctypes.POINTER(BatchItem), _i32], _u64),
     "mj_batch_count": ([_vp, ctypes.POINTER(BatchItem), _i32, _vp, _u64, _vp], _i32),
     "mj_autotune": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64,
@@ -274,6 +284,25 @@ class Context:
         ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
         return Batch(self, items, len(joins), ws, outs, [j[1:4] for j in joins])
 
+    # ------------------------------------------------------- learned planner
+    def sketch(self, kind, R, S, T, out=None, stream=None) -> torch.Tensor:
+        """Degree-sketch features of a join (device fp32[100])."""
+        if out is None:
+            out = torch.empty(100, dtype=torch.float32, device=R.device)
+        need = _lib.mj_sketch_workspace(R.shape[0], S.shape[0], T.shape[0])
+        ws = self.workspace(need, R.device)
+        _check(_lib.mj_sketch(self._h, kind, rel(R), rel(S), rel(T), ctypes.c_void_p(out.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
+               "mj_sketch")
+        return out
+
+    def set_planner(self, params):
+        """Use the network in `params` (a LearnedPlanner buffer) for
+        planner='learned'; None restores the analytic planner."""
+        self._planner_keep = params
+        _check(_lib.mj_ctx_set_planner(self._h, ctypes.c_void_p(params.data_ptr()) if params is not None
+                                       else None), "mj_ctx_set_planner")
+
     def join2_size(self, R, S, stream=None) -> int:
         need = _lib.mj_join2_size_workspace(R.shape[0], S.shape[0])
         ws = self.workspace(need, R.device)
@@ -296,6 +325,37 @@ class Batch:
                                    ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
                                    _stream_ptr(stream)), "mj_batch_count")
         return self.outs
+
+
+def mlp_param_bytes() -> int:
+    return int(_lib.mj_mlp_param_bytes())
+
+
+def mlp_sync(ctx, params, stream=None):
+    _check(_lib.mj_mlp_sync(ctx._h, ctypes.c_void_p(params.data_ptr()), _stream_ptr(stream)), "mj_mlp_sync")
+
+
+def mlp_forward(ctx, params, X, Y, stream=None):
+    _check(_lib.mj_mlp_forward(ctx._h, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                               X.shape[0], ctypes.c_void_p(Y.data_ptr()), _stream_ptr(stream)),
+           "mj_mlp_forward")
+
+
+def mlp_grads(ctx, params, X, targets, plan_label, share_label, loss, workspace, stream=None):
+    _check(_lib.mj_mlp_grads(ctx._h, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                             X.shape[0], ctypes.c_void_p(targets.data_ptr()),
+                             ctypes.c_void_p(plan_label.data_ptr()), ctypes.c_void_p(share_label.data_ptr()),
+                             ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                             workspace.numel(), _stream_ptr(stream)), "mj_mlp_grads")
+
+
+def mlp_workspace_bytes(B: int) -> int:
+    return int(_lib.mj_mlp_workspace(B))
+
+
+def mlp_adamw(ctx, params, lr, wd, step, stream=None):
+    _check(_lib.mj_mlp_adamw(ctx._h, ctypes.c_void_p(params.data_ptr()), float(lr), float(wd), int(step),
+                             _stream_ptr(stream)), "mj_mlp_adamw")
 
 
 def as_u64(t: torch.Tensor):

@@ -78,6 +78,7 @@ struct mj_ctx {
     DeviceModel model = default_model();
     std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
     std::vector<void*> pinned;                  // batch argument tables (kept alive)
+    const void* planner = nullptr;              // learned planner parameters (device)
 };
 
 namespace {
@@ -766,6 +767,27 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     if (planner != MJ_PLANNER_FIXED) {
         st = analytic_plan(kind, p, ctx->num_cu, ctx->model);
         if (st) return st;
+        if (planner == MJ_PLANNER_LEARNED && ctx->planner) {
+            // the network's choice replaces the analytic one; the analytic
+            // estimates stay in the plan as its judge
+            const size_t need = mj_sketch_workspace(R->n, S->n, T->n) + 512;
+            if ((st = ensure_scratch(ctx, need))) return st;
+            float* feat = reinterpret_cast<float*>(static_cast<char*>(ctx->stats) + 256);
+            float* y = feat + MLP_IN;
+            if ((st = mj_sketch(ctx, kind, R, S, T, feat, ctx->scratch, ctx->scratch_bytes, stream))) return st;
+            if ((st = mj_mlp_forward(ctx, ctx->planner, feat, 1, y, stream))) return st;
+            float h[MLP_OUT];
+            MJ_HIP(hipMemcpyAsync(h, y, sizeof h, hipMemcpyDeviceToHost, s));
+            MJ_HIP(hipStreamSynchronize(s));
+            p.pred_log2_join2 = h[0];
+            p.pred_log2_out = h[1];
+            p.algo = h[3] > h[2] ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
+            if (kind == MJ_TRIANGLE) {
+                int best = 0;
+                for (int k = 1; k < 3; ++k) if (h[4 + k] > h[4 + best]) best = k;
+                p.log2_share = 3 + best;
+            }
+        }
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;
@@ -916,6 +938,112 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         Q.count = count; Q.a_domain = a_domain; Q.err = L.T.err;
         MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
     }
+    return MJ_OK;
+}
+
+// ------------------------------------------------------------ learned planner
+static float* mlp_master(void* p) { return static_cast<float*>(p); }
+static uint16_t* mlp_wbf16(void* p) { return reinterpret_cast<uint16_t*>(static_cast<float*>(p) + 4 * MLP_P); }
+
+uint64_t mj_mlp_param_bytes(void) { return uint64_t(4) * MLP_P * 4 + uint64_t(MLP_WB) * 2; }
+
+uint64_t mj_mlp_workspace(uint32_t B) {
+    return (uint64_t(B) * MLP_ACT + 2 * uint64_t(B) * MLP_OUT) * 4 + 512;
+}
+
+int mj_mlp_sync(mj_ctx* ctx, void* params, void* stream) {
+    if (!ctx || !params) return MJ_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MJ_LAUNCH(&ctx->prof, "k_mlp_sync", k_mlp_sync, dim3((MLP_P + 255) / 256), dim3(256), 0, s,
+              mlp_master(params), mlp_wbf16(params));
+    return MJ_OK;
+}
+
+int mj_mlp_forward(mj_ctx* ctx, const void* params, const float* X, uint32_t B, float* Y,
+                   void* stream) {
+    if (!ctx || !params || (B && (!X || !Y))) return MJ_ERR_INVALID_ARG;
+    if (B == 0) return MJ_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void* pp = const_cast<void*>(params);
+    MlpFwdArgs F{mlp_master(pp), mlp_wbf16(pp), X, Y, nullptr};
+    MJ_LAUNCH(&ctx->prof, "k_mlp_fwd", k_mlp_fwd, dim3(B), dim3(MLP_H), 0, s, F);
+    return MJ_OK;
+}
+
+int mj_mlp_grads(mj_ctx* ctx, void* params, const float* X, uint32_t B, const float* targets,
+                 const int32_t* plan_label, const int32_t* share_label, float* loss,
+                 void* ws, uint64_t ws_bytes, void* stream) {
+    if (!ctx || !params || !loss || (B && (!X || !targets || !plan_label || !share_label)))
+        return MJ_ERR_INVALID_ARG;
+    if (B == 0) return MJ_OK;
+    if (!ws || ws_bytes < mj_mlp_workspace(B)) return MJ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    Bump W(ws);
+    float* act = W.take<float>(uint64_t(B) * MLP_ACT);
+    float* Y = W.take<float>(uint64_t(B) * MLP_OUT);
+    float* dY = W.take<float>(uint64_t(B) * MLP_OUT);
+    MlpFwdArgs F{mlp_master(params), mlp_wbf16(params), X, Y, act};
+    MJ_LAUNCH(prof, "k_mlp_fwd", k_mlp_fwd, dim3(B), dim3(MLP_H), 0, s, F);
+    MlpLossArgs Lo{Y, dY, targets, plan_label, share_label, B, loss};
+    MJ_LAUNCH(prof, "k_mlp_loss", k_mlp_loss, dim3((B + 255) / 256), dim3(256), 0, s, Lo);
+    MlpBwdArgs Bw{mlp_wbf16(params), X, act, dY, B, mlp_master(params) + MLP_P};
+    MJ_LAUNCH(prof, "k_mlp_bwd", k_mlp_bwd, dim3((B + MLP_SPB - 1) / MLP_SPB), dim3(MLP_H), 0, s, Bw);
+    return MJ_OK;
+}
+
+int mj_mlp_adamw(mj_ctx* ctx, void* params, float lr, float wd, uint32_t step, void* stream) {
+    if (!ctx || !params || step == 0) return MJ_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MlpAdamArgs A;
+    A.buf = mlp_master(params); A.wbf16 = mlp_wbf16(params);
+    A.lr = lr; A.wd = wd; A.beta1 = 0.9f; A.beta2 = 0.999f; A.eps = 1e-8f;
+    A.bc1 = (float)(1.0 - std::pow(0.9, (double)step));
+    A.bc2 = (float)(1.0 - std::pow(0.999, (double)step));
+    MJ_LAUNCH(&ctx->prof, "k_mlp_adamw", k_mlp_adamw, dim3((MLP_P + 255) / 256), dim3(256), 0, s, A);
+    return MJ_OK;
+}
+
+uint64_t mj_sketch_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t) {
+    const uint64_t n = std::max<uint64_t>({n_r, n_s, n_t, 1});
+    Bump B(nullptr);
+    TableLayout L;
+    take_table(B, L, n, join2_bits(n));
+    B.take<uint32_t>(96);
+    return B.off + 256;
+}
+
+int mj_sketch(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+              float* features, void* ws, uint64_t ws_bytes, void* stream) {
+    if (!ctx || !features || (kind != MJ_LINEAR && kind != MJ_TRIANGLE)) return MJ_ERR_INVALID_ARG;
+    int st;
+    if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
+    if (!ws || ws_bytes < mj_sketch_workspace(R->n, S->n, T->n)) return MJ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    const uint64_t n = std::max<uint64_t>({R->n, S->n, T->n, 1});
+    const uint32_t bits = join2_bits(n);
+    Bump B(ws);
+    TableLayout L;
+    take_table(B, L, n, bits);
+    uint32_t* hist = B.take<uint32_t>(96);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(96), 0, s, hist, (uint64_t)96, 0u);
+    const mj_rel* rels[3] = {R, S, T};
+    const int cols[3] = {1, 0, 0};
+    for (int h = 0; h < 3; ++h) {
+        if (rels[h]->n == 0) continue;
+        if ((st = launch_tables(prof, L, *rels[h], cols[h], bits, 0x6A09E667u + h, 0xBB67AE85u, s))) return st;
+        MJ_LAUNCH(prof, "k_deg_hist", k_deg_hist, dim3(1u << bits), dim3(256), 0, s,
+                  L.dir, L.pool, 1u << bits, hist + 32 * h);
+    }
+    MJ_LAUNCH(prof, "k_sketch_features", k_sketch_features, dim3(1), dim3(128), 0, s,
+              hist, R->n, S->n, T->n, kind, features);
+    return MJ_OK;
+}
+
+int mj_ctx_set_planner(mj_ctx* ctx, const void* params) {
+    if (!ctx) return MJ_ERR_INVALID_ARG;
+    ctx->planner = params;
     return MJ_OK;
 }
 

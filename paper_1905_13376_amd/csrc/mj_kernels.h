@@ -330,6 +330,60 @@ __global__ void k_tri_classify(TriClassifyArgs A);
 __global__ void k_tri_light(TriJoinArgs A);
 __global__ void k_tri_heavy(TriJoinArgs A);
 
+// ------------------------------------------------------------ learned planner
+constexpr int MLP_IN = 100, MLP_H = 64, MLP_OUT = 7;
+constexpr int MLP_OFF_W1 = 0;
+constexpr int MLP_OFF_B1 = MLP_OFF_W1 + MLP_H * MLP_IN;
+constexpr int MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_H * MLP_H;
+constexpr int MLP_OFF_W3 = MLP_OFF_B2 + MLP_H;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_OUT * MLP_H;
+constexpr int MLP_P = MLP_OFF_B3 + MLP_OUT;
+constexpr int MLP_WB_W1 = 0;
+constexpr int MLP_WB_W2 = MLP_WB_W1 + MLP_H * MLP_IN;
+constexpr int MLP_WB_W3 = MLP_WB_W2 + MLP_H * MLP_H;
+constexpr int MLP_WB = MLP_WB_W3 + MLP_OUT * MLP_H;
+constexpr int MLP_ACT = 4 * MLP_H;        // z1, a1, z2, a2 per sample
+constexpr int MLP_SPB = 32;               // samples per backward block
+
+struct MlpFwdArgs {
+    const float* params;                  // fp32 masters (biases read here)
+    const uint16_t* wbf16;
+    const float* X;                       // [B][MLP_IN]
+    float* Y;                             // [B][MLP_OUT]
+    float* act;                           // [B][MLP_ACT] or null
+};
+struct MlpLossArgs {
+    const float* Y;
+    float* dY;
+    const float* targets;                 // [B][2]
+    const int* plan_label;                // [B]
+    const int* share_label;               // [B], -1 = none
+    uint32_t B;
+    float* loss;                          // += mean loss
+};
+struct MlpBwdArgs {
+    const uint16_t* wbf16;
+    const float* X;
+    const float* act;
+    const float* dY;
+    uint32_t B;
+    float* grad;                          // [MLP_P]
+};
+struct MlpAdamArgs {
+    float* buf;                           // master | grad | m | v
+    uint16_t* wbf16;
+    float lr, wd, beta1, beta2, eps, bc1, bc2;
+};
+__global__ void k_mlp_fwd(MlpFwdArgs A);
+__global__ void k_mlp_loss(MlpLossArgs A);
+__global__ void k_mlp_bwd(MlpBwdArgs A);
+__global__ void k_mlp_adamw(MlpAdamArgs A);
+__global__ void k_mlp_sync(float* buf, uint16_t* wbf16);
+__global__ void k_deg_hist(const DirEntry* dir, const uint2* pool, uint32_t nbkt, uint32_t* hist);
+__global__ void k_sketch_features(const uint32_t* hist3, uint64_t nr, uint64_t ns, uint64_t nt,
+                                  int kind, float* f);
+
 // max of a column (key-range check)
 __global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out);
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v);
