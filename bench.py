@@ -265,7 +265,24 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     out["triangle_rmat22"] = tri
     del Ed, E
     out["batch_512"] = batch_path(mj, ctx)
+    out["planner"] = planner_path(ctx)
     return out
+
+
+def planner_path(ctx, n=300):
+    """Learned vs plain planners on held-out join instances (sizes 10^3 to
+    10^5, the families the network was trained on, other seeds): the
+    summed measured time of each planner's plans, with counts checked."""
+    import numpy as np
+    from paper_1905_13376_amd import learned
+    log(f"planner comparison on {n} held-out instances")
+    pl = learned.use_shipped(ctx)
+    rows = [learned.label_instance(ctx, x) for x in learned.planner_instances(n, 7_000_000)]
+    res = learned.evaluate(pl, rows)
+    res["counts_exact_all_plans"] = all(r["cascade_equals_3way"] for r in rows)
+    res["plan_ms_median_analytic"] = round(float(np.median([r["plan_ms"] for r in rows])), 3)
+    ctx.set_planner(None)
+    return res
 
 
 def batch_path(mj, ctx):

@@ -788,6 +788,10 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
                 p.log2_share = 3 + best;
             }
         }
+        // an intermediate beyond one workspace-sized chunk is never worth
+        // materialising: the three-way join reads each input a bounded
+        // number of times
+        if (p.algo == MJ_ALGO_CASCADE && p.join2_size > CAS_DEFAULT_I_CAP) p.algo = MJ_ALGO_3WAY;
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;

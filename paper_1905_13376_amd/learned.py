@@ -29,6 +29,7 @@ IN, H, OUT = 100, 64, 7
 SHAPES = [("W1", (H, IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (OUT, H)), ("b3", (OUT,))]
 P = sum(int(np.prod(s)) for _, s in SHAPES)
 SHARES = (3, 4, 5)                     # log2 of the shares 8, 16, 32
+CASCADE_CAP = 1 << 28                  # the planner never materialises more pairs
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "planner_weights.npy")
 
 
@@ -105,6 +106,16 @@ class LearnedPlanner:
         return hist
 
 
+def use_shipped(ctx, path=WEIGHTS):
+    """Load the network trained by this module (planner_weights.npy) and
+    make it the context's learned planner; returns the LearnedPlanner,
+    which must stay alive while plans are made."""
+    pl = LearnedPlanner(ctx)
+    pl.load(path)
+    ctx.set_planner(pl.buf)
+    return pl
+
+
 # ---------------------------------------------------------------- data
 def planner_instances(count, base_seed, lo_exp=3.0, hi_exp=5.0):
     """Join instances shaped like the benchmark families, at small sizes:
@@ -176,12 +187,12 @@ def label_instance(ctx, inst):
             ps = plan.copy(); ps.algo = L.ALGO_3WAY; ps.log2_share = k
             times[f"share{k}"] = _time(lambda: ctx.triangle3_count(Fd, Fd, Fd, plan=ps, out=out, workspace=ws), 1)
         res = int(L.as_u64(out)[0])
-        if plan.join2_size <= 64 * max(1, Fd.shape[0]):
+        if plan.join2_size <= CASCADE_CAP:
             pc = plan.copy(); pc.algo = L.ALGO_CASCADE
             times["cascade"] = _time(lambda: ctx.cascade2_count(L.TRIANGLE, Fd, Fd, Fd, plan=pc, out=out, workspace=ws), 1)
             exact = int(L.as_u64(out)[0]) == res
         else:
-            times["cascade"] = float("inf")      # intermediate too large to time
+            times["cascade"] = float("inf")      # never chosen: the planner caps the intermediate
             exact = True
     best3 = min(v for k, v in times.items() if k != "cascade")
     return dict(kind=kind, features=feat, join2=plan.join2_size, out=res, times=times,
@@ -215,7 +226,7 @@ def evaluate(planner, rows):
     tot = {"learned": 0.0, "analytic": 0.0, "always_3way": 0.0, "always_cascade": 0.0, "best": 0.0}
     qI, qO = [], []
     for r, y in zip(rows, Y):
-        algo = L.ALGO_CASCADE if y[3] > y[2] else L.ALGO_3WAY
+        algo = L.ALGO_CASCADE if (y[3] > y[2] and r["join2"] <= CASCADE_CAP) else L.ALGO_3WAY
         share = SHARES[int(np.argmax(y[4:7]))]
         tot["learned"] += plan_time(r, algo, share)
         tot["analytic"] += plan_time(r, r["analytic"]["algo"], r["analytic"]["share"] or 3)
