@@ -69,14 +69,17 @@ typedef enum {
 /* Execution plan.  The hyper-parameters are the paper's bucket counts
  * (Sec. 3.1: a hash function's name stands for its number of buckets):
  *   linear:   nb = H*h buckets on B, nc = g buckets on C (Sec. 4)
- *   cyclic:   share = buckets on each of A, B, C (Sec. 5, equal shares)
+ *   cyclic:   share = least number of buckets on A of a hub list (Sec. 5:
+ *             R is split by H(A) x G(B); here G is one list per B value,
+ *             and a list is cut into max(share, ceil(len / 4096)) ranges
+ *             of A so that every piece fits in one workgroup's LDS)
  * All bucket counts are powers of two, given by their log2.             */
 typedef struct {
     int32_t kind;              /* mj_kind                                   */
     int32_t algo;              /* mj_algo chosen                            */
     uint32_t log2_nb;          /* linear: buckets on B                      */
     uint32_t log2_nc;          /* linear: buckets on C                      */
-    uint32_t log2_share;       /* cyclic: buckets per attribute             */
+    uint32_t log2_share;       /* cyclic: least buckets on A of a hub list  */
     uint32_t seed;             /* hash seed                                 */
     uint64_t n_r, n_s, n_t;    /* sizes the plan was made for               */
     uint32_t a_domain;         /* linear: length of the per-A output        */
@@ -166,7 +169,7 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* workspa
 /* Autotuner: times candidate plans of this join on the device (HIP events
  * on `stream`; synchronous) and keeps the fastest: for the linear kind
  * both algorithms and B / C bucket counts 2^8..2^10, for the cyclic kind
- * the shares 8, 16, 32 (and the cascade when the planner rated it within a
+ * the shares 1, 4, 16 (and the cascade when the planner rated it within a
  * factor of 4).  `plan` must come from mj_plan for these relations; it is
  * overwritten with the winner.  Results are cached in the context per size
  * class (log2 of the three sizes and of the intermediate), so a second

@@ -333,9 +333,19 @@ struct RunBuf {
     unsigned long long* nruns;
 };
 
+struct PassBuf {                      // work queues of one pass of the cyclic join
+    uint32_t* light;
+    uint32_t* ctr;                    // nlight, light_next, nheavy_groups, heavy_next
+    uint32_t* heavy_group;
+    uint32_t* heavy_items;
+    unsigned long long* heavy_off;
+    uint32_t n_heavy_cap;
+};
+
 struct TriLayout {
     unsigned long long* Rk;
-    unsigned long long* Sk;
+    unsigned long long* Sk;           // S by (m(b), m(c))
+    unsigned long long* Sk2;          // S by (m(c), m(b))
     unsigned long long* Tk;
     unsigned long long* tmp;          // radix double buffer
     uint32_t* rs_hist;
@@ -344,13 +354,8 @@ struct TriLayout {
     uint32_t* flags;
     unsigned long long* ridx;
     unsigned long long* partial;
-    RunBuf R, S, T;
-    uint32_t* light;
-    uint32_t* ctr;                    // nlight, light_next, nheavy_groups, heavy_next
-    uint32_t* heavy_group;
-    uint32_t* heavy_items;
-    unsigned long long* heavy_off;
-    uint32_t n_heavy_cap;
+    RunBuf R, S, S2, T;
+    PassBuf P[2];
     size_t bytes;
 };
 
@@ -364,12 +369,22 @@ void take_runs(Bump& B, RunBuf& X, uint64_t n, bool with_dir) {
     X.nruns = B.take<unsigned long long>(1);
 }
 
+void take_pass(Bump& B, PassBuf& P, uint64_t n_stage, uint64_t n_s) {
+    P.light = B.take<uint32_t>(std::max<uint64_t>(n_s, 1));
+    P.ctr = B.take<uint32_t>(4);
+    P.n_heavy_cap = (uint32_t)(n_stage / (TRI_LIGHT_X + 1) + n_s / (TRI_LIGHT_S + 1) + 2);
+    P.heavy_group = B.take<uint32_t>(P.n_heavy_cap);
+    P.heavy_items = B.take<uint32_t>(P.n_heavy_cap);
+    P.heavy_off = B.take<unsigned long long>(P.n_heavy_cap + 1);
+}
+
 TriLayout tri_layout(void* ws, const mj_plan_t& p) {
     Bump B(ws);
     TriLayout L;
     const uint64_t nmax = std::max<uint64_t>({p.n_r, p.n_s, p.n_t, 1});
     L.Rk = B.take<unsigned long long>(std::max<uint64_t>(p.n_r, 1));
     L.Sk = B.take<unsigned long long>(std::max<uint64_t>(p.n_s, 1));
+    L.Sk2 = B.take<unsigned long long>(std::max<uint64_t>(p.n_s, 1));
     L.Tk = B.take<unsigned long long>(std::max<uint64_t>(p.n_t, 1));
     L.tmp = B.take<unsigned long long>(nmax);
     const uint64_t ntiles = (nmax + RS_TILE - 1) / RS_TILE;
@@ -381,13 +396,10 @@ TriLayout tri_layout(void* ws, const mj_plan_t& p) {
     L.partial = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
     take_runs(B, L.R, p.n_r, true);
     take_runs(B, L.S, p.n_s, false);
+    take_runs(B, L.S2, p.n_s, false);
     take_runs(B, L.T, p.n_t, true);
-    L.light = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
-    L.ctr = B.take<uint32_t>(4);
-    L.n_heavy_cap = (uint32_t)(p.n_r / (TRI_LIGHT_X + 1) + p.n_s / (TRI_LIGHT_S + 1) + 2);
-    L.heavy_group = B.take<uint32_t>(L.n_heavy_cap);
-    L.heavy_items = B.take<uint32_t>(L.n_heavy_cap);
-    L.heavy_off = B.take<unsigned long long>(L.n_heavy_cap + 1);
+    take_pass(B, L.P[0], p.n_r, p.n_s);
+    take_pass(B, L.P[1], p.n_t, p.n_s);
     L.bytes = B.off + 256;
     return L;
 }
@@ -521,36 +533,54 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
     (void)num_cu; (void)out;
     int st;
     const uint32_t seed = p.seed;
-    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)), T -> (m(c), m(a)); sorted
+    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)) and (m(c), m(b)), T -> (m(c), m(a))
     if ((st = tri_keys(prof, R, 1, L.Rk, seed, s))) return st;
     if ((st = tri_keys(prof, S, 0, L.Sk, seed, s))) return st;
+    if ((st = tri_keys(prof, S, 1, L.Sk2, seed, s))) return st;
     if ((st = tri_keys(prof, T, 0, L.Tk, seed, s))) return st;
     if ((st = launch_radix_sort(prof, L.Rk, L.tmp, R.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk2, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    // lists of R per B, of T per C; groups of S per B
+    // lists of R per B and of T per C; groups of S per B and per C
     if ((st = launch_runs(prof, L, L.Rk, R.n, L.R, s))) return st;
     if ((st = launch_runs(prof, L, L.Tk, T.n, L.T, s))) return st;
     if ((st = launch_runs(prof, L, L.Sk, S.n, L.S, s))) return st;
-    // work queues
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.ctr, (uint64_t)4, 0u);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(L.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
-              L.heavy_items, (uint64_t)L.n_heavy_cap, 0u);
-    TriClassifyArgs C;
-    C.R = run_index(L.R); C.S = run_index(L.S); C.share = 1u << p.log2_share;
-    C.nlight = L.ctr + 0; C.light = L.light;
-    C.nheavy_groups = L.ctr + 2; C.heavy_group = L.heavy_group; C.heavy_items = L.heavy_items;
-    MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S.n, 256, 16384)), dim3(256), 0, s, C);
-    return launch_scan_u32(prof, L.heavy_items, L.n_heavy_cap, L.partial, L.heavy_off, s);
+    if ((st = launch_runs(prof, L, L.Sk2, S.n, L.S2, s))) return st;
+    // work queues of the two passes
+    for (int q = 0; q < 2; ++q) {
+        const PassBuf& P = L.P[q];
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, P.ctr, (uint64_t)4, 0u);
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(P.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
+                  P.heavy_items, (uint64_t)P.n_heavy_cap, 0u);
+        TriClassifyArgs C;
+        C.Stg = run_index(q == 0 ? L.R : L.T);
+        C.Grp = run_index(q == 0 ? L.S : L.S2);
+        C.share = 1u << p.log2_share;
+        C.nlight = P.ctr + 0; C.light = P.light;
+        C.nheavy_groups = P.ctr + 2; C.heavy_group = P.heavy_group; C.heavy_items = P.heavy_items;
+        MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S.n, 256, 16384)), dim3(256), 0, s, C);
+        if ((st = launch_scan_u32(prof, P.heavy_items, P.n_heavy_cap, L.partial, P.heavy_off, s))) return st;
+    }
+    return MJ_OK;
 }
 
-TriJoinArgs tri_join_args(const TriLayout& L, const mj_plan_t& p, unsigned long long* out) {
+// pass 0 stages R's lists per B (groups: S by B, iterated: T's lists per C,
+// taken when strictly shorter); pass 1 stages T's lists per C (groups: S by
+// C, iterated: R's lists per B, taken when not longer)
+TriJoinArgs tri_join_args(const TriLayout& L, const mj_plan_t& p, unsigned long long* out, int pass) {
     TriJoinArgs J;
-    J.R = run_index(L.R); J.S = run_index(L.S); J.T = run_index(L.T);
-    J.Rk = L.Rk; J.Sk = L.Sk; J.Tk = L.Tk;
-    J.nlight = L.ctr + 0; J.light = L.light; J.light_next = L.ctr + 1;
-    J.heavy_group = L.heavy_group; J.heavy_off = L.heavy_off; J.n_heavy_cap = L.n_heavy_cap;
-    J.heavy_next = L.ctr + 3; J.share = 1u << p.log2_share; J.total = out;
+    const PassBuf& P = L.P[pass];
+    J.Stg = run_index(pass == 0 ? L.R : L.T);
+    J.Grp = run_index(pass == 0 ? L.S : L.S2);
+    J.Itr = run_index(pass == 0 ? L.T : L.R);
+    J.Stgk = pass == 0 ? L.Rk : L.Tk;
+    J.Grpk = pass == 0 ? L.Sk : L.Sk2;
+    J.Itrk = pass == 0 ? L.Tk : L.Rk;
+    J.strict = pass == 0 ? 1u : 0u;
+    J.nlight = P.ctr + 0; J.light = P.light; J.light_next = P.ctr + 1;
+    J.heavy_group = P.heavy_group; J.heavy_off = P.heavy_off; J.n_heavy_cap = P.n_heavy_cap;
+    J.heavy_next = P.ctr + 3; J.share = 1u << p.log2_share; J.total = out;
     return J;
 }
 
@@ -871,10 +901,12 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
     MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0) return MJ_OK;
     if ((st = tri_prepare(prof, ctx->num_cu, *R, *S, *T, p, L, out, s))) return st;
-    TriJoinArgs J = tri_join_args(L, p, out);
     const uint32_t persistent = (uint32_t)ctx->num_cu * 8;
-    MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
-    MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_THREADS), 0, s, J);
+    for (int pass = 0; pass < 2; ++pass) {
+        TriJoinArgs J = tri_join_args(L, p, out, pass);
+        MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
+        MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s, J);
+    }
     return MJ_OK;
 }
 
@@ -1066,7 +1098,7 @@ uint64_t mj_batch_workspace(const mj_batch_item* items, int n) {
     for (int i = 0; i < n; ++i) off += align256(batch_item_bytes(items[i]));
     const size_t nn = (size_t)n;
     off += align256(nn * sizeof(LinearCellArgs)) + align256((nn + 1) * 4) +
-           align256(nn * sizeof(TriJoinArgs)) + 2 * align256((nn + 1) * 8) + align256(16);
+           align256(2 * nn * sizeof(TriJoinArgs)) + 2 * align256((2 * nn + 1) * 8) + align256(16);
     return off + 256;
 }
 
@@ -1136,7 +1168,8 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
             MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
             if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) continue;
             if ((st = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, s))) return st;
-            tri.push_back(tri_join_args(L, p, out));
+            tri.push_back(tri_join_args(L, p, out, 0));
+            tri.push_back(tri_join_args(L, p, out, 1));
         }
     }
     // device argument tables, staged through a pinned buffer kept by the context
@@ -1172,7 +1205,7 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         MJ_LAUNCH(prof, "k_tri_light_batch", k_tri_light_batch, dim3((uint32_t)ctx->num_cu * 8),
                   dim3(TRI_THREADS), 0, s, B);
         MJ_LAUNCH(prof, "k_tri_heavy_batch", k_tri_heavy_batch, dim3((uint32_t)ctx->num_cu * 2),
-                  dim3(TRI_THREADS), 0, s, B);
+                  dim3(TRI_HEAVY_THREADS), 0, s, B);
     }
     return MJ_OK;
 }
@@ -1220,7 +1253,7 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
             cand.push_back(c);
         }
     } else {
-        for (uint32_t k = 3; k <= 5; ++k) {
+        for (uint32_t k = 0; k <= 4; k += 2) {
             mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; c.log2_share = k; cand.push_back(c);
         }
         if (base.est_ms_cascade < 4.0 * base.est_ms_3way) {

@@ -239,7 +239,8 @@ __global__ void k_rs_hist(RsArgs A);
 __global__ void k_rs_scatter(RsArgs A);
 
 // --------------------------------------------------------------- triangle
-constexpr int TRI_THREADS = 256;
+constexpr int TRI_THREADS = 256;           // light kernel: one table per wave
+constexpr int TRI_HEAVY_THREADS = 1024;    // heavy kernel: one table per workgroup
 constexpr uint32_t TRI_LIGHT_X = 512;      // R list length handled by one wave
 constexpr uint32_t TRI_LIGHT_CAP = 1024;   // its LDS table (load <= 1/2)
 constexpr uint32_t TRI_LIGHT_S = 4096;     // S group size handled by one wave
@@ -266,8 +267,15 @@ struct TriKeyArgs {
 
 struct TriHeavyItem { uint32_t r0, r1, s0, s1; };
 
+// One pass of the cyclic join: the lists of the staged relation (R per B,
+// or T per C) are loaded into LDS one group at a time; the groups come from
+// S sorted by that same attribute; each s of a group whose iterated list
+// (T's list of c, or R's list of b) is the shorter one -- strictly shorter
+// when `strict` -- streams that list past the staged one.  Two passes
+// (staging R with strict = 1, staging T with strict = 0) see every S tuple
+// exactly once, always iterating the shorter of its two lists.
 struct TriClassifyArgs {
-    RunIndex R, S;
+    RunIndex Stg, Grp;
     uint32_t share;
     uint32_t* nlight;
     uint32_t* light;
@@ -277,10 +285,11 @@ struct TriClassifyArgs {
 };
 
 struct TriJoinArgs {
-    RunIndex R, S, T;
-    const unsigned long long* Rk;
-    const unsigned long long* Sk;
-    const unsigned long long* Tk;
+    RunIndex Stg, Grp, Itr;
+    const unsigned long long* Stgk;
+    const unsigned long long* Grpk;
+    const unsigned long long* Itrk;
+    uint32_t strict;
     const uint32_t* nlight;
     const uint32_t* light;
     uint32_t* light_next;

@@ -113,10 +113,11 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
         p.est_ms_3way = model_linear_3way_ms(m, R, S, T);
         p.est_ms_cascade = model_linear_cascade_ms(m, R, S, T, I);
     } else {
-        // share on A: the candidate of {8, 16, 32} the time model prefers
+        // share on A (the least number of slices of a hub list): the
+        // candidate of {1, 2, ..., 32} the time model prefers
         double best = INFINITY;
-        uint32_t best_k = 3;
-        for (uint32_t k = 3; k <= 5; ++k) {
+        uint32_t best_k = 0;
+        for (uint32_t k = 0; k <= 5; ++k) {
             const double t = model_cyclic_ms(m, R, S, T, I, double(1u << k));
             if (t < best) { best = t; best_k = k; }
         }

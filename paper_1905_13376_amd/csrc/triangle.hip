@@ -1,24 +1,28 @@
 // Cyclic three-way join R(A,B) |x| S(B,C) |x| T(C,A), total count (Sec. 5).
 //
 // Every relation is turned into 64-bit keys of mixed 32-bit values and
-// sorted (radix.hip):  R -> (m(b), m(a)),  T -> (m(c), m(a)),  S -> (m(b), m(c)).
-// m is a bijection of the 32-bit keys, so equal mixed values mean equal keys
-// and every join predicate can be evaluated on mixed values.  After sorting,
-// R's tuples with one B value form a contiguous list ordered by m(a), and so
-// do T's tuples with one C value; S's tuples with one B value form a group.
+// sorted (radix.hip):  R -> (m(b), m(a)),  T -> (m(c), m(a)),  S -> (m(b), m(c))
+// and a second copy S' -> (m(c), m(b)).  m is a bijection of the 32-bit keys,
+// so equal mixed values mean equal keys and every join predicate can be
+// evaluated on mixed values.  After sorting, R's tuples with one B value form
+// a contiguous list ordered by m(a), and so do T's tuples with one C value.
 //
 // The paper keeps a partition R' of R on chip and streams S' and T' past it
-// (Sec. 5.1).  Here the unit kept on chip is R's list for one B value:
-//   * k_tri_light : one wave per S group whose R list has at most TRI_LIGHT_X
-//                   tuples; the wave loads that list into its LDS table
-//                   (A -> multiplicity) and, for every s(b,c) of the group,
-//                   streams T's list of c past it (or, when T's list is much
-//                   longer, searches T's sorted list for each R tuple);
-//   * k_tri_heavy : R lists of hub B values are cut into slices of at most
-//                   TRI_HEAVY_X tuples by ranges of m(a) -- the share on A --
-//                   and the groups' S tuples into ranges; one workgroup per
-//                   (slice, S range) loads the slice into LDS and streams the
-//                   part of each T list that falls into the slice's A range.
+// (Sec. 5.1).  Here the unit kept on chip is one relation's list for one
+// join value, and every S tuple is handled once, by its shorter list:
+//   * pass 1 stages R's list of b and, for the s(b, c) whose T list is
+//     strictly shorter, streams T's list of c past it;
+//   * pass 2 stages T's list of c and, for the remaining s (R's list not
+//     longer), streams R's list of b past it.
+// In each pass:
+//   * k_tri_light : one wave per group whose staged list has at most
+//                   TRI_LIGHT_X tuples (its LDS table maps m(a) to a
+//                   multiplicity);
+//   * k_tri_heavy : staged lists of hub values are cut into slices of at
+//                   most TRI_HEAVY_X tuples by ranges of m(a) -- the share on
+//                   A -- and the groups into ranges; one workgroup per
+//                   (slice, range) streams the part of each iterated list that
+//                   falls in the slice's A range.
 // Work items come from device queues filled by k_tri_classify.  Each wave
 // sums its counts in registers and adds them to the total once.
 #include "mj_kernels.h"
@@ -102,12 +106,12 @@ __device__ __forceinline__ void heavy_shape(uint32_t x, uint32_t gn, uint32_t sh
 }
 
 __global__ void k_tri_classify(TriClassifyArgs A) {
-    const uint64_t ng = *A.S.nruns;
+    const uint64_t ng = *A.Grp.nruns;
     for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ng;
          g += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t rs, x;
-        if (!run_lookup(A.R, A.S.run_key[g], rs, x)) continue;
-        const uint32_t gn = A.S.run_start[g + 1] - A.S.run_start[g];
+        if (!run_lookup(A.Stg, A.Grp.run_key[g], rs, x)) continue;
+        const uint32_t gn = A.Grp.run_start[g + 1] - A.Grp.run_start[g];
         if (x <= TRI_LIGHT_X && gn <= TRI_LIGHT_S) {
             const uint32_t q = atomicAdd(A.nlight, 1u);
             A.light[q] = (uint32_t)g;
@@ -179,12 +183,12 @@ struct WaveTable {
 __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, const WaveTable& W) {
     const int lane = lane_id();
     const uint32_t mask = TRI_LIGHT_CAP - 1;
-    const uint32_t mb = A.S.run_key[g];
-    const uint32_t gs = A.S.run_start[g], ge = A.S.run_start[g + 1];
+    const uint32_t gkey = A.Grp.run_key[g];
+    const uint32_t gs = A.Grp.run_start[g], ge = A.Grp.run_start[g + 1];
     uint32_t rs = 0, x = 0;
-    run_lookup(A.R, mb, rs, x);
+    run_lookup(A.Stg, gkey, rs, x);
     for (uint32_t q = lane; q < x; q += WAVE) {
-        const uint32_t a = (uint32_t)A.Rk[rs + q];
+        const uint32_t a = (uint32_t)A.Stgk[rs + q];
         if (a == EMPTY_KEY) { atomicAdd(W.spec, 1u); continue; }
         uint32_t s = a & mask;
         while (true) {
@@ -202,16 +206,11 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     const uint32_t spec = *W.spec;
     unsigned long long acc = 0;
     for (uint32_t si = gs + lane; si < ge; si += WAVE) {
-        const uint32_t mc = (uint32_t)A.Sk[si];
         uint32_t ts, y;
-        if (!run_lookup(A.T, mc, ts, y)) continue;
-        if (y <= 4 * x) {
-            for (uint32_t t = ts; t < ts + y; ++t)
-                acc += atab_get(W.keys, W.vals, mask, spec, (uint32_t)A.Tk[t]);
-        } else {
-            for (uint32_t q = rs; q < rs + x; ++q)
-                acc += count_low(A.Tk, ts, ts + y, (uint32_t)A.Rk[q]);
-        }
+        if (!run_lookup(A.Itr, (uint32_t)A.Grpk[si], ts, y)) continue;
+        if (A.strict ? y >= x : y > x) continue;     // the other pass owns this s
+        for (uint32_t t = ts; t < ts + y; ++t)
+            acc += atab_get(W.keys, W.vals, mask, spec, (uint32_t)A.Itrk[t]);
     }
     wave_fence();
     const uint32_t nu = *W.nused;
@@ -260,18 +259,46 @@ struct BlockTable {
     uint32_t* spec;
 };
 
+// First index in [lo, hi) of a list sorted by low word whose low word is not
+// below v (or, with `upper`, above v).  The wave probes 64 evenly spaced
+// pivots per round, so a list of n entries takes about log_65(n) rounds of
+// independent loads instead of log_2(n) dependent ones.
+__device__ __forceinline__ uint32_t wave_bound(const unsigned long long* keys, uint32_t lo,
+                                               uint32_t hi, uint32_t v, bool upper) {
+    const int lane = lane_id();
+    while (hi - lo > WAVE) {
+        const uint32_t n = hi - lo;                   // n >= 65: pivots strictly increase
+        const uint32_t p = lo + (uint32_t)((uint64_t)n * (lane + 1) / (WAVE + 1));
+        const uint32_t k = (uint32_t)keys[p];
+        const int below = __popcll(__ballot(upper ? k <= v : k < v));
+        const uint32_t nlo = below == 0 ? lo : lo + (uint32_t)((uint64_t)n * below / (WAVE + 1)) + 1;
+        const uint32_t nhi = below == WAVE ? hi : lo + (uint32_t)((uint64_t)n * (below + 1) / (WAVE + 1));
+        lo = nlo;
+        hi = nhi;
+    }
+    bool in = false;
+    if (lo + lane < hi) {
+        const uint32_t k = (uint32_t)keys[lo + lane];
+        in = upper ? k <= v : k < v;
+    }
+    return lo + (uint32_t)__popcll(__ballot(in));
+}
+
+// One workgroup, one item: a slice of a staged list into LDS, then the
+// item's S tuples, one wave per S tuple, stream the iterated list (only its
+// part in the slice's A range when the staged list is sliced).
 __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, const BlockTable& B) {
     const int w = threadIdx.x / WAVE, lane = lane_id();
-    constexpr int NW = TRI_THREADS / WAVE;
+    constexpr int NW = TRI_HEAVY_THREADS / WAVE;
     const uint32_t mask = TRI_HEAVY_CAP - 1;
-    // item -> (heavy group, slice of R's list, range of S tuples)
+    // item -> (heavy group, slice of the staged list, range of the group)
     uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
     while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (A.heavy_off[m] <= it) lo = m; else hi = m; }
     const uint32_t g = A.heavy_group[lo];
     const uint32_t local = (uint32_t)(it - A.heavy_off[lo]);
     uint32_t rs = 0, x = 0;
-    run_lookup(A.R, A.S.run_key[g], rs, x);
-    const uint32_t gs = A.S.run_start[g], gn = A.S.run_start[g + 1] - gs;
+    run_lookup(A.Stg, A.Grp.run_key[g], rs, x);
+    const uint32_t gs = A.Grp.run_start[g], gn = A.Grp.run_start[g + 1] - gs;
     uint32_t nsl, nsr;
     heavy_shape(x, gn, A.share, nsl, nsr);
     const uint32_t sa = local / nsr, sb = local % nsr;
@@ -283,28 +310,21 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
     unsigned long long acc = 0;
     if (H.r0 == H.r1) return 0;                       // uniform across the block
     for (uint32_t q = H.r0 + threadIdx.x; q < H.r1; q += blockDim.x)
-        atab_add(B.keys, B.vals, mask, B.spec, (uint32_t)A.Rk[q]);
+        atab_add(B.keys, B.vals, mask, B.spec, (uint32_t)A.Stgk[q]);
     __syncthreads();
     const uint32_t sp = *B.spec;
-    const uint32_t alo = (uint32_t)A.Rk[H.r0], ahi = (uint32_t)A.Rk[H.r1 - 1];
-    const uint32_t xs = H.r1 - H.r0;
+    const uint32_t alo = (uint32_t)A.Stgk[H.r0], ahi = (uint32_t)A.Stgk[H.r1 - 1];
     for (uint32_t si = H.s0 + w; si < H.s1; si += NW) {
-        const uint32_t mc = (uint32_t)A.Sk[si];
         uint32_t ts, y;
-        if (!run_lookup(A.T, mc, ts, y)) continue;
-        // the part of T's list (sorted by m(a)) inside [alo, ahi]
-        uint32_t l = ts, h = ts + y;
-        while (l < h) { uint32_t m = (l + h) >> 1; if ((uint32_t)A.Tk[m] < alo) l = m + 1; else h = m; }
-        uint32_t l2 = l, h2 = ts + y;
-        while (l2 < h2) { uint32_t m = (l2 + h2) >> 1; if ((uint32_t)A.Tk[m] <= ahi) l2 = m + 1; else h2 = m; }
-        const uint32_t ysub = l2 - l;
-        if (ysub <= 4 * xs) {
-            for (uint32_t t = l + lane; t < l2; t += WAVE)
-                acc += atab_get(B.keys, B.vals, mask, sp, (uint32_t)A.Tk[t]);
-        } else {
-            for (uint32_t q = H.r0 + lane; q < H.r1; q += WAVE)
-                acc += count_low(A.Tk, l, l2, (uint32_t)A.Rk[q]);
+        if (!run_lookup(A.Itr, (uint32_t)A.Grpk[si], ts, y)) continue;
+        if (A.strict ? y >= x : y > x) continue;     // the other pass owns this s
+        uint32_t l = ts, l2 = ts + y;
+        if (nsl > 1 && y > WAVE) {                    // the part inside [alo, ahi]
+            l = wave_bound(A.Itrk, ts, ts + y, alo, false);
+            l2 = wave_bound(A.Itrk, l, ts + y, ahi, true);
         }
+        for (uint32_t t = l + lane; t < l2; t += WAVE)
+            acc += atab_get(B.keys, B.vals, mask, sp, (uint32_t)A.Itrk[t]);
     }
     return acc;
 }
@@ -317,7 +337,7 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
     BlockTable B{hkeys, hvals, &hspec};                                   \
     const int lane = lane_id();
 
-__global__ void __launch_bounds__(TRI_THREADS)
+__global__ void __launch_bounds__(TRI_HEAVY_THREADS)
 k_tri_heavy(TriJoinArgs A) {
     TRI_HEAVY_SETUP
     const uint32_t nitems = (uint32_t)A.heavy_off[A.n_heavy_cap];
@@ -363,7 +383,7 @@ k_tri_light_batch(TriBatchArgs Bt) {
     }
 }
 
-__global__ void __launch_bounds__(TRI_THREADS)
+__global__ void __launch_bounds__(TRI_HEAVY_THREADS)
 k_tri_heavy_batch(TriBatchArgs Bt) {
     TRI_HEAVY_SETUP
     __shared__ unsigned long long s_bitem;

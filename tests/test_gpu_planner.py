@@ -81,7 +81,7 @@ def test_autotune_triangle(mj, ctx):
     Ed = dev(E)
     plan, ms, out = ctx.autotune(mj.TRIANGLE, Ed, Ed, Ed)
     assert int(mj.as_u64(out)[0]) == oracle.triangle3_count(E, E, E)
-    assert plan.log2_share in (3, 4, 5) or plan.algo == mj.ALGO_CASCADE
+    assert plan.log2_share <= 5 or plan.algo == mj.ALGO_CASCADE
 
 
 @pytest.mark.parametrize("seed", range(4))
