@@ -294,7 +294,7 @@ int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st)
     MJ_LAUNCH(prof, t + ":k_part_scan", k_part_scan, dim3(P.njobs), dim3(PART_THREADS),
               (size_t(1) << maxbits) * 4, st, P);
     if (tiles)
-        MJ_LAUNCH(prof, t + ":k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_THREADS),
+        MJ_LAUNCH(prof, t + ":k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_SCATTER_THREADS),
                   part_scatter_smem(maxbits), st, P);
     return MJ_OK;
 }
@@ -347,6 +347,10 @@ struct TriLayout {
     unsigned long long* Sk;           // S by (m(b), m(c))
     unsigned long long* Sk2;          // S by (m(c), m(b))
     unsigned long long* Tk;
+    uint32_t* Rl;                     // low words of the sorted keys
+    uint32_t* Sl;
+    uint32_t* Sl2;
+    uint32_t* Tl;
     unsigned long long* tmp;          // radix double buffer
     uint32_t* rs_hist;
     uint32_t* rs_counts;
@@ -386,6 +390,10 @@ TriLayout tri_layout(void* ws, const mj_plan_t& p) {
     L.Sk = B.take<unsigned long long>(std::max<uint64_t>(p.n_s, 1));
     L.Sk2 = B.take<unsigned long long>(std::max<uint64_t>(p.n_s, 1));
     L.Tk = B.take<unsigned long long>(std::max<uint64_t>(p.n_t, 1));
+    L.Rl = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+    L.Sl = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.Sl2 = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.Tl = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
     L.tmp = B.take<unsigned long long>(nmax);
     const uint64_t ntiles = (nmax + RS_TILE - 1) / RS_TILE;
     L.rs_hist = B.take<uint32_t>(256 * ntiles);
@@ -443,13 +451,13 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
 }
 
 int launch_runs(Prof* prof, const TriLayout& L, const unsigned long long* keys, uint64_t n,
-                const RunBuf& X, hipStream_t s) {
+                const RunBuf& X, uint32_t* low, hipStream_t s) {
     if (n == 0) {
         MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, X.nruns, (uint64_t)1, 0ull);
         MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, X.run_start, (uint64_t)1, 0u);
     } else {
         MJ_LAUNCH(prof, "k_run_flags", k_run_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
-                  keys, n, L.flags);
+                  keys, n, L.flags, low);
         int st = launch_scan_u32(prof, L.flags, n, L.partial, L.ridx, s);
         if (st) return st;
         MJ_LAUNCH(prof, "k_run_compact", k_run_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
@@ -543,10 +551,10 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
     if ((st = launch_radix_sort(prof, L.Sk2, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     // lists of R per B and of T per C; groups of S per B and per C
-    if ((st = launch_runs(prof, L, L.Rk, R.n, L.R, s))) return st;
-    if ((st = launch_runs(prof, L, L.Tk, T.n, L.T, s))) return st;
-    if ((st = launch_runs(prof, L, L.Sk, S.n, L.S, s))) return st;
-    if ((st = launch_runs(prof, L, L.Sk2, S.n, L.S2, s))) return st;
+    if ((st = launch_runs(prof, L, L.Rk, R.n, L.R, L.Rl, s))) return st;
+    if ((st = launch_runs(prof, L, L.Tk, T.n, L.T, L.Tl, s))) return st;
+    if ((st = launch_runs(prof, L, L.Sk, S.n, L.S, L.Sl, s))) return st;
+    if ((st = launch_runs(prof, L, L.Sk2, S.n, L.S2, L.Sl2, s))) return st;
     // work queues of the two passes
     for (int q = 0; q < 2; ++q) {
         const PassBuf& P = L.P[q];
@@ -574,9 +582,9 @@ TriJoinArgs tri_join_args(const TriLayout& L, const mj_plan_t& p, unsigned long 
     J.Stg = run_index(pass == 0 ? L.R : L.T);
     J.Grp = run_index(pass == 0 ? L.S : L.S2);
     J.Itr = run_index(pass == 0 ? L.T : L.R);
-    J.Stgk = pass == 0 ? L.Rk : L.Tk;
-    J.Grpk = pass == 0 ? L.Sk : L.Sk2;
-    J.Itrk = pass == 0 ? L.Tk : L.Rk;
+    J.Stgl = pass == 0 ? L.Rl : L.Tl;
+    J.Grpl = pass == 0 ? L.Sl : L.Sl2;
+    J.Itrl = pass == 0 ? L.Tl : L.Rl;
     J.strict = pass == 0 ? 1u : 0u;
     J.nlight = P.ctr + 0; J.light = P.light; J.light_next = P.ctr + 1;
     J.heavy_group = P.heavy_group; J.heavy_off = P.heavy_off; J.n_heavy_cap = P.n_heavy_cap;
@@ -601,7 +609,7 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     TriLayout TL{};                    // launch_runs only uses flags / ridx / partial
     TL.flags = L.flags; TL.ridx = L.ridx; TL.partial = L.partial;
-    if ((st = launch_runs(prof, TL, L.Tk, T->n, L.Trun, s))) return st;
+    if ((st = launch_runs(prof, TL, L.Tk, T->n, L.Trun, nullptr, s))) return st;
     // join 1: as in the linear cascade
     const uint32_t nb = 1u << p.log2_nb;
     PartLaunch P{};

@@ -104,6 +104,9 @@ k_dbuild(DBuildArgs A) {
     }
     __syncthreads();
     const bool spill = s_over != 0;
+    // a table of at most DB_CAP / 2 keys is rehashed in LDS at its final
+    // capacity and written out whole; larger ones are inserted key by key
+    const bool local = !spill && 2u * s_distinct <= DB_CAP;
     if (threadIdx.x == 0) {
         const uint32_t want = spill ? (n > (1u << 30) ? (1u << 31) : 2u * n) : 2u * s_distinct;
         uint32_t cap = max(DB_MIN_CAP, next_pow2_u32(want));
@@ -121,7 +124,31 @@ k_dbuild(DBuildArgs A) {
     const unsigned long long base = s_base;
     const uint32_t cap = 1u << s_log2;
     uint2* region = A.pool + base;
-    if (base != 0) {
+    if (base != 0 && local) {
+        // take the entries out, clear, reinsert with mask cap - 1 (the
+        // lookup's probe sequence), then copy slots [0, cap) out coalesced
+        constexpr int PER = DB_CAP / DB_THREADS;
+        uint32_t ek[PER], ev[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t s = threadIdx.x + u * DB_THREADS;
+            ek[u] = tkeys[s];
+            ev[u] = tvals[s];
+        }
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
+        __syncthreads();
+        const uint32_t cmask = cap - 1;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (ek[u] == EMPTY_KEY) continue;
+            uint32_t s = slot_hash(ek[u], A.slot_seed) & cmask;
+            while (atomicCAS(&tkeys[s], EMPTY_KEY, ek[u]) != EMPTY_KEY) s = (s + 1u) & cmask;
+            tvals[s] = ev[u];
+        }
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) region[s] = make_uint2(tkeys[s], tvals[s]);
+    } else if (base != 0) {
         for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) region[s] = make_uint2(EMPTY_KEY, 0u);
         __threadfence();
         __syncthreads();

@@ -38,6 +38,19 @@ __host__ __device__ __forceinline__ uint32_t slot_hash(uint32_t k, uint32_t seed
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups of a launch are handed to the 8 XCDs of the chip in turn
+// (block b runs on XCD b % 8), and each XCD has its own L2.  xcd_remap maps
+// the launch order onto a work index so that every XCD receives one
+// contiguous range of work items: neighbouring items (adjacent output runs,
+// shared table regions) then meet in the same L2.  It is a bijection on
+// [0, n) for any n; only locality depends on the hardware's hand-out order.
+constexpr uint32_t NUM_XCD = 8;
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
+    const uint32_t x = b % NUM_XCD, local = b / NUM_XCD;
+    const uint32_t per = n / NUM_XCD, tall = n % NUM_XCD;   // first `tall` XCDs get per + 1
+    return x < tall ? x * (per + 1) + local : tall * (per + 1) + (x - tall) * per + local;
+}
+
 // Wave-wide sum of a 64-bit value (DPP/permute based reduction via shuffles).
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll

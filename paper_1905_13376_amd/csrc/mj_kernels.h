@@ -18,10 +18,21 @@ namespace mj {
 #define MJ_CELL_THREADS 512
 #endif
 constexpr int PART_THREADS = MJ_PART_THREADS;
+#ifndef MJ_PART_SCATTER_THREADS
+#define MJ_PART_SCATTER_THREADS 1024
+#endif
+constexpr int PART_SCATTER_THREADS = MJ_PART_SCATTER_THREADS;   // scatter: more tuples in flight per tile
 constexpr int PART_TILE = MJ_PART_TILE;  // tuples per block (<= 2^16)
 constexpr int PART_SCAN_CHUNK = 4096;    // row-scan chunk (LDS entries)
 constexpr int MJ_PART_MAX_JOBS = 4;
 constexpr uint32_t PART_MAX_BITS = 12;   // at most 4096 buckets per pass
+constexpr size_t LDS_BYTES = 160 * 1024; // per workgroup on gfx950
+// the scatter's dynamic LDS (two words per bucket, a staged tile of pairs)
+// plus its static wave scratch must fit one workgroup
+static_assert((size_t(8) << PART_MAX_BITS) + size_t(8) * PART_TILE + 4 * (PART_SCATTER_THREADS / 64 + 1) <= LDS_BYTES,
+              "partition tile does not fit LDS");
+static_assert(PART_TILE <= 65536 && PART_TILE % (2 * PART_THREADS) == 0 &&
+              PART_TILE % (2 * PART_SCATTER_THREADS) == 0, "partition tile shape");
 
 struct PartJob {
     const uint32_t* col0;
@@ -69,6 +80,7 @@ constexpr uint32_t DB_CAP = 8192;                  // LDS slots per build
 // one more slot, so the table keeps at least one empty slot
 constexpr uint32_t DB_LIMIT = DB_CAP - (DB_CAP / 8 > DB_THREADS ? DB_CAP / 8 : DB_THREADS) - 1;
 static_assert(DB_LIMIT + DB_THREADS < DB_CAP, "LDS table slack");
+static_assert(DB_CAP % DB_THREADS == 0, "rehash takes DB_CAP / DB_THREADS slots per thread");
 constexpr uint32_t DB_MIN_CAP = 16;
 
 struct DBuildArgs {
@@ -246,7 +258,8 @@ constexpr uint32_t TRI_LIGHT_CAP = 1024;   // its LDS table (load <= 1/2)
 constexpr uint32_t TRI_LIGHT_S = 4096;     // S group size handled by one wave
 constexpr uint32_t TRI_HEAVY_X = 4096;     // R slice handled by one workgroup
 constexpr uint32_t TRI_HEAVY_CAP = 8192;
-constexpr uint32_t TRI_HEAVY_S = 512;      // S tuples per heavy item
+constexpr uint32_t TRI_HEAVY_S = 2048;     // S tuples per heavy item (chunks of 64 per wave)
+constexpr uint32_t TRI_SHORT_LIST = 16;    // heavy: lists walked by one lane
 
 struct RunIndex {                          // runs of equal high words of sorted keys
     const uint32_t* run_key;               // [nruns]
@@ -286,9 +299,9 @@ struct TriClassifyArgs {
 
 struct TriJoinArgs {
     RunIndex Stg, Grp, Itr;
-    const unsigned long long* Stgk;
-    const unsigned long long* Grpk;
-    const unsigned long long* Itrk;
+    const uint32_t* Stgl;                  // low words (the other key) of the
+    const uint32_t* Grpl;                  // sorted staged, grouped and
+    const uint32_t* Itrl;                  // iterated relations
     uint32_t strict;
     const uint32_t* nlight;
     const uint32_t* light;
@@ -329,7 +342,7 @@ struct LinearBatchArgs {
 __global__ void k_linear_cell_batch(LinearBatchArgs B);
 
 __global__ void k_tri_keys(TriKeyArgs A);
-__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags);
+__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags, uint32_t* low);
 __global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,
                               const unsigned long long* ridx, uint32_t* run_key,
                               uint32_t* run_start, unsigned long long* nruns);

@@ -32,6 +32,29 @@ __device__ __forceinline__ uint32_t part_bucket(const PartJob& J, uint32_t x0, u
     return d;
 }
 
+#ifndef MJ_PART_NT_STORE
+#define MJ_PART_NT_STORE 0
+#endif
+#ifndef MJ_PART_XCD_REMAP
+#define MJ_PART_XCD_REMAP 1
+#endif
+
+// Output stores.  Plain stores let an XCD's write-back L2 merge the two
+// halves of a cache line that adjacent tiles' runs share; nontemporal ones
+// stream past it.
+template <typename T>
+__device__ __forceinline__ void part_store(T v, T* p) {
+    if constexpr (MJ_PART_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// The tile a block works on: tiles of one XCD are contiguous, so the runs
+// adjacent tiles write into one bucket (adjacent in the output) meet in the
+// same L2.
+__device__ __forceinline__ uint32_t part_block() {
+    return MJ_PART_XCD_REMAP ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+}
+
 __device__ __forceinline__ int find_job(const PartLaunch& L, uint32_t blk) {
     int j = 0;
 #pragma unroll
@@ -79,12 +102,13 @@ __device__ __forceinline__ void load_tile(const PartJob& J, uint64_t beg, uint32
 __global__ void __launch_bounds__(PART_THREADS)
 k_part_hist(PartLaunch L) {
     extern __shared__ uint32_t lhist[];
-    const int jid = find_job(L, blockIdx.x);
+    const uint32_t blk = part_block();
+    const int jid = find_job(L, blk);
     const PartJob& J = L.job[jid];
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lhist[d] = 0;
     __syncthreads();
-    const uint32_t tile = blockIdx.x - J.tile_begin;
+    const uint32_t tile = blk - J.tile_begin;
     const uint64_t beg = uint64_t(tile) * PART_TILE;
     const uint32_t cnt = (uint32_t)min<uint64_t>(PART_TILE, J.n - beg);
     constexpr int ITEMS = PART_TILE / PART_THREADS;
@@ -143,11 +167,12 @@ k_part_scan(PartLaunch L) {
     if (threadIdx.x == 0) J.starts[nb] = total;
 }
 
-__global__ void __launch_bounds__(PART_THREADS)
+__global__ void __launch_bounds__(PART_SCATTER_THREADS)
 k_part_scatter(PartLaunch L) {
     extern __shared__ uint32_t smem[];
-    __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
-    const int jid = find_job(L, blockIdx.x);
+    __shared__ uint32_t wave_tmp[PART_SCATTER_THREADS / WAVE + 1];
+    const uint32_t blk = part_block();
+    const int jid = find_job(L, blk);
     const PartJob& J = L.job[jid];
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
     uint32_t* lcount = smem;                 // [nb]  counts, then local starts
@@ -156,11 +181,11 @@ k_part_scatter(PartLaunch L) {
 
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lcount[d] = 0;
     __syncthreads();
-    const uint32_t tile = blockIdx.x - J.tile_begin;
+    const uint32_t tile = blk - J.tile_begin;
     const uint64_t beg = uint64_t(tile) * PART_TILE;
     const uint32_t cnt = (uint32_t)min<uint64_t>(PART_TILE, J.n - beg);
 
-    constexpr int ITEMS = PART_TILE / PART_THREADS;
+    constexpr int ITEMS = PART_TILE / PART_SCATTER_THREADS;
     uint32_t x0[ITEMS], x1[ITEMS], idx[ITEMS], rk[ITEMS];
     load_tile<ITEMS>(J, beg, cnt, x0, x1, idx);
 #pragma unroll
@@ -196,7 +221,7 @@ k_part_scatter(PartLaunch L) {
             const uint2 v = st[p];
             const uint32_t d = part_bucket(J, v.x, v.y);
             u32x2 w; w.x = v.x; w.y = v.y;
-            __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(J.out_pair) + gbase[d] + (p - lcount[d]));
+            part_store(w, reinterpret_cast<u32x2*>(J.out_pair) + gbase[d] + (p - lcount[d]));
         }
     } else {
         // single-column payloads are only used with a one-column bucket id
@@ -204,7 +229,7 @@ k_part_scatter(PartLaunch L) {
         for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
             const uint32_t v = stage[p];
             const uint32_t d = top_bits(mix32(v, J.seed0), J.bits0);
-            __builtin_nontemporal_store(v, J.out_single + gbase[d] + (p - lcount[d]));
+            part_store(v, J.out_single + gbase[d] + (p - lcount[d]));
         }
     }
 }

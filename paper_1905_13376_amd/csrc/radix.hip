@@ -16,7 +16,7 @@ namespace mj {
 __global__ void __launch_bounds__(RS_THREADS)
 k_rs_hist(RsArgs A) {
     __shared__ uint32_t lh[256];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
     for (uint32_t d = threadIdx.x; d < 256; d += blockDim.x) lh[d] = 0;
     __syncthreads();
     const uint64_t beg = uint64_t(tile) * RS_TILE;
@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(RS_THREADS)
 k_rs_scatter(RsArgs A) {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[RS_THREADS / WAVE][256];
-    const uint32_t tile = blockIdx.x;
+    // adjacent tiles write adjacent runs of every digit: keep them on one XCD
+    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = lane_id();
     const int w = threadIdx.x / WAVE;
     constexpr int NW = RS_THREADS / WAVE;

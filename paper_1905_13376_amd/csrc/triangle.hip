@@ -40,10 +40,15 @@ __global__ void k_tri_keys(TriKeyArgs A) {
 }
 
 // ------------------------------------------------------- runs of equal keys
-__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags) {
+// (and, when `low` is given, the low words: the joins read only those once
+// the runs of the high words are indexed)
+__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags, uint32_t* low) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        flags[i] = (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ? 1u : 0u;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = keys[i];
+        flags[i] = (i == 0 || (k >> 32) != (keys[i - 1] >> 32)) ? 1u : 0u;
+        if (low) low[i] = (uint32_t)k;
+    }
 }
 
 // run r starts at element i for every head i (ridx = exclusive scan of flags)
@@ -188,7 +193,7 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     uint32_t rs = 0, x = 0;
     run_lookup(A.Stg, gkey, rs, x);
     for (uint32_t q = lane; q < x; q += WAVE) {
-        const uint32_t a = (uint32_t)A.Stgk[rs + q];
+        const uint32_t a = A.Stgl[rs + q];
         if (a == EMPTY_KEY) { atomicAdd(W.spec, 1u); continue; }
         uint32_t s = a & mask;
         while (true) {
@@ -207,10 +212,10 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     unsigned long long acc = 0;
     for (uint32_t si = gs + lane; si < ge; si += WAVE) {
         uint32_t ts, y;
-        if (!run_lookup(A.Itr, (uint32_t)A.Grpk[si], ts, y)) continue;
+        if (!run_lookup(A.Itr, A.Grpl[si], ts, y)) continue;
         if (A.strict ? y >= x : y > x) continue;     // the other pass owns this s
         for (uint32_t t = ts; t < ts + y; ++t)
-            acc += atab_get(W.keys, W.vals, mask, spec, (uint32_t)A.Itrk[t]);
+            acc += atab_get(W.keys, W.vals, mask, spec, A.Itrl[t]);
     }
     wave_fence();
     const uint32_t nu = *W.nused;
@@ -257,19 +262,20 @@ struct BlockTable {
     uint32_t* keys;
     uint32_t* vals;
     uint32_t* spec;
+    uint32_t* chunk;                  // next chunk of 64 S tuples of the item
 };
 
-// First index in [lo, hi) of a list sorted by low word whose low word is not
-// below v (or, with `upper`, above v).  The wave probes 64 evenly spaced
-// pivots per round, so a list of n entries takes about log_65(n) rounds of
-// independent loads instead of log_2(n) dependent ones.
-__device__ __forceinline__ uint32_t wave_bound(const unsigned long long* keys, uint32_t lo,
-                                               uint32_t hi, uint32_t v, bool upper) {
+// First index in [lo, hi) of a sorted list whose value is not below v (or,
+// with `upper`, above v).  The wave probes 64 evenly spaced pivots per
+// round, so a list of n entries takes about log_65(n) rounds of independent
+// loads instead of log_2(n) dependent ones.
+__device__ __forceinline__ uint32_t wave_bound(const uint32_t* keys, uint32_t lo, uint32_t hi,
+                                               uint32_t v, bool upper) {
     const int lane = lane_id();
     while (hi - lo > WAVE) {
         const uint32_t n = hi - lo;                   // n >= 65: pivots strictly increase
         const uint32_t p = lo + (uint32_t)((uint64_t)n * (lane + 1) / (WAVE + 1));
-        const uint32_t k = (uint32_t)keys[p];
+        const uint32_t k = keys[p];
         const int below = __popcll(__ballot(upper ? k <= v : k < v));
         const uint32_t nlo = below == 0 ? lo : lo + (uint32_t)((uint64_t)n * below / (WAVE + 1)) + 1;
         const uint32_t nhi = below == WAVE ? hi : lo + (uint32_t)((uint64_t)n * (below + 1) / (WAVE + 1));
@@ -278,18 +284,22 @@ __device__ __forceinline__ uint32_t wave_bound(const unsigned long long* keys, u
     }
     bool in = false;
     if (lo + lane < hi) {
-        const uint32_t k = (uint32_t)keys[lo + lane];
+        const uint32_t k = keys[lo + lane];
         in = upper ? k <= v : k < v;
     }
     return lo + (uint32_t)__popcll(__ballot(in));
 }
 
 // One workgroup, one item: a slice of a staged list into LDS, then the
-// item's S tuples, one wave per S tuple, stream the iterated list (only its
-// part in the slice's A range when the staged list is sliced).
+// item's S tuples stream their iterated lists past it (only the part in the
+// slice's A range when the staged list is sliced).  Waves take chunks of 64
+// S tuples from a workgroup counter and lane j looks up tuple j's list; lists of at most
+// TRI_SHORT_LIST entries are then walked by their own lane, longer ones one
+// after another by the whole wave (64 consecutive entries per load, several
+// loads in flight per lane).
 __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, const BlockTable& B) {
-    const int w = threadIdx.x / WAVE, lane = lane_id();
-    constexpr int NW = TRI_HEAVY_THREADS / WAVE;
+    const int lane = lane_id();
+    constexpr int UNROLL = 4;
     const uint32_t mask = TRI_HEAVY_CAP - 1;
     // item -> (heavy group, slice of the staged list, range of the group)
     uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
@@ -310,21 +320,46 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
     unsigned long long acc = 0;
     if (H.r0 == H.r1) return 0;                       // uniform across the block
     for (uint32_t q = H.r0 + threadIdx.x; q < H.r1; q += blockDim.x)
-        atab_add(B.keys, B.vals, mask, B.spec, (uint32_t)A.Stgk[q]);
+        atab_add(B.keys, B.vals, mask, B.spec, A.Stgl[q]);
     __syncthreads();
     const uint32_t sp = *B.spec;
-    const uint32_t alo = (uint32_t)A.Stgk[H.r0], ahi = (uint32_t)A.Stgk[H.r1 - 1];
-    for (uint32_t si = H.s0 + w; si < H.s1; si += NW) {
-        uint32_t ts, y;
-        if (!run_lookup(A.Itr, (uint32_t)A.Grpk[si], ts, y)) continue;
-        if (A.strict ? y >= x : y > x) continue;     // the other pass owns this s
-        uint32_t l = ts, l2 = ts + y;
-        if (nsl > 1 && y > WAVE) {                    // the part inside [alo, ahi]
-            l = wave_bound(A.Itrk, ts, ts + y, alo, false);
-            l2 = wave_bound(A.Itrk, l, ts + y, ahi, true);
+    const bool sliced = nsl > 1;
+    const uint32_t alo = A.Stgl[H.r0], ahi = A.Stgl[H.r1 - 1];
+    while (true) {
+        uint32_t c = 0;
+        if (lane == 0) c = atomicAdd(B.chunk, 1u);
+        const uint32_t c0 = H.s0 + __shfl(c, 0, WAVE) * WAVE;
+        if (c0 >= H.s1) break;                        // wave-uniform
+        const uint32_t si = c0 + lane;
+        uint32_t ts = 0, y = 0;
+        if (!(si < H.s1 && run_lookup(A.Itr, A.Grpl[si], ts, y)) ||
+            (A.strict ? y >= x : y > x))              // the other pass owns this s
+            y = 0;
+        if (y <= TRI_SHORT_LIST) {
+            for (uint32_t t = ts; t < ts + y; ++t) acc += atab_get(B.keys, B.vals, mask, sp, A.Itrl[t]);
         }
-        for (uint32_t t = l + lane; t < l2; t += WAVE)
-            acc += atab_get(B.keys, B.vals, mask, sp, (uint32_t)A.Itrk[t]);
+        unsigned long long longm = __ballot(y > TRI_SHORT_LIST);
+        while (longm) {                               // wave-uniform
+            const int j = __ffsll((long long)longm) - 1;
+            longm &= longm - 1;
+            uint32_t l = __shfl(ts, j, WAVE);
+            uint32_t l2 = l + __shfl(y, j, WAVE);
+            if (sliced && l2 - l > WAVE) {            // the part inside [alo, ahi]
+                l = wave_bound(A.Itrl, l, l2, alo, false);
+                l2 = wave_bound(A.Itrl, l, l2, ahi, true);
+            }
+            for (uint32_t t0 = l; t0 < l2; t0 += UNROLL * WAVE) {
+                uint32_t key[UNROLL];
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u) {
+                    const uint32_t t = t0 + u * WAVE + lane;
+                    key[u] = t < l2 ? A.Itrl[t] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u)
+                    if (t0 + u * WAVE + lane < l2) acc += atab_get(B.keys, B.vals, mask, sp, key[u]);
+            }
+        }
     }
     return acc;
 }
@@ -333,8 +368,9 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
     __shared__ uint32_t hkeys[TRI_HEAVY_CAP];                             \
     __shared__ uint32_t hvals[TRI_HEAVY_CAP];                             \
     __shared__ uint32_t hspec;                                            \
+    __shared__ uint32_t hchunk;                                           \
     __shared__ uint32_t s_item;                                           \
-    BlockTable B{hkeys, hvals, &hspec};                                   \
+    BlockTable B{hkeys, hvals, &hspec, &hchunk};                          \
     const int lane = lane_id();
 
 __global__ void __launch_bounds__(TRI_HEAVY_THREADS)
@@ -344,7 +380,7 @@ k_tri_heavy(TriJoinArgs A) {
     unsigned long long acc = 0;
     while (true) {
         __syncthreads();
-        if (threadIdx.x == 0) { s_item = atomicAdd(A.heavy_next, 1u); hspec = 0; }
+        if (threadIdx.x == 0) { s_item = atomicAdd(A.heavy_next, 1u); hspec = 0; hchunk = 0; }
         for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { hkeys[s] = EMPTY_KEY; hvals[s] = 0; }
         __syncthreads();
         const uint32_t it = s_item;
@@ -391,7 +427,7 @@ k_tri_heavy_batch(TriBatchArgs Bt) {
     const unsigned long long nitems = Bt.heavy_base[Bt.njoins];
     while (true) {
         __syncthreads();
-        if (threadIdx.x == 0) { s_bitem = atomicAdd(Bt.next + 1, 1ull); hspec = 0; s_sum = 0; }
+        if (threadIdx.x == 0) { s_bitem = atomicAdd(Bt.next + 1, 1ull); hspec = 0; hchunk = 0; s_sum = 0; }
         for (uint32_t s = threadIdx.x; s < TRI_HEAVY_CAP; s += blockDim.x) { hkeys[s] = EMPTY_KEY; hvals[s] = 0; }
         __syncthreads();
         const unsigned long long it = s_bitem;
