@@ -29,14 +29,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, n_r, n_s, n_t, distinct_t):
+def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain):
     """Algorithmic HBM bytes of one launch of the named kernel."""
     table = {
-        "rs:k_part_hist": 4 * (n_r + n_s),              # read the B column
+        "rs:k_part_hist": 4 * (n_r + n_s),              # read the bucketed columns
         "rs:k_part_scatter": 16 * (n_r + n_s),          # read + write 8-byte tuples
         "tab:k_part_hist": 4 * n_t,                     # read the C column
         "tab:k_part_scatter": 8 * n_t,                  # read + write the C column
         "tab:k_dbuild": 4 * n_t + 16 * distinct_t,      # read C, write the table
+        # S, one 8-byte multiplicity slot per s, the W table (16-byte slots, load 1/2)
+        "k_wbuild": 16 * n_s + 32 * distinct_b,
+        # R, one 16-byte W slot per r, the counts written once
+        "k_count": 24 * n_r + 8 * a_domain,
         "k_linear_cell": 16 * n_s + 16 * n_r,           # S, R, one table slot per s, one count per r
     }
     return table.get(name)
@@ -149,10 +153,10 @@ def main():
     for k, (avg, per) in sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
         log(f"  {k:24s} {avg * 1e3:9.1f} us x {per}")
 
-    distinct_t = int(np.unique(F[:, 0]).size)
+    distinct_t = int(np.unique(F[:, 0]).size)       # T.c and S.b are both F's first column
     dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
     avg_ms = kern[dom][0]
-    nbytes = kernel_bytes(dom, n, n, n, distinct_t)
+    nbytes = kernel_bytes(dom, n, n, n, distinct_t, distinct_t, a_domain)
     roof = None
     if nbytes:
         ach = nbytes / (avg_ms * 1e-3) / 1e9

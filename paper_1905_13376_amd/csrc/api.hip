@@ -199,9 +199,28 @@ void take_part(Bump& B, RelPart& P, uint64_t n, uint32_t bits) {
     P.pairs = B.take<uint2>(std::max<uint64_t>(n, 1));
 }
 
+// Ranges of A for the per-A counts: about 32K R tuples per range, at most
+// 2^PART_MAX_BITS ranges of at most 2^ACELL_MAX_SHIFT values.  False when
+// a_domain needs more (the cells then add into the output with atomics).
+bool a_ranges(const mj_plan_t& p, uint32_t& bits, uint32_t& shift) {
+    if (p.a_domain == 0) return false;
+    const uint32_t L = ceil_log2(p.a_domain);
+    bits = std::min<uint32_t>({ceil_log2((p.n_r + 32767) / 32768), PART_MAX_BITS, L});
+    if (L - bits > ACELL_MAX_SHIFT) bits = L - ACELL_MAX_SHIFT;
+    shift = L - bits;
+    return bits <= PART_MAX_BITS;
+}
+
 struct LinearLayout {
-    RelPart R, S;
+    RelPart R, S;                     // R and S by bucket of B (cells)
+    RelPart Ra;                       // R by range of A (shares R's pair buffer)
     TableLayout T;
+    WDirEntry* wdir;                  // W tables per bucket of B
+    WSlot* wpool;
+    unsigned long long* wcursor;
+    uint64_t wslots;
+    uint32_t a_bits, a_shift;
+    bool by_range;                    // per-A counts by ranges of A (no atomics)
     size_t bytes;
 };
 
@@ -211,6 +230,22 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
     take_part(B, L.R, p.n_r, p.log2_nb);
     take_part(B, L.S, p.n_s, p.log2_nb);
     take_table(B, L.T, p.n_t, p.log2_nc);
+    L.by_range = a_ranges(p, L.a_bits, L.a_shift);
+    L.wdir = nullptr; L.wpool = nullptr; L.wcursor = nullptr; L.wslots = 0;
+    L.Ra = L.R;
+    if (L.by_range) {
+        const uint32_t na = 1u << L.a_bits;
+        L.Ra.hist = B.take<uint32_t>(uint64_t(na) * ntiles_of(p.n_r));
+        L.Ra.counts = B.take<uint32_t>(na);
+        L.Ra.starts = B.take<uint32_t>(na + 1);
+        const uint32_t nb = 1u << p.log2_nb;
+        L.wdir = B.take<WDirEntry>(nb);
+        // a bucket's table holds at most 4 slots per S tuple (a power of two
+        // >= twice its keys), plus the minimum per bucket and the empty head
+        L.wslots = 4 * p.n_s + uint64_t(W_MIN_CAP) * (nb + 1);
+        L.wpool = B.take<WSlot>(L.wslots);
+        L.wcursor = B.take<unsigned long long>(1);
+    }
     L.bytes = B.off + 256;
     return L;
 }
@@ -858,16 +893,50 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     L = linear_layout(ws, p);
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    if (a_domain) {
+    const bool empty = R->n == 0 || S->n == 0 || T->n == 0;
+    if (a_domain && (empty || !L.by_range)) {
         MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                            reinterpret_cast<unsigned long long*>(count), (uint64_t)a_domain, 0ull);
     }
-    if (R->n == 0 || S->n == 0 || T->n == 0) return MJ_OK;
+    if (empty || a_domain == 0) return MJ_OK;
 
     const uint32_t nb = 1u << p.log2_nb;
     // T: partition by g(C) and reduce each bucket to C -> multiplicity
     st = launch_tables(&ctx->prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
     if (st) return st;
+    if (L.by_range) {
+        // S by bucket of B, R by range of A (one group of launches)
+        PartLaunch P{};
+        P.njobs = 2;
+        P.job[0] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+        P.job[0].out_pair = L.S.pairs;
+        P.job[1] = make_job(*R, L.Ra.hist, L.Ra.counts, L.Ra.starts, 0, 0, L.a_bits, 0, 0, 0);
+        P.job[1].range_on = 1;
+        P.job[1].range_shift = L.a_shift;
+        P.job[1].out_pair = L.Ra.pairs;
+        if ((st = launch_partition(&ctx->prof, "rs", P, s))) return st;
+        // W[b] per bucket of B into the pool (slots [0, W_MIN_CAP) stay empty)
+        MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s,
+                  reinterpret_cast<uint32_t*>(L.wpool), (uint64_t)(4 * W_MIN_CAP), EMPTY_KEY);
+        MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
+                  (unsigned long long)W_MIN_CAP);
+        WBuildArgs Wb;
+        Wb.S = L.S.pairs; Wb.sstarts = L.S.starts; Wb.ddir = L.T.dir; Wb.dpool = L.T.pool;
+        Wb.c_seed = seed_c(p); Wb.c_bits = p.log2_nc; Wb.slot_seed = seed_slot(p); Wb.w_seed = seed_w(p);
+        Wb.wdir = L.wdir; Wb.wpool = L.wpool; Wb.wcursor = L.wcursor; Wb.wcap = L.wslots;
+        Wb.err = L.T.err;
+        MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
+        // per range of A: count[a] = sum of W[r.b], written once
+        CountArgs Cn;
+        Cn.R = L.Ra.pairs; Cn.rstarts = L.Ra.starts; Cn.wdir = L.wdir; Cn.wpool = L.wpool;
+        Cn.b_seed = seed_b(p); Cn.b_bits = p.log2_nb; Cn.w_seed = seed_w(p);
+        Cn.a_shift = L.a_shift; Cn.a_domain = a_domain;
+        Cn.count = reinterpret_cast<unsigned long long*>(count);
+        Cn.err = L.T.err;
+        MJ_LAUNCH(&ctx->prof, "k_count", k_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
+                  (size_t(8) << L.a_shift), s, Cn);
+        return MJ_OK;
+    }
     // R and S: partition by the bucket of B (one group of launches for both)
     PartLaunch P{};
     P.njobs = 2;

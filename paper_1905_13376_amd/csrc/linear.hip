@@ -192,6 +192,64 @@ __device__ __forceinline__ uint32_t pass_of(uint32_t b, uint32_t seed, uint32_t 
     return top_bits(mix32(b, seed ^ 0x3C6EF372u), level);
 }
 
+// A cell's LDS table of W[b] (key 0xFFFFFFFF kept in `special`).
+struct WTable {
+    uint32_t* keys;
+    unsigned long long* vals;
+    unsigned long long* special;
+    uint32_t* distinct;
+    uint32_t* over;
+};
+
+// W[b] += mult_T(c) over the S tuples of [s0, s1) whose b belongs to the
+// pass (level, pass); sets *over when the distinct b exceed CELL_LIMIT (no
+// slot is claimed after that, so every probe still ends).
+__device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const DirEntry* ddir,
+                             const uint2* dpool, uint32_t c_seed, uint32_t c_bits,
+                             uint32_t slot_seed, uint32_t w_seed, uint32_t level, uint32_t pass,
+                             const WTable& T) {
+    const uint32_t mask = CELL_CAP - 1;
+    const int nthr = blockDim.x;
+    for (uint32_t q = s0 + threadIdx.x; q < s1; q += 4 * nthr) {
+        if (*(volatile uint32_t*)T.over) break;
+        uint2 sv[4];
+        uint32_t w[4], cc[4];
+        bool live[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t idx = q + u * nthr;
+            sv[u] = idx < s1 ? S[idx] : make_uint2(0u, 0u);
+            live[u] = idx < s1 && (level == 0 || pass_of(sv[u].x, w_seed, level) == pass);
+            cc[u] = sv[u].y;
+        }
+        dtab_lookup4(ddir, dpool, cc, live, c_seed, c_bits, slot_seed, w);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (w[u] == 0) continue;
+            const uint32_t b = sv[u].x;
+            if (b == EMPTY_KEY) { atomicAdd(T.special, (unsigned long long)w[u]); continue; }
+            uint32_t s = slot_hash(b, w_seed) & mask;
+            for (uint32_t step = 0;; ++step) {
+                uint32_t cur = T.keys[s];
+                if (cur == b) { atomicAdd(&T.vals[s], (unsigned long long)w[u]); break; }
+                if (cur == EMPTY_KEY || step >= CELL_CAP) {
+                    // a new key: once the pass has overflowed no new slot is
+                    // claimed (the pass is redone split), so the table can
+                    // never fill up and every probe finds an empty slot
+                    if (*(volatile uint32_t*)T.over || step >= CELL_CAP) { *T.over = 1; break; }
+                    uint32_t old = atomicCAS(&T.keys[s], EMPTY_KEY, b);
+                    if (old == EMPTY_KEY || old == b) {
+                        if (old == EMPTY_KEY && atomicAdd(T.distinct, 1u) + 1 >= CELL_LIMIT) *T.over = 1;
+                        atomicAdd(&T.vals[s], (unsigned long long)w[u]);
+                        break;
+                    }
+                }
+                s = (s + 1u) & mask;
+            }
+        }
+    }
+}
+
 __device__ void linear_cell_run(const LinearCellArgs& A, uint32_t i) {
     __shared__ uint32_t wkeys[CELL_CAP];
     __shared__ unsigned long long wvals[CELL_CAP];
@@ -199,6 +257,7 @@ __device__ void linear_cell_run(const LinearCellArgs& A, uint32_t i) {
     __shared__ uint32_t s_distinct, s_over;
     __shared__ uint32_t st_level[64], st_pass[64];
     __shared__ int s_sp;
+    const WTable T{wkeys, wvals, &w_special, &s_distinct, &s_over};
 
     const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
     const uint32_t r0 = A.rstarts[i], r1 = A.rstarts[i + 1];
@@ -220,44 +279,8 @@ __device__ void linear_cell_run(const LinearCellArgs& A, uint32_t i) {
         __syncthreads();
 
         // phase 1: W[b] += mult_T(c) over the S tuples of this (sub-)bucket
-        for (uint32_t q = s0 + threadIdx.x; q < s1; q += 4 * nthr) {
-            if (*(volatile uint32_t*)&s_over) break;
-            uint2 sv[4];
-            uint32_t w[4], cc[4];
-            bool live[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                uint32_t idx = q + u * nthr;
-                sv[u] = idx < s1 ? A.S[idx] : make_uint2(0u, 0u);
-                live[u] = idx < s1 && (level == 0 || pass_of(sv[u].x, A.w_seed, level) == pass);
-                cc[u] = sv[u].y;
-            }
-            dtab_lookup4(A.ddir, A.dpool, cc, live, A.c_seed, A.c_bits, A.slot_seed, w);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (w[u] == 0) continue;
-                const uint32_t b = sv[u].x;
-                if (b == EMPTY_KEY) { atomicAdd(&w_special, (unsigned long long)w[u]); continue; }
-                uint32_t s = slot_hash(b, A.w_seed) & mask;
-                for (uint32_t step = 0;; ++step) {
-                    uint32_t cur = wkeys[s];
-                    if (cur == b) { atomicAdd(&wvals[s], (unsigned long long)w[u]); break; }
-                    if (cur == EMPTY_KEY || step >= CELL_CAP) {
-                        // a new key: once the pass has overflowed no new slot is
-                        // claimed (the pass is redone split), so the table can
-                        // never fill up and every probe finds an empty slot
-                        if (*(volatile uint32_t*)&s_over || step >= CELL_CAP) { s_over = 1; break; }
-                        uint32_t old = atomicCAS(&wkeys[s], EMPTY_KEY, b);
-                        if (old == EMPTY_KEY || old == b) {
-                            if (old == EMPTY_KEY && atomicAdd(&s_distinct, 1u) + 1 >= CELL_LIMIT) s_over = 1;
-                            atomicAdd(&wvals[s], (unsigned long long)w[u]);
-                            break;
-                        }
-                    }
-                    s = (s + 1u) & mask;
-                }
-            }
-        }
+        w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
+                     level, pass, T);
         __syncthreads();
         if (s_over) {
             // too many distinct B values: split this pass in two by one more
@@ -307,6 +330,224 @@ k_linear_cell_batch(LinearBatchArgs B) {
     uint32_t lo = 0, hi = B.njoins;
     while (hi - lo > 1) { uint32_t m = (lo + hi) >> 1; if (B.cell_base[m] <= b) lo = m; else hi = m; }
     linear_cell_run(B.joins[lo], b - B.cell_base[lo]);
+}
+
+// ------------------------------------------------------------- W tables
+// One workgroup per b-bucket: W[b] for the bucket's S tuples in LDS (split
+// into passes by hash bits of b while the distinct b overflow the table, as
+// in the cells), then one table per bucket in the pool.  A bucket done in
+// one pass is copied out whole (rehashed in LDS first at the least power of
+// two >= twice its keys when that is below CELL_CAP); a split bucket gets a
+// region sized for every S tuple of the bucket, cleared, into which each
+// pass inserts its keys (every key belongs to one pass, so a claimed slot's
+// W is stored once).
+__global__ void __launch_bounds__(CELL_THREADS)
+k_wbuild(WBuildArgs A) {
+    __shared__ uint32_t wkeys[CELL_CAP];
+    __shared__ unsigned long long wvals[CELL_CAP];
+    __shared__ unsigned long long w_special, s_special_tot, s_base;
+    __shared__ uint32_t s_distinct, s_over, s_log2, s_global;
+    __shared__ uint32_t st_level[64], st_pass[64];
+    __shared__ int s_sp;
+    const WTable T{wkeys, wvals, &w_special, &s_distinct, &s_over};
+    const uint32_t i = blockIdx.x;
+    const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
+    const int nthr = blockDim.x;
+    if (s0 == s1) {                       // an empty table: the pool's first slots
+        if (threadIdx.x == 0) {
+            WDirEntry e;
+            e.offset = 0; e.special = 0; e.log2cap = 31 - __clz(W_MIN_CAP); e.pad = 0;
+            A.wdir[i] = e;
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        s_sp = 1; st_level[0] = 0; st_pass[0] = 0;
+        s_global = 0; s_base = 0; s_log2 = 31 - __clz(W_MIN_CAP); s_special_tot = 0;
+    }
+    while (true) {
+        __syncthreads();
+        const int sp = s_sp;
+        if (sp == 0) break;
+        const uint32_t level = st_level[sp - 1];
+        const uint32_t pass = st_pass[sp - 1];
+        for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) { wkeys[s] = EMPTY_KEY; wvals[s] = 0; }
+        __syncthreads();
+        if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; s_sp = sp - 1; }
+        __syncthreads();
+        w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
+                     level, pass, T);
+        __syncthreads();
+        if (s_over) {
+            if (threadIdx.x == 0) {
+                st_level[sp - 1] = level + 1; st_pass[sp - 1] = 2 * pass + 1;
+                st_level[sp] = level + 1;     st_pass[sp] = 2 * pass;
+                s_sp = sp + 1;
+            }
+            continue;
+        }
+        if (threadIdx.x == 0) s_special_tot += w_special;
+        const bool whole = level == 0;       // the bucket's table is complete in LDS
+        const bool need_region = !whole && !s_global;
+        __syncthreads();
+        if (whole || need_region) {
+            if (threadIdx.x == 0) {
+                // a whole table keeps load <= 1/2 when it can be halved, else
+                // it leaves LDS as it is (CELL_CAP slots, load < 7/8)
+                const uint64_t want = whole ? min<uint64_t>(2ull * s_distinct, CELL_CAP) : 2ull * (s1 - s0);
+                uint32_t cap = max(W_MIN_CAP, (uint32_t)min<uint64_t>(uint64_t(1) << 31,
+                                                                      next_pow2_u32((uint32_t)min<uint64_t>(want, 1ull << 31))));
+                unsigned long long base = atomicAdd(A.wcursor, (unsigned long long)cap);
+                if (base + cap > A.wcap) {   // cannot happen with a planned workspace
+                    atomicExch(A.err, 1u);
+                    base = 0;                // the pool's first W_MIN_CAP slots stay empty
+                    cap = W_MIN_CAP;
+                }
+                s_base = base;
+                s_log2 = 31 - __clz(cap);
+                s_global = 1;
+            }
+            __syncthreads();
+        }
+        const unsigned long long base = s_base;
+        const uint32_t cap = 1u << s_log2;
+        WSlot* region = A.wpool + base;
+        if (base == 0) continue;             // pool exhausted: reported above
+        if (whole && cap < CELL_CAP) {
+            // rehash in place at mask cap - 1, then copy slots [0, cap) out
+            constexpr int PER = CELL_CAP / CELL_THREADS;
+            uint32_t ek[PER];
+            unsigned long long ev[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t s = threadIdx.x + u * CELL_THREADS;
+                ek[u] = wkeys[s];
+                ev[u] = wvals[s];
+            }
+            __syncthreads();
+            for (uint32_t s = threadIdx.x; s < cap; s += nthr) { wkeys[s] = EMPTY_KEY; wvals[s] = 0; }
+            __syncthreads();
+            const uint32_t cmask = cap - 1;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                if (ek[u] == EMPTY_KEY) continue;
+                uint32_t s = slot_hash(ek[u], A.w_seed) & cmask;
+                while (atomicCAS(&wkeys[s], EMPTY_KEY, ek[u]) != EMPTY_KEY) s = (s + 1u) & cmask;
+                wvals[s] = ev[u];
+            }
+            __syncthreads();
+            for (uint32_t s = threadIdx.x; s < cap; s += nthr) {
+                WSlot v;
+                v.key = wkeys[s]; v.pad = 0; v.w = wvals[s];
+                region[s] = v;
+            }
+        } else if (whole) {                  // same mask: the LDS table as it is
+            for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) {
+                WSlot v;
+                v.key = wkeys[s]; v.pad = 0; v.w = wvals[s];
+                region[s] = v;
+            }
+        } else {
+            if (need_region) {
+                for (uint32_t s = threadIdx.x; s < cap; s += nthr) {
+                    WSlot v;
+                    v.key = EMPTY_KEY; v.pad = 0; v.w = 0;
+                    region[s] = v;
+                }
+                __threadfence();
+                __syncthreads();
+            }
+            const uint32_t cmask = cap - 1;
+            for (uint32_t t = threadIdx.x; t < CELL_CAP; t += nthr) {
+                const uint32_t k = wkeys[t];
+                if (k == EMPTY_KEY) continue;
+                uint32_t s = slot_hash(k, A.w_seed) & cmask;
+                while (atomicCAS(&region[s].key, EMPTY_KEY, k) != EMPTY_KEY) s = (s + 1u) & cmask;
+                region[s].w = wvals[t];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        WDirEntry e;
+        e.offset = s_base; e.special = s_special_tot; e.log2cap = s_log2; e.pad = 0;
+        A.wdir[i] = e;
+    }
+}
+
+// Four independent W lookups (directory loads, then first slots, in flight
+// together; only keys that collide walk further); 0 when absent.
+__device__ __forceinline__ void wtab_lookup4(const WDirEntry* __restrict__ dir,
+                                             const WSlot* __restrict__ pool,
+                                             const uint32_t (&key)[4], const bool (&live)[4],
+                                             uint32_t bkt_seed, uint32_t bkt_bits,
+                                             uint32_t slot_seed, unsigned long long (&out)[4]) {
+    WDirEntry e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (live[u]) e[u] = dir[top_bits(mix32(key[u], bkt_seed), bkt_bits)];
+    uint32_t s[4];
+    WSlot kv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (live[u] && key[u] != EMPTY_KEY) {
+            s[u] = slot_hash(key[u], slot_seed) & ((1u << e[u].log2cap) - 1u);
+            kv[u] = pool[e[u].offset + s[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (!live[u]) { out[u] = 0; continue; }
+        if (key[u] == EMPTY_KEY) { out[u] = e[u].special; continue; }
+        const uint32_t mask = (1u << e[u].log2cap) - 1u;
+        WSlot v = kv[u];
+        uint32_t t = s[u];
+        while (v.key != key[u] && v.key != EMPTY_KEY) {
+            t = (t + 1u) & mask;
+            v = pool[e[u].offset + t];
+        }
+        out[u] = v.key == key[u] ? v.w : 0ull;
+    }
+}
+
+// ------------------------------------------------------------- counts
+// One workgroup per range of A values: count[a] = sum over r(a, b) of W[b]
+// in LDS, then the range is written out whole (zeros included).
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_count(CountArgs A) {
+    extern __shared__ unsigned long long cnt[];          // [1 << a_shift]
+    const uint32_t k = blockIdx.x;
+    const uint64_t base = uint64_t(k) << A.a_shift;
+    // ranges past a_domain only receive keys out of range (reported)
+    const uint32_t span = base < A.a_domain
+                              ? (uint32_t)min<uint64_t>(uint64_t(1) << A.a_shift, A.a_domain - base) : 0u;
+    const int nthr = blockDim.x;
+    for (uint32_t j = threadIdx.x; j < span; j += nthr) cnt[j] = 0;
+    __syncthreads();
+    const uint32_t r0 = A.rstarts[k], r1 = A.rstarts[k + 1];
+    for (uint32_t q = r0 + threadIdx.x; q < r1; q += 4 * nthr) {
+        uint2 rv[4];
+        uint32_t bb[4];
+        bool live[4];
+        unsigned long long w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t idx = q + u * nthr;
+            live[u] = idx < r1;
+            rv[u] = live[u] ? A.R[idx] : make_uint2(0u, 0u);
+            bb[u] = rv[u].y;
+        }
+        wtab_lookup4(A.wdir, A.wpool, bb, live, A.b_seed, A.b_bits, A.w_seed, w);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!live[u] || w[u] == 0) continue;
+            const uint64_t off = uint64_t(rv[u].x) - base;   // < span unless a >= a_domain
+            if (rv[u].x >= A.a_domain || off >= span) { atomicExch(A.err, 1u); continue; }
+            atomicAdd(&cnt[off], w[u]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < span; j += nthr) A.count[base + j] = cnt[j];
 }
 
 }  // namespace mj

@@ -50,6 +50,8 @@ struct PartJob {
     uint2* out_pair;     // both columns as (col0, col1), or
     uint32_t* out_single;// one column (single_col, also the bucketed column)
     uint32_t single_col;
+    uint32_t range_on;   // bucket = min(key0 >> range_shift, 2^bits0 - 1) (no hash; pairs only)
+    uint32_t range_shift;
     uint32_t tile_begin; // first block of this job in the grid
     uint32_t ntiles;
 };
@@ -171,6 +173,56 @@ struct LinearCellArgs {
     uint32_t* err;
 };
 __global__ void k_linear_cell(LinearCellArgs A);
+
+// ------------------------------ linear: W tables and counts per range of A
+// W[b] = sum over s(b, c) in S of mult_T(c), one open-addressing table per
+// b-bucket (the cells' buckets) in a pool of 16-byte slots; then one
+// workgroup per range of A values adds W[r.b] into an LDS count per a and
+// writes its range of the output once.
+struct WDirEntry {
+    unsigned long long offset;   // first slot in the pool
+    unsigned long long special;  // W of key 0xFFFFFFFF in this bucket
+    uint32_t log2cap;
+    uint32_t pad;
+};
+struct __align__(16) WSlot {
+    uint32_t key;
+    uint32_t pad;
+    unsigned long long w;
+};
+constexpr uint32_t W_MIN_CAP = 16;
+
+struct WBuildArgs {
+    const uint2* S;              // partitioned (b, c) by bucket of b
+    const uint32_t* sstarts;     // [nb + 1]
+    const DirEntry* ddir;        // multiplicity tables of T.c
+    const uint2* dpool;
+    uint32_t c_seed, c_bits, slot_seed;
+    uint32_t w_seed;             // hash of W slots and of the pass split
+    WDirEntry* wdir;             // [nb]
+    WSlot* wpool;                // slots [0, W_MIN_CAP) stay empty
+    unsigned long long* wcursor;
+    unsigned long long wcap;
+    uint32_t* err;               // set to 1 if the pool is exhausted
+};
+__global__ void k_wbuild(WBuildArgs A);
+
+static_assert(CELL_CAP % CELL_THREADS == 0, "rehash takes CELL_CAP / CELL_THREADS slots per thread");
+constexpr int COUNT_THREADS = 512;
+constexpr uint32_t ACELL_MAX_SHIFT = 12;     // at most 4096 A values (32 KB of LDS) per range
+
+struct CountArgs {
+    const uint2* R;              // partitioned (a, b) by range of a
+    const uint32_t* rstarts;     // [number of ranges + 1]
+    const WDirEntry* wdir;
+    const WSlot* wpool;
+    uint32_t b_seed, b_bits, w_seed;
+    uint32_t a_shift;            // range k holds a in [k << a_shift, (k + 1) << a_shift)
+    uint32_t a_domain;
+    unsigned long long* count;   // [a_domain], every entry written
+    uint32_t* err;               // set to 1 for an a >= a_domain
+};
+__global__ void k_count(CountArgs A);
 
 // probe S.b (or any column) against a bucketed multiplicity table and sum
 struct ProbeSumArgs {

@@ -24,6 +24,7 @@ namespace mj {
 
 __device__ __forceinline__ uint32_t part_bucket(const PartJob& J, uint32_t x0, uint32_t x1) {
     uint32_t k0 = J.key0_col ? x1 : x0;
+    if (J.range_on) return min(k0 >> J.range_shift, (1u << J.bits0) - 1u);
     uint32_t d = top_bits(mix32(k0, J.seed0), J.bits0);
     if (J.bits1) {
         uint32_t k1 = J.key1_col ? x1 : x0;

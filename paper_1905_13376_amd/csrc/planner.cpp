@@ -106,9 +106,9 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
     const double R = (double)p.n_r, S = (double)p.n_s, T = (double)p.n_t;
     const double I = (double)p.join2_size;
     if (kind == MJ_LINEAR) {
-        // b-buckets: about 32K S tuples per cell; c-buckets: about 32K T
+        // b-buckets: about 16K S tuples per W table; c-buckets: about 32K T
         // tuples per multiplicity table (at most 2^10 of either)
-        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 32767) / 32768));
+        p.log2_nb = std::min<uint32_t>(10, ceil_log2((p.n_s + 16383) / 16384));
         p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
         p.est_ms_3way = model_linear_3way_ms(m, R, S, T);
         p.est_ms_cascade = model_linear_cascade_ms(m, R, S, T, I);

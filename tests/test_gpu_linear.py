@@ -172,3 +172,27 @@ def test_linear_workspace_and_plan_errors(mj, ctx):
     with pytest.raises(mj.MJError) as e:
         ctx.linear3_count(Fd[:999], Fd, Fd, 4096, plan=p)
     assert "PLAN_MISMATCH" in str(e.value)
+
+
+@pytest.mark.parametrize("a_domain", [(1 << 25) + 1, 1 << 24, 1, 3])
+def test_linear_a_domain_extremes(mj, ctx, a_domain):
+    # a_domain above 2^(PART_MAX_BITS + ACELL_MAX_SHIFT) = 2^24 takes the
+    # cells' atomic adds; at or below it, the ranges of A; every entry of the
+    # output is written either way (it starts as garbage here)
+    banner(f"linear a_domain={a_domain}")
+    import torch
+    rng = np.random.default_rng(a_domain & 0xFFFF)
+    n = 20000
+    R = np.stack([rng.integers(0, a_domain, size=n), rng.integers(0, 300, size=n)], axis=1).astype(np.uint32)
+    R[:5, 0] = a_domain - 1
+    S = rng.integers(0, 300, size=(n, 2)).astype(np.uint32)
+    T = rng.integers(0, 300, size=(n, 2)).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    out = torch.full((a_domain,), -1, dtype=torch.int64, device="cuda")
+    ctx.linear3_count(Rd, Sd, Td, a_domain, out=out)
+    got = mj.as_u64(out)
+    a_u, want_nz = oracle.linear3_count_sampled(R, S, T, R[:, 0])
+    np.testing.assert_array_equal(got[a_u], want_nz)
+    untouched = np.ones(a_domain, dtype=bool)
+    untouched[a_u] = False
+    assert not got[untouched].any()
