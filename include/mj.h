@@ -207,7 +207,7 @@ int mj_cost_model(int which, const double* args, int nargs, double* out);
  * log2(1 + keys in the bin) / 32), then log2(1 + |R|), (1 + |S|), (1 + |T|)
  * over 32, then the kind.  A network MJ_SKETCH_DIM -> 64 -> 64 -> 7 with
  * GELU maps it to: predicted log2(1 + |R |x| S|), log2(1 + |output|),
- * logits of (three-way, cascade) and of the share (8, 16, 32).
+ * logits of (three-way, cascade) and of the share (1, 4, 16).
  * Weights are BF16 (W1, W2, W3), biases and arithmetic FP32.
  * The parameter buffer is device memory of mj_mlp_param_bytes() bytes:
  *   float master[P], grad[P], adam_m[P], adam_v[P]; uint16 bf16_weights[]
@@ -228,7 +228,7 @@ int mj_mlp_forward(mj_ctx* ctx, const void* params, const float* X, uint32_t B, 
  * mean loss: squared error of heads 0-1 against targets[B][2], softmax
  * cross entropy of heads 2-3 against plan_label[B] (0 = three-way,
  * 1 = cascade) and of heads 4-6 against share_label[B] (0, 1, 2 for
- * 8, 16, 32; -1 = no share term).  Workspace: mj_mlp_workspace(B).     */
+ * 1, 4, 16; -1 = no share term).  Workspace: mj_mlp_workspace(B).     */
 uint64_t mj_mlp_workspace(uint32_t B);
 int mj_mlp_grads(mj_ctx* ctx, void* params, const float* X, uint32_t B, const float* targets,
                  const int32_t* plan_label, const int32_t* share_label, float* loss,

@@ -9,7 +9,7 @@ Loss for a batch of B samples (the planner's heads):
   y[0], y[1]   : predicted log2(1 + |I|), log2(1 + |OUT|); squared error
                  against the targets, weight 1 each, averaged over B
   y[2:4]       : logits of (three-way, cascade); cross entropy, averaged
-  y[4:7]       : logits of the share (8, 16, 32); cross entropy over the
+  y[4:7]       : logits of the share (1, 4, 16); cross entropy over the
                  samples whose share label is >= 0, divided by B
 This module restates those definitions directly; it shares nothing with
 the HIP kernels.  Parity of the reference itself is pinned by finite

@@ -855,10 +855,10 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
             p.pred_log2_join2 = h[0];
             p.pred_log2_out = h[1];
             p.algo = h[3] > h[2] ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
-            if (kind == MJ_TRIANGLE) {
+            if (kind == MJ_TRIANGLE) {            // share classes 1, 4, 16
                 int best = 0;
                 for (int k = 1; k < 3; ++k) if (h[4 + k] > h[4 + best]) best = k;
-                p.log2_share = 3 + best;
+                p.log2_share = 2 * best;
             }
         }
         // an intermediate beyond one workspace-sized chunk is never worth

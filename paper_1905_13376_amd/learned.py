@@ -28,7 +28,7 @@ from . import _lib as L
 IN, H, OUT = 100, 64, 7
 SHAPES = [("W1", (H, IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (OUT, H)), ("b3", (OUT,))]
 P = sum(int(np.prod(s)) for _, s in SHAPES)
-SHARES = (3, 4, 5)                     # log2 of the shares 8, 16, 32
+SHARES = (0, 2, 4)                     # log2 of the shares 1, 4, 16 (the share head's classes)
 CASCADE_CAP = 1 << 28                  # the planner never materialises more pairs
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "planner_weights.npy")
 
@@ -211,6 +211,11 @@ def stack(rows):
     return X, targets, pl, sl
 
 
+def nearest_share(k):
+    """The timed share class closest to log2 share k."""
+    return min(SHARES, key=lambda c: (abs(c - k), c))
+
+
 def plan_time(r, algo, share):
     if algo == L.ALGO_CASCADE:
         return r["times"]["cascade"]
@@ -229,8 +234,8 @@ def evaluate(planner, rows):
         algo = L.ALGO_CASCADE if (y[3] > y[2] and r["join2"] <= CASCADE_CAP) else L.ALGO_3WAY
         share = SHARES[int(np.argmax(y[4:7]))]
         tot["learned"] += plan_time(r, algo, share)
-        tot["analytic"] += plan_time(r, r["analytic"]["algo"], r["analytic"]["share"] or 3)
-        tot["always_3way"] += plan_time(r, L.ALGO_3WAY, 3)
+        tot["analytic"] += plan_time(r, r["analytic"]["algo"], nearest_share(r["analytic"]["share"]))
+        tot["always_3way"] += plan_time(r, L.ALGO_3WAY, SHARES[0])
         tot["always_cascade"] += r["times"]["cascade"]
         tot["best"] += min(r["times"].values())
         qI.append(2 ** abs(float(y[0]) - math.log2(1 + r["join2"])))

@@ -140,7 +140,7 @@ def test_learned_plans_give_exact_counts(mods, ctx):
     E = G.gnm_symmetric(2000, 30000, seed=2)
     Ed = dev(E)
     q = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed, planner="learned")
-    assert q.log2_share in (3, 4, 5)
+    assert q.log2_share in (0, 2, 4)
     tot = (ctx.cascade2_count(mj.TRIANGLE, Ed, Ed, Ed, plan=q) if q.algo == mj.ALGO_CASCADE
            else ctx.triangle3_count(Ed, Ed, Ed, plan=q))
     assert int(mj.as_u64(tot)[0]) == oracle.triangle3_count(E, E, E)
