@@ -59,7 +59,13 @@ typedef struct {
 } mj_rel;
 
 typedef enum { MJ_LINEAR = 0, MJ_TRIANGLE = 1 } mj_kind;
-typedef enum { MJ_ALGO_3WAY = 0, MJ_ALGO_CASCADE = 1 } mj_algo;
+typedef enum {
+    MJ_ALGO_3WAY = 0,          /* partitioned three-way join (Sec. 4 / Sec. 5)      */
+    MJ_ALGO_CASCADE = 1,       /* cascade of two binary hash joins (Sec. 6.3)       */
+    MJ_ALGO_STAR = 2,          /* linear only: star three-way join, R and T         */
+                               /* resident, S streamed once (Sec. 6, star join)     */
+    MJ_ALGO_STAR_CASCADE = 3   /* linear only: cascade of two binary star joins     */
+} mj_algo;
 typedef enum {
     MJ_PLANNER_ANALYTIC = 0,   /* cost model with measured device constants        */
     MJ_PLANNER_LEARNED = 1,    /* MLP on degree sketches; analytic fallback         */
@@ -90,6 +96,8 @@ typedef struct {
     double est_ms_cascade;
     double pred_log2_join2;    /* learned planner: predicted log2(1 + |R |x| S|) */
     double pred_log2_out;      /* learned planner: predicted log2(1 + |output|)  */
+    double est_ms_star;        /* linear: star three-way estimate (0 = not eligible) */
+    double est_ms_star_cascade;/* linear: star cascade estimate (0 = not eligible)   */
 } mj_plan_t;
 
 /* Context: binds the library to a device (the current one if device < 0). */
@@ -120,7 +128,13 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
 /* Linear three-way join with per-A count (Sec. 4, Algorithm 1; Example 1):
  *   count_per_a[a] = #{ (r,s,t) in R x S x T : r.a = a, r.b = s.b, s.c = t.c }
  * for a in [0, a_domain); T's second column (D) takes no part.
- * count_per_a: device uint64[a_domain], fully overwritten.             */
+ * count_per_a: device uint64[a_domain], fully overwritten.
+ * A plan with algo MJ_ALGO_STAR runs the star three-way join (Sec. 6,
+ * linear star join: R and T small dimension relations held resident, the
+ * fact relation S streamed once and grouped by B); any other algo runs the
+ * partitioned three-way join.  The star join is exact at any size; it is
+ * fast while R has at most 4096 distinct B values (its per-B sums then live
+ * in one workgroup's LDS), and the planner only picks it then.           */
 int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                      uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan,
                      void* workspace, uint64_t workspace_bytes, void* stream);
@@ -137,7 +151,10 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
  * materialised in the workspace (in chunks when it does not fit), then
  * I |x| T is counted.  Same outputs as mj_linear3_count (kind MJ_LINEAR,
  * out = uint64[a_domain]) or mj_triangle3_count (kind MJ_TRIANGLE,
- * out = uint64[1]).                                                      */
+ * out = uint64[1]).  For the linear kind a plan with algo
+ * MJ_ALGO_STAR_CASCADE runs the cascade of binary star joins (R resident,
+ * S streamed into I, then T resident and I streamed); it needs
+ * |R |x| S| <= 2^28 and returns MJ_ERR_UNSUPPORTED otherwise.            */
 int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                       uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
                       void* workspace, uint64_t workspace_bytes, void* stream);

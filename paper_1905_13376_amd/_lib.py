@@ -25,7 +25,7 @@ STATUS = {0: "MJ_OK", -1: "MJ_ERR_INVALID_ARG", -2: "MJ_ERR_KEY_RANGE", -3: "MJ_
           -4: "MJ_ERR_PLAN_MISMATCH", -5: "MJ_ERR_HIP", -6: "MJ_ERR_OVERFLOW",
           -7: "MJ_ERR_UNSUPPORTED"}
 LINEAR, TRIANGLE = 0, 1
-ALGO_3WAY, ALGO_CASCADE = 0, 1
+ALGO_3WAY, ALGO_CASCADE, ALGO_STAR, ALGO_STAR_CASCADE = 0, 1, 2, 3
 PLANNERS = {"analytic": 0, "learned": 1, "fixed": 2}
 
 
@@ -48,7 +48,8 @@ class Plan(ctypes.Structure):
                 ("a_domain", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("join2_size", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
                 ("est_ms_3way", ctypes.c_double), ("est_ms_cascade", ctypes.c_double),
-                ("pred_log2_join2", ctypes.c_double), ("pred_log2_out", ctypes.c_double)]
+                ("pred_log2_join2", ctypes.c_double), ("pred_log2_out", ctypes.c_double),
+                ("est_ms_star", ctypes.c_double), ("est_ms_star_cascade", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -674,6 +674,173 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     return MJ_OK;
 }
 
+// ------------------------------------------------------------- star join
+static_assert(STAR_GROUPS == STAR_PLAN_MAX_R, "planner and kernels agree on the star limit");
+
+struct StarLayout {
+    TableLayout Rt, Tt;               // one-bucket tables: R on B, T on C
+    uint32_t* occ;                    // [R slots + 1]
+    unsigned long long* rid;          // [R slots + 2] ids of R's B values
+    unsigned long long* partial;      // [STAR_GRID][STAR_GROUPS] per-block sums
+    unsigned long long* W;            // [n_r + 1] per-B sums
+    unsigned long long* scan_part;
+    // binary star cascade
+    uint32_t* mult;                   // [n_r + 1] multiplicity per id
+    unsigned long long* roff;         // [n_r + 2]
+    uint32_t* rcur;                   // [n_r + 1]
+    uint32_t* ra;                     // [n_r] R's A values grouped by id
+    uint32_t* icnt;                   // [n_s]
+    unsigned long long* ioff;         // [n_s + 1]
+    uint2* I;                         // [i_cap] (a, c) pairs
+    uint64_t i_cap;
+    size_t bytes;
+};
+
+StarLayout star_layout(void* ws, const mj_plan_t& p, bool cascade) {
+    Bump B(ws);
+    StarLayout L{};
+    take_table(B, L.Rt, p.n_r, 0);
+    take_table(B, L.Tt, p.n_t, 0);
+    const uint64_t slots = L.Rt.pool_slots;
+    L.occ = B.take<uint32_t>(slots + 1);
+    L.rid = B.take<unsigned long long>(slots + 2);
+    L.partial = B.take<unsigned long long>(uint64_t(STAR_GRID) * STAR_GROUPS);
+    L.W = B.take<unsigned long long>(p.n_r + 1);
+    const uint64_t nmax = std::max<uint64_t>({slots + 2, p.n_s + 1, p.n_r + 2});
+    L.scan_part = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
+    if (cascade) {
+        L.mult = B.take<uint32_t>(p.n_r + 1);
+        L.roff = B.take<unsigned long long>(p.n_r + 2);
+        L.rcur = B.take<uint32_t>(p.n_r + 1);
+        L.ra = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+        L.icnt = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+        L.ioff = B.take<unsigned long long>(p.n_s + 1);
+        L.i_cap = std::max<uint64_t>(1, std::min<uint64_t>(p.join2_size, STAR_PLAN_MAX_I));
+        L.I = B.take<uint2>(L.i_cap);
+    }
+    L.bytes = B.off + 256;
+    return L;
+}
+
+StarTable star_table(const TableLayout& T, uint32_t bseed, uint32_t sseed) {
+    StarTable X;
+    X.dir = T.dir; X.pool = T.pool; X.bkt_seed = bseed; X.slot_seed = sseed;
+    X.pool_slots = (uint32_t)T.pool_slots;
+    return X;
+}
+
+uint32_t star_grid(uint64_t n) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(STAR_GRID, (n + STAR_ROWS_PER_BLOCK - 1) / STAR_ROWS_PER_BLOCK));
+}
+
+// both tables, then ids 0..k-1 of R's distinct B values
+int star_prepare(Prof* prof, const mj_rel& R, const mj_rel& T, const mj_plan_t& p,
+                 const StarLayout& L, hipStream_t s) {
+    int st;
+    if ((st = launch_tables(prof, L.Rt, R, 1, 0, seed_b(p), seed_slot(p), s))) return st;
+    if ((st = launch_tables(prof, L.Tt, T, 0, 0, seed_c(p), seed_slot(p), s))) return st;
+    StarOccArgs O;
+    O.R = star_table(L.Rt, seed_b(p), seed_slot(p));
+    O.cursor = L.Rt.pool_cursor; O.occ = L.occ;
+    const uint64_t slots = L.Rt.pool_slots;
+    MJ_LAUNCH(prof, "k_star_occ", k_star_occ, dim3(grid_for(slots + 1, 256, 4096)), dim3(256), 0, s, O);
+    return launch_scan_u32(prof, L.occ, slots + 1, L.scan_part, L.rid, s);
+}
+
+// group-by of (key, c) rows weighted by mult_T(c): W per id of B (by_rid) or
+// counts per A; `out` receives the sums
+int star_group(Prof* prof, const char* name, const uint32_t* col0, const uint32_t* col1,
+               int64_t stride, uint64_t n, bool by_rid, uint32_t ngroups_max, const mj_plan_t& p,
+               const StarLayout& L, unsigned long long* out, uint64_t out_len, hipStream_t s) {
+    // zeroed first: the LDS mode overwrites, the global mode adds
+    if (out_len)
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(out_len, 256, 4096)), dim3(256), 0, s,
+                  out, out_len, 0ull);
+    const uint32_t grid = star_grid(n);
+    StarGroupArgs G;
+    G.col0 = col0; G.col1 = col1; G.stride = stride; G.n = n;
+    G.T = star_table(L.Tt, seed_c(p), seed_slot(p));
+    G.by_rid = by_rid ? 1u : 0u;
+    G.R = star_table(L.Rt, seed_b(p), seed_slot(p));
+    G.rid = L.rid; G.ngroups_max = ngroups_max;
+    G.partial = L.partial; G.out = out; G.err = L.Rt.err;
+    MJ_LAUNCH(prof, name, k_star_group, dim3(grid), dim3(STAR_THREADS), 0, s, G);
+    StarReduceArgs Rd;
+    Rd.partial = L.partial; Rd.nblocks = grid; Rd.by_rid = G.by_rid; Rd.rid = L.rid;
+    Rd.pool_slots = G.R.pool_slots; Rd.ngroups_max = ngroups_max; Rd.out = out;
+    MJ_LAUNCH(prof, "k_star_reduce", k_star_reduce, dim3(STAR_GROUPS / 256), dim3(256), 0, s, Rd);
+    return MJ_OK;
+}
+
+int run_star3(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, uint32_t a_domain,
+              uint64_t* count_out, const mj_plan_t& p, void* ws, uint64_t ws_bytes, hipStream_t s) {
+    StarLayout L = star_layout(nullptr, p, false);
+    if (!ws || ws_bytes < L.bytes) return MJ_ERR_WORKSPACE;
+    if (L.Rt.pool_slots >= 0xFFFFFFF0ull || L.Tt.pool_slots >= 0xFFFFFFF0ull) return MJ_ERR_UNSUPPORTED;
+    L = star_layout(ws, p, false);
+    Prof* prof = &ctx->prof;
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(count_out);
+    if (a_domain)
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+                  count, (uint64_t)a_domain, 0ull);
+    if (R->n == 0 || S->n == 0 || T->n == 0 || a_domain == 0) return MJ_OK;
+    int st;
+    if ((st = star_prepare(prof, *R, *T, p, L, s))) return st;
+    // W[id(b)] = sum of mult_T(c) over S, one pass over the fact relation
+    if ((st = star_group(prof, "k_star_group", S->col0, S->col1, S->stride, S->n, true, 0, p, L,
+                         L.W, p.n_r + 1, s))) return st;
+    StarCountArgs C;
+    C.col0 = R->col0; C.col1 = R->col1; C.stride = R->stride; C.n = R->n;
+    C.R = star_table(L.Rt, seed_b(p), seed_slot(p)); C.rid = L.rid; C.W = L.W;
+    C.count = count; C.a_domain = a_domain; C.err = L.Rt.err;
+    MJ_LAUNCH(prof, "k_star_count", k_star_count, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, C);
+    return MJ_OK;
+}
+
+int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, uint32_t a_domain,
+                     uint64_t* count_out, const mj_plan_t& p, void* ws, uint64_t ws_bytes, hipStream_t s) {
+    if (p.join2_size > STAR_PLAN_MAX_I) return MJ_ERR_UNSUPPORTED;
+    StarLayout L = star_layout(nullptr, p, true);
+    if (!ws || ws_bytes < L.bytes) return MJ_ERR_WORKSPACE;
+    if (L.Rt.pool_slots >= 0xFFFFFFF0ull || L.Tt.pool_slots >= 0xFFFFFFF0ull) return MJ_ERR_UNSUPPORTED;
+    L = star_layout(ws, p, true);
+    Prof* prof = &ctx->prof;
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(count_out);
+    if (R->n == 0 || S->n == 0 || T->n == 0 || a_domain == 0 || p.join2_size == 0) {
+        if (a_domain)
+            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+                      count, (uint64_t)a_domain, 0ull);
+        return MJ_OK;
+    }
+    int st;
+    if ((st = star_prepare(prof, *R, *T, p, L, s))) return st;
+    // join 1's build side: R's A values grouped by the id of B
+    StarRIndexArgs X;
+    X.col0 = R->col0; X.col1 = R->col1; X.stride = R->stride; X.n = R->n;
+    X.R = star_table(L.Rt, seed_b(p), seed_slot(p)); X.rid = L.rid; X.roff = L.roff;
+    X.rcur = L.rcur; X.ra = L.ra;
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
+              L.mult, p.n_r + 1, 0u);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
+              L.rcur, p.n_r + 1, 0u);
+    MJ_LAUNCH(prof, "k_star_rmult", k_star_rmult, dim3(grid_for(uint64_t(X.R.pool_slots) + 1, 256, 4096)),
+              dim3(256), 0, s, X, L.mult);
+    if ((st = launch_scan_u32(prof, L.mult, p.n_r + 1, L.scan_part, L.roff, s))) return st;
+    MJ_LAUNCH(prof, "k_star_rfill", k_star_rfill, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, X);
+    // join 1: S streamed, I = R |x| S written as (a, c) pairs
+    StarExpandArgs E;
+    E.col0 = S->col0; E.col1 = S->col1; E.stride = S->stride; E.n = S->n;
+    E.R = X.R; E.rid = L.rid; E.roff = L.roff; E.ra = L.ra; E.icnt = L.icnt; E.ioff = L.ioff; E.I = L.I;
+    E.i_cap = L.i_cap; E.err = L.Rt.err;
+    MJ_LAUNCH(prof, "k_star_icount", k_star_icount, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, E);
+    if ((st = launch_scan_u32(prof, L.icnt, S->n, L.scan_part, L.ioff, s))) return st;
+    MJ_LAUNCH(prof, "k_star_expand", k_star_expand, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, E);
+    // join 2: I streamed past T, grouped by A
+    const uint32_t* icol = reinterpret_cast<const uint32_t*>(L.I);
+    return star_group(prof, "k_star_group_i", icol, icol + 1, 2, std::min<uint64_t>(p.join2_size, L.i_cap),
+                      false, a_domain, p, L, count, a_domain, s);
+}
+
 }  // namespace
 
 // =================================================================== API
@@ -855,6 +1022,13 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
             p.pred_log2_join2 = h[0];
             p.pred_log2_out = h[1];
             p.algo = h[3] > h[2] ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
+            // the star plans specialise the two classes when the dimension
+            // relations are small and the model rates them faster
+            if (p.algo == MJ_ALGO_3WAY && p.est_ms_star > 0.0 && p.est_ms_star < p.est_ms_3way)
+                p.algo = MJ_ALGO_STAR;
+            if (p.algo == MJ_ALGO_CASCADE && p.est_ms_star_cascade > 0.0 &&
+                p.est_ms_star_cascade < p.est_ms_cascade)
+                p.algo = MJ_ALGO_STAR_CASCADE;
             if (kind == MJ_TRIANGLE) {            // share classes 1, 4, 16
                 int best = 0;
                 for (int k = 1; k < 3; ++k) if (h[4 + k] > h[4 + best]) best = k;
@@ -868,7 +1042,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;
-        if (kind == MJ_LINEAR && p.algo != MJ_ALGO_3WAY && p.algo != MJ_ALGO_CASCADE)
+        if (p.algo < MJ_ALGO_3WAY || p.algo > (kind == MJ_LINEAR ? MJ_ALGO_STAR_CASCADE : MJ_ALGO_CASCADE))
             return MJ_ERR_INVALID_ARG;
     }
     st = plan_workspace(p);
@@ -888,6 +1062,8 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         p.a_domain != a_domain)
         return MJ_ERR_PLAN_MISMATCH;
     if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
+    if (p.algo == MJ_ALGO_STAR)
+        return run_star3(ctx, R, S, T, a_domain, count, p, ws, ws_bytes, static_cast<hipStream_t>(stream));
     LinearLayout L = linear_layout(nullptr, p);
     if (ws_bytes < L.bytes || (!ws && L.bytes)) return MJ_ERR_WORKSPACE;
     L = linear_layout(ws, p);
@@ -1000,6 +1176,8 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         return MJ_ERR_PLAN_MISMATCH;
     if (kind == MJ_TRIANGLE) return cascade_triangle(ctx, R, S, T, out, p, ws, ws_bytes, stream);
     if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
+    if (p.algo == MJ_ALGO_STAR_CASCADE)
+        return run_star_cascade(ctx, R, S, T, a_domain, out, p, ws, ws_bytes, static_cast<hipStream_t>(stream));
     if (!ws) return MJ_ERR_WORKSPACE;
     CascadeLayout L = cascade_layout(ws, p, ws_bytes);
     if (ws_bytes < L.base_bytes || (p.join2_size && L.i_cap == 0)) return MJ_ERR_WORKSPACE;
@@ -1162,7 +1340,7 @@ int mj_ctx_set_planner(mj_ctx* ctx, const void* params) {
 
 // ------------------------------------------------------------------ batch
 static size_t batch_item_bytes(const mj_batch_item& it) {
-    if (it.plan.algo == MJ_ALGO_CASCADE) return it.plan.workspace_bytes;
+    if (it.plan.algo != MJ_ALGO_3WAY) return it.plan.workspace_bytes;
     if (it.kind == MJ_LINEAR) return linear_layout(nullptr, it.plan).bytes;
     return tri_layout(nullptr, it.plan).bytes;
 }
@@ -1178,6 +1356,10 @@ uint64_t mj_batch_workspace(const mj_batch_item* items, int n) {
            align256(2 * nn * sizeof(TriJoinArgs)) + 2 * align256((2 * nn + 1) * 8) + align256(16);
     return off + 256;
 }
+
+static int run_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                    uint32_t a_domain, uint64_t* out, const mj_plan_t& p, void* ws,
+                    uint64_t ws_bytes, void* stream);
 
 int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uint64_t ws_bytes,
                    void* stream) {
@@ -1211,9 +1393,8 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         const size_t bytes = batch_item_bytes(it);
         off += align256(bytes);
         int st;
-        if (p.algo == MJ_ALGO_CASCADE) {
-            st = mj_cascade2_count(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, &p, wsi,
-                                   bytes, stream);
+        if (p.algo != MJ_ALGO_3WAY) {        // cascades and star plans run their own path
+            st = run_plan(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, p, wsi, bytes, stream);
             if (st) return st;
             continue;
         }
@@ -1290,7 +1471,7 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
 static int run_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                     uint32_t a_domain, uint64_t* out, const mj_plan_t& p, void* ws,
                     uint64_t ws_bytes, void* stream) {
-    if (p.algo == MJ_ALGO_CASCADE)
+    if (p.algo == MJ_ALGO_CASCADE || p.algo == MJ_ALGO_STAR_CASCADE)
         return mj_cascade2_count(ctx, kind, R, S, T, a_domain, out, &p, ws, ws_bytes, stream);
     if (kind == MJ_LINEAR)
         return mj_linear3_count(ctx, R, S, T, a_domain, out, &p, ws, ws_bytes, stream);
@@ -1329,6 +1510,8 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
             mj_plan_t c = base; c.algo = MJ_ALGO_CASCADE; c.log2_nb = nb; c.log2_nc = 9;
             cand.push_back(c);
         }
+        if (base.est_ms_star > 0.0) { mj_plan_t c = base; c.algo = MJ_ALGO_STAR; cand.push_back(c); }
+        if (base.est_ms_star_cascade > 0.0) { mj_plan_t c = base; c.algo = MJ_ALGO_STAR_CASCADE; cand.push_back(c); }
     } else {
         for (uint32_t k = 0; k <= 4; k += 2) {
             mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; c.log2_share = k; cand.push_back(c);
@@ -1394,6 +1577,11 @@ int plan_workspace(mj_plan_t& p) {
             const size_t lin = linear_layout(nullptr, q).bytes;
             const CascadeLayout C = cascade_layout(nullptr, q, 0);
             need = std::max({need, lin, C.base_bytes + C.i_cap * sizeof(uint2) + 256});
+        }
+        // the star plans (planned or tuned only for small R)
+        if (p.n_r <= STAR_PLAN_MAX_R || p.algo == MJ_ALGO_STAR || p.algo == MJ_ALGO_STAR_CASCADE) {
+            need = std::max(need, star_layout(nullptr, p, false).bytes);
+            if (p.join2_size <= STAR_PLAN_MAX_I) need = std::max(need, star_layout(nullptr, p, true).bytes);
         }
         p.workspace_bytes = need;
     } else {

@@ -236,6 +236,112 @@ struct ProbeSumArgs {
 };
 __global__ void k_probe_sum(ProbeSumArgs A);
 
+// ------------------------------------------------------------- star join
+// The linear query when R and T are small dimension relations and S a large
+// fact relation (Sec. 6, star 3-way join): R's and T's tables stay resident
+// (one bucket each, L2-resident at these sizes) and S is streamed once.
+// R's distinct B values get dense ids 0..k-1 (a prefix sum over the
+// occupied slots of its table, the key 0xFFFFFFFF taking the extra slot
+// pool_slots); a workgroup adds mult_T(c) into an LDS array indexed by the
+// id of b when k <= STAR_GROUPS, else into the global array directly.
+constexpr int STAR_THREADS = 512;
+constexpr uint32_t STAR_GROUPS = 4096;     // ids per LDS array (32 KB of u64)
+constexpr uint32_t STAR_NONE = 0xFFFFFFFFu;
+constexpr uint32_t STAR_GRID = 1024;       // most workgroups of a group-by launch
+constexpr uint64_t STAR_ROWS_PER_BLOCK = 16384;
+
+struct StarTable {                 // a one-bucket table of (key, multiplicity) slots
+    const DirEntry* dir;           // [1]
+    const uint2* pool;
+    uint32_t bkt_seed, slot_seed;
+    uint32_t pool_slots;           // the slot of key 0xFFFFFFFF
+};
+
+// ids of a table's occupied slots: occ[i] = 1 for i < cursor holding a key,
+// and for i = pool_slots when key 0xFFFFFFFF occurs
+struct StarOccArgs {
+    StarTable R;
+    const unsigned long long* cursor;
+    uint32_t* occ;                 // [pool_slots + 1]
+};
+__global__ void k_star_occ(StarOccArgs A);
+
+struct StarGroupArgs {
+    const uint32_t* col0;          // (key, c) rows: S as (b, c) or I as (a, c)
+    const uint32_t* col1;
+    int64_t stride;
+    uint64_t n;
+    StarTable T;                   // weights mult_T(c)
+    uint32_t by_rid;               // 1: group id = id of key in R's table; 0: id = key
+    StarTable R;
+    const unsigned long long* rid; // [pool_slots + 2] exclusive prefix of occ
+    uint32_t ngroups_max;          // by_rid = 0: the number of ids (a_domain)
+    unsigned long long* partial;   // [gridDim][STAR_GROUPS] per-block sums (LDS mode)
+    unsigned long long* out;       // [ngroups] global sums (global mode)
+    uint32_t* err;                 // set for an id >= ngroups (key out of range)
+};
+__global__ void k_star_group(StarGroupArgs A);
+
+struct StarReduceArgs {
+    const unsigned long long* partial;
+    uint32_t nblocks;
+    uint32_t by_rid;
+    const unsigned long long* rid;
+    uint32_t pool_slots;
+    uint32_t ngroups_max;
+    unsigned long long* out;       // [ngroups], overwritten (LDS mode) or left (global mode)
+};
+__global__ void k_star_reduce(StarReduceArgs A);
+
+// count[a] += W[id(b)] over R's tuples
+struct StarCountArgs {
+    const uint32_t* col0;
+    const uint32_t* col1;
+    int64_t stride;
+    uint64_t n;
+    StarTable R;
+    const unsigned long long* rid;
+    const unsigned long long* W;
+    unsigned long long* count;
+    uint32_t a_domain;
+    uint32_t* err;
+};
+__global__ void k_star_count(StarCountArgs A);
+
+// Star cascade (binary joins): R grouped by the id of B, I = R |x| S
+// materialised as (a, c) pairs, then I grouped by a with weights mult_T(c).
+struct StarRIndexArgs {            // counting sort of R's A values by id(b)
+    const uint32_t* col0;
+    const uint32_t* col1;
+    int64_t stride;
+    uint64_t n;
+    StarTable R;
+    const unsigned long long* rid;
+    const unsigned long long* roff;  // [k + 1] exclusive prefix of multiplicities
+    uint32_t* rcur;                  // [k] fill cursors (zeroed)
+    uint32_t* ra;                    // [n] A values by id
+};
+__global__ void k_star_rmult(StarRIndexArgs A, uint32_t* mult);   // mult[id] = multiplicity
+__global__ void k_star_rfill(StarRIndexArgs A);
+
+struct StarExpandArgs {
+    const uint32_t* col0;            // S as (b, c)
+    const uint32_t* col1;
+    int64_t stride;
+    uint64_t n;
+    StarTable R;
+    const unsigned long long* rid;
+    const unsigned long long* roff;
+    const uint32_t* ra;
+    uint32_t* icnt;                  // [n] pairs per S tuple (count pass)
+    const unsigned long long* ioff;  // [n + 1] (write pass)
+    uint2* I;                        // (a, c) pairs
+    uint64_t i_cap;                  // pairs I holds; positions beyond are reported
+    uint32_t* err;
+};
+__global__ void k_star_icount(StarExpandArgs A);
+__global__ void k_star_expand(StarExpandArgs A);
+
 // ------------------------------------------------------------- cascade
 constexpr int CAS_THREADS = 512;
 constexpr uint32_t CAS_CAP = 4096;

@@ -15,6 +15,12 @@ struct DeviceModel {
     double list_ps;
 };
 
+// star plans: R's distinct B values must fit one workgroup's LDS array
+// (the kernels' STAR_GROUPS), and the star cascade's intermediate must fit
+// one chunk of the workspace
+constexpr uint64_t STAR_PLAN_MAX_R = 4096;
+constexpr uint64_t STAR_PLAN_MAX_I = uint64_t(1) << 28;
+
 DeviceModel default_model();
 int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m);
 
@@ -29,6 +35,8 @@ double branch_hit_probability(double g3, double d);
 
 double model_linear_3way_ms(const DeviceModel& m, double R, double S, double T);
 double model_linear_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
+double model_star_ms(const DeviceModel& m, double R, double S, double T);
+double model_star_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
 double model_cyclic_ms(const DeviceModel& m, double R, double S, double T, double I, double share);
 double model_cyclic_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
 

@@ -79,6 +79,26 @@ double model_linear_cascade_ms(const DeviceModel& m, double R, double S, double 
     return t * 1e3;
 }
 
+// Star three-way join: one-bucket tables of R's B and T's C (a partition
+// pass and a table build each), one pass over S with two probes of
+// L2-resident tables per tuple, the per-block sums, a pass over R.
+double model_star_ms(const DeviceModel& m, double R, double S, double T) {
+    const double bytes = 8.0 * S + 28.0 * (R + T);
+    const double t = bytes / (m.stream_gbs * 1e9) + 2.0 * S * m.lds_ps * 1e-12 +
+                     16.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
+// Binary star cascade: the same tables, R grouped by B, two passes over S
+// (count, then expand I with a prefix sum between), I written and read
+// (8 B each way per pair) with one probe of T per pair.
+double model_star_cascade_ms(const DeviceModel& m, double R, double S, double T, double I) {
+    const double bytes = 28.0 * S + 16.0 * I + 40.0 * (R + T);
+    const double t = bytes / (m.stream_gbs * 1e9) + (2.0 * S + I) * m.lds_ps * 1e-12 +
+                     26.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
 // Cyclic join: three sorts (8 passes of 24 B/tuple), the run indexes, and
 // the intersection work, bounded by the wedges the cascade would
 // materialise (I); `share` slices hub lists and adds a list search per
@@ -112,6 +132,9 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
         p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
         p.est_ms_3way = model_linear_3way_ms(m, R, S, T);
         p.est_ms_cascade = model_linear_cascade_ms(m, R, S, T, I);
+        p.est_ms_star = p.n_r <= STAR_PLAN_MAX_R ? model_star_ms(m, R, S, T) : 0.0;
+        p.est_ms_star_cascade = p.n_r <= STAR_PLAN_MAX_R && p.join2_size <= STAR_PLAN_MAX_I
+                                    ? model_star_cascade_ms(m, R, S, T, I) : 0.0;
     } else {
         // share on A (the least number of slices of a hub list): the
         // candidate of {1, 2, ..., 32} the time model prefers
@@ -128,6 +151,12 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
         p.est_ms_cascade = model_cyclic_cascade_ms(m, R, S, T, I);
     }
     p.algo = p.est_ms_cascade < p.est_ms_3way ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
+    if (kind == MJ_LINEAR) {
+        // the star plans (when eligible) compete with the one chosen so far
+        double best = std::min(p.est_ms_3way, p.est_ms_cascade);
+        if (p.est_ms_star > 0.0 && p.est_ms_star < best) { p.algo = MJ_ALGO_STAR; best = p.est_ms_star; }
+        if (p.est_ms_star_cascade > 0.0 && p.est_ms_star_cascade < best) p.algo = MJ_ALGO_STAR_CASCADE;
+    }
     return MJ_OK;
 }
 

@@ -60,3 +60,29 @@ def test_null_arguments_rejected_without_device(lib):
     g = lib.mj_plan
     g.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_uint32, ctypes.c_int, vp, vp]
     assert g(None, 0, None, None, None, 0, 0, None, None) == INVALID
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of mj_rel, mj_plan_t and mj_batch_item have the C
+    layout: every field offset and the struct sizes, as a C compiler reads
+    include/mj.h."""
+    import subprocess
+    import paper_1905_13376_amd._lib as L
+    structs = {"mj_rel": L.Rel, "mj_plan_t": L.Plan, "mj_batch_item": L.BatchItem}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mj.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

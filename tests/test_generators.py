@@ -57,3 +57,15 @@ def test_batch_mix():
     for x in inst:
         assert 10 ** 3 - 1 <= x["m"] <= 10 ** 3.5 + 1
         assert x["n"] == max(64, x["m"] // 16)
+
+
+def test_star_schema_shape_and_keys():
+    R, S, T = G.star_schema(n_fact=1 << 16, k_r=512, k_t=256, a_domain=100, seed=9)
+    R2, S2, T2 = G.star_schema(n_fact=1 << 16, k_r=512, k_t=256, a_domain=100, seed=9)
+    assert all(np.array_equal(x, y) for x, y in ((R, R2), (S, S2), (T, T2)))
+    assert R.shape == (512, 2) and S.shape == (1 << 16, 2) and T.shape == (256, 2)
+    assert np.unique(R[:, 1]).size == 512                       # R's B values are keys
+    assert R[:, 0].min() >= 0 and R[:, 0].max() < 100
+    assert T[:, 0].min() >= 0 and T[:, 0].max() < 256 and S[:, 1].max() < 256
+    hit = np.isin(S[:, 0], R[:, 1]).mean()
+    assert abs(hit - 15 / 16) < 0.01                              # fact keys found in R

@@ -249,6 +249,7 @@ def chung_lu_symmetric(n: int, m: int, seed: int, s: float = 1.1,
 LINEAR_SMALL = dict(n=65536, domain=4096, seed=1001, a_domain=4096)
 LINEAR_POWERLAW = dict(n_vertices=1 << 20, m=1 << 24, seed=2001, a_domain=1 << 20)
 TRIANGLE_RMAT = dict(scale=22, m_undirected=1 << 26, seed=3001)
+STAR = dict(n_fact=1 << 26, k_r=4096, k_t=4096, a_domain=1024, seed=5001)
 
 
 def linear_small(seed: int = LINEAR_SMALL["seed"]) -> np.ndarray:
@@ -270,6 +271,34 @@ def triangle_rmat(scale: int = TRIANGLE_RMAT["scale"], m_undirected: int = None,
     """Symmetric simple R-MAT graph as 2*m directed int32 tuples."""
     mu = m_undirected or (16 << scale)
     return rmat_symmetric(scale, mu, seed)
+
+
+def star_schema(n_fact: int = STAR["n_fact"], k_r: int = STAR["k_r"], k_t: int = STAR["k_t"],
+                a_domain: int = STAR["a_domain"], seed: int = STAR["seed"]):
+    """A fact relation S(B, C) of ``n_fact`` tuples with two dimension
+    relations R(A, B) and T(C, D) (the star join's shape, N >> K).
+
+    R: ``k_r`` tuples whose B values are distinct keys drawn from [0, 2^31)
+    and whose A values are uniform in [0, a_domain).  T: ``k_t`` tuples with
+    C uniform in [0, k_t) (a bag: some C values repeat, some are missing)
+    and D uniform in [0, 2^31).  S: each B is one of R's keys (uniformly)
+    with probability 15/16, else a uniform key in [0, 2^31) (almost surely
+    absent from R); each C is uniform in [0, k_t).  Returns int32 arrays
+    (R, S, T) of shape [n, 2]."""
+    g = _rng(seed)
+    keys = np.unique(g.integers(0, 1 << 31, size=2 * k_r + 64, dtype=np.int64))
+    keys = keys[g.permutation(keys.size)][:k_r]
+    R = np.empty((k_r, 2), dtype=np.int32)
+    R[:, 0] = g.integers(0, a_domain, size=k_r)
+    R[:, 1] = keys
+    T = np.empty((k_t, 2), dtype=np.int32)
+    T[:, 0] = g.integers(0, k_t, size=k_t)
+    T[:, 1] = g.integers(0, 1 << 31, size=k_t)
+    S = np.empty((n_fact, 2), dtype=np.int32)
+    hit = g.random(n_fact) < 15.0 / 16.0
+    S[:, 0] = np.where(hit, keys[g.integers(0, k_r, size=n_fact)], g.integers(0, 1 << 31, size=n_fact))
+    S[:, 1] = g.integers(0, k_t, size=n_fact)
+    return R, S, T
 
 
 def batch_instances(count: int = 512, base_seed: int = 4000,
