@@ -207,6 +207,60 @@ def time_call(fn, steps, warmup=1):
     return e0.elapsed_time(e1) / steps
 
 
+def star_path(mj, ctx):
+    """The star join (Sec. 6): a 2^26-tuple fact relation with two 4096-tuple
+    dimension relations, under the plan the planner picks (the star
+    three-way join) and under the star cascade, the partitioned three-way
+    join and the cascade of binary hash joins."""
+    import numpy as np
+    import torch
+    from workloads import generators as G
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import brute
+    log("generating the star schema (2^26 fact tuples, 4096-tuple dimensions)")
+    R, S, T = G.star_schema()
+    a_dom = G.STAR["a_domain"]
+    Rd, Sd, Td = (torch.from_numpy(x).to("cuda") for x in (R, S, T))
+    closed = brute.linear_closed_total(R, S, T)
+    plan = ctx.plan(mj.LINEAR, Rd, Sd, Td, a_dom)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(a_dom, dtype=torch.int64, device="cuda")
+    res = {"planned_algo": int(plan.algo), "fact_tuples": int(S.shape[0]),
+           "est_ms": {"star": round(plan.est_ms_star, 3), "star_cascade": round(plan.est_ms_star_cascade, 3),
+                      "3way": round(plan.est_ms_3way, 3), "cascade": round(plan.est_ms_cascade, 3)}}
+    n_in = R.shape[0] + S.shape[0] + T.shape[0]
+    for name, algo in (("star", mj.ALGO_STAR), ("star_cascade", mj.ALGO_STAR_CASCADE),
+                       ("partitioned_3way", mj.ALGO_3WAY), ("cascade", mj.ALGO_CASCADE)):
+        p = plan.copy()
+        p.algo = algo
+        if algo in (mj.ALGO_STAR, mj.ALGO_3WAY):
+            fn = lambda: ctx.linear3_count(Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
+        else:
+            fn = lambda: ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
+        ctx.profile(True)
+        ctx.profile_read()
+        ms = time_call(fn, 5)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ok = int(mj.as_u64(cnt).sum(dtype=np.uint64)) == closed
+        kern = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+        ent = {"ms": round(ms, 4), "tuples_per_s": n_in / (ms * 1e-3), "sum_equals_closed_form": ok,
+               "kernels_us": {k: round(v * 1e3, 1) for k, v in sorted(kern.items(), key=lambda kv: -kv[1])[:6]}}
+        if name == "star" and "k_star_group" in kern:
+            us = kern["k_star_group"] * 1e3
+            nbytes = 8 * S.shape[0]                      # the fact relation, read once
+            ach = nbytes / (us * 1e-6) / 1e9
+            ent["roofline"] = {"bound": "hbm", "kernel": "k_star_group", "achieved": round(ach, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                               "algorithmic_bytes": nbytes, "avg_launch_us": round(us, 2)}
+        res[name] = ent
+        log(f"star schema, {name}: {ms:.3f} ms, sum ok {ok}")
+    res["speedup_star_over_star_cascade"] = round(res["star_cascade"]["ms"] / res["star"]["ms"], 2)
+    res["speedup_star_over_partitioned"] = round(res["partitioned_3way"]["ms"] / res["star"]["ms"], 2)
+    del ws, Rd, Sd, Td
+    return res
+
+
 def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     """The other paths of the method, each on its own workload."""
     import numpy as np
@@ -236,6 +290,7 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     out["linear_small"] = {"ms_3way": round(ms_s, 4), "ms_cascade": round(ms_sc, 4),
                            "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3)}
     del ws
+    out["star"] = star_path(mj, ctx)
     # cyclic join on the R-MAT scale-22 graph, shares 1 / 4 / 16 (Sec. 5)
     log("generating R-MAT scale 22 (2^26 undirected edges)")
     E = G.triangle_rmat()

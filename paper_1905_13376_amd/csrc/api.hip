@@ -681,8 +681,10 @@ struct StarLayout {
     TableLayout Rt, Tt;               // one-bucket tables: R on B, T on C
     uint32_t* occ;                    // [R slots + 1]
     unsigned long long* rid;          // [R slots + 2] ids of R's B values
-    unsigned long long* partial;      // [STAR_GRID][STAR_GROUPS] per-block sums
-    unsigned long long* W;            // [n_r + 1] per-B sums
+    uint2* idtab;                     // [R slots] (key, id)
+    unsigned long long* partial;      // per-block sums (both group-bys)
+    unsigned long long* W;            // [w_len] per-B sums, by id of b
+    uint64_t w_len;
     unsigned long long* scan_part;
     // binary star cascade
     uint32_t* mult;                   // [n_r + 1] multiplicity per id
@@ -704,8 +706,10 @@ StarLayout star_layout(void* ws, const mj_plan_t& p, bool cascade) {
     const uint64_t slots = L.Rt.pool_slots;
     L.occ = B.take<uint32_t>(slots + 1);
     L.rid = B.take<unsigned long long>(slots + 2);
-    L.partial = B.take<unsigned long long>(uint64_t(STAR_GRID) * STAR_GROUPS);
-    L.W = B.take<unsigned long long>(p.n_r + 1);
+    L.idtab = B.take<uint2>(std::max<uint64_t>(slots, 1));
+    L.partial = B.take<unsigned long long>(uint64_t(STAR_GRID) * STAR_STRIDE);
+    L.w_len = p.n_r + 1;
+    L.W = B.take<unsigned long long>(L.w_len);
     const uint64_t nmax = std::max<uint64_t>({slots + 2, p.n_s + 1, p.n_r + 2});
     L.scan_part = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
     if (cascade) {
@@ -744,31 +748,42 @@ int star_prepare(Prof* prof, const mj_rel& R, const mj_rel& T, const mj_plan_t& 
     O.cursor = L.Rt.pool_cursor; O.occ = L.occ;
     const uint64_t slots = L.Rt.pool_slots;
     MJ_LAUNCH(prof, "k_star_occ", k_star_occ, dim3(grid_for(slots + 1, 256, 4096)), dim3(256), 0, s, O);
-    return launch_scan_u32(prof, L.occ, slots + 1, L.scan_part, L.rid, s);
+    if ((st = launch_scan_u32(prof, L.occ, slots + 1, L.scan_part, L.rid, s))) return st;
+    StarIdArgs I;
+    I.R = O.R; I.rid = L.rid; I.idtab = L.idtab;
+    MJ_LAUNCH(prof, "k_star_ids", k_star_ids, dim3(grid_for(slots, 256, 4096)), dim3(256), 0, s, I);
+    return MJ_OK;
 }
 
-// group-by of (key, c) rows weighted by mult_T(c): W per id of B (by_rid) or
-// counts per A; `out` receives the sums
+uint32_t star_grid_cu(uint64_t n, int num_cu) {       // one workgroup per CU at most
+    return std::min<uint32_t>(star_grid(n), (uint32_t)std::max(num_cu, 1));
+}
+
+// group-by of (key, c) rows weighted by mult_T(c): by B (S, into W per id of
+// b) or by A (I, into the counts); `out` receives the sums
 int star_group(Prof* prof, const char* name, const uint32_t* col0, const uint32_t* col1,
-               int64_t stride, uint64_t n, bool by_rid, uint32_t ngroups_max, const mj_plan_t& p,
-               const StarLayout& L, unsigned long long* out, uint64_t out_len, hipStream_t s) {
-    // zeroed first: the LDS mode overwrites, the global mode adds
+               int64_t stride, uint64_t n, bool by_b, uint32_t ngroups_max, int num_cu,
+               const mj_plan_t& p, const StarLayout& L, unsigned long long* out, uint64_t out_len,
+               hipStream_t s) {
+    // zeroed first: the LDS modes overwrite, the global modes add
     if (out_len)
         MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(out_len, 256, 4096)), dim3(256), 0, s,
                   out, out_len, 0ull);
-    const uint32_t grid = star_grid(n);
     StarGroupArgs G;
     G.col0 = col0; G.col1 = col1; G.stride = stride; G.n = n;
     G.T = star_table(L.Tt, seed_c(p), seed_slot(p));
-    G.by_rid = by_rid ? 1u : 0u;
     G.R = star_table(L.Rt, seed_b(p), seed_slot(p));
-    G.rid = L.rid; G.ngroups_max = ngroups_max;
+    G.idtab = L.idtab; G.rid = L.rid; G.ngroups_max = ngroups_max;
     G.partial = L.partial; G.out = out; G.err = L.Rt.err;
-    MJ_LAUNCH(prof, name, k_star_group, dim3(grid), dim3(STAR_THREADS), 0, s, G);
+    const uint32_t grid = star_grid_cu(n, num_cu);
+    if (by_b) MJ_LAUNCH(prof, name, k_star_group_b, dim3(grid), dim3(STAR_THREADS), 0, s, G);
+    else MJ_LAUNCH(prof, name, k_star_group_a, dim3(grid), dim3(STAR_THREADS), 0, s, G);
     StarReduceArgs Rd;
-    Rd.partial = L.partial; Rd.nblocks = grid; Rd.by_rid = G.by_rid; Rd.rid = L.rid;
-    Rd.pool_slots = G.R.pool_slots; Rd.ngroups_max = ngroups_max; Rd.out = out;
-    MJ_LAUNCH(prof, "k_star_reduce", k_star_reduce, dim3(STAR_GROUPS / 256), dim3(256), 0, s, Rd);
+    Rd.partial = L.partial; Rd.nblocks = grid; Rd.by_b = by_b ? 1u : 0u;
+    Rd.rdir = L.Rt.dir; Rd.tdir = L.Tt.dir; Rd.rid = L.rid; Rd.pool_slots = G.R.pool_slots;
+    Rd.ngroups_max = ngroups_max; Rd.out = out;
+    MJ_LAUNCH(prof, "k_star_reduce", k_star_reduce, dim3((STAR_STRIDE + 63) / 64), dim3(STAR_REDUCE_THREADS),
+              0, s, Rd);
     return MJ_OK;
 }
 
@@ -787,8 +802,8 @@ int run_star3(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, ui
     int st;
     if ((st = star_prepare(prof, *R, *T, p, L, s))) return st;
     // W[id(b)] = sum of mult_T(c) over S, one pass over the fact relation
-    if ((st = star_group(prof, "k_star_group", S->col0, S->col1, S->stride, S->n, true, 0, p, L,
-                         L.W, p.n_r + 1, s))) return st;
+    if ((st = star_group(prof, "k_star_group_b", S->col0, S->col1, S->stride, S->n, true, 0, ctx->num_cu,
+                         p, L, L.W, L.w_len, s))) return st;
     StarCountArgs C;
     C.col0 = R->col0; C.col1 = R->col1; C.stride = R->stride; C.n = R->n;
     C.R = star_table(L.Rt, seed_b(p), seed_slot(p)); C.rid = L.rid; C.W = L.W;
@@ -830,15 +845,17 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     // join 1: S streamed, I = R |x| S written as (a, c) pairs
     StarExpandArgs E;
     E.col0 = S->col0; E.col1 = S->col1; E.stride = S->stride; E.n = S->n;
-    E.R = X.R; E.rid = L.rid; E.roff = L.roff; E.ra = L.ra; E.icnt = L.icnt; E.ioff = L.ioff; E.I = L.I;
+    E.R = X.R; E.idtab = L.idtab; E.rid = L.rid; E.roff = L.roff; E.ra = L.ra; E.icnt = L.icnt;
+    E.ioff = L.ioff; E.I = L.I;
     E.i_cap = L.i_cap; E.err = L.Rt.err;
-    MJ_LAUNCH(prof, "k_star_icount", k_star_icount, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, E);
+    const uint32_t g1 = star_grid_cu(S->n, ctx->num_cu);
+    MJ_LAUNCH(prof, "k_star_icount", k_star_icount, dim3(g1), dim3(STAR_THREADS), 0, s, E);
     if ((st = launch_scan_u32(prof, L.icnt, S->n, L.scan_part, L.ioff, s))) return st;
-    MJ_LAUNCH(prof, "k_star_expand", k_star_expand, dim3(grid_for(S->n, 256, 16384)), dim3(256), 0, s, E);
+    MJ_LAUNCH(prof, "k_star_expand", k_star_expand, dim3(g1), dim3(STAR_THREADS), 0, s, E);
     // join 2: I streamed past T, grouped by A
     const uint32_t* icol = reinterpret_cast<const uint32_t*>(L.I);
     return star_group(prof, "k_star_group_i", icol, icol + 1, 2, std::min<uint64_t>(p.join2_size, L.i_cap),
-                      false, a_domain, p, L, count, a_domain, s);
+                      false, a_domain, ctx->num_cu, p, L, count, a_domain, s);
 }
 
 }  // namespace

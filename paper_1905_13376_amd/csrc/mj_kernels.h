@@ -238,17 +238,23 @@ __global__ void k_probe_sum(ProbeSumArgs A);
 
 // ------------------------------------------------------------- star join
 // The linear query when R and T are small dimension relations and S a large
-// fact relation (Sec. 6, star 3-way join): R's and T's tables stay resident
-// (one bucket each, L2-resident at these sizes) and S is streamed once.
-// R's distinct B values get dense ids 0..k-1 (a prefix sum over the
-// occupied slots of its table, the key 0xFFFFFFFF taking the extra slot
-// pool_slots); a workgroup adds mult_T(c) into an LDS array indexed by the
-// id of b when k <= STAR_GROUPS, else into the global array directly.
-constexpr int STAR_THREADS = 512;
-constexpr uint32_t STAR_GROUPS = 4096;     // ids per LDS array (32 KB of u64)
+// fact relation (Sec. 6, star 3-way join): R's and T's tables (one bucket
+// each) are held on chip -- copied into every workgroup's LDS while each has
+// at most STAR_LDS_SLOTS slots -- and S is streamed once.  R's distinct B
+// values are numbered 0..k-1 (a prefix sum over the occupied slots of its
+// table, the key 0xFFFFFFFF taking the extra slot pool_slots); the pass over
+// S adds mult_T(c) per number in LDS and each workgroup writes its sums once.
+// Tables too large for LDS are probed in L2 and the sums go to global
+// memory.  The star cascade materialises I = R |x| S and groups it by A.
+constexpr int STAR_THREADS = 1024;         // one workgroup per CU
+constexpr int STAR_REDUCE_THREADS = 1024;  // 64 groups x 16 rows of per-block sums
+constexpr uint32_t STAR_LDS_SLOTS = 8192;  // table slots held in LDS
+constexpr uint32_t STAR_GROUPS = 4096;     // A values per LDS array (the cascade)
+constexpr uint32_t STAR_STRIDE = STAR_LDS_SLOTS / 2 + 1;   // sums per workgroup (ids, or A values)
 constexpr uint32_t STAR_NONE = 0xFFFFFFFFu;
-constexpr uint32_t STAR_GRID = 1024;       // most workgroups of a group-by launch
+constexpr uint32_t STAR_GRID = 1024;       // most workgroups of a launch
 constexpr uint64_t STAR_ROWS_PER_BLOCK = 16384;
+static_assert(STAR_GROUPS < STAR_STRIDE, "the cascade's sums fit a workgroup's stride");
 
 struct StarTable {                 // a one-bucket table of (key, multiplicity) slots
     const DirEntry* dir;           // [1]
@@ -257,8 +263,8 @@ struct StarTable {                 // a one-bucket table of (key, multiplicity) 
     uint32_t pool_slots;           // the slot of key 0xFFFFFFFF
 };
 
-// ids of a table's occupied slots: occ[i] = 1 for i < cursor holding a key,
-// and for i = pool_slots when key 0xFFFFFFFF occurs
+// occ[i] = 1 for i < cursor holding a key, and for i = pool_slots when key
+// 0xFFFFFFFF occurs
 struct StarOccArgs {
     StarTable R;
     const unsigned long long* cursor;
@@ -266,30 +272,44 @@ struct StarOccArgs {
 };
 __global__ void k_star_occ(StarOccArgs A);
 
+// idtab[slot] = (key, id) for the occupied slots of R's table (same
+// positions, so a probe of idtab with the table's hash yields the id)
+struct StarIdArgs {
+    StarTable R;
+    const unsigned long long* rid;
+    uint2* idtab;                  // [pool_slots]
+};
+__global__ void k_star_ids(StarIdArgs A);
+
 struct StarGroupArgs {
     const uint32_t* col0;          // (key, c) rows: S as (b, c) or I as (a, c)
     const uint32_t* col1;
     int64_t stride;
     uint64_t n;
     StarTable T;                   // weights mult_T(c)
-    uint32_t by_rid;               // 1: group id = id of key in R's table; 0: id = key
-    StarTable R;
+    StarTable R;                   // grouping by B: R's table
+    const uint2* idtab;            // (key, id) slots of R's table
     const unsigned long long* rid; // [pool_slots + 2] exclusive prefix of occ
-    uint32_t ngroups_max;          // by_rid = 0: the number of ids (a_domain)
-    unsigned long long* partial;   // [gridDim][STAR_GROUPS] per-block sums (LDS mode)
-    unsigned long long* out;       // [ngroups] global sums (global mode)
-    uint32_t* err;                 // set for an id >= ngroups (key out of range)
+    uint32_t ngroups_max;          // grouping by A: a_domain
+    unsigned long long* partial;   // [gridDim][STAR_STRIDE] per-block sums (LDS modes)
+    unsigned long long* out;       // global sums (global modes)
+    uint32_t* err;                 // set for an A value >= a_domain
 };
-__global__ void k_star_group(StarGroupArgs A);
+// by B (the star three-way join's pass over S): sums per id of b
+__global__ void k_star_group_b(StarGroupArgs A);
+// by A value (the star cascade's second join): sums per a
+__global__ void k_star_group_a(StarGroupArgs A);
 
 struct StarReduceArgs {
     const unsigned long long* partial;
     uint32_t nblocks;
-    uint32_t by_rid;
+    uint32_t by_b;                 // 1: per id of b (when both tables were in LDS); 0: per a
+    const DirEntry* rdir;
+    const DirEntry* tdir;
     const unsigned long long* rid;
-    uint32_t pool_slots;
-    uint32_t ngroups_max;
-    unsigned long long* out;       // [ngroups], overwritten (LDS mode) or left (global mode)
+    uint32_t pool_slots;           // R's
+    uint32_t ngroups_max;          // by A: a_domain
+    unsigned long long* out;       // overwritten (LDS modes) or left (global modes)
 };
 __global__ void k_star_reduce(StarReduceArgs A);
 
@@ -330,6 +350,7 @@ struct StarExpandArgs {
     int64_t stride;
     uint64_t n;
     StarTable R;
+    const uint2* idtab;
     const unsigned long long* rid;
     const unsigned long long* roff;
     const uint32_t* ra;

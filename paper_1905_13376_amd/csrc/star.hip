@@ -4,15 +4,18 @@
 // T on chip and streams S once past them; no partitioning of S is needed.
 //
 // On MI355X the dimension tables are one-bucket multiplicity tables (built
-// by the partitioner and k_dbuild of the linear path) that stay L2-resident,
-// and streaming S is a group-by on B weighted by mult_T(C):
+// by the partitioner and k_dbuild of the linear path), and streaming S is a
+// group-by on B weighted by mult_T(C):
 //   W[b] = sum over s(b, c) in S of mult_T(c),   count[a] = sum over r(a, b) of W[b].
 // R's distinct B values are numbered 0..k-1 (a prefix sum over the occupied
-// slots of R's table), so a workgroup can keep W in an LDS array indexed by
-// that number when k <= STAR_GROUPS; each workgroup then writes its sums
-// once and k_star_reduce adds them up.  With more groups the sums go to the
-// global array with atomics (correct at any size; the planner only picks the
-// star plans when the groups fit LDS).
+// slots of R's table).  "On chip" is each workgroup's LDS: one workgroup
+// per CU copies T's table and R's (key, number) table there, streams its
+// contiguous chunk of S, adds the weights per number in LDS and writes its
+// sums once; k_star_reduce adds them up.  A random read of an L2-resident
+// table costs about as much as a whole streamed tuple at these rates, which
+// is why both tables are copied.  Tables larger than the LDS copies are
+// probed in L2 and the sums go to global memory (exact at any size; the
+// planner only picks the star plans for small R).
 //
 // The binary star cascade materialises I = R |x| S as (a, c) pairs (R
 // grouped by B with a counting sort, one prefix sum over S for the output
@@ -36,16 +39,17 @@ __device__ __forceinline__ uint32_t star_slot(const StarTable& T, uint32_t key) 
     }
 }
 
-// multiplicity of `key` in a one-bucket table (0 when absent)
-__device__ __forceinline__ uint32_t star_mult(const StarTable& T, uint32_t key) {
-    const DirEntry e = T.dir[0];
-    if (key == EMPTY_KEY) return e.special;
+// id of `key` through R's (key, id) table in global memory, or STAR_NONE
+__device__ __forceinline__ uint32_t star_id(const StarTable& R, const uint2* idtab,
+                                            const unsigned long long* rid, uint32_t key) {
+    const DirEntry e = R.dir[0];
+    if (key == EMPTY_KEY) return e.special ? (uint32_t)rid[R.pool_slots] : STAR_NONE;
     const uint32_t mask = (1u << e.log2cap) - 1u;
-    uint32_t s = slot_hash(key, T.slot_seed) & mask;
+    uint32_t s = slot_hash(key, R.slot_seed) & mask;
     while (true) {
-        const uint2 kv = T.pool[e.offset + s];
+        const uint2 kv = idtab[e.offset + s];
         if (kv.x == key) return kv.y;
-        if (kv.x == EMPTY_KEY) return 0u;
+        if (kv.x == EMPTY_KEY) return STAR_NONE;
         s = (s + 1u) & mask;
     }
 }
@@ -56,6 +60,128 @@ __device__ __forceinline__ uint2 star_row(const uint32_t* col0, const uint32_t* 
     if (stride == 2 && col1 == col0 + 1 && (reinterpret_cast<uintptr_t>(col0) & 7) == 0)
         return reinterpret_cast<const uint2*>(col0)[i];
     return make_uint2(ld_col(col0, i, stride), ld_col(col1, i, stride));
+}
+
+// rows [beg, end) of this workgroup's contiguous chunk
+__device__ __forceinline__ void star_chunk(uint64_t n, uint64_t& beg, uint64_t& end) {
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    beg = uint64_t(blockIdx.x) * per;
+    end = min<uint64_t>(n, beg + per);
+}
+
+// STAR_U lookups in a one-bucket table in global memory at once: the
+// first-slot loads are in flight together and only colliding keys walk
+// further.  `tab` holds (key, value) slots; an absent key gives `none`, key
+// 0xFFFFFFFF gives `special`.
+#ifndef MJ_STAR_U
+#define MJ_STAR_U 4
+#endif
+constexpr int STAR_U = MJ_STAR_U;   // rows per thread per step
+__device__ __forceinline__ void star_lookup4(const DirEntry& e, const uint2* __restrict__ tab,
+                                             uint32_t slot_seed, const uint32_t (&key)[STAR_U],
+                                             const bool (&live)[STAR_U], uint32_t none,
+                                             uint32_t special, uint32_t (&out)[STAR_U]) {
+    const uint32_t mask = (1u << e.log2cap) - 1u;
+    const uint2* base = tab + e.offset;
+    uint32_t s[STAR_U];
+    uint2 kv[STAR_U];
+#pragma unroll
+    for (int u = 0; u < STAR_U; ++u) {
+        s[u] = slot_hash(key[u], slot_seed) & mask;
+        kv[u] = live[u] && key[u] != EMPTY_KEY ? base[s[u]] : make_uint2(EMPTY_KEY, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < STAR_U; ++u) {
+        if (!live[u]) { out[u] = none; continue; }
+        if (key[u] == EMPTY_KEY) { out[u] = special; continue; }
+        uint2 v = kv[u];
+        uint32_t t = s[u];
+        while (v.x != key[u] && v.x != EMPTY_KEY) {
+            t = (t + 1u) & mask;
+            v = base[t];
+        }
+        out[u] = v.x == key[u] ? v.y : none;
+    }
+}
+
+// LDS copies of the dimension tables: STAR_LDS_SLOTS packed (key, value)
+// slots, rebuilt by every workgroup from a table region with a cheaper
+// hash than the global tables' (one multiply; a poor spread only lengthens
+// probes).  Every table copied holds at most STAR_LDS_SLOTS / 2 keys.
+__device__ __forceinline__ uint32_t lds_hash(uint32_t key) {
+    uint32_t h = key * 0x9E3779B1u;
+    return h ^ (h >> 15);
+}
+
+__device__ __forceinline__ void lds_build(uint2* tab, const uint2* region, uint32_t cap) {
+    constexpr uint32_t mask = STAR_LDS_SLOTS - 1u;
+    for (uint32_t s = threadIdx.x; s < STAR_LDS_SLOTS; s += blockDim.x) tab[s] = make_uint2(EMPTY_KEY, 0u);
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < cap; s += blockDim.x) {
+        const uint2 kv = region[s];
+        if (kv.x == EMPTY_KEY) continue;
+        uint32_t h = lds_hash(kv.x) & mask;
+        while (atomicCAS(&tab[h].x, EMPTY_KEY, kv.x) != EMPTY_KEY) h = (h + 1u) & mask;   // keys are distinct
+        tab[h].y = kv.y;
+    }
+}
+
+// STAR_U LDS lookups at once: every row's first slot is read together (a
+// hit or an empty slot costs one round trip), collisions walk further.
+__device__ __forceinline__ void lds_get4(const uint2* tab, const uint32_t (&key)[STAR_U],
+                                         const bool (&live)[STAR_U], uint32_t none, uint32_t special,
+                                         uint32_t (&out)[STAR_U]) {
+    constexpr uint32_t mask = STAR_LDS_SLOTS - 1u;
+    uint32_t h[STAR_U];
+    uint2 kv[STAR_U];
+#pragma unroll
+    for (int u = 0; u < STAR_U; ++u) {
+        h[u] = lds_hash(key[u]) & mask;
+        kv[u] = tab[h[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < STAR_U; ++u) {
+        if (!live[u]) { out[u] = none; continue; }
+        if (key[u] == EMPTY_KEY) { out[u] = special; continue; }
+        uint2 v = kv[u];
+        uint32_t t = h[u];
+        while (v.x != key[u] && v.x != EMPTY_KEY) { t = (t + 1u) & mask; v = tab[t]; }
+        out[u] = v.x == key[u] ? v.y : none;
+    }
+}
+
+// The rows of this workgroup's chunk, STAR_U per thread per step, with the
+// next step's rows loaded before the current ones are processed.
+template <typename F>
+__device__ __forceinline__ void star_stream(const uint32_t* col0, const uint32_t* col1, int64_t stride,
+                                            uint64_t n, F&& body) {
+    uint64_t beg, end;
+    star_chunk(n, beg, end);
+    const uint64_t nthr = blockDim.x, step = STAR_U * nthr;
+    uint2 cur[STAR_U], nxt[STAR_U];
+#pragma unroll
+    for (int u = 0; u < STAR_U; ++u) {
+        const uint64_t idx = beg + threadIdx.x + u * nthr;
+        cur[u] = idx < end ? star_row(col0, col1, stride, idx) : make_uint2(0u, 0u);
+    }
+    for (uint64_t q = beg + threadIdx.x; q < end; q += step) {
+#pragma unroll
+        for (int u = 0; u < STAR_U; ++u) {
+            const uint64_t idx = q + step + u * nthr;
+            nxt[u] = idx < end ? star_row(col0, col1, stride, idx) : make_uint2(0u, 0u);
+        }
+        uint32_t key[STAR_U], c[STAR_U];
+        bool live[STAR_U];
+#pragma unroll
+        for (int u = 0; u < STAR_U; ++u) {
+            live[u] = q + u * nthr < end;
+            key[u] = cur[u].x;
+            c[u] = cur[u].y;
+        }
+        body(q, key, c, live);
+#pragma unroll
+        for (int u = 0; u < STAR_U; ++u) cur[u] = nxt[u];
+    }
 }
 
 __global__ void k_star_occ(StarOccArgs A) {
@@ -69,63 +195,132 @@ __global__ void k_star_occ(StarOccArgs A) {
     }
 }
 
-// Group-by of a stream of (key, c) rows, weight mult_T(c).  Each workgroup
-// takes one contiguous chunk of the rows (coalesced reads, four rows per
-// thread in flight).
+__global__ void k_star_ids(StarIdArgs A) {
+    const uint32_t ps = A.R.pool_slots;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ps;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const bool occ = A.rid[i + 1] != A.rid[i];
+        A.idtab[i] = make_uint2(occ ? A.R.pool[i].x : EMPTY_KEY, occ ? (uint32_t)A.rid[i] : 0u);
+    }
+}
+
+// Group-by of S = (b, c) rows by B, weight mult_T(c): the star three-way
+// join's one pass over the fact relation.
 __global__ void __launch_bounds__(STAR_THREADS)
-k_star_group(StarGroupArgs A) {
-    __shared__ unsigned long long acc[STAR_GROUPS];
-    const uint32_t ngroups = A.by_rid ? (uint32_t)A.rid[A.R.pool_slots + 1] : A.ngroups_max;
-    const bool local = ngroups <= STAR_GROUPS;           // uniform over the launch
+k_star_group_b(StarGroupArgs A) {
+    __shared__ uint2 ttab[STAR_LDS_SLOTS];
+    __shared__ uint2 rtab[STAR_LDS_SLOTS];
+    __shared__ unsigned long long acc[STAR_LDS_SLOTS / 2];
+    const DirEntry re = A.R.dir[0];
+    const DirEntry te = A.T.dir[0];
+    const uint32_t rcap = 1u << re.log2cap, tcap = 1u << te.log2cap;
+    const uint32_t k = (uint32_t)A.rid[A.R.pool_slots + 1];
+    // both tables (and the k sums) in LDS; uniform over the launch
+    const bool lds = rcap <= STAR_LDS_SLOTS && tcap <= STAR_LDS_SLOTS && k <= STAR_LDS_SLOTS / 2;
+    const uint32_t rspecial = re.special ? (uint32_t)A.rid[A.R.pool_slots] : STAR_NONE;
     const int nthr = blockDim.x;
+    if (lds) {
+        lds_build(ttab, A.T.pool + te.offset, tcap);
+        lds_build(rtab, A.idtab + re.offset, rcap);
+        for (uint32_t i = threadIdx.x; i < k; i += nthr) acc[i] = 0;
+    }
+    __syncthreads();
+    star_stream(A.col0, A.col1, A.stride, A.n,
+                [&](uint64_t, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
+                    const bool (&live)[STAR_U]) {
+        uint32_t w[STAR_U], id[STAR_U];
+        bool need[STAR_U];
+        if (lds) {
+            lds_get4(ttab, c, live, 0u, te.special, w);
+#pragma unroll
+            for (int u = 0; u < STAR_U; ++u) need[u] = w[u] != 0;
+            lds_get4(rtab, key, need, STAR_NONE, rspecial, id);
+#pragma unroll
+            for (int u = 0; u < STAR_U; ++u)                 // an absent b is not in R
+                if (id[u] != STAR_NONE) atomicAdd(&acc[id[u]], (unsigned long long)w[u]);
+        } else {
+            star_lookup4(te, A.T.pool, A.T.slot_seed, c, live, 0u, te.special, w);
+#pragma unroll
+            for (int u = 0; u < STAR_U; ++u) need[u] = w[u] != 0;
+            star_lookup4(re, A.idtab, A.R.slot_seed, key, need, STAR_NONE, rspecial, id);
+#pragma unroll
+            for (int u = 0; u < STAR_U; ++u)
+                if (id[u] != STAR_NONE) atomicAdd(&A.out[id[u]], (unsigned long long)w[u]);
+        }
+    });
+    __syncthreads();
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < k; i += nthr)
+            A.partial[uint64_t(blockIdx.x) * STAR_STRIDE + i] = acc[i];
+}
+
+// Group-by of (a, c) rows by A value, weight mult_T(c): the star cascade's
+// second join.  T's table in LDS when it fits, the sums in LDS while
+// a_domain <= STAR_GROUPS.
+__global__ void __launch_bounds__(STAR_THREADS)
+k_star_group_a(StarGroupArgs A) {
+    __shared__ uint2 ttab[STAR_LDS_SLOTS];
+    __shared__ unsigned long long acc[STAR_GROUPS];
+    const DirEntry te = A.T.dir[0];
+    const uint32_t tcap = 1u << te.log2cap;
+    const bool tlds = tcap <= STAR_LDS_SLOTS;            // uniform over the launch
+    const uint32_t ngroups = A.ngroups_max;
+    const bool local = ngroups <= STAR_GROUPS;
+    const int nthr = blockDim.x;
+    if (tlds) lds_build(ttab, A.T.pool + te.offset, tcap);
     if (local)
         for (uint32_t i = threadIdx.x; i < ngroups; i += nthr) acc[i] = 0;
     __syncthreads();
-    const uint64_t per = (A.n + gridDim.x - 1) / gridDim.x;
-    const uint64_t beg = uint64_t(blockIdx.x) * per;
-    const uint64_t end = min<uint64_t>(A.n, beg + per);
-    for (uint64_t q = beg + threadIdx.x; q < end; q += 4 * (uint64_t)nthr) {
-        uint2 row[4];
-        uint32_t w[4];
+    star_stream(A.col0, A.col1, A.stride, A.n,
+                [&](uint64_t, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
+                    const bool (&live)[STAR_U]) {
+        uint32_t w[STAR_U];
+        if (tlds) lds_get4(ttab, c, live, 0u, te.special, w);
+        else star_lookup4(te, A.T.pool, A.T.slot_seed, c, live, 0u, te.special, w);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t idx = q + u * (uint64_t)nthr;
-            row[u] = idx < end ? star_row(A.col0, A.col1, A.stride, idx) : make_uint2(0u, 0u);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            w[u] = q + u * (uint64_t)nthr < end ? star_mult(A.T, row[u].y) : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < STAR_U; ++u) {
             if (w[u] == 0) continue;
-            uint32_t id;
-            if (A.by_rid) {
-                const uint32_t sl = star_slot(A.R, row[u].x);
-                if (sl == STAR_NONE) continue;                   // b not in R
-                id = (uint32_t)A.rid[sl];
-            } else {
-                id = row[u].x;
-            }
-            if (id >= ngroups) { atomicExch(A.err, 1u); continue; }
-            if (local) atomicAdd(&acc[id], (unsigned long long)w[u]);
-            else atomicAdd(&A.out[id], (unsigned long long)w[u]);
+            if (key[u] >= ngroups) { atomicExch(A.err, 1u); continue; }
+            if (local) atomicAdd(&acc[key[u]], (unsigned long long)w[u]);
+            else atomicAdd(&A.out[key[u]], (unsigned long long)w[u]);
         }
-    }
+    });
     __syncthreads();
     if (local)
         for (uint32_t i = threadIdx.x; i < ngroups; i += nthr)
-            A.partial[uint64_t(blockIdx.x) * STAR_GROUPS + i] = acc[i];
+            A.partial[uint64_t(blockIdx.x) * STAR_STRIDE + i] = acc[i];
 }
 
-// out[id] = sum over blocks of partial[block][id] (LDS mode only)
-__global__ void k_star_reduce(StarReduceArgs A) {
-    const uint32_t ngroups = A.by_rid ? (uint32_t)A.rid[A.pool_slots + 1] : A.ngroups_max;
-    if (ngroups > STAR_GROUPS) return;                  // the sums are already global
-    for (uint32_t id = blockIdx.x * blockDim.x + threadIdx.x; id < ngroups;
-         id += gridDim.x * blockDim.x) {
+// out[g] = sum over blocks of partial[block][g] (LDS modes only): a block
+// takes 64 groups, its 16 rows of threads each sum every 16th block's
+// partials (64 consecutive groups per load), then the rows are added in LDS.
+__global__ void __launch_bounds__(STAR_REDUCE_THREADS)
+k_star_reduce(StarReduceArgs A) {
+    __shared__ unsigned long long part[STAR_REDUCE_THREADS / 64][64];
+    uint32_t ngroups;
+    if (A.by_b) {
+        const bool lds = (1u << A.rdir[0].log2cap) <= STAR_LDS_SLOTS &&
+                         (1u << A.tdir[0].log2cap) <= STAR_LDS_SLOTS;
+        ngroups = lds ? (uint32_t)A.rid[A.pool_slots + 1] : 0u;
+    } else {
+        ngroups = A.ngroups_max <= STAR_GROUPS ? A.ngroups_max : 0u;
+    }
+    constexpr uint32_t ROWS = STAR_REDUCE_THREADS / 64;
+    const uint32_t col = threadIdx.x & 63u, row = threadIdx.x >> 6;
+    for (uint32_t g0 = blockIdx.x * 64; g0 < ngroups; g0 += gridDim.x * 64) {
+        const uint32_t g = g0 + col;
         unsigned long long s = 0;
-        for (uint32_t b = 0; b < A.nblocks; ++b) s += A.partial[uint64_t(b) * STAR_GROUPS + id];
-        A.out[id] = s;
+        if (g < ngroups)
+            for (uint32_t b = row; b < A.nblocks; b += ROWS) s += A.partial[uint64_t(b) * STAR_STRIDE + g];
+        part[row][col] = s;
+        __syncthreads();
+        if (row == 0 && g < ngroups) {
+            unsigned long long t = 0;
+#pragma unroll
+            for (uint32_t r = 0; r < ROWS; ++r) t += part[r][col];
+            A.out[g] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -164,30 +359,62 @@ __global__ void k_star_rfill(StarRIndexArgs A) {
     }
 }
 
-__global__ void k_star_icount(StarExpandArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint2 s = star_row(A.col0, A.col1, A.stride, i);
-        const uint32_t sl = star_slot(A.R, s.x);
-        uint32_t c = 0;
-        if (sl != STAR_NONE) {
-            const unsigned long long id = A.rid[sl];
-            c = (uint32_t)(A.roff[id + 1] - A.roff[id]);
-        }
-        A.icnt[i] = c;
+// Join 1 of the cascade in two passes over S (pairs per tuple, then the
+// pairs themselves at prefix-sum positions), R's (key, id) table and the
+// group offsets in LDS when they fit.
+template <bool WRITE>
+__device__ void star_join1(const StarExpandArgs& A, uint2* rtab, unsigned long long* roffs) {
+    const DirEntry re = A.R.dir[0];
+    const uint32_t rcap = 1u << re.log2cap;
+    const uint32_t k = (uint32_t)A.rid[A.R.pool_slots + 1];
+    const bool lds = rcap <= STAR_LDS_SLOTS && k < STAR_STRIDE;   // uniform over the launch
+    const uint32_t rspecial = re.special ? (uint32_t)A.rid[A.R.pool_slots] : STAR_NONE;
+    if (lds) {
+        lds_build(rtab, A.idtab + re.offset, rcap);
+        for (uint32_t i = threadIdx.x; i <= k; i += blockDim.x) roffs[i] = A.roff[i];
     }
+    __syncthreads();
+    const uint64_t nthr = blockDim.x;
+    star_stream(A.col0, A.col1, A.stride, A.n,
+                [&](uint64_t q, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
+                    const bool (&live)[STAR_U]) {
+        uint32_t id[STAR_U];
+        if (lds) {
+            lds_get4(rtab, key, live, STAR_NONE, rspecial, id);
+        } else {
+#pragma unroll
+            for (int u = 0; u < STAR_U; ++u) id[u] = live[u] ? star_id(A.R, A.idtab, A.rid, key[u]) : STAR_NONE;
+        }
+#pragma unroll
+        for (int u = 0; u < STAR_U; ++u) {
+            if (!live[u]) continue;
+            const uint64_t i = q + u * nthr;
+            if (!WRITE) {
+                A.icnt[i] = id[u] == STAR_NONE ? 0u
+                            : (uint32_t)(lds ? roffs[id[u] + 1] - roffs[id[u]] : A.roff[id[u] + 1] - A.roff[id[u]]);
+                continue;
+            }
+            const unsigned long long o = A.ioff[i], cnt = A.ioff[i + 1] - o;
+            if (cnt == 0) continue;
+            if (o + cnt > A.i_cap) { atomicExch(A.err, 1u); continue; }   // relations other than planned
+            const unsigned long long base = lds ? roffs[id[u]] : A.roff[id[u]];
+            for (unsigned long long j = 0; j < cnt; ++j) A.I[o + j] = make_uint2(A.ra[base + j], c[u]);
+        }
+    });
 }
 
-__global__ void k_star_expand(StarExpandArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const unsigned long long o = A.ioff[i], cnt = A.ioff[i + 1] - o;
-        if (cnt == 0) continue;
-        const uint2 s = star_row(A.col0, A.col1, A.stride, i);
-        if (o + cnt > A.i_cap) { atomicExch(A.err, 1u); continue; }   // relations other than planned
-        const unsigned long long base = A.roff[A.rid[star_slot(A.R, s.x)]];
-        for (unsigned long long k = 0; k < cnt; ++k) A.I[o + k] = make_uint2(A.ra[base + k], s.y);
-    }
+__global__ void __launch_bounds__(STAR_THREADS)
+k_star_icount(StarExpandArgs A) {
+    __shared__ uint2 rtab[STAR_LDS_SLOTS];
+    __shared__ unsigned long long roffs[STAR_STRIDE + 1];
+    star_join1<false>(A, rtab, roffs);
+}
+
+__global__ void __launch_bounds__(STAR_THREADS)
+k_star_expand(StarExpandArgs A) {
+    __shared__ uint2 rtab[STAR_LDS_SLOTS];
+    __shared__ unsigned long long roffs[STAR_STRIDE + 1];
+    star_join1<true>(A, rtab, roffs);
 }
 
 }  // namespace mj

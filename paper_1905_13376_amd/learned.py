@@ -182,6 +182,16 @@ def label_instance(ctx, inst):
         pc = plan.copy(); pc.algo = L.ALGO_CASCADE
         times["cascade"] = _time(lambda: ctx.cascade2_count(L.LINEAR, Fd, Fd, Fd, a, plan=pc, out=out, workspace=ws))
         exact = int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
+        # the star plans specialise the two when R is small (planner rule)
+        if plan.est_ms_star > 0.0:
+            pst = plan.copy(); pst.algo = L.ALGO_STAR
+            times["star"] = _time(lambda: ctx.linear3_count(Fd, Fd, Fd, a, plan=pst, out=out, workspace=ws))
+            exact = exact and int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
+        if plan.est_ms_star_cascade > 0.0:
+            psc = plan.copy(); psc.algo = L.ALGO_STAR_CASCADE
+            times["star_cascade"] = _time(lambda: ctx.cascade2_count(L.LINEAR, Fd, Fd, Fd, a, plan=psc, out=out,
+                                                                     workspace=ws))
+            exact = exact and int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
     else:
         for k in SHARES:
             ps = plan.copy(); ps.algo = L.ALGO_3WAY; ps.log2_share = k
@@ -194,9 +204,12 @@ def label_instance(ctx, inst):
         else:
             times["cascade"] = float("inf")      # never chosen: the planner caps the intermediate
             exact = True
-    best3 = min(v for k, v in times.items() if k != "cascade")
+    best3 = min(v for k, v in times.items() if k in ("3way", "star") or k.startswith("share"))
+    bestc = min(v for k, v in times.items() if k in ("cascade", "star_cascade"))
     return dict(kind=kind, features=feat, join2=plan.join2_size, out=res, times=times,
-                plan_label=int(times["cascade"] < best3),
+                est=dict(star=plan.est_ms_star, star_cascade=plan.est_ms_star_cascade,
+                         three=plan.est_ms_3way, cascade=plan.est_ms_cascade),
+                plan_label=int(bestc < best3),
                 share_label=(int(np.argmin([times[f"share{k}"] for k in SHARES])) if kind == L.TRIANGLE else -1),
                 analytic=dict(algo=plan.algo, share=plan.log2_share), plan_ms=plan_ms,
                 cascade_equals_3way=exact, n=int(Fd.shape[0]))
@@ -217,9 +230,28 @@ def nearest_share(k):
 
 
 def plan_time(r, algo, share):
+    t = r["times"]
+    if algo == L.ALGO_STAR_CASCADE:
+        return t["star_cascade"]
+    if algo == L.ALGO_STAR:
+        return t["star"]
     if algo == L.ALGO_CASCADE:
-        return r["times"]["cascade"]
-    return r["times"]["3way"] if r["kind"] == L.LINEAR else r["times"][f"share{share}"]
+        return t["cascade"]
+    return t["3way"] if r["kind"] == L.LINEAR else t[f"share{share}"]
+
+
+def specialise(r, algo):
+    """mj_plan's rule: a three-way (cascade) choice becomes the star
+    three-way join (star cascade) when that plan is eligible and rated
+    faster by the analytic model."""
+    e = r.get("est")
+    if r["kind"] != L.LINEAR or not e:
+        return algo
+    if algo == L.ALGO_3WAY and 0.0 < e["star"] < e["three"]:
+        return L.ALGO_STAR
+    if algo == L.ALGO_CASCADE and 0.0 < e["star_cascade"] < e["cascade"]:
+        return L.ALGO_STAR_CASCADE
+    return algo
 
 
 def evaluate(planner, rows):
@@ -231,7 +263,7 @@ def evaluate(planner, rows):
     tot = {"learned": 0.0, "analytic": 0.0, "always_3way": 0.0, "always_cascade": 0.0, "best": 0.0}
     qI, qO = [], []
     for r, y in zip(rows, Y):
-        algo = L.ALGO_CASCADE if (y[3] > y[2] and r["join2"] <= CASCADE_CAP) else L.ALGO_3WAY
+        algo = specialise(r, L.ALGO_CASCADE if (y[3] > y[2] and r["join2"] <= CASCADE_CAP) else L.ALGO_3WAY)
         share = SHARES[int(np.argmax(y[4:7]))]
         tot["learned"] += plan_time(r, algo, share)
         tot["analytic"] += plan_time(r, r["analytic"]["algo"], nearest_share(r["analytic"]["share"]))
