@@ -9,6 +9,8 @@ Contents
   * the join counts (plain nested-loop joins in C, Sec. 3 / Sec. 5):
       ``linear3_count``, ``triangle3_count``, ``join2_size``,
       ``triangle3_count_masked``, ``linear3_count_sampled``
+  * the Flajolet-Martin distinct count of D per A: ``linear3_distinct``,
+    ``fm_sketch``
   * ``cost_model``: the paper's analytic cost formulas (Sec. 4.2, 5.2, 6.3,
     6.5 footnote, App. A), in float64
   * ``mlp_ref``: a float64 reference of the learned planner's network
@@ -52,8 +54,13 @@ def bind(lib):
                                                u32p, u32p, u32p, i64, u64, u32p, u32p]
     lib.orc_linear3_count_sampled.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
                                               u32p, i64, u64, u32p, u64, u32p]
+    lib.orc_linear3_distinct.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                         u32p, u32p, i64, u64, u32p, u64, ctypes.c_uint32,
+                                         u32p, u32p, u32p]
+    lib.orc_fm_sketch.argtypes = [u32p, u64, ctypes.c_uint32, u32p, u32p]
     for f in ("orc_linear3_count", "orc_join2_size", "orc_triangle3_count",
-              "orc_triangle3_count_masked", "orc_linear3_count_sampled"):
+              "orc_triangle3_count_masked", "orc_linear3_count_sampled",
+              "orc_linear3_distinct", "orc_fm_sketch"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -115,6 +122,39 @@ def linear3_count_sampled(R, S, T, alist) -> np.ndarray:
                                        al.ctypes.data, al.size, out.ctypes.data)
     _check(st, "linear3_count_sampled")
     return al, out[:al.size]
+
+
+def linear3_distinct(R, S, T, alist, seed: int):
+    """For each A value in ``np.unique(alist)``: the Flajolet-Martin sketch
+    (uint32[16]) of the set of D values it reaches through R |x| S |x| T,
+    the sketch's estimate (float64) and the exact size of the set.
+    Returns (a_values, sketches [na, 16], estimates [na], exact [na])."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, t1, ts, nt = _rel(T)
+    al = np.ascontiguousarray(np.unique(np.asarray(alist).astype(np.int64) & 0xFFFFFFFF).astype(np.uint32))
+    sk = np.zeros((max(al.size, 1), 16), dtype=np.uint32)
+    est = np.zeros(max(al.size, 1), dtype=np.float64)
+    exact = np.zeros(max(al.size, 1), dtype=np.uint64)
+    st = lib.orc_linear3_distinct(r0, r1, rs, nr, s0, s1, ss, ns, t0, t1, ts, nt,
+                                  al.ctypes.data, al.size, ctypes.c_uint32(seed & 0xFFFFFFFF),
+                                  sk.ctypes.data, est.ctypes.data, exact.ctypes.data)
+    _check(st, "linear3_distinct")
+    return al, sk[:al.size], est[:al.size], exact[:al.size]
+
+
+def fm_sketch(values, seed: int):
+    """The Flajolet-Martin sketch (uint32[16]) and estimate of a set of
+    32-bit values (duplicates are harmless: the sketch is a union)."""
+    lib = _load()
+    v = np.ascontiguousarray(np.asarray(values).astype(np.int64) & 0xFFFFFFFF).astype(np.uint32)
+    sk = np.zeros(16, dtype=np.uint32)
+    est = np.zeros(1, dtype=np.float64)
+    st = lib.orc_fm_sketch(v.ctypes.data, v.size, ctypes.c_uint32(seed & 0xFFFFFFFF),
+                           sk.ctypes.data, est.ctypes.data)
+    _check(st, "fm_sketch")
+    return sk, float(est[0])
 
 
 def join2_size(R, S) -> int:

@@ -265,3 +265,110 @@ int orc_linear3_count_sampled(const uint32_t* r0, const uint32_t* r1, int64_t rs
     free(tc); free(s); free(acc);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Distinct count of the linear join's D values per A, estimated with a     */
+/* Flajolet-Martin sketch (the footnotes to Example 1 and to Sec. 4's step  */
+/* list: the union of overlapping sets of friends of friends of friends,    */
+/* each kept as a small sketch).  For each requested a the exact set        */
+/*   D(a) = { t.d : r.a = a, r.b = s.b, s.c = t.c }                          */
+/* is collected, its size reported, and its sketch built element by        */
+/* element:                                                                  */
+/*   h = MurmurHash3's 32-bit finaliser of (d xor seed);                     */
+/*   bitmap j = the low 4 bits of h (16 bitmaps of 32 bits, stochastic       */
+/*   averaging); bit r = the number of trailing zeros of h >> 4 (28 when     */
+/*   h >> 4 is zero).                                                        */
+/* The estimate is Flajolet and Martin's: with R_j the lowest zero bit of    */
+/* bitmap j, E = (16 / 0.77351) * 2^(sum R_j / 16), and 0 for an empty set.  */
+/* ------------------------------------------------------------------------ */
+static uint32_t fm_mix(uint32_t x, uint32_t seed) {
+    uint32_t h = x ^ seed;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+static uint32_t ctz32(uint32_t x) {           /* x != 0 */
+    uint32_t n = 0;
+    while (!(x & 1u)) { x >>= 1; ++n; }
+    return n;
+}
+
+static void fm_add(uint32_t* sk, uint32_t d, uint32_t seed) {
+    uint32_t h = fm_mix(d, seed);
+    uint32_t rest = h >> 4;
+    sk[h & 15u] |= 1u << (rest ? ctz32(rest) : 28u);
+}
+
+static double fm_estimate(const uint32_t* sk) {
+    int any = 0;
+    uint32_t sum = 0;
+    for (int j = 0; j < 16; ++j) {
+        if (sk[j]) any = 1;
+        sum += sk[j] == 0xFFFFFFFFu ? 32u : ctz32(~sk[j]);
+    }
+    if (!any) return 0.0;
+    /* 2^(sum / 16) as a product of exact powers of two and 2^(1/16)^k */
+    double p = 1.0;
+    for (uint32_t i = 0; i < sum / 16; ++i) p *= 2.0;
+    double f = 1.0;
+    for (uint32_t i = 0; i < sum % 16; ++i) f *= 1.0442737824274138;   /* 2^(1/16) */
+    return 16.0 / 0.77351 * p * f;
+}
+
+int orc_linear3_distinct(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                         const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                         const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
+                         const uint32_t* alist, uint64_t na, uint32_t seed,
+                         uint32_t* sketch, double* est, uint64_t* exact) {
+    pair_t* r = load_pairs(r0, r1, rstride, nr, 0);   /* (a, b) by a */
+    pair_t* s = load_pairs(s0, s1, sstride, ns, 0);   /* (b, c) by b */
+    pair_t* t = load_pairs(t0, t1, tstride, nt, 0);   /* (c, d) by c */
+    uint64_t cap = 1024, len = 0;
+    uint32_t* dset = (uint32_t*)malloc(cap * sizeof(uint32_t));
+    if (!r || !s || !t || !dset) { free(r); free(s); free(t); free(dset); return ORC_NOMEM; }
+    for (uint64_t q = 0; q < na; ++q) {
+        const uint32_t a = alist[q];
+        len = 0;
+        uint64_t rlo = lower_key(r, 0, nr, a), rhi = upper_key(r, rlo, nr, a);
+        for (uint64_t i = rlo; i < rhi; ++i) {                 /* r with r.a = a */
+            uint64_t lo = lower_key(s, 0, ns, r[i].val), hi = upper_key(s, lo, ns, r[i].val);
+            for (uint64_t j = lo; j < hi; ++j) {                /* s with s.b = r.b */
+                uint64_t tlo = lower_key(t, 0, nt, s[j].val), thi = upper_key(t, tlo, nt, s[j].val);
+                for (uint64_t k = tlo; k < thi; ++k) {          /* t with t.c = s.c */
+                    if (len == cap) {
+                        uint32_t* g = (uint32_t*)realloc(dset, 2 * cap * sizeof(uint32_t));
+                        if (!g) { free(r); free(s); free(t); free(dset); return ORC_NOMEM; }
+                        dset = g;
+                        cap *= 2;
+                    }
+                    dset[len++] = t[k].val;
+                }
+            }
+        }
+        qsort(dset, len, sizeof(uint32_t), cmp_u32);
+        uint64_t distinct = 0;
+        uint32_t* sk = sketch + 16 * q;
+        for (int j = 0; j < 16; ++j) sk[j] = 0;
+        for (uint64_t i = 0; i < len; ++i) {
+            if (i > 0 && dset[i] == dset[i - 1]) continue;
+            ++distinct;
+            fm_add(sk, dset[i], seed);
+        }
+        exact[q] = distinct;
+        est[q] = fm_estimate(sk);
+    }
+    free(r); free(s); free(t); free(dset);
+    return ORC_OK;
+}
+
+/* The sketch and estimate of an explicit set of values (for the pins). */
+int orc_fm_sketch(const uint32_t* vals, uint64_t n, uint32_t seed, uint32_t* sketch, double* est) {
+    for (int j = 0; j < 16; ++j) sketch[j] = 0;
+    for (uint64_t i = 0; i < n; ++i) fm_add(sketch, vals[i], seed);
+    *est = fm_estimate(sketch);
+    return ORC_OK;
+}
