@@ -272,8 +272,8 @@ int orc_linear3_count_sampled(const uint32_t* r0, const uint32_t* r1, int64_t rs
 /* list: the union of overlapping sets of friends of friends of friends,    */
 /* each kept as a small sketch).  For each requested a the exact set        */
 /*   D(a) = { t.d : r.a = a, r.b = s.b, s.c = t.c }                          */
-/* is collected, its size reported, and its sketch built element by        */
-/* element:                                                                  */
+/* is collected (level by level, below), its size reported, and its sketch  */
+/* built element by element:                                                 */
 /*   h = MurmurHash3's 32-bit finaliser of (d xor seed);                     */
 /*   bitmap j = the low 4 bits of h (16 bitmaps of 32 bits, stochastic       */
 /*   averaging); bit r = the number of trailing zeros of h >> 4 (28 when     */
@@ -319,6 +319,30 @@ static double fm_estimate(const uint32_t* sk) {
     return 16.0 / 0.77351 * p * f;
 }
 
+/* grow *buf (capacity *cap) to hold at least need values */
+static int reserve_u32(uint32_t** buf, uint64_t* cap, uint64_t need) {
+    if (need <= *cap) return 1;
+    uint64_t c = *cap ? *cap : 1024;
+    while (c < need) c *= 2;
+    uint32_t* g = (uint32_t*)realloc(*buf, c * sizeof(uint32_t));
+    if (!g) return 0;
+    *buf = g;
+    *cap = c;
+    return 1;
+}
+
+/* sort and drop repeats; returns the new length */
+static uint64_t sort_unique(uint32_t* v, uint64_t n) {
+    qsort(v, n, sizeof(uint32_t), cmp_u32);
+    uint64_t m = 0;
+    for (uint64_t i = 0; i < n; ++i)
+        if (m == 0 || v[i] != v[m - 1]) v[m++] = v[i];
+    return m;
+}
+
+/* D(a) level by level: B(a) = { r.b : r.a = a }, C(a) = { s.c : s.b in
+ * B(a) }, D(a) = { t.d : t.c in C(a) } -- the same set as the paths
+ * (a, b, c, d) give, without enumerating the paths. */
 int orc_linear3_distinct(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
                          const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
                          const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
@@ -327,42 +351,38 @@ int orc_linear3_distinct(const uint32_t* r0, const uint32_t* r1, int64_t rstride
     pair_t* r = load_pairs(r0, r1, rstride, nr, 0);   /* (a, b) by a */
     pair_t* s = load_pairs(s0, s1, sstride, ns, 0);   /* (b, c) by b */
     pair_t* t = load_pairs(t0, t1, tstride, nt, 0);   /* (c, d) by c */
-    uint64_t cap = 1024, len = 0;
-    uint32_t* dset = (uint32_t*)malloc(cap * sizeof(uint32_t));
-    if (!r || !s || !t || !dset) { free(r); free(s); free(t); free(dset); return ORC_NOMEM; }
+    uint32_t *bs = NULL, *cs = NULL, *ds = NULL;
+    uint64_t bcap = 0, ccap = 0, dcap = 0;
+    int status = ORC_OK;
+    if (!r || !s || !t) { status = ORC_NOMEM; goto done; }
     for (uint64_t q = 0; q < na; ++q) {
         const uint32_t a = alist[q];
-        len = 0;
         uint64_t rlo = lower_key(r, 0, nr, a), rhi = upper_key(r, rlo, nr, a);
-        for (uint64_t i = rlo; i < rhi; ++i) {                 /* r with r.a = a */
-            uint64_t lo = lower_key(s, 0, ns, r[i].val), hi = upper_key(s, lo, ns, r[i].val);
-            for (uint64_t j = lo; j < hi; ++j) {                /* s with s.b = r.b */
-                uint64_t tlo = lower_key(t, 0, nt, s[j].val), thi = upper_key(t, tlo, nt, s[j].val);
-                for (uint64_t k = tlo; k < thi; ++k) {          /* t with t.c = s.c */
-                    if (len == cap) {
-                        uint32_t* g = (uint32_t*)realloc(dset, 2 * cap * sizeof(uint32_t));
-                        if (!g) { free(r); free(s); free(t); free(dset); return ORC_NOMEM; }
-                        dset = g;
-                        cap *= 2;
-                    }
-                    dset[len++] = t[k].val;
-                }
-            }
+        uint64_t nb = 0, nc = 0, nd = 0;
+        if (!reserve_u32(&bs, &bcap, rhi - rlo)) { status = ORC_NOMEM; goto done; }
+        for (uint64_t i = rlo; i < rhi; ++i) bs[nb++] = r[i].val;           /* r with r.a = a */
+        nb = sort_unique(bs, nb);
+        for (uint64_t i = 0; i < nb; ++i) {                                   /* s with s.b in B(a) */
+            uint64_t lo = lower_key(s, 0, ns, bs[i]), hi = upper_key(s, lo, ns, bs[i]);
+            if (!reserve_u32(&cs, &ccap, nc + (hi - lo))) { status = ORC_NOMEM; goto done; }
+            for (uint64_t j = lo; j < hi; ++j) cs[nc++] = s[j].val;
         }
-        qsort(dset, len, sizeof(uint32_t), cmp_u32);
-        uint64_t distinct = 0;
+        nc = sort_unique(cs, nc);
+        for (uint64_t i = 0; i < nc; ++i) {                                   /* t with t.c in C(a) */
+            uint64_t lo = lower_key(t, 0, nt, cs[i]), hi = upper_key(t, lo, nt, cs[i]);
+            if (!reserve_u32(&ds, &dcap, nd + (hi - lo))) { status = ORC_NOMEM; goto done; }
+            for (uint64_t j = lo; j < hi; ++j) ds[nd++] = t[j].val;
+        }
+        nd = sort_unique(ds, nd);
         uint32_t* sk = sketch + 16 * q;
         for (int j = 0; j < 16; ++j) sk[j] = 0;
-        for (uint64_t i = 0; i < len; ++i) {
-            if (i > 0 && dset[i] == dset[i - 1]) continue;
-            ++distinct;
-            fm_add(sk, dset[i], seed);
-        }
-        exact[q] = distinct;
+        for (uint64_t i = 0; i < nd; ++i) fm_add(sk, ds[i], seed);
+        exact[q] = nd;
         est[q] = fm_estimate(sk);
     }
-    free(r); free(s); free(t); free(dset);
-    return ORC_OK;
+done:
+    free(r); free(s); free(t); free(bs); free(cs); free(ds);
+    return status;
 }
 
 /* The sketch and estimate of an explicit set of values (for the pins). */
