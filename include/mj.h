@@ -159,6 +159,26 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
                       uint32_t a_domain, uint64_t* out, const mj_plan_t* plan,
                       void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* Distinct count of the linear join's D values per A (the footnotes to
+ * Example 1 and to Sec. 4's step list: friends of friends of friends per
+ * person, estimated with Flajolet-Martin sketches that merge by union):
+ *   D(a) = { t.d : r in R, s in S, t in T, r.a = a, r.b = s.b, s.c = t.c }
+ *   sketch[a] = uint32[16] bitmaps: every d in D(a) with
+ *               h = MurmurHash3's 32-bit finaliser of (d xor seed) sets bit
+ *               (trailing zeros of h >> 4, or 28 when h >> 4 = 0) of bitmap
+ *               h & 15
+ *   est[a]    = 0 for an empty set, else (16 / 0.77351) * 2^(sum over the
+ *               bitmaps of their lowest zero bit / 16)
+ * sketch: device uint32[a_domain][16], fully overwritten; est: device
+ * double[a_domain] or NULL.  A values must be < a_domain (mj_plan checks
+ * this for the linear kind); larger ones are skipped.  The workspace size
+ * comes from mj_linear3_distinct_workspace.  Sketches are exact functions
+ * of the sets, so they do not depend on the order of the work.          */
+uint64_t mj_linear3_distinct_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t a_domain);
+int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                        uint32_t a_domain, uint32_t seed, uint32_t* sketch, double* est,
+                        void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* A batch of independent joins (many joins of uneven size).  Every item
  * carries its relations, its output (uint64[a_domain] or uint64[1], device)
  * and a plan from mj_plan (or the autotuner).  The preparation of every join

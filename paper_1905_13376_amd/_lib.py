@@ -78,6 +78,8 @@ _SIGS = {
     "mj_triangle3_count": ([_vp, _RP, _RP, _RP, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_cascade2_count": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
+    "mj_linear3_distinct_workspace": ([_u64, _u64, _u64, _u32], _u64),
+    "mj_linear3_distinct": ([_vp, _RP, _RP, _RP, _u32, _u32, _vp, _vp, _vp, _u64, _vp], _i32),
     "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
     "mj_ctx_profile": ([_vp, _i32], _i32),
     "mj_mlp_param_bytes": ([], _u64),
@@ -217,6 +219,22 @@ class Context:
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream_ptr(stream)), "mj_linear3_count")
         return out[:a_domain]
+
+    def linear3_distinct(self, R, S, T, a_domain, seed=0x9E3779B9, sketch=None, est=None,
+                         workspace=None, stream=None):
+        """Flajolet-Martin sketches (int32 [a_domain, 16] holding the uint32
+        bits) and estimates (float64 [a_domain]) of the D values per A."""
+        if sketch is None:
+            sketch = torch.empty((max(a_domain, 1), 16), dtype=torch.int32, device=R.device)
+        if est is None:
+            est = torch.empty(max(a_domain, 1), dtype=torch.float64, device=R.device)
+        need = _lib.mj_linear3_distinct_workspace(R.shape[0], S.shape[0], T.shape[0], a_domain)
+        ws = workspace if workspace is not None else self.workspace(need, R.device)
+        _check(_lib.mj_linear3_distinct(self._h, rel(R), rel(S), rel(T), a_domain, seed & 0xFFFFFFFF,
+                                        ctypes.c_void_p(sketch.data_ptr()), ctypes.c_void_p(est.data_ptr()),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
+               "mj_linear3_distinct")
+        return sketch[:a_domain], est[:a_domain]
 
     def triangle3_count(self, R, S, T, plan: Plan | None = None, out=None, workspace=None,
                         stream=None) -> torch.Tensor:

@@ -858,6 +858,64 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
                       false, a_domain, ctx->num_cu, p, L, count, a_domain, s);
 }
 
+// ---------------------------------------------- FM distinct count per A
+struct FmLayout {
+    unsigned long long* Tk;
+    unsigned long long* Sk;
+    unsigned long long* tmp;
+    uint32_t* rs_hist;
+    uint32_t* rs_counts;
+    uint32_t* rs_starts;
+    uint32_t* flags;
+    unsigned long long* ridx;
+    unsigned long long* partial;
+    RunBuf T, S;
+    uint32_t* tsk;                    // [T runs][FM_WORDS]
+    uint32_t* wsk;                    // [S runs][FM_WORDS]
+    RelPart Ra;                       // R by range of A
+    uint32_t* err;
+    uint32_t a_bits, a_shift;
+    bool by_range;
+    size_t bytes;
+};
+
+// ranges of A of at most 2^FM_RANGE_MAX_SHIFT values, about 32K R tuples
+// each, at most 2^PART_MAX_BITS of them; beyond that the sketches are ORed
+// straight into the output
+void fm_ranges(uint64_t n_r, uint32_t a_domain, uint32_t& bits, uint32_t& shift, bool& by_range) {
+    const uint32_t L = ceil_log2(std::max<uint32_t>(a_domain, 1));
+    const uint32_t want = ceil_log2((n_r + 32767) / 32768);
+    bits = std::max<uint32_t>(std::min<uint32_t>(want, L), L > FM_RANGE_MAX_SHIFT ? L - FM_RANGE_MAX_SHIFT : 0);
+    shift = L - bits;
+    by_range = bits <= PART_MAX_BITS;
+    if (!by_range) { bits = 0; shift = 0; }
+}
+
+FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_domain) {
+    Bump B(ws);
+    FmLayout L{};
+    const uint64_t nmax = std::max<uint64_t>({nr, ns, nt, 1});
+    L.Tk = B.take<unsigned long long>(std::max<uint64_t>(nt, 1));
+    L.Sk = B.take<unsigned long long>(std::max<uint64_t>(ns, 1));
+    L.tmp = B.take<unsigned long long>(nmax);
+    const uint64_t ntiles = (nmax + RS_TILE - 1) / RS_TILE;
+    L.rs_hist = B.take<uint32_t>(256 * ntiles);
+    L.rs_counts = B.take<uint32_t>(256);
+    L.rs_starts = B.take<uint32_t>(257);
+    L.flags = B.take<uint32_t>(nmax);
+    L.ridx = B.take<unsigned long long>(nmax + 1);
+    L.partial = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
+    take_runs(B, L.T, nt, true);
+    take_runs(B, L.S, ns, true);
+    L.tsk = B.take<uint32_t>(std::max<uint64_t>(nt, 1) * FM_WORDS);
+    L.wsk = B.take<uint32_t>(std::max<uint64_t>(ns, 1) * FM_WORDS);
+    fm_ranges(nr, a_domain, L.a_bits, L.a_shift, L.by_range);
+    take_part(B, L.Ra, nr, L.a_bits);
+    L.err = B.take<uint32_t>(1);
+    L.bytes = B.off + 256;
+    return L;
+}
+
 }  // namespace
 
 // =================================================================== API
@@ -1257,6 +1315,78 @@ uint64_t mj_mlp_param_bytes(void) { return uint64_t(4) * MLP_P * 4 + uint64_t(ML
 
 uint64_t mj_mlp_workspace(uint32_t B) {
     return (uint64_t(B) * MLP_ACT + 2 * uint64_t(B) * MLP_OUT) * 4 + 512;
+}
+
+uint64_t mj_linear3_distinct_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t a_domain) {
+    return fm_layout(nullptr, n_r, n_s, n_t, a_domain).bytes;
+}
+
+int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                        uint32_t a_domain, uint32_t seed, uint32_t* sketch, double* est,
+                        void* ws, uint64_t ws_bytes, void* stream) {
+    if (!ctx || (!sketch && a_domain)) return MJ_ERR_INVALID_ARG;
+    int st;
+    if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
+    FmLayout L = fm_layout(nullptr, R->n, S->n, T->n, a_domain);
+    if (!ws || ws_bytes < L.bytes) return MJ_ERR_WORKSPACE;
+    L = fm_layout(ws, R->n, S->n, T->n, a_domain);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    if (a_domain == 0) return MJ_OK;
+    const uint64_t words = uint64_t(a_domain) * FM_WORDS;
+    if (R->n == 0 || S->n == 0 || T->n == 0) {
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+                  sketch, words, 0u);
+        if (est)
+            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+                      reinterpret_cast<unsigned long long*>(est), (uint64_t)a_domain, 0ull);   // 0.0
+        return MJ_OK;
+    }
+    TriLayout TL{};                    // launch_runs only uses flags / ridx / partial
+    TL.flags = L.flags; TL.ridx = L.ridx; TL.partial = L.partial;
+    // T grouped by C: (mix(c), mix(d)) sorted; per run the OR of bit(mix(d))
+    if ((st = tri_keys(prof, *T, 0, L.Tk, seed, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_runs(prof, TL, L.Tk, T->n, L.T, nullptr, s))) return st;
+    FmTArgs Ft;
+    Ft.T = run_index(L.T); Ft.Tk = L.Tk; Ft.tsk = L.tsk;
+    MJ_LAUNCH(prof, "k_fm_tsketch", k_fm_tsketch, dim3(grid_for(T->n, FM_THREADS, 16384)), dim3(FM_THREADS),
+              0, s, Ft);
+    MJ_LAUNCH(prof, "k_fm_tsketch_long", k_fm_tsketch_long, dim3(grid_for(T->n, FM_THREADS, 4096)),
+              dim3(FM_THREADS), 0, s, Ft);
+    // S grouped by B: per run the OR of T's sketches of its C values
+    if ((st = tri_keys(prof, *S, 0, L.Sk, seed, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_runs(prof, TL, L.Sk, S->n, L.S, nullptr, s))) return st;
+    FmWArgs Fw;
+    Fw.S = run_index(L.S); Fw.Sk = L.Sk; Fw.T = run_index(L.T); Fw.tsk = L.tsk; Fw.wsk = L.wsk;
+    MJ_LAUNCH(prof, "k_fm_wsketch", k_fm_wsketch, dim3(grid_for(S->n, FM_THREADS, 16384)), dim3(FM_THREADS),
+              0, s, Fw);
+    MJ_LAUNCH(prof, "k_fm_wsketch_long", k_fm_wsketch_long, dim3(grid_for(S->n, FM_THREADS, 4096)),
+              dim3(FM_THREADS), 0, s, Fw);
+    // R by range of A (or as one bucket in the global mode): per a the OR of
+    // the sketches of its B values
+    PartLaunch P{};
+    P.njobs = 1;
+    P.job[0] = make_job(*R, L.Ra.hist, L.Ra.counts, L.Ra.starts, 0, 0, L.a_bits, 0, 0, 0);
+    P.job[0].range_on = 1;
+    P.job[0].range_shift = L.a_shift;
+    P.job[0].out_pair = L.Ra.pairs;
+    if ((st = launch_partition(prof, "r", P, s))) return st;
+    FmAArgs Fa;
+    Fa.R = L.Ra.pairs; Fa.rstarts = L.Ra.starts; Fa.n = R->n; Fa.a_shift = L.a_shift; Fa.a_domain = a_domain;
+    Fa.seed = seed; Fa.S = run_index(L.S); Fa.wsk = L.wsk; Fa.sketch = sketch; Fa.est = est;
+    Fa.err = L.err;
+    if (L.by_range) {
+        MJ_LAUNCH(prof, "k_fm_asketch", k_fm_asketch, dim3(1u << L.a_bits), dim3(FM_THREADS), 0, s, Fa);
+    } else {
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+                  sketch, words, 0u);
+        MJ_LAUNCH(prof, "k_fm_asketch_global", k_fm_asketch_global, dim3(grid_for(R->n, 256, 16384)), dim3(256),
+                  0, s, Fa);
+        MJ_LAUNCH(prof, "k_fm_estimate", k_fm_estimate, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s, Fa);
+    }
+    return MJ_OK;
 }
 
 int mj_mlp_sync(mj_ctx* ctx, void* params, void* stream) {

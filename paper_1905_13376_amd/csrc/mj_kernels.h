@@ -448,6 +448,85 @@ struct RunIndex {                          // runs of equal high words of sorted
     const unsigned long long* nruns;
 };
 
+// the run of `key` (start and length) through the prefix directory
+__device__ __forceinline__ bool run_lookup(const RunIndex& X, uint32_t key, uint32_t& start,
+                                           uint32_t& len) {
+    const uint32_t p = top_bits(key, X.bits);
+    uint32_t r = X.dir[p];
+    const uint32_t rend = X.dir[p + 1];
+    for (; r < rend; ++r) {
+        const uint32_t k = X.run_key[r];
+        if (k == key) {
+            start = X.run_start[r];
+            len = X.run_start[r + 1] - start;
+            return true;
+        }
+        if (k > key) break;
+    }
+    return false;
+}
+
+// the index of the run of `key`, or 0xFFFFFFFF
+__device__ __forceinline__ uint32_t run_find(const RunIndex& X, uint32_t key) {
+    const uint32_t p = top_bits(key, X.bits);
+    const uint32_t rend = X.dir[p + 1];
+    for (uint32_t r = X.dir[p]; r < rend; ++r) {
+        const uint32_t k = X.run_key[r];
+        if (k == key) return r;
+        if (k > key) break;
+    }
+    return 0xFFFFFFFFu;
+}
+
+// ------------------------------------- Flajolet-Martin distinct count per A
+// sketch[a] = the FM sketch (FM_WORDS bitmaps of 32 bits) of the set of D
+// values a reaches through R |x| S |x| T.  A sketch is a union, so it is
+// built along the linear join with OR in place of +: per C value from T's
+// D values, per B value from S's C values, per A value from R's B values.
+// T and S are grouped by sorting mixed 64-bit keys (runs of equal high
+// words, as in the cyclic join); T's low words, mix(d) with the sketch's
+// seed, are the sketch's hash values.
+constexpr int FM_WORDS = 16;
+constexpr int FM_THREADS = 256;
+constexpr uint32_t FM_RANGE_MAX_SHIFT = 10;   // A values per LDS range (64 KB of sketches)
+constexpr uint32_t FM_NONE = 0xFFFFFFFFu;
+constexpr uint32_t FM_SHORT = 64;             // runs up to this length: one thread; longer: one wave
+
+struct FmTArgs {                   // per run of T by C: OR of the bits of its D values
+    RunIndex T;
+    const unsigned long long* Tk;  // (mix(c) << 32 | mix(d)), sorted
+    uint32_t* tsk;                 // [runs][FM_WORDS]
+};
+__global__ void k_fm_tsketch(FmTArgs A);        // runs of at most FM_SHORT elements, one thread each
+__global__ void k_fm_tsketch_long(FmTArgs A);   // longer runs, one wave each
+
+struct FmWArgs {                   // per run of S by B: OR of T's sketches of its C values
+    RunIndex S;
+    const unsigned long long* Sk;  // (mix(b) << 32 | mix(c)), sorted
+    RunIndex T;
+    const uint32_t* tsk;
+    uint32_t* wsk;                 // [runs][FM_WORDS]
+};
+__global__ void k_fm_wsketch(FmWArgs A);
+__global__ void k_fm_wsketch_long(FmWArgs A);
+
+struct FmAArgs {                   // per A value: OR of the sketches of its B values
+    const uint2* R;                // (a, b): by range of a (range mode), or as given (global mode)
+    const uint32_t* rstarts;       // range mode: [ranges + 1]
+    uint64_t n;                    // global mode: rows
+    uint32_t a_shift;              // range mode: range k holds a in [k << a_shift, (k + 1) << a_shift)
+    uint32_t a_domain;
+    uint32_t seed;                 // mixes B the way S's keys were mixed
+    RunIndex S;
+    const uint32_t* wsk;
+    uint32_t* sketch;              // [a_domain][FM_WORDS]
+    double* est;                   // [a_domain] or null
+    uint32_t* err;                 // set for an a >= a_domain
+};
+__global__ void k_fm_asketch(FmAArgs A);         // range mode: writes sketches and estimates
+__global__ void k_fm_asketch_global(FmAArgs A);  // global mode: ORs into the zeroed output
+__global__ void k_fm_estimate(FmAArgs A);        // global mode: estimates
+
 struct TriKeyArgs {
     const uint32_t* key_col;
     const uint32_t* val_col;

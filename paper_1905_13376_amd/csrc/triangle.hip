@@ -82,23 +82,6 @@ __global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nru
     }
 }
 
-__device__ __forceinline__ bool run_lookup(const RunIndex& X, uint32_t key, uint32_t& start,
-                                           uint32_t& len) {
-    const uint32_t p = top_bits(key, X.bits);
-    uint32_t r = X.dir[p];
-    const uint32_t rend = X.dir[p + 1];
-    for (; r < rend; ++r) {
-        const uint32_t k = X.run_key[r];
-        if (k == key) {
-            start = X.run_start[r];
-            len = X.run_start[r + 1] - start;
-            return true;
-        }
-        if (k > key) break;
-    }
-    return false;
-}
-
 // --------------------------------------------------------------- classify
 // Light: R list of b short and S group small -> one wave.  Heavy: otherwise
 // -> (slice of R's list) x (range of the S group) workgroup items, counted
