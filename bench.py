@@ -261,6 +261,69 @@ def star_path(mj, ctx):
     return res
 
 
+def fm_exact_sizes(F, a_vals):
+    """|D(a)| for the sampled a, by set operations on the edge list (for the
+    accuracy figure of the distinct-count path)."""
+    import numpy as np
+    order = np.argsort(F[:, 0], kind="stable")
+    src, dst = F[order, 0], F[order, 1]
+    n_v = int(F.max()) + 1
+    off = np.searchsorted(src, np.arange(n_v + 1, dtype=np.uint64))
+
+    def nbrs(vs):
+        lo, hi = off[vs], off[vs + 1]
+        lens = (hi - lo).astype(np.int64)
+        if lens.sum() == 0:
+            return np.zeros(0, dtype=np.int64)
+        first = np.repeat(lo.astype(np.int64) - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+        return np.unique(dst[first + np.arange(lens.sum())]).astype(np.int64)
+    return [int(nbrs(nbrs(nbrs(np.array([a], dtype=np.int64)))).size) for a in a_vals]
+
+
+def fm_path(mj, ctx, F, Fd, a_domain):
+    """Flajolet-Martin distinct count of D per A (the non-decomposable
+    aggregate of Sec. 1 / Sec. 6) on the power-law graph: one call sketches
+    T per C, S per B and R per A and writes an estimate per A."""
+    import numpy as np
+    import torch
+    log("distinct count (Flajolet-Martin) on the power-law graph")
+    n = F.shape[0]
+    sk = torch.empty((a_domain, 16), dtype=torch.int32, device="cuda")
+    est = torch.empty(a_domain, dtype=torch.float64, device="cuda")
+    fn = lambda: ctx.linear3_distinct(Fd, Fd, Fd, a_domain, seed=0x5EED, sketch=sk, est=est)
+    ctx.profile(True)
+    ctx.profile_read()
+    ms = time_call(fn, 5, 2)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ncalls = 7                                        # 2 warm-up + 5 timed calls were profiled
+    kern = {k: (v[0] / max(v[1], 1), v[1] / ncalls) for k, v in prof.items()}
+    e = est.cpu().numpy()
+    rng = np.random.default_rng(11)
+    outdeg = np.bincount(F[:, 0], minlength=a_domain)
+    cand = np.flatnonzero(outdeg > 0)
+    sample = rng.choice(cand, size=48, replace=False)
+    exact = np.array(fm_exact_sizes(F, sample))
+    big = exact >= 1000
+    ratio = e[sample[big]] / exact[big]
+    # bytes the path must move at least: R, S, T read once (8 B per tuple),
+    # one 64-byte sketch per distinct C and per distinct B written and read
+    # once, and the sketches and estimates per A written
+    n_keys = int(np.unique(F[:, 0]).size)
+    alg = 3 * 8 * n + 2 * 2 * 64 * n_keys + 72 * a_domain
+    ach = alg / (ms * 1e-3) / 1e9
+    res = {"ms": round(ms, 3), "tuples_per_s": 3 * n / (ms * 1e-3),
+           "path_hbm": {"algorithmic_bytes": alg, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4)},
+           "est_over_exact": {"sampled_a": int(big.sum()), "median": round(float(np.median(ratio)), 4),
+                              "p10": round(float(np.percentile(ratio, 10)), 4),
+                              "p90": round(float(np.percentile(ratio, 90)), 4)},
+           "kernels_us": {k: [round(v[0] * 1e3, 1), round(v[1], 2)]
+                          for k, v in sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1])[:8]}}
+    log(f"distinct count: {ms:.3f} ms, est/exact median {res['est_over_exact']['median']}")
+    return res
+
+
 def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     """The other paths of the method, each on its own workload."""
     import numpy as np
@@ -290,6 +353,7 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     out["linear_small"] = {"ms_3way": round(ms_s, 4), "ms_cascade": round(ms_sc, 4),
                            "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3)}
     del ws
+    out["distinct_fm"] = fm_path(mj, ctx, F, Fd, a_domain)
     out["star"] = star_path(mj, ctx)
     # cyclic join on the R-MAT scale-22 graph, shares 1 / 4 / 16 (Sec. 5)
     log("generating R-MAT scale 22 (2^26 undirected edges)")

@@ -461,13 +461,18 @@ int launch_scan_u32(Prof* prof, const uint32_t* in, uint64_t n, unsigned long lo
 }
 
 // Sort n 64-bit keys in place (8 stable passes of 8 bits; tmp is the other buffer).
+// LSD radix sort of 64-bit keys on bytes first_pass..7 (first_pass = 4:
+// grouped by the high word, stable in the low word); first_pass must be even
+// so that the result is back in `keys`
 int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* tmp, uint64_t n,
-                      uint32_t* hist, uint32_t* counts, uint32_t* starts, hipStream_t s) {
+                      uint32_t* hist, uint32_t* counts, uint32_t* starts, hipStream_t s,
+                      uint32_t first_pass = 0) {
     if (n <= 1) return MJ_OK;
+    if (first_pass & 1) return MJ_ERR_INVALID_ARG;
     const uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
     unsigned long long* src = keys;
     unsigned long long* dst = tmp;
-    for (uint32_t pass = 0; pass < 8; ++pass) {
+    for (uint32_t pass = first_pass; pass < 8; ++pass) {
         RsArgs A;
         A.in = src; A.out = dst; A.n = n; A.shift = 8 * pass; A.ntiles = ntiles;
         A.hist = hist; A.starts = starts;
@@ -482,7 +487,7 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
         MJ_LAUNCH(prof, "k_rs_scatter", k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
         std::swap(src, dst);
     }
-    return MJ_OK;            // eight passes: the result is back in `keys`
+    return MJ_OK;            // an even number of passes: the result is back in `keys`
 }
 
 int launch_runs(Prof* prof, const TriLayout& L, const unsigned long long* keys, uint64_t n,
@@ -1346,7 +1351,8 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
     TL.flags = L.flags; TL.ridx = L.ridx; TL.partial = L.partial;
     // T grouped by C: (mix(c), mix(d)) sorted; per run the OR of bit(mix(d))
     if ((st = tri_keys(prof, *T, 0, L.Tk, seed, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    // (only the grouping by the high word matters to an OR of sketches)
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s, 4))) return st;
     if ((st = launch_runs(prof, TL, L.Tk, T->n, L.T, nullptr, s))) return st;
     FmTArgs Ft;
     Ft.T = run_index(L.T); Ft.Tk = L.Tk; Ft.tsk = L.tsk;
@@ -1356,7 +1362,7 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
               dim3(FM_THREADS), 0, s, Ft);
     // S grouped by B: per run the OR of T's sketches of its C values
     if ((st = tri_keys(prof, *S, 0, L.Sk, seed, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s, 4))) return st;
     if ((st = launch_runs(prof, TL, L.Sk, S->n, L.S, nullptr, s))) return st;
     FmWArgs Fw;
     Fw.S = run_index(L.S); Fw.Sk = L.Sk; Fw.T = run_index(L.T); Fw.tsk = L.tsk; Fw.wsk = L.wsk;

@@ -75,10 +75,6 @@ __device__ __forceinline__ void fm_t_elem(const FmTArgs& A, uint32_t i, uint32_t
     fm_bit((uint32_t)A.Tk[i], sk);
 }
 
-__device__ __forceinline__ void fm_w_elem(const FmWArgs& A, uint32_t i, uint32_t (&sk)[FM_WORDS]) {
-    const uint32_t t = run_find(A.T, (uint32_t)A.Sk[i]);          // c's run in T, if any
-    if (t != FM_NONE) fm_or(A.tsk + uint64_t(t) * FM_WORDS, sk);
-}
 
 __global__ void __launch_bounds__(FM_THREADS)
 k_fm_tsketch(FmTArgs A) {
@@ -108,6 +104,35 @@ k_fm_tsketch_long(FmTArgs A) {
     }
 }
 
+// OR into sk T's sketches of the C values of S's elements i0, i0 + step, ...
+// (four of them, those below e), with the four lookups in flight together
+__device__ __forceinline__ void fm_w_elem4(const FmWArgs& A, uint32_t i0, uint32_t step, uint32_t e,
+                                           uint32_t (&sk)[FM_WORDS]) {
+    uint32_t key[4], t[4];
+    bool live[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t i = i0 + u * step;
+        live[u] = i < e;
+        key[u] = live[u] ? (uint32_t)A.Sk[i] : 0u;
+    }
+    run_find4(A.T, key, live, t);
+    uint4 v[4][FM_WORDS / 4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < FM_WORDS / 4; ++q)
+            v[u][q] = t[u] != FM_NONE ? reinterpret_cast<const uint4*>(A.tsk + uint64_t(t[u]) * FM_WORDS)[q]
+                                      : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < FM_WORDS / 4; ++q) {
+            sk[4 * q] |= v[u][q].x; sk[4 * q + 1] |= v[u][q].y;
+            sk[4 * q + 2] |= v[u][q].z; sk[4 * q + 3] |= v[u][q].w;
+        }
+}
+
 __global__ void __launch_bounds__(FM_THREADS)
 k_fm_wsketch(FmWArgs A) {
     const uint64_t nruns = *A.S.nruns;
@@ -116,7 +141,7 @@ k_fm_wsketch(FmWArgs A) {
         const uint32_t b = A.S.run_start[r], e = A.S.run_start[r + 1];
         if (e - b > FM_SHORT) continue;
         uint32_t sk[FM_WORDS] = {};
-        for (uint32_t i = b; i < e; ++i) fm_w_elem(A, i, sk);
+        for (uint32_t i = b; i < e; i += 4) fm_w_elem4(A, i, 1, e, sk);
         fm_store(A.wsk + r * FM_WORDS, sk);
     }
 }
@@ -130,7 +155,7 @@ k_fm_wsketch_long(FmWArgs A) {
         const uint32_t b = A.S.run_start[r], e = A.S.run_start[r + 1];
         if (e - b <= FM_SHORT) continue;                              // wave-uniform
         uint32_t sk[FM_WORDS] = {};
-        for (uint32_t i = b + lane; i < e; i += WAVE) fm_w_elem(A, i, sk);
+        for (uint32_t i = b + lane; i < e; i += 4 * WAVE) fm_w_elem4(A, i, WAVE, e, sk);
         fm_wave_or(sk);
         if (lane == 0) fm_store(A.wsk + r * FM_WORDS, sk);
     }
@@ -146,21 +171,43 @@ k_fm_asketch(FmAArgs A) {
                               ? (uint32_t)min<uint64_t>(uint64_t(1) << A.a_shift, A.a_domain - base) : 0u;
     for (uint32_t i = threadIdx.x; i < span * FM_WORDS; i += blockDim.x) acc[i] = 0;
     __syncthreads();
-    for (uint32_t q = A.rstarts[k] + threadIdx.x; q < A.rstarts[k + 1]; q += blockDim.x) {
-        const uint2 r = A.R[q];
-        const uint64_t off = uint64_t(r.x) - base;
-        if (r.x >= A.a_domain || off >= span) { atomicExch(A.err, 1u); continue; }
-        const uint32_t w = run_find(A.S, mix32(r.y, A.seed));         // b's run in S, if any
-        if (w == FM_NONE) continue;
-        const uint4* src = reinterpret_cast<const uint4*>(A.wsk + uint64_t(w) * FM_WORDS);
-        uint32_t* dst = acc + off * FM_WORDS;
+    // four R tuples per thread and step, their lookups and gathers in flight together
+    const uint32_t qe = A.rstarts[k + 1];
+    for (uint32_t q0 = A.rstarts[k] + threadIdx.x; q0 < qe; q0 += 4 * blockDim.x) {
+        uint32_t key[4], w[4], off[4];
+        bool live[4];
 #pragma unroll
-        for (int q4 = 0; q4 < FM_WORDS / 4; ++q4) {
-            const uint4 v = src[q4];
-            if (v.x) atomicOr(dst + 4 * q4, v.x);
-            if (v.y) atomicOr(dst + 4 * q4 + 1, v.y);
-            if (v.z) atomicOr(dst + 4 * q4 + 2, v.z);
-            if (v.w) atomicOr(dst + 4 * q4 + 3, v.w);
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t q = q0 + u * blockDim.x;
+            live[u] = false;
+            key[u] = off[u] = 0;
+            if (q < qe) {
+                const uint2 r = A.R[q];
+                const uint64_t o = uint64_t(r.x) - base;
+                if (r.x >= A.a_domain || o >= span) { atomicExch(A.err, 1u); continue; }
+                live[u] = true;
+                off[u] = (uint32_t)o;
+                key[u] = mix32(r.y, A.seed);
+            }
+        }
+        run_find4(A.S, key, live, w);                                 // b's run in S, if any
+        uint4 v[4][FM_WORDS / 4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q4 = 0; q4 < FM_WORDS / 4; ++q4)
+                v[u][q4] = w[u] != FM_NONE ? reinterpret_cast<const uint4*>(A.wsk + uint64_t(w[u]) * FM_WORDS)[q4]
+                                           : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            uint32_t* dst = acc + off[u] * FM_WORDS;
+#pragma unroll
+            for (int q4 = 0; q4 < FM_WORDS / 4; ++q4) {
+                if (v[u][q4].x) atomicOr(dst + 4 * q4, v[u][q4].x);
+                if (v[u][q4].y) atomicOr(dst + 4 * q4 + 1, v[u][q4].y);
+                if (v[u][q4].z) atomicOr(dst + 4 * q4 + 2, v[u][q4].z);
+                if (v[u][q4].w) atomicOr(dst + 4 * q4 + 3, v[u][q4].w);
+            }
         }
     }
     __syncthreads();

@@ -478,6 +478,37 @@ __device__ __forceinline__ uint32_t run_find(const RunIndex& X, uint32_t key) {
     return 0xFFFFFFFFu;
 }
 
+// run_find for four keys at once: their dependent loads (directory, then run
+// keys) are issued together, so that one thread keeps four lookups in flight
+__device__ __forceinline__ void run_find4(const RunIndex& X, const uint32_t (&key)[4], const bool (&live)[4],
+                                          uint32_t (&out)[4]) {
+    uint32_t r[4], rend[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        out[u] = 0xFFFFFFFFu;
+        r[u] = rend[u] = 0;
+        if (live[u]) {
+            const uint32_t p = top_bits(key[u], X.bits);
+            r[u] = X.dir[p];
+            rend[u] = X.dir[p + 1];
+        }
+    }
+    bool more = true;
+    while (more) {
+        more = false;
+        uint32_t k[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) k[u] = r[u] < rend[u] ? X.run_key[r[u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (r[u] >= rend[u]) continue;
+            if (k[u] == key[u]) { out[u] = r[u]; rend[u] = 0; }
+            else if (k[u] > key[u]) rend[u] = 0;
+            else if (++r[u] < rend[u]) more = true;
+        }
+    }
+}
+
 // ------------------------------------- Flajolet-Martin distinct count per A
 // sketch[a] = the FM sketch (FM_WORDS bitmaps of 32 bits) of the set of D
 // values a reaches through R |x| S |x| T.  A sketch is a union, so it is
@@ -507,8 +538,8 @@ struct FmWArgs {                   // per run of S by B: OR of T's sketches of i
     const uint32_t* tsk;
     uint32_t* wsk;                 // [runs][FM_WORDS]
 };
-__global__ void k_fm_wsketch(FmWArgs A);
-__global__ void k_fm_wsketch_long(FmWArgs A);
+__global__ void k_fm_wsketch(FmWArgs A);        // runs of at most FM_SHORT elements, one thread each
+__global__ void k_fm_wsketch_long(FmWArgs A);   // longer runs, one wave each
 
 struct FmAArgs {                   // per A value: OR of the sketches of its B values
     const uint2* R;                // (a, b): by range of a (range mode), or as given (global mode)
