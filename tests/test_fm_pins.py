@@ -79,3 +79,16 @@ def test_estimator_accuracy(n):
     r = np.array(ratios)
     assert abs(r.mean() - 1.0) < 0.08           # asymptotically unbiased
     assert 0.12 < r.std() < 0.30                # 0.78 / sqrt(16) = 0.195
+
+
+def test_hash_against_murmur3_vectors():
+    # MurmurHash3_x86_32 of the empty input with seed s is the finaliser
+    # applied to s; the published test vectors give 0x514E28B7 for s = 1 and
+    # 0x81F16F39 for s = 0xFFFFFFFF.  The value 0 with those seeds hashes to
+    # them: bitmap h & 15 (7, then 9), bit = trailing zeros of h >> 4 (0 for both)
+    sk, est = oracle.fm_sketch(np.array([0], dtype=np.uint32), 1)
+    assert int(sk[7]) == 1 and sk.sum() == 1
+    sk, _ = oracle.fm_sketch(np.array([0], dtype=np.uint32), 0xFFFFFFFF)
+    assert int(sk[9]) == 1 and sk.sum() == 1
+    # one bitmap with lowest zero bit 1, the others 0: 2^(1/16) * 16 / 0.77351
+    assert est == pytest.approx(16 / 0.77351 * 2 ** (1 / 16), rel=1e-14)
