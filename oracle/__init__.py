@@ -11,6 +11,8 @@ Contents
       ``triangle3_count_masked``, ``linear3_count_sampled``
   * the Flajolet-Martin distinct count of D per A: ``linear3_distinct``,
     ``fm_sketch``
+  * the linear join's result written out, in nested-loop order:
+    ``linear3_materialize``, ``linear3_materialize_at``
   * ``cost_model``: the paper's analytic cost formulas (Sec. 4.2, 5.2, 6.3,
     6.5 footnote, App. A), in float64
   * ``mlp_ref``: a float64 reference of the learned planner's network
@@ -58,9 +60,14 @@ def bind(lib):
                                          u32p, u32p, i64, u64, u32p, u64, ctypes.c_uint32,
                                          u32p, u32p, u32p]
     lib.orc_fm_sketch.argtypes = [u32p, u64, ctypes.c_uint32, u32p, u32p]
+    lib.orc_linear3_materialize.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                            u32p, u32p, i64, u64, u64, u64, u32p, u32p]
+    lib.orc_linear3_materialize_at.argtypes = [u32p, u32p, i64, u64, u32p, u32p, i64, u64,
+                                               u32p, u32p, i64, u64, u32p, u64, u32p, u32p]
     for f in ("orc_linear3_count", "orc_join2_size", "orc_triangle3_count",
               "orc_triangle3_count_masked", "orc_linear3_count_sampled",
-              "orc_linear3_distinct", "orc_fm_sketch"):
+              "orc_linear3_distinct", "orc_fm_sketch", "orc_linear3_materialize",
+              "orc_linear3_materialize_at"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -188,3 +195,42 @@ def triangle3_count(R, S, T, smask=None) -> int:
     if st == NOMEM:
         raise MemoryError("triangle3_count")
     return int(lo[0]) + (int(hi[0]) << 64)
+
+
+def linear3_materialize(R, S, T, lo: int = 0, cap: int | None = None):
+    """The result tuples (a, b, c, d) of R |x| S |x| T in nested-loop order
+    (r in R's order, then the matching s in S's order, then the matching t
+    in T's order): elements [lo, lo + cap) as uint32 [k, 4], and the total
+    length of the sequence."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, t1, ts, nt = _rel(T)
+    total = np.zeros(1, dtype=np.uint64)
+    if cap is None:
+        st = lib.orc_linear3_materialize(r0, r1, rs, nr, s0, s1, ss, ns, t0, t1, ts, nt,
+                                         0, 0, None, total.ctypes.data)
+        _check(st, "linear3_materialize")
+        cap = max(int(total[0]) - lo, 0)
+    out = np.zeros((max(cap, 1), 4), dtype=np.uint32)
+    st = lib.orc_linear3_materialize(r0, r1, rs, nr, s0, s1, ss, ns, t0, t1, ts, nt,
+                                     lo, cap, out.ctypes.data, total.ctypes.data)
+    _check(st, "linear3_materialize")
+    n = max(0, min(cap, int(total[0]) - lo))
+    return out[:n], int(total[0])
+
+
+def linear3_materialize_at(R, S, T, positions):
+    """The elements of the same sequence at the given positions (uint32
+    [k, 4]; all-ones rows past its end), and its total length."""
+    lib = _load()
+    ra, r0, r1, rs, nr = _rel(R)
+    sa, s0, s1, ss, ns = _rel(S)
+    ta, t0, t1, ts, nt = _rel(T)
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.uint64))
+    out = np.zeros((max(pos.size, 1), 4), dtype=np.uint32)
+    total = np.zeros(1, dtype=np.uint64)
+    st = lib.orc_linear3_materialize_at(r0, r1, rs, nr, s0, s1, ss, ns, t0, t1, ts, nt,
+                                        pos.ctypes.data, pos.size, out.ctypes.data, total.ctypes.data)
+    _check(st, "linear3_materialize_at")
+    return out[:pos.size], int(total[0])

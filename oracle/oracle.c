@@ -392,3 +392,129 @@ int orc_fm_sketch(const uint32_t* vals, uint64_t n, uint32_t seed, uint32_t* ske
     *est = fm_estimate(sketch);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Linear join with its result written out: the materialised form of the    */
+/* join of Sec. 4 (Sec. 6's experiments aggregate it instead).  The result   */
+/* is the sequence of tuples (a, b, c, d) of R |x| S |x| T in nested-loop    */
+/* order: r in R's order; for each r, the s with s.b = r.b in S's order; for */
+/* each s, the t with t.c = s.c in T's order.  Bags: every combination of    */
+/* matching tuples is one element, duplicates included.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint32_t key; uint32_t pad; uint64_t idx; } kidx_t;
+
+static int cmp_kidx(const void* x, const void* y) {
+    const kidx_t* p = (const kidx_t*)x;
+    const kidx_t* q = (const kidx_t*)y;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    if (p->idx != q->idx) return p->idx < q->idx ? -1 : 1;
+    return 0;
+}
+
+/* indices of a relation ordered by (key column kcol, position): the tuples */
+/* with one key keep the relation's own order                               */
+static kidx_t* key_order(const uint32_t* c0, const uint32_t* c1, int64_t stride, uint64_t n, int kcol) {
+    kidx_t* p = (kidx_t*)malloc((n ? n : 1) * sizeof(kidx_t));
+    if (!p) return NULL;
+    for (uint64_t i = 0; i < n; ++i) {
+        p[i].key = kcol == 0 ? c0[i * stride] : c1[i * stride];
+        p[i].pad = 0;
+        p[i].idx = i;
+    }
+    qsort(p, n, sizeof(kidx_t), cmp_kidx);
+    return p;
+}
+
+/* [lo, hi) of the entries of p[0, n) with key k */
+static void key_range(const kidx_t* p, uint64_t n, uint32_t k, uint64_t* lo, uint64_t* hi) {
+    uint64_t a = 0, b = n;
+    while (a < b) { uint64_t m = a + (b - a) / 2; if (p[m].key < k) a = m + 1; else b = m; }
+    *lo = a;
+    b = n;
+    while (a < b) { uint64_t m = a + (b - a) / 2; if (p[m].key <= k) a = m + 1; else b = m; }
+    *hi = a;
+}
+
+/* Elements [lo, lo + cap) of the sequence (those that exist) go to         */
+/* out[4 * (pos - lo) ...] as (a, b, c, d); its length goes to *total.        */
+int orc_linear3_materialize(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                            const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                            const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
+                            uint64_t lo, uint64_t cap, uint32_t* out, uint64_t* total) {
+    kidx_t* S = key_order(s0, s1, sstride, ns, 0);   /* S by b */
+    kidx_t* T = key_order(t0, t1, tstride, nt, 0);   /* T by c */
+    if (!S || !T) { free(S); free(T); return ORC_NOMEM; }
+    u128 pos = 0;
+    for (uint64_t i = 0; i < nr; ++i) {                                  /* r in R's order */
+        const uint32_t a = r0[i * rstride], b = r1[i * rstride];
+        uint64_t slo, shi;
+        key_range(S, ns, b, &slo, &shi);
+        for (uint64_t j = slo; j < shi; ++j) {                           /* s with s.b = b */
+            const uint32_t c = s1[S[j].idx * sstride];
+            uint64_t tlo, thi;
+            key_range(T, nt, c, &tlo, &thi);
+            for (uint64_t k = tlo; k < thi; ++k, ++pos) {                /* t with t.c = c */
+                if (pos < lo || pos - lo >= cap) continue;
+                uint32_t* o = out + 4 * (uint64_t)(pos - lo);
+                o[0] = a; o[1] = b; o[2] = c; o[3] = t1[T[k].idx * tstride];
+            }
+        }
+    }
+    free(S); free(T);
+    if (pos >> 64) return ORC_OVERFLOW;
+    *total = (uint64_t)pos;
+    return ORC_OK;
+}
+
+/* The elements at the positions pos[0, npos) of the same sequence, each     */
+/* found from the length of every r's block (the sum over its s of the       */
+/* number of t); a position past the end gives (0xFFFFFFFF x 4).  The        */
+/* sequence's length goes to *total.                                         */
+int orc_linear3_materialize_at(const uint32_t* r0, const uint32_t* r1, int64_t rstride, uint64_t nr,
+                               const uint32_t* s0, const uint32_t* s1, int64_t sstride, uint64_t ns,
+                               const uint32_t* t0, const uint32_t* t1, int64_t tstride, uint64_t nt,
+                               const uint64_t* pos, uint64_t npos, uint32_t* out, uint64_t* total) {
+    kidx_t* S = key_order(s0, s1, sstride, ns, 0);
+    kidx_t* T = key_order(t0, t1, tstride, nt, 0);
+    uint64_t* tdeg = (uint64_t*)malloc((ns ? ns : 1) * sizeof(uint64_t));   /* #t for S[j] */
+    uint64_t* start = (uint64_t*)malloc((nr + 1) * sizeof(uint64_t));       /* r's first position */
+    int status = ORC_OK;
+    if (!S || !T || !tdeg || !start) { status = ORC_NOMEM; goto done; }
+    for (uint64_t j = 0; j < ns; ++j) {
+        uint64_t tlo, thi;
+        key_range(T, nt, s1[S[j].idx * sstride], &tlo, &thi);
+        tdeg[j] = thi - tlo;
+    }
+    u128 acc = 0;
+    for (uint64_t i = 0; i < nr; ++i) {
+        start[i] = (uint64_t)acc;
+        uint64_t slo, shi;
+        key_range(S, ns, r1[i * rstride], &slo, &shi);
+        for (uint64_t j = slo; j < shi; ++j) acc += tdeg[j];
+        if (acc >> 64) { status = ORC_OVERFLOW; goto done; }
+    }
+    start[nr] = (uint64_t)acc;
+    *total = (uint64_t)acc;
+    for (uint64_t q = 0; q < npos; ++q) {
+        uint32_t* o = out + 4 * q;
+        const uint64_t p = pos[q];
+        if (p >= start[nr]) { o[0] = o[1] = o[2] = o[3] = 0xFFFFFFFFu; continue; }
+        uint64_t a = 0, b = nr;                       /* last r with start[r] <= p */
+        while (b - a > 1) { uint64_t m = a + (b - a) / 2; if (start[m] <= p) a = m; else b = m; }
+        uint64_t k = p - start[a];
+        const uint32_t rb = r1[a * rstride];
+        uint64_t slo, shi;
+        key_range(S, ns, rb, &slo, &shi);
+        for (uint64_t j = slo; j < shi; ++j) {
+            if (k >= tdeg[j]) { k -= tdeg[j]; continue; }
+            const uint32_t c = s1[S[j].idx * sstride];
+            uint64_t tlo, thi;
+            key_range(T, nt, c, &tlo, &thi);
+            o[0] = r0[a * rstride]; o[1] = rb; o[2] = c; o[3] = t1[T[tlo + k].idx * tstride];
+            break;
+        }
+    }
+done:
+    free(S); free(T); free(tdeg); free(start);
+    return status;
+}
