@@ -179,6 +179,23 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
                         uint32_t a_domain, uint32_t seed, uint32_t* sketch, double* est,
                         void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* The linear join with its result written out (the join of Sec. 4; the
+ * paper's experiments aggregate the result instead of storing it, Sec. 6):
+ * the tuples (a, b, c, d) of R |x| S |x| T, bags, in nested-loop order --
+ * R's tuples in R's order; for each, the S tuples with s.b = r.b in S's
+ * order; for each of those, the T tuples with t.c = s.c in T's order.
+ * out: device uint32[cap][4]; receives the elements at positions
+ * [first, first + cap) of that sequence, as many as exist (rows past the
+ * end are not touched).  total: device uint64[1], always written with the
+ * sequence's length, so a first call with cap = 0 (out may be NULL) sizes
+ * the output, and windows of any size can be taken one after another.
+ * The workspace size comes from mj_linear3_materialize_workspace.  Keys are
+ * arbitrary 32-bit patterns; no a_domain applies.                        */
+uint64_t mj_linear3_materialize_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t);
+int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                           uint64_t first, uint64_t cap, uint32_t* out, uint64_t* total,
+                           void* workspace, uint64_t workspace_bytes, void* stream);
+
 /* A batch of independent joins (many joins of uneven size).  Every item
  * carries its relations, its output (uint64[a_domain] or uint64[1], device)
  * and a plan from mj_plan (or the autotuner).  The preparation of every join

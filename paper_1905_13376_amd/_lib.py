@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libmj.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libmj.so not found at {LIB_PATH}; build it with "
-                      "`python -m paper_1905_13376_amd.build` (no CPU fallback exists)")
+                      "`python paper_1905_13376_amd/build.py` (no CPU fallback exists)")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -80,6 +80,8 @@ _SIGS = {
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
     "mj_linear3_distinct_workspace": ([_u64, _u64, _u64, _u32], _u64),
     "mj_linear3_distinct": ([_vp, _RP, _RP, _RP, _u32, _u32, _vp, _vp, _vp, _u64, _vp], _i32),
+    "mj_linear3_materialize_workspace": ([_u64, _u64, _u64], _u64),
+    "mj_linear3_materialize": ([_vp, _RP, _RP, _RP, _u64, _u64, _vp, _vp, _vp, _u64, _vp], _i32),
     "mj_join2_size": ([_vp, _RP, _RP, ctypes.POINTER(_u64), _vp, _u64, _vp], _i32),
     "mj_ctx_profile": ([_vp, _i32], _i32),
     "mj_mlp_param_bytes": ([], _u64),
@@ -235,6 +237,36 @@ class Context:
                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)),
                "mj_linear3_distinct")
         return sketch[:a_domain], est[:a_domain]
+
+    def linear3_materialize(self, R, S, T, first=0, out=None, total=None, workspace=None, stream=None):
+        """The result tuples (a, b, c, d) of R |x| S |x| T in nested-loop order
+        (R's order, then the matching S tuples in S's order, then the matching
+        T tuples in T's order), from position ``first``: written to ``out``
+        (int32 [cap, 4]; as many rows as exist are written).  Without ``out``
+        the total is read first and ``out`` is sized to hold the rest.
+        Returns (out, total), ``total`` an int64 [1] device tensor."""
+        if total is None:
+            total = torch.empty(1, dtype=torch.int64, device=R.device)
+        need = _lib.mj_linear3_materialize_workspace(R.shape[0], S.shape[0], T.shape[0])
+        ws = workspace if workspace is not None else self.workspace(need, R.device)
+
+        def call(o, cap):
+            _check(_lib.mj_linear3_materialize(self._h, rel(R), rel(S), rel(T), first, cap,
+                                               ctypes.c_void_p(o.data_ptr() if o is not None else 0),
+                                               ctypes.c_void_p(total.data_ptr()),
+                                               ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                               _stream_ptr(stream)), "mj_linear3_materialize")
+        if out is None:
+            call(None, 0)
+            n = max(int(total.item()) - first, 0)
+            out = torch.empty((max(n, 1), 4), dtype=torch.int32, device=R.device)
+            if n:
+                call(out, n)
+            return out[:n], total
+        if out.dim() != 2 or out.shape[1] != 4 or out.dtype != torch.int32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 [cap, 4] tensor")
+        call(out, out.shape[0])
+        return out, total
 
     def triangle3_count(self, R, S, T, plan: Plan | None = None, out=None, workspace=None,
                         stream=None) -> torch.Tensor:

@@ -1,7 +1,9 @@
 """Build libmj.so (gfx950) in place with hipcc.
 
-    python -m paper_1905_13376_amd.build          # incremental
-    python -m paper_1905_13376_amd.build --force  # rebuild everything
+    python paper_1905_13376_amd/build.py          # incremental
+    python paper_1905_13376_amd/build.py --force  # rebuild everything
+
+(run as a script: importing the package would load the old libmj.so)
 """
 from __future__ import annotations
 

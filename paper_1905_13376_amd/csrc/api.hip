@@ -460,6 +460,19 @@ int launch_scan_u32(Prof* prof, const uint32_t* in, uint64_t n, unsigned long lo
     return MJ_OK;
 }
 
+int launch_scan_u64(Prof* prof, const unsigned long long* in, uint64_t n, unsigned long long* partial,
+                    unsigned long long* out, hipStream_t s) {
+    const uint32_t nblk = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
+    if (nblk == 0) {
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+        return MJ_OK;
+    }
+    MJ_LAUNCH(prof, "k_scan_reduce64", k_scan_reduce64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
+    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, nblk);
+    MJ_LAUNCH(prof, "k_scan_apply64", k_scan_apply64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    return MJ_OK;
+}
+
 // Sort n 64-bit keys in place (8 stable passes of 8 bits; tmp is the other buffer).
 // LSD radix sort of 64-bit keys on bytes first_pass..7 (first_pass = 4:
 // grouped by the high word, stable in the low word); first_pass must be even
@@ -516,13 +529,14 @@ RunIndex run_index(const RunBuf& X) {
     return I;
 }
 
+// (mix(key) << 32 | mix(other)), or the other value itself as low word
 int tri_keys(Prof* prof, const mj_rel& r, int key_col, unsigned long long* out, uint32_t seed,
-             hipStream_t s) {
+             hipStream_t s, bool raw_low = false) {
     if (r.n == 0) return MJ_OK;
     TriKeyArgs K;
     K.key_col = key_col ? r.col1 : r.col0;
     K.val_col = key_col ? r.col0 : r.col1;
-    K.stride = r.stride; K.n = r.n; K.seed = seed; K.out = out;
+    K.stride = r.stride; K.n = r.n; K.seed = seed; K.raw_low = raw_low ? 1u : 0u; K.out = out;
     MJ_LAUNCH(prof, "k_tri_keys", k_tri_keys, dim3(grid_for(r.n, 256, 16384)), dim3(256), 0, s, K);
     return MJ_OK;
 }
@@ -917,6 +931,50 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
     fm_ranges(nr, a_domain, L.a_bits, L.a_shift, L.by_range);
     take_part(B, L.Ra, nr, L.a_bits);
     L.err = B.take<uint32_t>(1);
+    L.bytes = B.off + 256;
+    return L;
+}
+
+// --------------------------------------------------- materialised linear join
+struct EmitLayout {
+    unsigned long long *Sk, *Tk, *tmp;
+    uint32_t *rs_hist, *rs_counts, *rs_starts;
+    uint32_t* flags;
+    unsigned long long *ridx, *partial;
+    RunBuf S, T;
+    uint32_t *sc, *td, *tdeg, *tst, *sst, *pdeg;
+    unsigned long long *P_S, *wout, *O_I, *O_R;
+    ulonglong4* tiles;
+    size_t bytes;
+};
+
+EmitLayout emit_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt) {
+    Bump B(ws);
+    EmitLayout L{};
+    const uint64_t nmax = std::max<uint64_t>({nr, ns, nt, 1});
+    L.Sk = B.take<unsigned long long>(std::max<uint64_t>(ns, 1));
+    L.Tk = B.take<unsigned long long>(std::max<uint64_t>(nt, 1));
+    L.tmp = B.take<unsigned long long>(nmax);
+    const uint64_t ntiles = (nmax + RS_TILE - 1) / RS_TILE;
+    L.rs_hist = B.take<uint32_t>(256 * ntiles);
+    L.rs_counts = B.take<uint32_t>(256);
+    L.rs_starts = B.take<uint32_t>(257);
+    L.flags = B.take<uint32_t>(nmax);
+    L.ridx = B.take<unsigned long long>(nmax + 1);
+    L.partial = B.take<unsigned long long>((nmax + SCAN_TILE - 1) / SCAN_TILE + 1);
+    take_runs(B, L.S, ns, true);
+    take_runs(B, L.T, nt, true);
+    L.sc = B.take<uint32_t>(std::max<uint64_t>(ns, 1));
+    L.td = B.take<uint32_t>(std::max<uint64_t>(nt, 1));
+    L.tdeg = B.take<uint32_t>(std::max<uint64_t>(ns, 1));
+    L.tst = B.take<uint32_t>(std::max<uint64_t>(ns, 1));
+    L.P_S = B.take<unsigned long long>(ns + 1);
+    L.sst = B.take<uint32_t>(std::max<uint64_t>(nr, 1));
+    L.pdeg = B.take<uint32_t>(std::max<uint64_t>(nr, 1));
+    L.wout = B.take<unsigned long long>(std::max<uint64_t>(nr, 1));
+    L.O_I = B.take<unsigned long long>(nr + 1);
+    L.O_R = B.take<unsigned long long>(nr + 1);
+    L.tiles = B.take<ulonglong4>(EMIT_CHUNK_TILES);
     L.bytes = B.off + 256;
     return L;
 }
@@ -1391,6 +1449,67 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
         MJ_LAUNCH(prof, "k_fm_asketch_global", k_fm_asketch_global, dim3(grid_for(R->n, 256, 16384)), dim3(256),
                   0, s, Fa);
         MJ_LAUNCH(prof, "k_fm_estimate", k_fm_estimate, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s, Fa);
+    }
+    return MJ_OK;
+}
+
+uint64_t mj_linear3_materialize_workspace(uint64_t n_r, uint64_t n_s, uint64_t n_t) {
+    return emit_layout(nullptr, n_r, n_s, n_t).bytes;
+}
+
+int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                           uint64_t first, uint64_t cap, uint32_t* out, uint64_t* total,
+                           void* ws, uint64_t ws_bytes, void* stream) {
+    if (!ctx || !total || (cap && !out)) return MJ_ERR_INVALID_ARG;
+    int st;
+    if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
+    EmitLayout L = emit_layout(nullptr, R->n, S->n, T->n);
+    if (!ws || ws_bytes < L.bytes) return MJ_ERR_WORKSPACE;
+    L = emit_layout(ws, R->n, S->n, T->n);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Prof* prof = &ctx->prof;
+    unsigned long long* tot = reinterpret_cast<unsigned long long*>(total);
+    if (R->n == 0 || S->n == 0 || T->n == 0) {
+        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, tot, (uint64_t)1, 0ull);
+        return MJ_OK;
+    }
+    // the seed only groups equal keys; the output order does not depend on it
+    const uint32_t seed = 0x2545F491u;
+    TriLayout TL{};                    // launch_runs only uses flags / ridx / partial
+    TL.flags = L.flags; TL.ridx = L.ridx; TL.partial = L.partial;
+    // T grouped by C with its raw D values, S by B with its raw C values; the
+    // sort is stable, so every run keeps its relation's order
+    if ((st = tri_keys(prof, *T, 0, L.Tk, seed, s, true))) return st;
+    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T->n, L.rs_hist, L.rs_counts, L.rs_starts, s, 4))) return st;
+    if ((st = launch_runs(prof, TL, L.Tk, T->n, L.T, L.td, s))) return st;
+    if ((st = tri_keys(prof, *S, 0, L.Sk, seed, s, true))) return st;
+    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S->n, L.rs_hist, L.rs_counts, L.rs_starts, s, 4))) return st;
+    if ((st = launch_runs(prof, TL, L.Sk, S->n, L.S, L.sc, s))) return st;
+    EmitSArgs Es;
+    Es.sc = L.sc; Es.ns = S->n; Es.T = run_index(L.T); Es.seed = seed; Es.tdeg = L.tdeg; Es.tst = L.tst;
+    MJ_LAUNCH(prof, "k_emit_sdeg", k_emit_sdeg, dim3(grid_for((S->n + 3) / 4, 256, 16384)), dim3(256), 0, s, Es);
+    if ((st = launch_scan_u32(prof, L.tdeg, S->n, L.partial, L.P_S, s))) return st;
+    EmitRArgs Er;
+    Er.r1 = R->col1; Er.rstride = R->stride; Er.nr = R->n; Er.S = run_index(L.S); Er.seed = seed;
+    Er.P_S = L.P_S; Er.sst = L.sst; Er.pdeg = L.pdeg; Er.wout = L.wout;
+    MJ_LAUNCH(prof, "k_emit_rdeg", k_emit_rdeg, dim3(grid_for((R->n + 3) / 4, 256, 16384)), dim3(256), 0, s, Er);
+    if ((st = launch_scan_u32(prof, L.pdeg, R->n, L.partial, L.O_I, s))) return st;
+    if ((st = launch_scan_u64(prof, L.wout, R->n, L.partial, L.O_R, s))) return st;
+    if (hipMemcpyAsync(tot, L.O_R + R->n, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MJ_ERR_HIP;
+    // the window, in chunks of EMIT_CHUNK_TILES tiles
+    const uint64_t chunk_max = uint64_t(EMIT_CHUNK_TILES) * EMIT_TILE;
+    for (uint64_t c0 = 0; c0 < cap; c0 += chunk_max) {
+        const uint64_t n = std::min<uint64_t>(cap - c0, chunk_max);
+        const uint32_t ntiles = (uint32_t)((n + EMIT_TILE - 1) / EMIT_TILE);
+        EmitArgs E;
+        E.r0 = R->col0; E.r1 = R->col1; E.rstride = R->stride; E.nr = R->n;
+        E.O_R = L.O_R; E.O_I = L.O_I; E.sst = L.sst; E.P_S = L.P_S; E.sc = L.sc; E.tst = L.tst; E.td = L.td;
+        E.first = first + c0; E.cap = n;
+        E.out = reinterpret_cast<uint4*>(out) + c0;
+        E.tiles = L.tiles;
+        MJ_LAUNCH(prof, "k_emit_tiles", k_emit_tiles, dim3((ntiles + 255) / 256), dim3(256), 0, s, E, ntiles);
+        MJ_LAUNCH(prof, "k_emit", k_emit, dim3(ntiles), dim3(EMIT_THREADS), 0, s, E);
     }
     return MJ_OK;
 }

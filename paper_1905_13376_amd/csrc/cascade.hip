@@ -130,10 +130,10 @@ k_cas_index(CasIndexArgs A) {
     }
 }
 
-// ------------------------------------------------------------- u32 -> u64 scan
+// ------------------------------------------------------------- u32/u64 -> u64 scan
 // out[i] = sum of in[0..i) for i in [0, n]; three launches.
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial) {
+template <class In>
+__device__ __forceinline__ void scan_reduce(const In* in, uint64_t n, unsigned long long* partial) {
     const uint64_t beg = uint64_t(blockIdx.x) * SCAN_TILE;
     const uint64_t end = min<uint64_t>(beg + SCAN_TILE, n);
     unsigned long long s = 0;
@@ -147,6 +147,14 @@ k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial) {
         for (int w = 0; w < SCAN_THREADS / WAVE; ++w) t += ws[w];
         partial[blockIdx.x] = t;
     }
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial) { scan_reduce(in, n, partial); }
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_reduce64(const unsigned long long* in, uint64_t n, unsigned long long* partial) {
+    scan_reduce(in, n, partial);
 }
 
 // exclusive scan of the partials in place (one block); partial[nblk] = total
@@ -184,9 +192,9 @@ k_scan_partials(unsigned long long* partial, uint32_t nblk) {
     if (threadIdx.x == 0) partial[nblk] = carry;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
-             unsigned long long* out) {
+template <class In>
+__device__ __forceinline__ void scan_apply(const In* in, uint64_t n, const unsigned long long* partial,
+                                           unsigned long long* out) {
     __shared__ unsigned long long ws[SCAN_THREADS / WAVE + 1];
     const uint64_t beg = uint64_t(blockIdx.x) * SCAN_TILE;
     const uint64_t end = min<uint64_t>(beg + SCAN_TILE, n);
@@ -215,6 +223,17 @@ k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
         __syncthreads();
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[gridDim.x];
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial, unsigned long long* out) {
+    scan_apply(in, n, partial, out);
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_apply64(const unsigned long long* in, uint64_t n, const unsigned long long* partial,
+               unsigned long long* out) {
+    scan_apply(in, n, partial, out);
 }
 
 // ------------------------------------------------------------- expansion

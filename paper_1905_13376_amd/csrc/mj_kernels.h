@@ -410,6 +410,9 @@ __global__ void k_cas_probe(CasProbeArgs A);
 
 
 __global__ void k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial);
+__global__ void k_scan_reduce64(const unsigned long long* in, uint64_t n, unsigned long long* partial);
+__global__ void k_scan_apply64(const unsigned long long* in, uint64_t n, const unsigned long long* partial,
+                               unsigned long long* out);
 __global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
 __global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
                              unsigned long long* out);
@@ -564,6 +567,7 @@ struct TriKeyArgs {
     int64_t stride;
     uint64_t n;
     uint32_t seed;
+    uint32_t raw_low;              // 1: the low word is the value itself, not its mix
     unsigned long long* out;
 };
 
@@ -640,6 +644,59 @@ __global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nru
 __global__ void k_tri_classify(TriClassifyArgs A);
 __global__ void k_tri_light(TriJoinArgs A);
 __global__ void k_tri_heavy(TriJoinArgs A);
+
+// ------------------------------------------------ materialised linear join
+// The result tuples (a, b, c, d) of R |x| S |x| T written out in nested-loop
+// order: r in R's order, then the s with s.b = r.b in S's order, then the t
+// with t.c = s.c in T's order.  S and T are grouped by a stable sort on the
+// mixed key (high word) with the raw other value as low word, so a run keeps
+// its relation's order.  Positions come from three prefix sums:
+//   P_S[i]  over S in run order: number of t for the S elements before i
+//   O_I[j]  over R: number of (r, s) pairs of the R tuples before j
+//   O_R[j]  over R: number of result tuples of the R tuples before j
+struct EmitSArgs {                 // per S element (run order): its T run
+    const uint32_t* sc;            // [ns] c, raw
+    uint64_t ns;
+    RunIndex T;
+    uint32_t seed;
+    uint32_t* tdeg;                // [ns] number of t with t.c = c
+    uint32_t* tst;                 // [ns] first of them in T's run order
+};
+struct EmitRArgs {                 // per R tuple (R's order): its S run
+    const uint32_t* r1;            // R's B column
+    int64_t rstride;
+    uint64_t nr;
+    RunIndex S;
+    uint32_t seed;
+    const unsigned long long* P_S; // [ns + 1]
+    uint32_t* sst;                 // [nr] first s with s.b = r.b in S's run order
+    uint32_t* pdeg;                // [nr] number of such s
+    unsigned long long* wout;      // [nr] number of result tuples of r
+};
+constexpr int EMIT_THREADS = 256;
+constexpr uint32_t EMIT_TILE = 16384;      // output positions per workgroup
+constexpr uint32_t EMIT_JWIN = 2048;       // R tuples of a tile whose pair starts fit LDS
+struct EmitArgs {
+    const uint32_t* r0;            // R's columns (a, b)
+    const uint32_t* r1;
+    int64_t rstride;
+    uint64_t nr;
+    const unsigned long long* O_R; // [nr + 1]
+    const unsigned long long* O_I; // [nr + 1]
+    const uint32_t* sst;           // [nr]
+    const unsigned long long* P_S; // [ns + 1]
+    const uint32_t* sc;            // [ns]
+    const uint32_t* tst;           // [ns]
+    const uint32_t* td;            // [nt] d, raw, in T's run order
+    uint64_t first, cap;           // window of output positions (one launch's chunk)
+    uint4* out;                    // [cap]
+    ulonglong4* tiles;             // per tile: first and last pair, first and last R tuple
+};
+constexpr uint32_t EMIT_CHUNK_TILES = 65536;   // tiles per launch (2^30 output positions)
+__global__ void k_emit_sdeg(EmitSArgs A);
+__global__ void k_emit_rdeg(EmitRArgs A);
+__global__ void k_emit_tiles(EmitArgs A, uint32_t ntiles);
+__global__ void k_emit(EmitArgs A);
 
 // ------------------------------------------------------------ learned planner
 constexpr int MLP_IN = 100, MLP_H = 64, MLP_OUT = 7;

@@ -35,7 +35,7 @@ __global__ void k_tri_keys(TriKeyArgs A) {
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t hi = ld_col(A.key_col, i, A.stride);
         const uint32_t lo = ld_col(A.val_col, i, A.stride);
-        A.out[i] = ((unsigned long long)mix32(hi, A.seed) << 32) | mix32(lo, A.seed);
+        A.out[i] = ((unsigned long long)mix32(hi, A.seed) << 32) | (A.raw_low ? lo : mix32(lo, A.seed));
     }
 }
 
