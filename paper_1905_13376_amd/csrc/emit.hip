@@ -17,7 +17,7 @@
 // pair (its R tuple found by a binary search over the tile's pair starts in
 // LDS), and then all threads write the pairs' result tuples in order, each
 // finding its pair by a binary search over the batch in LDS.  Writes are
-// 16-byte and consecutive across the workgroup.
+// 16-byte, consecutive across the workgroup, and nontemporal.
 #include "mj_kernels.h"
 
 namespace mj {
@@ -159,10 +159,30 @@ k_emit(EmitArgs A) {
         }
         __syncthreads();
         const uint32_t qend = s_qend;
-        for (uint32_t q = pstart[0] + threadIdx.x; q < qend; q += blockDim.x) {
-            const uint32_t k = (uint32_t)last_le(pstart, 0, nvalid, q);
-            const uint4 r = prec[k];
-            A.out[p0 - A.first + q] = make_uint4(r.x, r.y, r.z, A.td[r.w + (q - pstart[k])]);
+        // four outputs per thread and step: their searches and loads overlap
+        for (uint32_t q0 = pstart[0] + threadIdx.x; q0 < qend; q0 += 4 * blockDim.x) {
+            uint32_t d[4];
+            uint4 r[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = min(q0 + u * blockDim.x, qend - 1);      // clamped: stays in range
+                const uint32_t k = (uint32_t)last_le(pstart, 0, nvalid, q);
+                r[u] = prec[k];
+                r[u].w += q - pstart[k];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u] = A.td[r[u].w];
+            // streaming stores: the output is not read again here, and keeping
+            // it out of the caches leaves them to T's runs
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = q0 + u * blockDim.x;
+                if (q < qend) {
+                    u32x4 v;
+                    v.x = r[u].x; v.y = r[u].y; v.z = r[u].z; v.w = d[u];
+                    __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(A.out) + (p0 - A.first + q));
+                }
+            }
         }
         __syncthreads();
     }
