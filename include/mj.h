@@ -64,8 +64,17 @@ typedef enum {
     MJ_ALGO_CASCADE = 1,       /* cascade of two binary hash joins (Sec. 6.3)       */
     MJ_ALGO_STAR = 2,          /* linear only: star three-way join, R and T         */
                                /* resident, S streamed once (Sec. 6, star join)     */
-    MJ_ALGO_STAR_CASCADE = 3   /* linear only: cascade of two binary star joins     */
+    MJ_ALGO_STAR_CASCADE = 3,  /* linear only: cascade of two binary star joins     */
+    MJ_ALGO_ORIENTED = 4       /* cyclic only: one symmetric simple relation, each  */
+                               /* triangle counted once along degree-ordered edges  */
 } mj_algo;
+
+/* mj_plan_t.flags bits, set by mj_plan */
+enum {
+    MJ_PLAN_SYMMETRIC_SIMPLE = 1 /* cyclic: R, S and T are one relation (same columns, */
+                                 /* stride and size) that is symmetric, without        */
+                                 /* duplicate tuples and without loops (a, a)          */
+};
 typedef enum {
     MJ_PLANNER_ANALYTIC = 0,   /* cost model with measured device constants        */
     MJ_PLANNER_LEARNED = 1,    /* MLP on degree sketches; analytic fallback         */
@@ -89,7 +98,7 @@ typedef struct {
     uint32_t seed;             /* hash seed                                 */
     uint64_t n_r, n_s, n_t;    /* sizes the plan was made for               */
     uint32_t a_domain;         /* linear: length of the per-A output        */
-    uint32_t flags;            /* reserved, 0                               */
+    uint32_t flags;            /* MJ_PLAN_* properties mj_plan found        */
     uint64_t join2_size;       /* |R |x| S| on B, exact when known, else 0  */
     uint64_t workspace_bytes;  /* bytes the count call needs                */
     double est_ms_3way;        /* planner's time estimates (0 = not known)  */
@@ -142,7 +151,15 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
 /* Cyclic three-way join, total count (Sec. 5):
  *   total[0] = #{ (r,s,t) : r.b = s.b, s.c = t.c, t.a = r.a }
  * With R = S = T = the symmetric edge relation of a simple graph this is
- * trace(A^3) = 6 x (number of triangles).  total: device uint64[1].      */
+ * trace(A^3) = 6 x (number of triangles).  total: device uint64[1].
+ * A plan with algo MJ_ALGO_ORIENTED, which mj_plan offers only when it has
+ * found MJ_PLAN_SYMMETRIC_SIMPLE, keeps every edge in one direction (from
+ * the end of lower degree, ties broken by a hash of the id) and counts each
+ * triangle once by intersecting the out-lists of an edge's ends; total is
+ * six times that, the same value.  The plan certifies the property for the
+ * data it was made on: if at count time the kept edges are not exactly
+ * half of them, or a loop or an end without edges of its own appears,
+ * total is set to all ones (UINT64_MAX).                                 */
 int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                        uint64_t* total, const mj_plan_t* plan,
                        void* workspace, uint64_t workspace_bytes, void* stream);

@@ -25,7 +25,8 @@ STATUS = {0: "MJ_OK", -1: "MJ_ERR_INVALID_ARG", -2: "MJ_ERR_KEY_RANGE", -3: "MJ_
           -4: "MJ_ERR_PLAN_MISMATCH", -5: "MJ_ERR_HIP", -6: "MJ_ERR_OVERFLOW",
           -7: "MJ_ERR_UNSUPPORTED"}
 LINEAR, TRIANGLE = 0, 1
-ALGO_3WAY, ALGO_CASCADE, ALGO_STAR, ALGO_STAR_CASCADE = 0, 1, 2, 3
+ALGO_3WAY, ALGO_CASCADE, ALGO_STAR, ALGO_STAR_CASCADE, ALGO_ORIENTED = 0, 1, 2, 3, 4
+PLAN_SYMMETRIC_SIMPLE = 1          # mj_plan_t.flags: R = S = T, symmetric, no duplicates or loops
 PLANNERS = {"analytic": 0, "learned": 1, "fixed": 2}
 
 

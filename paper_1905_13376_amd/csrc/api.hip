@@ -129,6 +129,10 @@ int check_rel(const mj_rel* r) {
     return MJ_OK;
 }
 
+bool same_rel(const mj_rel& x, const mj_rel& y) {
+    return x.col0 == y.col0 && x.col1 == y.col1 && x.n == y.n && x.stride == y.stride;
+}
+
 uint32_t ceil_log2(uint64_t x) {
     uint32_t b = 0;
     while ((uint64_t(1) << b) < x) ++b;
@@ -595,15 +599,37 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
     (void)num_cu; (void)out;
     int st;
     const uint32_t seed = p.seed;
-    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)) and (m(c), m(b)), T -> (m(c), m(a))
-    if ((st = tri_keys(prof, R, 1, L.Rk, seed, s))) return st;
-    if ((st = tri_keys(prof, S, 0, L.Sk, seed, s))) return st;
-    if ((st = tri_keys(prof, S, 1, L.Sk2, seed, s))) return st;
-    if ((st = tri_keys(prof, T, 0, L.Tk, seed, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Rk, L.tmp, R.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Sk, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Sk2, L.tmp, S.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    if ((st = launch_radix_sort(prof, L.Tk, L.tmp, T.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    // keys: R -> (m(b), m(a)), S -> (m(b), m(c)) and (m(c), m(b)), T -> (m(c), m(a)).
+    // An array made from the same (key column, other column) as an earlier
+    // one -- R = S = T as one symmetric relation gives two distinct arrays,
+    // not four -- is copied from it instead of sorted again.
+    struct KeySrc { const mj_rel* r; int key_col; unsigned long long* dst; };
+    const KeySrc src[4] = {{&R, 1, L.Rk}, {&S, 0, L.Sk}, {&S, 1, L.Sk2}, {&T, 0, L.Tk}};
+    auto cols = [](const KeySrc& k, const uint32_t*& kc, const uint32_t*& vc) {
+        kc = k.key_col ? k.r->col1 : k.r->col0;
+        vc = k.key_col ? k.r->col0 : k.r->col1;
+    };
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t *ki, *vi;
+        cols(src[i], ki, vi);
+        int same = -1;
+        for (int j = 0; j < i && same < 0; ++j) {
+            const uint32_t *kj, *vj;
+            cols(src[j], kj, vj);
+            if (ki == kj && vi == vj && src[i].r->stride == src[j].r->stride && src[i].r->n == src[j].r->n)
+                same = j;
+        }
+        const uint64_t n = src[i].r->n;
+        if (same >= 0) {
+            if (n && hipMemcpyAsync(src[i].dst, src[same].dst, n * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return MJ_ERR_HIP;
+            continue;
+        }
+        if ((st = tri_keys(prof, *src[i].r, src[i].key_col, src[i].dst, seed, s))) return st;
+        if ((st = launch_radix_sort(prof, src[i].dst, L.tmp, n, L.rs_hist, L.rs_counts, L.rs_starts, s)))
+            return st;
+    }
     // lists of R per B and of T per C; groups of S per B and per C
     if ((st = launch_runs(prof, L, L.Rk, R.n, L.R, L.Rl, s))) return st;
     if ((st = launch_runs(prof, L, L.Tk, T.n, L.T, L.Tl, s))) return st;
@@ -935,6 +961,113 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
     return L;
 }
 
+// --------------------------------------------- degree-oriented cyclic join
+struct OrientLayout {
+    unsigned long long *K, *K2, *tmp;
+    uint32_t *rs_hist, *rs_counts, *rs_starts;
+    uint32_t* flags;
+    unsigned long long *ridx, *partial;
+    RunBuf U;
+    uint2* E;                          // kept edges (at most n)
+    uint32_t* err;
+    size_t bytes;
+};
+
+// with_check: the second key array of the planner's symmetry check
+OrientLayout orient_layout(void* ws, uint64_t n, bool with_check) {
+    Bump B(ws);
+    OrientLayout L{};
+    const uint64_t m = std::max<uint64_t>(n, 1);
+    L.K = B.take<unsigned long long>(m);
+    L.K2 = with_check ? B.take<unsigned long long>(m) : nullptr;
+    L.tmp = B.take<unsigned long long>(m);
+    L.rs_hist = B.take<uint32_t>(256 * ((m + RS_TILE - 1) / RS_TILE));
+    L.rs_counts = B.take<uint32_t>(256);
+    L.rs_starts = B.take<uint32_t>(257);
+    L.flags = B.take<uint32_t>(m);
+    L.ridx = B.take<unsigned long long>(m + 1);
+    L.partial = B.take<unsigned long long>((m + SCAN_TILE - 1) / SCAN_TILE + 1);
+    take_runs(B, L.U, n, true);
+    L.E = B.take<uint2>(m);
+    L.err = B.take<uint32_t>(1);
+    L.bytes = (B.off + 511) & ~size_t(255);      // a multiple of 256: the cyclic join's layout follows
+    return L;
+}
+
+// the plan of the cyclic join over the kept edges
+mj_plan_t oriented_inner(const mj_plan_t& p) {
+    mj_plan_t q = p;
+    q.algo = MJ_ALGO_3WAY;
+    q.n_r = q.n_s = q.n_t = p.n_r / 2;
+    return q;
+}
+
+size_t oriented_bytes(const mj_plan_t& p) {
+    return orient_layout(nullptr, p.n_r, false).bytes + tri_layout(nullptr, oriented_inner(p)).bytes;
+}
+
+// Is R = S = T one symmetric relation without duplicates or loops?  Sorts
+// (m(u), m(v)) and (m(v), m(u)) fully and compares them (synchronous).
+int symmetric_simple(Prof* prof, const mj_rel& E, uint32_t seed, void* ws, bool& yes, hipStream_t s) {
+    OrientLayout L = orient_layout(ws, E.n, true);
+    int st;
+    if ((st = tri_keys(prof, E, 0, L.K, seed, s))) return st;
+    if ((st = tri_keys(prof, E, 1, L.K2, seed, s))) return st;
+    if ((st = launch_radix_sort(prof, L.K, L.tmp, E.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    if ((st = launch_radix_sort(prof, L.K2, L.tmp, E.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCH(prof, "k_sym_check", k_sym_check, dim3(grid_for(E.n, 256, 8192)), dim3(256), 0, s, L.K, L.K2,
+              E.n, L.err);
+    uint32_t bad = 1;
+    MJ_HIP(hipMemcpyAsync(&bad, L.err, 4, hipMemcpyDeviceToHost, s));
+    MJ_HIP(hipStreamSynchronize(s));
+    yes = bad == 0;
+    return MJ_OK;
+}
+
+int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p, unsigned long long* out,
+                 void* ws, hipStream_t s) {
+    OrientLayout O = orient_layout(ws, Erel.n, false);
+    const mj_plan_t q = oriented_inner(p);
+    TriLayout L = tri_layout(static_cast<char*>(ws) + O.bytes, q);
+    int st;
+    // degrees: runs of m(u) over the relation (grouped on the high word)
+    if ((st = tri_keys(prof, Erel, 0, O.K, p.seed, s))) return st;
+    if ((st = launch_radix_sort(prof, O.K, O.tmp, Erel.n, O.rs_hist, O.rs_counts, O.rs_starts, s, 4))) return st;
+    TriLayout TL{};
+    TL.flags = O.flags; TL.ridx = O.ridx; TL.partial = O.partial;
+    if ((st = launch_runs(prof, TL, O.K, Erel.n, O.U, nullptr, s))) return st;
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, O.err, (uint64_t)1, 0u);
+    OrientArgs A;
+    A.c0 = Erel.col0; A.c1 = Erel.col1; A.stride = Erel.stride; A.n = Erel.n;
+    A.U = run_index(O.U); A.seed = p.seed;
+    A.flags = O.flags; A.ridx = O.ridx; A.E = O.E; A.err = O.err; A.total = out;
+    MJ_LAUNCH(prof, "k_orient_flags", k_orient_flags, dim3(grid_for((Erel.n + 1) / 2, 256, 16384)), dim3(256),
+              0, s, A);
+    if ((st = launch_scan_u32(prof, O.flags, Erel.n, O.partial, O.ridx, s))) return st;
+    MJ_LAUNCH(prof, "k_orient_compact", k_orient_compact, dim3(grid_for(Erel.n, 256, 16384)), dim3(256), 0, s, A);
+    // R' = the kept edges reversed, S' = T' = the kept edges
+    mj_rel Rp, Sp;
+    Sp.col0 = reinterpret_cast<const uint32_t*>(O.E);
+    Sp.col1 = Sp.col0 + 1;
+    Sp.n = q.n_s;
+    Sp.stride = 2;
+    Rp = Sp;
+    std::swap(Rp.col0, Rp.col1);
+    if (q.n_s) {
+        if ((st = tri_prepare(prof, num_cu, Rp, Sp, Sp, q, L, out, s))) return st;
+        const uint32_t persistent = (uint32_t)num_cu * 8;
+        for (int pass = 0; pass < 2; ++pass) {
+            TriJoinArgs J = tri_join_args(L, q, out, pass);
+            MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
+            MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s,
+                      J);
+        }
+    }
+    MJ_LAUNCH(prof, "k_orient_finish", k_orient_finish, dim3(1), dim3(64), 0, s, A, q.n_s);
+    return MJ_OK;
+}
+
 // --------------------------------------------------- materialised linear join
 struct EmitLayout {
     unsigned long long *Sk, *Tk, *tmp;
@@ -1117,6 +1250,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
 
     mj_plan_t p = planner == MJ_PLANNER_FIXED ? *plan : mj_plan_t{};
     p.kind = kind;
+    p.flags = 0;                               // properties are found here, never taken on trust
     p.n_r = R->n; p.n_s = S->n; p.n_t = T->n;
     p.a_domain = kind == MJ_LINEAR ? a_domain : 0;
 
@@ -1141,6 +1275,14 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         st = mj_join2_size(ctx, R, S, &I, ctx->scratch, ctx->scratch_bytes, stream);
         if (st) return st;
         p.join2_size = I;
+    }
+    // one symmetric relation without duplicates or loops: the degree-oriented
+    // cyclic join applies
+    if (kind == MJ_TRIANGLE && R->n >= 2 && same_rel(*R, *S) && same_rel(*R, *T)) {
+        if ((st = ensure_scratch(ctx, orient_layout(nullptr, R->n, true).bytes))) return st;
+        bool yes = false;
+        if ((st = symmetric_simple(&ctx->prof, *R, 0x1B873593u, ctx->scratch, yes, s))) return st;
+        if (yes) p.flags |= MJ_PLAN_SYMMETRIC_SIMPLE;
     }
     if (planner != MJ_PLANNER_FIXED) {
         st = analytic_plan(kind, p, ctx->num_cu, ctx->model);
@@ -1177,11 +1319,17 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         // materialising: the three-way join reads each input a bounded
         // number of times
         if (p.algo == MJ_ALGO_CASCADE && p.join2_size > CAS_DEFAULT_I_CAP) p.algo = MJ_ALGO_3WAY;
+        // counting each triangle once does strictly less work than either
+        // form of the general cyclic join, for the same total
+        if (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) p.algo = MJ_ALGO_ORIENTED;
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;
-        if (p.algo < MJ_ALGO_3WAY || p.algo > (kind == MJ_LINEAR ? MJ_ALGO_STAR_CASCADE : MJ_ALGO_CASCADE))
-            return MJ_ERR_INVALID_ARG;
+        const bool ok = kind == MJ_LINEAR ? (p.algo >= MJ_ALGO_3WAY && p.algo <= MJ_ALGO_STAR_CASCADE)
+                                          : (p.algo == MJ_ALGO_3WAY || p.algo == MJ_ALGO_CASCADE ||
+                                             p.algo == MJ_ALGO_ORIENTED);
+        if (!ok) return MJ_ERR_INVALID_ARG;
+        if (p.algo == MJ_ALGO_ORIENTED && !(p.flags & MJ_PLAN_SYMMETRIC_SIMPLE)) return MJ_ERR_UNSUPPORTED;
     }
     st = plan_workspace(p);
     if (st) return st;
@@ -1283,6 +1431,16 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
     if (p.kind != MJ_TRIANGLE || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n)
         return MJ_ERR_PLAN_MISMATCH;
     if (p.log2_share > 16) return MJ_ERR_INVALID_ARG;
+    if (p.algo == MJ_ALGO_ORIENTED) {
+        if (!(p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) || !same_rel(*R, *S) || !same_rel(*R, *T))
+            return MJ_ERR_PLAN_MISMATCH;
+        if (!ws || ws_bytes < oriented_bytes(p)) return MJ_ERR_WORKSPACE;
+        hipStream_t so = static_cast<hipStream_t>(stream);
+        unsigned long long* o = reinterpret_cast<unsigned long long*>(total);
+        MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, so, o, (uint64_t)1, 0ull);
+        if (R->n == 0) return MJ_OK;
+        return run_oriented(&ctx->prof, ctx->num_cu, *R, p, o, ws, so);
+    }
     TriLayout L = tri_layout(nullptr, p);
     if (ws_bytes < L.bytes || !ws) return MJ_ERR_WORKSPACE;
     L = tri_layout(ws, p);
@@ -1791,6 +1949,10 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
         if (base.est_ms_cascade < 4.0 * base.est_ms_3way) {
             mj_plan_t c = base; c.algo = MJ_ALGO_CASCADE; cand.push_back(c);
         }
+        if (base.flags & MJ_PLAN_SYMMETRIC_SIMPLE)
+            for (uint32_t k = 0; k <= 4; k += 2) {
+                mj_plan_t c = base; c.algo = MJ_ALGO_ORIENTED; c.log2_share = k; cand.push_back(c);
+            }
     }
     hipEvent_t e0, e1;
     MJ_HIP(hipEventCreate(&e0));
@@ -1860,6 +2022,8 @@ int plan_workspace(mj_plan_t& p) {
         const CasTriLayout C = cas_tri_layout(nullptr, p, 0);
         p.workspace_bytes = std::max<size_t>(tri_layout(nullptr, p).bytes,
                                              C.base_bytes + C.i_cap * sizeof(uint2) + 256);
+        if (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE)
+            p.workspace_bytes = std::max<size_t>(p.workspace_bytes, oriented_bytes(p));
     }
     return MJ_OK;
 }

@@ -698,6 +698,25 @@ __global__ void k_emit_rdeg(EmitRArgs A);
 __global__ void k_emit_tiles(EmitArgs A, uint32_t ntiles);
 __global__ void k_emit(EmitArgs A);
 
+// ------------------------------------------- degree-oriented cyclic join
+struct OrientArgs {
+    const uint32_t* c0;            // the relation (u, v)
+    const uint32_t* c1;
+    int64_t stride;
+    uint64_t n;
+    RunIndex U;                    // runs of mix(u): the degrees
+    uint32_t seed;
+    uint32_t* flags;               // [n] 1: edge kept (points up in rank)
+    const unsigned long long* ridx;// [n + 1] exclusive scan of flags
+    uint2* E;                      // [n] kept edges, compacted in input order
+    uint32_t* err;                 // set when the relation is not symmetric and simple
+    unsigned long long* total;
+};
+__global__ void k_orient_flags(OrientArgs A);
+__global__ void k_orient_compact(OrientArgs A);
+__global__ void k_orient_finish(OrientArgs A, uint64_t expect);
+__global__ void k_sym_check(const unsigned long long* K1, const unsigned long long* K2, uint64_t n, uint32_t* bad);
+
 // ------------------------------------------------------------ learned planner
 constexpr int MLP_IN = 100, MLP_H = 64, MLP_OUT = 7;
 constexpr int MLP_OFF_W1 = 0;

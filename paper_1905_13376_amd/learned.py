@@ -204,6 +204,11 @@ def label_instance(ctx, inst):
         else:
             times["cascade"] = float("inf")      # never chosen: the planner caps the intermediate
             exact = True
+        # one symmetric simple relation: the degree-oriented join (planner rule)
+        if plan.flags & L.PLAN_SYMMETRIC_SIMPLE:
+            po = plan.copy(); po.algo = L.ALGO_ORIENTED
+            times["oriented"] = _time(lambda: ctx.triangle3_count(Fd, Fd, Fd, plan=po, out=out, workspace=ws), 1)
+            exact = exact and int(L.as_u64(out)[0]) == res
     best3 = min(v for k, v in times.items() if k in ("3way", "star") or k.startswith("share"))
     bestc = min(v for k, v in times.items() if k in ("cascade", "star_cascade"))
     return dict(kind=kind, features=feat, join2=plan.join2_size, out=res, times=times,
@@ -212,6 +217,7 @@ def label_instance(ctx, inst):
                 plan_label=int(bestc < best3),
                 share_label=(int(np.argmin([times[f"share{k}"] for k in SHARES])) if kind == L.TRIANGLE else -1),
                 analytic=dict(algo=plan.algo, share=plan.log2_share), plan_ms=plan_ms,
+                oriented_ok=bool(plan.flags & L.PLAN_SYMMETRIC_SIMPLE),
                 cascade_equals_3way=exact, n=int(Fd.shape[0]))
 
 
@@ -231,6 +237,8 @@ def nearest_share(k):
 
 def plan_time(r, algo, share):
     t = r["times"]
+    if algo == L.ALGO_ORIENTED:
+        return t["oriented"]
     if algo == L.ALGO_STAR_CASCADE:
         return t["star_cascade"]
     if algo == L.ALGO_STAR:
@@ -241,9 +249,12 @@ def plan_time(r, algo, share):
 
 
 def specialise(r, algo):
-    """mj_plan's rule: a three-way (cascade) choice becomes the star
-    three-way join (star cascade) when that plan is eligible and rated
-    faster by the analytic model."""
+    """mj_plan's rules: a cyclic join of one symmetric simple relation
+    becomes the degree-oriented join; a three-way (cascade) choice becomes
+    the star three-way join (star cascade) when that plan is eligible and
+    rated faster by the analytic model."""
+    if r["kind"] == L.TRIANGLE and r.get("oriented_ok"):
+        return L.ALGO_ORIENTED
     e = r.get("est")
     if r["kind"] != L.LINEAR or not e:
         return algo
