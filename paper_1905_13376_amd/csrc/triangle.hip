@@ -157,9 +157,83 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// ------------------------------------------------------- streaming lists
+// First index in [lo, hi) of a sorted list whose value is not below v (or,
+// with `upper`, above v).  The wave probes 64 evenly spaced pivots per
+// round, so a list of n entries takes about log_65(n) rounds of independent
+// loads instead of log_2(n) dependent ones.
+__device__ __forceinline__ uint32_t wave_bound(const uint32_t* keys, uint32_t lo, uint32_t hi,
+                                               uint32_t v, bool upper) {
+    const int lane = lane_id();
+    while (hi - lo > WAVE) {
+        const uint32_t n = hi - lo;                   // n >= 65: pivots strictly increase
+        const uint32_t p = lo + (uint32_t)((uint64_t)n * (lane + 1) / (WAVE + 1));
+        const uint32_t k = keys[p];
+        const int below = __popcll(__ballot(upper ? k <= v : k < v));
+        const uint32_t nlo = below == 0 ? lo : lo + (uint32_t)((uint64_t)n * below / (WAVE + 1)) + 1;
+        const uint32_t nhi = below == WAVE ? hi : lo + (uint32_t)((uint64_t)n * (below + 1) / (WAVE + 1));
+        lo = nlo;
+        hi = nhi;
+    }
+    bool in = false;
+    if (lo + lane < hi) {
+        const uint32_t k = keys[lo + lane];
+        in = upper ? k <= v : k < v;
+    }
+    return lo + (uint32_t)__popcll(__ballot(in));
+}
+
+// One chunk of up to 64 S tuples of a group, lane j holding tuple si (when
+// `valid`): each tuple's iterated list streams past the staged table.  Lists
+// of at most TRI_SHORT_LIST entries are walked by their own lane; longer
+// ones one after another by the whole wave (64 consecutive entries per load,
+// UNROLL loads in flight per lane), so a long list is read with coalesced
+// loads.  When the staged list is a slice, only the part of a long list in
+// the slice's A range [alo, ahi] is read (a short list's other entries find
+// nothing).  Returns the lane's partial sum.
+__device__ __forceinline__ unsigned long long stream_chunk(const TriJoinArgs& A, uint32_t si, bool valid,
+                                                           uint32_t x, const uint32_t* keys,
+                                                           const uint32_t* vals, uint32_t mask, uint32_t sp,
+                                                           bool sliced, uint32_t alo, uint32_t ahi) {
+    const int lane = lane_id();
+    constexpr int UNROLL = 4;
+    unsigned long long acc = 0;
+    uint32_t ts = 0, y = 0;
+    if (!(valid && run_lookup(A.Itr, A.Grpl[si], ts, y)) ||
+        (A.strict ? y >= x : y > x))                  // the other pass owns this s
+        y = 0;
+    if (y <= TRI_SHORT_LIST) {
+        for (uint32_t t = ts; t < ts + y; ++t) acc += atab_get(keys, vals, mask, sp, A.Itrl[t]);
+    }
+    unsigned long long longm = __ballot(y > TRI_SHORT_LIST);
+    while (longm) {                                   // wave-uniform
+        const int j = __ffsll((long long)longm) - 1;
+        longm &= longm - 1;
+        uint32_t l = __shfl(ts, j, WAVE);
+        uint32_t l2 = l + __shfl(y, j, WAVE);
+        if (sliced && l2 - l > WAVE) {                // the part inside [alo, ahi]
+            l = wave_bound(A.Itrl, l, l2, alo, false);
+            l2 = wave_bound(A.Itrl, l, l2, ahi, true);
+        }
+        for (uint32_t t0 = l; t0 < l2; t0 += UNROLL * WAVE) {
+            uint32_t key[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint32_t t = t0 + u * WAVE + lane;
+                key[u] = t < l2 ? A.Itrl[t] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                if (t0 + u * WAVE + lane < l2) acc += atab_get(keys, vals, mask, sp, key[u]);
+        }
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------- light groups
 // One wave, one S group: R's list of b into the wave's LDS table, then every
-// s(b,c) of the group streams T's list of c past it.  Returns the lane's sum.
+// s(b,c) of the group streams T's list of c past it, 64 tuples at a time
+// (stream_chunk).  Returns the lane's sum.
 struct WaveTable {
     uint32_t* keys;
     uint32_t* vals;
@@ -193,13 +267,8 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     wave_fence();
     const uint32_t spec = *W.spec;
     unsigned long long acc = 0;
-    for (uint32_t si = gs + lane; si < ge; si += WAVE) {
-        uint32_t ts, y;
-        if (!run_lookup(A.Itr, A.Grpl[si], ts, y)) continue;
-        if (A.strict ? y >= x : y > x) continue;     // the other pass owns this s
-        for (uint32_t t = ts; t < ts + y; ++t)
-            acc += atab_get(W.keys, W.vals, mask, spec, A.Itrl[t]);
-    }
+    for (uint32_t c0 = gs; c0 < ge; c0 += WAVE)
+        acc += stream_chunk(A, c0 + lane, c0 + lane < ge, x, W.keys, W.vals, mask, spec, false, 0u, 0u);
     wave_fence();
     const uint32_t nu = *W.nused;
     for (uint32_t q = lane; q < nu; q += WAVE) { const uint32_t s = W.used[q]; W.keys[s] = EMPTY_KEY; W.vals[s] = 0; }
@@ -248,31 +317,6 @@ struct BlockTable {
     uint32_t* chunk;                  // next chunk of 64 S tuples of the item
 };
 
-// First index in [lo, hi) of a sorted list whose value is not below v (or,
-// with `upper`, above v).  The wave probes 64 evenly spaced pivots per
-// round, so a list of n entries takes about log_65(n) rounds of independent
-// loads instead of log_2(n) dependent ones.
-__device__ __forceinline__ uint32_t wave_bound(const uint32_t* keys, uint32_t lo, uint32_t hi,
-                                               uint32_t v, bool upper) {
-    const int lane = lane_id();
-    while (hi - lo > WAVE) {
-        const uint32_t n = hi - lo;                   // n >= 65: pivots strictly increase
-        const uint32_t p = lo + (uint32_t)((uint64_t)n * (lane + 1) / (WAVE + 1));
-        const uint32_t k = keys[p];
-        const int below = __popcll(__ballot(upper ? k <= v : k < v));
-        const uint32_t nlo = below == 0 ? lo : lo + (uint32_t)((uint64_t)n * below / (WAVE + 1)) + 1;
-        const uint32_t nhi = below == WAVE ? hi : lo + (uint32_t)((uint64_t)n * (below + 1) / (WAVE + 1));
-        lo = nlo;
-        hi = nhi;
-    }
-    bool in = false;
-    if (lo + lane < hi) {
-        const uint32_t k = keys[lo + lane];
-        in = upper ? k <= v : k < v;
-    }
-    return lo + (uint32_t)__popcll(__ballot(in));
-}
-
 // One workgroup, one item: a slice of a staged list into LDS, then the
 // item's S tuples stream their iterated lists past it (only the part in the
 // slice's A range when the staged list is sliced).  Waves take chunks of 64
@@ -282,7 +326,6 @@ __device__ __forceinline__ uint32_t wave_bound(const uint32_t* keys, uint32_t lo
 // loads in flight per lane).
 __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, const BlockTable& B) {
     const int lane = lane_id();
-    constexpr int UNROLL = 4;
     const uint32_t mask = TRI_HEAVY_CAP - 1;
     // item -> (heavy group, slice of the staged list, range of the group)
     uint32_t lo = 0, hi = A.n_heavy_cap;              // last h with off[h] <= it
@@ -314,35 +357,7 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
         const uint32_t c0 = H.s0 + __shfl(c, 0, WAVE) * WAVE;
         if (c0 >= H.s1) break;                        // wave-uniform
         const uint32_t si = c0 + lane;
-        uint32_t ts = 0, y = 0;
-        if (!(si < H.s1 && run_lookup(A.Itr, A.Grpl[si], ts, y)) ||
-            (A.strict ? y >= x : y > x))              // the other pass owns this s
-            y = 0;
-        if (y <= TRI_SHORT_LIST) {
-            for (uint32_t t = ts; t < ts + y; ++t) acc += atab_get(B.keys, B.vals, mask, sp, A.Itrl[t]);
-        }
-        unsigned long long longm = __ballot(y > TRI_SHORT_LIST);
-        while (longm) {                               // wave-uniform
-            const int j = __ffsll((long long)longm) - 1;
-            longm &= longm - 1;
-            uint32_t l = __shfl(ts, j, WAVE);
-            uint32_t l2 = l + __shfl(y, j, WAVE);
-            if (sliced && l2 - l > WAVE) {            // the part inside [alo, ahi]
-                l = wave_bound(A.Itrl, l, l2, alo, false);
-                l2 = wave_bound(A.Itrl, l, l2, ahi, true);
-            }
-            for (uint32_t t0 = l; t0 < l2; t0 += UNROLL * WAVE) {
-                uint32_t key[UNROLL];
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u) {
-                    const uint32_t t = t0 + u * WAVE + lane;
-                    key[u] = t < l2 ? A.Itrl[t] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u)
-                    if (t0 + u * WAVE + lane < l2) acc += atab_get(B.keys, B.vals, mask, sp, key[u]);
-            }
-        }
+        acc += stream_chunk(A, si, si < H.s1, x, B.keys, B.vals, mask, sp, sliced, alo, ahi);
     }
     return acc;
 }
