@@ -87,6 +87,8 @@ def main():
                     help="also run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the main workload (no cascade / cyclic / small runs)")
+    ap.add_argument("--only", choices=LEGS, default=None,
+                    help="run one of the other paths alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -119,6 +121,10 @@ def main():
     plan = ctx.plan(mj.LINEAR, Fd, Fd, Fd, a_domain)
     plan_ms = (time.perf_counter() - t0) * 1e3
     log(f"plan {plan.as_dict()} ({plan_ms:.1f} ms)")
+    if args.only:
+        print(json.dumps({args.only: extra_paths(mj, ctx, F, Fd, a_domain, plan, None, only=args.only)}),
+              flush=True)
+        return
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     out = torch.empty(a_domain, dtype=torch.int64, device="cuda")
 
@@ -373,23 +379,41 @@ def emit_path(mj, ctx, F, Fd):
     return res
 
 
-def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
-    """The other paths of the method, each on its own workload."""
+LEGS = ("cascade", "small", "fm", "emit", "star", "triangle", "batch", "planner")
+
+
+def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
+    """The other paths of the method, each on its own workload (all of them,
+    or the one named by `only`)."""
+    out = {}
+    if only in (None, "cascade", "small"):
+        out.update(linear_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only))
+    if only in (None, "fm"):
+        out["distinct_fm"] = fm_path(mj, ctx, F, Fd, a_domain)
+    if only in (None, "emit"):
+        out["materialised"] = emit_path(mj, ctx, F, Fd)
+    if only in (None, "star"):
+        out["star"] = star_path(mj, ctx)
+    if only in (None, "triangle"):
+        out["triangle_rmat22"] = triangle_path(mj, ctx)
+    if only in (None, "batch"):
+        out["batch_512"] = batch_path(mj, ctx)
+    if only in (None, "planner"):
+        out["planner"] = planner_path(ctx)
+    return out
+
+
+def linear_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
+    """The cascade on the benchmarked input, and the small uniform input."""
     import numpy as np
     import torch
     from workloads import generators as G
     out = {}
     n = F.shape[0]
-    # cascade of binary joins on the same power-law input (Sec. 6.3)
-    log("cascade on the power-law graph")
-    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
-    cnt = torch.empty(a_domain, dtype=torch.int64, device="cuda")
-    ms_c = time_call(lambda: ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, a_domain, plan=plan,
-                                                out=cnt, workspace=ws), 3)
-    out["cascade_linear"] = {"ms": round(ms_c, 3), "tuples_per_s": 3 * n / (ms_c * 1e-3),
-                             "intermediate_pairs": plan.join2_size,
-                             "speedup_3way_over_cascade": round(ms_c / ms_3way, 2)}
-    del ws
+    if only in (None, "cascade"):
+        out["cascade_linear"] = cascade_path(mj, ctx, Fd, n, a_domain, plan, ms_3way)
+    if only == "cascade":
+        return out
     # small uniform linear workload (65,536 tuples, keys in [0, 4096))
     Fs = G.linear_small()
     Fsd = torch.from_numpy(Fs.view(np.int32)).to("cuda")
@@ -402,10 +426,28 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
     out["linear_small"] = {"ms_3way": round(ms_s, 4), "ms_cascade": round(ms_sc, 4),
                            "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3)}
     del ws
-    out["distinct_fm"] = fm_path(mj, ctx, F, Fd, a_domain)
-    out["materialised"] = emit_path(mj, ctx, F, Fd)
-    out["star"] = star_path(mj, ctx)
-    # cyclic join on the R-MAT scale-22 graph, shares 1 / 4 / 16 (Sec. 5)
+    return out
+
+
+def cascade_path(mj, ctx, Fd, n, a_domain, plan, ms_3way):
+    """The cascade of binary joins on the benchmarked input (Sec. 6.3)."""
+    import torch
+    log("cascade on the power-law graph")
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(a_domain, dtype=torch.int64, device="cuda")
+    ms_c = time_call(lambda: ctx.cascade2_count(mj.LINEAR, Fd, Fd, Fd, a_domain, plan=plan,
+                                                out=cnt, workspace=ws), 3)
+    del ws
+    return {"ms": round(ms_c, 3), "tuples_per_s": 3 * n / (ms_c * 1e-3),
+            "intermediate_pairs": plan.join2_size,
+            "speedup_3way_over_cascade": round(ms_c / ms_3way, 2) if ms_3way else None}
+
+
+def triangle_path(mj, ctx):
+    """The cyclic join on the R-MAT scale-22 graph (Sec. 5): the general
+    join at shares 1 / 4 / 16, and the planner's choice."""
+    import torch
+    from workloads import generators as G
     log("generating R-MAT scale 22 (2^26 undirected edges)")
     E = G.triangle_rmat()
     Ed = torch.from_numpy(E).to("cuda")
@@ -435,11 +477,27 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way):
                            for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]}}
         log(f"cyclic share {1 << share}: {ms_t:.1f} ms total {got}")
         del ws
-    out["triangle_rmat22"] = tri
-    del Ed, E
-    out["batch_512"] = batch_path(mj, ctx)
-    out["planner"] = planner_path(ctx)
-    return out
+    # the planner's choice: it finds R = S = T symmetric and simple and picks
+    # the degree-oriented join (each triangle once)
+    t0 = time.perf_counter()
+    po = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    ws = torch.empty(po.workspace_bytes, dtype=torch.uint8, device="cuda")
+    ctx.profile(True)
+    ctx.profile_read()
+    ms_o = time_call(lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=po, out=tot, workspace=ws), 3)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    got = int(mj.as_u64(tot)[0])
+    tri["planned_oriented"] = {
+        "algo": int(po.algo), "plan_ms": round(plan_ms, 1), "ms": round(ms_o, 2),
+        "tuples_per_s": 3 * E.shape[0] / (ms_o * 1e-3), "total": got, "triangles": got // 6,
+        "matches_oracle_total": (got == golden) if golden is not None else None,
+        "speedup_over_share_1": round(tri["share_1"]["ms"] / ms_o, 2),
+        "kernels_ms": {k: round(v[0] / 4, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]}}
+    log(f"cyclic, planned (oriented): {ms_o:.1f} ms total {got}")
+    del ws, Ed, E
+    return tri
 
 
 def planner_path(ctx, n=300):

@@ -1319,9 +1319,10 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         // materialising: the three-way join reads each input a bounded
         // number of times
         if (p.algo == MJ_ALGO_CASCADE && p.join2_size > CAS_DEFAULT_I_CAP) p.algo = MJ_ALGO_3WAY;
-        // counting each triangle once does strictly less work than either
-        // form of the general cyclic join, for the same total
-        if (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) p.algo = MJ_ALGO_ORIENTED;
+        // counting each triangle once does less work than either form of
+        // the general cyclic join, for the same total, once the relation is
+        // large and skewed enough to pay for orienting it
+        if ((p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) && orient_pays(p)) p.algo = MJ_ALGO_ORIENTED;
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;

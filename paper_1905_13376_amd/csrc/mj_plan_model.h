@@ -21,6 +21,18 @@ struct DeviceModel {
 constexpr uint64_t STAR_PLAN_MAX_R = 4096;
 constexpr uint64_t STAR_PLAN_MAX_I = uint64_t(1) << 28;
 
+// the degree-oriented cyclic join pays for its orientation pass (about
+// 0.4 ms of extra launches) when the relation is large and its wedges dense:
+// |R |x| S| = sum of squared degrees at least ORIENT_MIN_WEDGES per tuple
+// (degree skew), and at least ORIENT_MIN_N tuples; both fitted on measured
+// times of both algorithms over generated G(n, m), Chung-Lu and R-MAT
+// graphs of 10^3 to 2 x 10^6 edges
+constexpr uint64_t ORIENT_MIN_N = 32768;
+constexpr uint64_t ORIENT_MIN_WEDGES = 64;
+inline bool orient_pays(const mj_plan_t& p) {
+    return p.n_r >= ORIENT_MIN_N && p.join2_size >= ORIENT_MIN_WEDGES * p.n_r;
+}
+
 DeviceModel default_model();
 int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m);
 

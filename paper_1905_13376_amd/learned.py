@@ -248,12 +248,17 @@ def plan_time(r, algo, share):
     return t["3way"] if r["kind"] == L.LINEAR else t[f"share{share}"]
 
 
+# mj_plan's rule for the degree-oriented cyclic join (mj_plan_model.h)
+ORIENT_MIN_N, ORIENT_MIN_WEDGES = 32768, 64
+
+
 def specialise(r, algo):
-    """mj_plan's rules: a cyclic join of one symmetric simple relation
-    becomes the degree-oriented join; a three-way (cascade) choice becomes
+    """mj_plan's rules: a cyclic join of one large, skewed, symmetric simple
+    relation becomes the degree-oriented join; a three-way (cascade) choice becomes
     the star three-way join (star cascade) when that plan is eligible and
     rated faster by the analytic model."""
-    if r["kind"] == L.TRIANGLE and r.get("oriented_ok"):
+    if (r["kind"] == L.TRIANGLE and r.get("oriented_ok") and r["n"] >= ORIENT_MIN_N
+            and r["join2"] >= ORIENT_MIN_WEDGES * r["n"]):
         return L.ALGO_ORIENTED
     e = r.get("est")
     if r["kind"] != L.LINEAR or not e:

@@ -55,7 +55,7 @@ def test_oriented_matches_oracle(mj, ctx, case):
     banner(f"oriented cyclic join, {case}")
     E = CASES[case]()
     Ed = dev(E)
-    p = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
+    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED)
     assert p.flags & mj.PLAN_SYMMETRIC_SIMPLE and p.algo == mj.ALGO_ORIENTED
     got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
     assert got == oracle.triangle3_count(E, E, E)
@@ -66,7 +66,8 @@ def test_oriented_complete_graph_closed_form(mj, ctx):
     banner("oriented cyclic join, complete graph K_300")
     n = 300
     Ed = dev(complete(n))
-    got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed))[0])
+    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED)
+    got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
     assert got == 6 * math.comb(n, 3)
 
 
@@ -80,6 +81,22 @@ def test_oriented_share_sweep_rmat18(mj, ctx):
                        algo=mj.ALGO_ORIENTED)
         assert p.algo == mj.ALGO_ORIENTED
         assert int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0]) == want
+
+
+def test_planner_rule(mj, ctx):
+    """The planner offers the oriented join only to large skewed relations:
+    an R-MAT graph of 2^16 vertices (2^21 tuples) is oriented; a G(n, m)
+    graph of the same size (few wedges per edge) and a small R-MAT graph
+    are not."""
+    banner("oriented join: the planner's rule")
+    for E, want in ((G.triangle_rmat(scale=16, m_undirected=16 << 16, seed=3001), True),
+                    (G.gnm_symmetric(1 << 16, 1 << 20, seed=4), False),
+                    (G.triangle_rmat(scale=9, m_undirected=16 << 9, seed=3001), False)):
+        Ed = dev(E)
+        p = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
+        assert p.flags & mj.PLAN_SYMMETRIC_SIMPLE
+        assert (p.algo == mj.ALGO_ORIENTED) == want, (E.shape, p.join2_size)
+        assert int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0]) == oracle.triangle3_count(E, E, E)
 
 
 def not_eligible_cases():
@@ -119,7 +136,7 @@ def test_data_changed_after_planning(mj, ctx, change):
     banner(f"oriented plan on changed data: {change}")
     E = G.gnm_symmetric(2000, 20000, seed=9)
     Ed = dev(E)
-    p = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
+    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED)
     assert p.algo == mj.ALGO_ORIENTED
     if change == "loop":
         Ed[0, 1] = Ed[0, 0]
