@@ -142,19 +142,28 @@ def main():
     exact = int(got.sum(dtype=np.uint64)) == closed
     log(f"sum of counts {int(got.sum(dtype=np.uint64))} vs closed form {closed}: {exact}")
 
+    stream = torch.cuda.current_stream()
+
+    def timed_steps():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    # the timed region: K steps with nothing else on the stream
+    ms = timed_steps()
+    # the same K steps again with the library's HIP events around every
+    # kernel, on the stream the kernels run on: per-kernel launch times
     ctx.profile(True)
     ctx.profile_read()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms_profiled = timed_steps()
     prof = ctx.profile_read()
     ctx.profile(False)
+    log(f"{ms:.4f} ms per step ({ms_profiled:.4f} ms with per-kernel events)")
     kern = {k: (v[0] / max(v[1], 1), v[1] // args.steps) for k, v in prof.items()}
     for k, (avg, per) in sorted(kern.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
         log(f"  {k:24s} {avg * 1e3:9.1f} us x {per}")
@@ -188,6 +197,7 @@ def main():
                                "at 4096, preferential-attachment destinations, seed 2001",
                    "a_domain": a_domain, "log2_nb": plan.log2_nb, "log2_nc": plan.log2_nc,
                    "plan_ms": round(plan_ms, 2), "exact_sum_check": exact,
+                   "ms_per_step_with_kernel_events": round(ms_profiled, 4),
                    "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kern.items()}},
         "roofline": roof,
     }
@@ -211,6 +221,23 @@ def time_call(fn, steps, warmup=1):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def time_and_profile(ctx, fn, steps, warmup=1, prof_calls=None):
+    """Milliseconds per call of `fn` timed with the library's per-kernel
+    events off, then per-kernel figures from further calls with them on:
+    {kernel: (ms per call, launches per call)}."""
+    import torch
+    ms = time_call(fn, steps, warmup)
+    n = prof_calls or steps
+    ctx.profile(True)
+    ctx.profile_read()
+    for _ in range(n):
+        fn()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    return ms, {k: (v[0] / n, v[1] / n) for k, v in prof.items()}
 
 
 def star_path(mj, ctx):
@@ -243,20 +270,17 @@ def star_path(mj, ctx):
             fn = lambda: ctx.linear3_count(Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
         else:
             fn = lambda: ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
-        ctx.profile(True)
-        ctx.profile_read()
-        ms = time_call(fn, 5)
-        prof = ctx.profile_read()
-        ctx.profile(False)
+        ms, kp = time_and_profile(ctx, fn, 5)
         ok = int(mj.as_u64(cnt).sum(dtype=np.uint64)) == closed
-        kern = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+        kern = {k: v[0] / max(v[1], 1) for k, v in kp.items()}          # ms per launch
         ent = {"ms": round(ms, 4), "tuples_per_s": n_in / (ms * 1e-3), "sum_equals_closed_form": ok,
                "kernels_us": {k: round(v * 1e3, 1) for k, v in sorted(kern.items(), key=lambda kv: -kv[1])[:6]}}
-        if name == "star" and "k_star_group" in kern:
-            us = kern["k_star_group"] * 1e3
+        kg = next((k for k in ("k_star_group_b", "k_star_group_a") if k in kern), None)
+        if name == "star" and kg:
+            us = kern[kg] * 1e3
             nbytes = 8 * S.shape[0]                      # the fact relation, read once
             ach = nbytes / (us * 1e-6) / 1e9
-            ent["roofline"] = {"bound": "hbm", "kernel": "k_star_group", "achieved": round(ach, 1),
+            ent["roofline"] = {"bound": "hbm", "kernel": kg, "achieved": round(ach, 1),
                                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                "algorithmic_bytes": nbytes, "avg_launch_us": round(us, 2)}
         res[name] = ent
@@ -297,13 +321,8 @@ def fm_path(mj, ctx, F, Fd, a_domain):
     sk = torch.empty((a_domain, 16), dtype=torch.int32, device="cuda")
     est = torch.empty(a_domain, dtype=torch.float64, device="cuda")
     fn = lambda: ctx.linear3_distinct(Fd, Fd, Fd, a_domain, seed=0x5EED, sketch=sk, est=est)
-    ctx.profile(True)
-    ctx.profile_read()
-    ms = time_call(fn, 5, 2)
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ncalls = 7                                        # 2 warm-up + 5 timed calls were profiled
-    kern = {k: (v[0] / max(v[1], 1), v[1] / ncalls) for k, v in prof.items()}
+    ms, kp = time_and_profile(ctx, fn, 5, 2, 3)
+    kern = {k: (v[0] / max(v[1], 1), v[1]) for k, v in kp.items()}     # (ms per launch, launches per call)
     e = est.cpu().numpy()
     rng = np.random.default_rng(11)
     outdeg = np.bincount(F[:, 0], minlength=a_domain)
@@ -345,11 +364,7 @@ def emit_path(mj, ctx, F, Fd):
     total = torch.empty(1, dtype=torch.int64, device="cuda")
     out = torch.empty((closed, 4), dtype=torch.int32, device="cuda")
     fn = lambda: ctx.linear3_materialize(Fd, Fd, Fd, out=out, total=total)
-    ctx.profile(True)
-    ctx.profile_read()
-    ms = time_call(fn, 3, 1)
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    ms, kern = time_and_profile(ctx, fn, 3, 1, 2)
     got_total = int(total.item())
     rng = np.random.default_rng(3)
     pos = torch.from_numpy(rng.integers(0, closed, 2000)).to("cuda")
@@ -361,9 +376,7 @@ def emit_path(mj, ctx, F, Fd):
     valid = bool(np.isin(enc(smp[:, 0], smp[:, 1]), edges).all() and
                  np.isin(enc(smp[:, 1], smp[:, 2]), edges).all() and
                  np.isin(enc(smp[:, 2], smp[:, 3]), edges).all())
-    calls = 4                                         # 1 warm-up + 3 timed calls were profiled
-    kern = {k: (v[0] / calls, v[1] / calls) for k, v in prof.items()}
-    k_ms = kern.get("k_emit", (0.0, 0))[0]
+    k_ms = kern.get("k_emit", (0.0, 0))[0]                           # ms per call, all chunks
     res = {"ms": round(ms, 3), "result_tuples": got_total, "total_equals_closed_form": got_total == closed,
            "sampled_tuples_are_join_results": valid,
            "result_tuples_per_s": got_total / (ms * 1e-3), "input_tuples_per_s": 3 * n / (ms * 1e-3),
@@ -463,18 +476,14 @@ def triangle_path(mj, ctx):
         p.seed = 0x1B873593
         pt = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed, 0, planner="fixed", fixed=p)
         ws = torch.empty(pt.workspace_bytes, dtype=torch.uint8, device="cuda")
-        ctx.profile(True)
-        ctx.profile_read()
-        ms_t = time_call(lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=pt, out=tot, workspace=ws), 2)
-        prof = ctx.profile_read()
-        ctx.profile(False)
+        ms_t, kp = time_and_profile(ctx, lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=pt, out=tot, workspace=ws),
+                                    2, 1, 1)
         got = int(mj.as_u64(tot)[0])
         tri[f"share_{1 << share}"] = {
             "ms": round(ms_t, 2), "tuples_per_s": 3 * E.shape[0] / (ms_t * 1e-3),
             "total": got, "triangles": got // 6,
             "matches_oracle_total": (got == golden) if golden is not None else None,
-            "kernels_ms": {k: round(v[0] / max(v[1], 1) * v[1] / 3, 3)
-                           for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]}}
+            "kernels_ms_per_call": {k: round(v[0], 3) for k, v in sorted(kp.items(), key=lambda kv: -kv[1][0])[:8]}}
         log(f"cyclic share {1 << share}: {ms_t:.1f} ms total {got}")
         del ws
     # the planner's choice: it finds R = S = T symmetric and simple and picks
@@ -483,18 +492,14 @@ def triangle_path(mj, ctx):
     po = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
     plan_ms = (time.perf_counter() - t0) * 1e3
     ws = torch.empty(po.workspace_bytes, dtype=torch.uint8, device="cuda")
-    ctx.profile(True)
-    ctx.profile_read()
-    ms_o = time_call(lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=po, out=tot, workspace=ws), 3)
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    ms_o, kp = time_and_profile(ctx, lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=po, out=tot, workspace=ws), 3)
     got = int(mj.as_u64(tot)[0])
     tri["planned_oriented"] = {
         "algo": int(po.algo), "plan_ms": round(plan_ms, 1), "ms": round(ms_o, 2),
         "tuples_per_s": 3 * E.shape[0] / (ms_o * 1e-3), "total": got, "triangles": got // 6,
         "matches_oracle_total": (got == golden) if golden is not None else None,
         "speedup_over_share_1": round(tri["share_1"]["ms"] / ms_o, 2),
-        "kernels_ms": {k: round(v[0] / 4, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])[:8]}}
+        "kernels_ms_per_call": {k: round(v[0], 3) for k, v in sorted(kp.items(), key=lambda kv: -kv[1][0])[:8]}}
     log(f"cyclic, planned (oriented): {ms_o:.1f} ms total {got}")
     del ws, Ed, E
     return tri
