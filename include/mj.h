@@ -69,11 +69,17 @@ typedef enum {
                                /* triangle counted once along degree-ordered edges  */
 } mj_algo;
 
-/* mj_plan_t.flags bits, set by mj_plan */
+/* mj_plan_t.flags bits.  mj_plan sets the properties it finds; the
+ * request bits are read from the caller's plan (MJ_PLANNER_FIXED) and kept. */
 enum {
-    MJ_PLAN_SYMMETRIC_SIMPLE = 1 /* cyclic: R, S and T are one relation (same columns, */
+    MJ_PLAN_SYMMETRIC_SIMPLE = 1,/* cyclic: R, S and T are one relation (same columns, */
                                  /* stride and size) that is symmetric, without        */
                                  /* duplicate tuples and without loops (a, a)          */
+    MJ_PLAN_DENSE_KEYS = 2,      /* linear: every B value of R and S is < b_domain and */
+                                 /* every C value of S and T is < c_domain, both small */
+                                 /* enough for direct-indexed tables (see below)       */
+    MJ_PLAN_NO_DENSE = 0x100     /* request: keep the hashed tables even when the keys */
+                                 /* are dense                                          */
 };
 typedef enum {
     MJ_PLANNER_ANALYTIC = 0,   /* cost model with measured device constants        */
@@ -107,6 +113,8 @@ typedef struct {
     double pred_log2_out;      /* learned planner: predicted log2(1 + |output|)  */
     double est_ms_star;        /* linear: star three-way estimate (0 = not eligible) */
     double est_ms_star_cascade;/* linear: star cascade estimate (0 = not eligible)   */
+    uint32_t b_domain;         /* linear, MJ_PLAN_DENSE_KEYS: 1 + largest B value    */
+    uint32_t c_domain;         /* linear, MJ_PLAN_DENSE_KEYS: 1 + largest C value    */
 } mj_plan_t;
 
 /* Context: binds the library to a device (the current one if device < 0). */
@@ -143,7 +151,14 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
  * fact relation S streamed once and grouped by B); any other algo runs the
  * partitioned three-way join.  The star join is exact at any size; it is
  * fast while R has at most 4096 distinct B values (its per-B sums then live
- * in one workgroup's LDS), and the planner only picks it then.           */
+ * in one workgroup's LDS), and the planner only picks it then.
+ * A three-way plan with MJ_PLAN_DENSE_KEYS (mj_plan sets it when the B and
+ * C values it finds are below 2^24 and not much sparser than the tuples)
+ * keeps T's multiplicities and the per-B sums in arrays indexed by the key
+ * itself rather than in hashed tables: the same join, each lookup one read.
+ * The plan certifies the key bounds for the data it was made on: a B or C
+ * value at or above its bound at count time sets every count to all ones
+ * (UINT64_MAX).                                                          */
 int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                      uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan,
                      void* workspace, uint64_t workspace_bytes, void* stream);

@@ -215,6 +215,62 @@ bool a_ranges(const mj_plan_t& p, uint32_t& bits, uint32_t& shift) {
     return bits <= PART_MAX_BITS;
 }
 
+// Ranges of a key domain [0, domain): about 32K of n tuples per range, at
+// most 2^PART_MAX_BITS ranges of at most 2^ACELL_MAX_SHIFT values; false
+// when the domain needs more.
+bool key_ranges(uint64_t n, uint32_t domain, uint32_t& bits, uint32_t& shift) {
+    if (domain == 0) return false;
+    const uint32_t L = ceil_log2(domain);
+    bits = std::min<uint32_t>({ceil_log2((n + 32767) / 32768), PART_MAX_BITS, L});
+    if (L - bits > ACELL_MAX_SHIFT) bits = L - ACELL_MAX_SHIFT;
+    shift = L - bits;
+    return bits <= PART_MAX_BITS;
+}
+
+// dense keys: B and C below these bounds, and not much sparser than the tuples
+constexpr uint32_t DENSE_MAX_DOMAIN = 1u << 24;
+bool dense_ok(uint64_t dom, uint64_t n) { return dom >= 1 && dom <= DENSE_MAX_DOMAIN && dom <= 2 * n + 4096; }
+
+struct DenseLayout {                  // the linear join with direct-indexed tables
+    RelPart T, S, R;                  // T.c by range of C (keys in T.pairs' space), S by B, R by A
+    uint32_t* tkeys;
+    uint32_t* deg;                    // [c_domain] multiplicity of each C value in T
+    unsigned long long* w;            // [b_domain] W[b]
+    uint32_t* err;
+    uint32_t c_bits, c_shift, b_bits, b_shift, a_bits, a_shift;
+    size_t bytes;
+};
+
+bool dense_plan(const mj_plan_t& p) {
+    uint32_t x, y;
+    return (p.flags & MJ_PLAN_DENSE_KEYS) && key_ranges(p.n_r, p.a_domain, x, y) &&
+           key_ranges(p.n_s, p.b_domain, x, y) && key_ranges(p.n_t, p.c_domain, x, y);
+}
+
+DenseLayout dense_layout(void* ws, const mj_plan_t& p) {
+    Bump B(ws);
+    DenseLayout L{};
+    key_ranges(p.n_t, p.c_domain, L.c_bits, L.c_shift);
+    key_ranges(p.n_s, p.b_domain, L.b_bits, L.b_shift);
+    key_ranges(p.n_r, p.a_domain, L.a_bits, L.a_shift);
+    auto part = [&](RelPart& P, uint64_t n, uint32_t bits, bool pairs) {
+        const uint32_t nb = 1u << bits;
+        P.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(n));
+        P.counts = B.take<uint32_t>(nb);
+        P.starts = B.take<uint32_t>(nb + 1);
+        P.pairs = pairs ? B.take<uint2>(std::max<uint64_t>(n, 1)) : nullptr;
+    };
+    part(L.T, p.n_t, L.c_bits, false);
+    L.tkeys = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
+    part(L.S, p.n_s, L.b_bits, true);
+    part(L.R, p.n_r, L.a_bits, true);
+    L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
+    L.w = B.take<unsigned long long>(std::max<uint32_t>(p.b_domain, 1));
+    L.err = B.take<uint32_t>(1);
+    L.bytes = B.off + 256;
+    return L;
+}
+
 struct LinearLayout {
     RelPart R, S;                     // R and S by bucket of B (cells)
     RelPart Ra;                       // R by range of A (shares R's pair buffer)
@@ -317,6 +373,12 @@ PartJob make_job(const mj_rel& r, uint32_t* hist, uint32_t* counts, uint32_t* st
 // Partition up to MJ_PART_MAX_JOBS relations (four launches in all).
 int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st) {
     uint32_t tiles = 0, rows = 0, maxbits = 0;
+    for (int q = 0; q < P.njobs; ++q) {
+        const PartJob& J = P.job[q];
+        // a one-column payload is re-bucketed from that column alone
+        if (!J.out_pair && (J.bits1 != 0 || J.key0_col != J.single_col)) return MJ_ERR_INVALID_ARG;
+        if ((J.out_pair != nullptr) == (J.out_single != nullptr)) return MJ_ERR_INVALID_ARG;
+    }
     for (int q = 0; q < P.njobs; ++q) {
         P.job[q].tile_begin = tiles;
         tiles += P.job[q].ntiles;
@@ -961,6 +1023,47 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
     return L;
 }
 
+// ------------------------------------------ linear join, direct-indexed tables
+// T by range of C, S by range of B and R by range of A in one partition
+// launch group; then deg[c] over T, W[b] = sum of deg[s.c] over S, and
+// count[a] = sum of W[r.b] over R, each one range per workgroup in LDS.
+int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, const mj_plan_t& p,
+              unsigned long long* count, void* ws, hipStream_t s) {
+    DenseLayout L = dense_layout(ws, p);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    PartLaunch P{};
+    P.njobs = 3;
+    P.job[0] = make_job(T, L.T.hist, L.T.counts, L.T.starts, 0, 0, L.c_bits, 0, 0, 0);
+    P.job[0].range_on = 1; P.job[0].range_shift = L.c_shift;
+    P.job[0].out_single = L.tkeys; P.job[0].single_col = 0;
+    P.job[1] = make_job(S, L.S.hist, L.S.counts, L.S.starts, 0, 0, L.b_bits, 0, 0, 0);
+    P.job[1].range_on = 1; P.job[1].range_shift = L.b_shift;
+    P.job[1].out_pair = L.S.pairs;
+    P.job[2] = make_job(R, L.R.hist, L.R.counts, L.R.starts, 0, 0, L.a_bits, 0, 0, 0);
+    P.job[2].range_on = 1; P.job[2].range_shift = L.a_shift;
+    P.job[2].out_pair = L.R.pairs;
+    int st = launch_partition(prof, "dense", P, s);
+    if (st) return st;
+    RangeAccArgs<uint32_t, uint32_t> Ad;
+    Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.T.starts; Ad.shift = L.c_shift;
+    Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
+    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
+              size_t(4) << L.c_shift, s, Ad);
+    RangeAccArgs<uint32_t, unsigned long long> Aw;
+    Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
+    Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
+    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(COUNT_THREADS),
+              size_t(8) << L.b_shift, s, Aw);
+    RangeAccArgs<unsigned long long, unsigned long long> Ac;
+    Ac.pairs = L.R.pairs; Ac.keys = nullptr; Ac.starts = L.R.starts; Ac.shift = L.a_shift;
+    Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
+    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
+              size_t(8) << L.a_shift, s, Ac);
+    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
+              count, (uint64_t)p.a_domain, L.err);
+    return MJ_OK;
+}
+
 // --------------------------------------------- degree-oriented cyclic join
 struct OrientLayout {
     unsigned long long *K, *K2, *tmp;
@@ -1250,7 +1353,9 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
 
     mj_plan_t p = planner == MJ_PLANNER_FIXED ? *plan : mj_plan_t{};
     p.kind = kind;
-    p.flags = 0;                               // properties are found here, never taken on trust
+    const uint32_t requests = planner == MJ_PLANNER_FIXED ? (plan->flags & MJ_PLAN_NO_DENSE) : 0u;
+    p.flags = requests;                        // properties are found here, never taken on trust
+    p.b_domain = p.c_domain = 0;
     p.n_r = R->n; p.n_s = S->n; p.n_t = T->n;
     p.a_domain = kind == MJ_LINEAR ? a_domain : 0;
 
@@ -1265,6 +1370,27 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
             MJ_HIP(hipMemcpyAsync(&mx, d, 4, hipMemcpyDeviceToHost, s));
             MJ_HIP(hipStreamSynchronize(s));
             if (mx >= a_domain) return MJ_ERR_KEY_RANGE;
+        }
+        // B and C in small dense domains: direct-indexed tables
+        if (!(requests & MJ_PLAN_NO_DENSE) && R->n && S->n && T->n) {
+            uint32_t* d = static_cast<uint32_t*>(ctx->stats);
+            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)2, 0u);
+            const mj_rel* src[4] = {R, S, S, T};
+            const int col[4] = {1, 0, 1, 0};          // B of R and S, C of S and T
+            for (int i = 0; i < 4; ++i) {
+                const mj_rel& r = *src[i];
+                MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(r.n, 256, 2048)), dim3(256), 0, s,
+                          col[i] ? r.col1 : r.col0, r.stride, r.n, d + (i < 2 ? 0 : 1));
+            }
+            uint32_t mx[2] = {0, 0};
+            MJ_HIP(hipMemcpyAsync(mx, d, 8, hipMemcpyDeviceToHost, s));
+            MJ_HIP(hipStreamSynchronize(s));
+            const uint64_t bdom = uint64_t(mx[0]) + 1, cdom = uint64_t(mx[1]) + 1;
+            if (dense_ok(bdom, std::max(R->n, S->n)) && dense_ok(cdom, std::max(S->n, T->n))) {
+                p.b_domain = (uint32_t)bdom;
+                p.c_domain = (uint32_t)cdom;
+                p.flags |= MJ_PLAN_DENSE_KEYS;
+            }
         }
     }
     // exact size of the binary intermediate (cascade workspace, cost model)
@@ -1351,6 +1477,17 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
     if (p.algo == MJ_ALGO_STAR)
         return run_star3(ctx, R, S, T, a_domain, count, p, ws, ws_bytes, static_cast<hipStream_t>(stream));
+    if (dense_plan(p)) {
+        if (!ws || ws_bytes < dense_layout(nullptr, p).bytes) return MJ_ERR_WORKSPACE;
+        hipStream_t sd = static_cast<hipStream_t>(stream);
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(count);
+        if (R->n == 0 || S->n == 0 || T->n == 0) {
+            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, sd,
+                      cnt, (uint64_t)a_domain, 0ull);
+            return MJ_OK;
+        }
+        return run_dense(&ctx->prof, *R, *S, *T, p, cnt, ws, sd);
+    }
     LinearLayout L = linear_layout(nullptr, p);
     if (ws_bytes < L.bytes || (!ws && L.bytes)) return MJ_ERR_WORKSPACE;
     L = linear_layout(ws, p);
@@ -1924,6 +2061,10 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
         const mj_plan_t& c = hit->second;
         plan->algo = c.algo; plan->log2_nb = c.log2_nb; plan->log2_nc = c.log2_nc;
         plan->log2_share = c.log2_share; plan->seed = c.seed;
+        // a hashed winner stays hashed; a dense winner applies only where this
+        // plan's own data was found dense (the key is the size class alone)
+        if (c.flags & MJ_PLAN_NO_DENSE)
+            plan->flags = (plan->flags & ~uint32_t(MJ_PLAN_DENSE_KEYS)) | MJ_PLAN_NO_DENSE;
         int st = plan_workspace(*plan);
         if (st) return st;
         if (tuned_ms) *tuned_ms = c.est_ms_3way;
@@ -1932,9 +2073,11 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
     std::vector<mj_plan_t> cand;
     mj_plan_t base = *plan;
     if (kind == MJ_LINEAR) {
+        if (base.flags & MJ_PLAN_DENSE_KEYS) { mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; cand.push_back(c); }
         for (uint32_t nb = 8; nb <= 10; ++nb)
             for (uint32_t nc = 8; nc <= 10; ++nc) {
                 mj_plan_t c = base; c.algo = MJ_ALGO_3WAY; c.log2_nb = nb; c.log2_nc = nc;
+                c.flags = (c.flags & ~uint32_t(MJ_PLAN_DENSE_KEYS)) | MJ_PLAN_NO_DENSE;
                 cand.push_back(c);
             }
         for (uint32_t nb = 8; nb <= 10; ++nb) {
@@ -2013,6 +2156,7 @@ int plan_workspace(mj_plan_t& p) {
             const CascadeLayout C = cascade_layout(nullptr, q, 0);
             need = std::max({need, lin, C.base_bytes + C.i_cap * sizeof(uint2) + 256});
         }
+        if (p.flags & MJ_PLAN_DENSE_KEYS) need = std::max(need, dense_layout(nullptr, p).bytes);
         // the star plans (planned or tuned only for small R)
         if (p.n_r <= STAR_PLAN_MAX_R || p.algo == MJ_ALGO_STAR || p.algo == MJ_ALGO_STAR_CASCADE) {
             need = std::max(need, star_layout(nullptr, p, false).bytes);

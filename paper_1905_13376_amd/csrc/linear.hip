@@ -550,4 +550,75 @@ k_count(CountArgs A) {
     for (uint32_t j = threadIdx.x; j < span; j += nthr) A.count[base + j] = cnt[j];
 }
 
+// ------------------------------------------------- direct-indexed tables
+// When every B and C value is below a small bound the planner has found,
+// T's multiplicities and the per-B sums W are arrays indexed by the key: the
+// same partition-then-accumulate structure with the identity as hash.  Each
+// workgroup owns one range of keys (the relation partitioned by range), sums
+// its weights in LDS and writes the range once; the weight of a tuple is one
+// read of the previous array.
+template <class TW, class TO>
+__device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, TO* acc) {
+    const uint32_t k = blockIdx.x;
+    const uint64_t base = uint64_t(k) << A.shift;
+    const uint32_t span = base < A.domain ? (uint32_t)min<uint64_t>(uint64_t(1) << A.shift, A.domain - base) : 0u;
+    const int nthr = blockDim.x;
+    for (uint32_t j = threadIdx.x; j < span; j += nthr) acc[j] = 0;
+    __syncthreads();
+    const uint32_t q0 = A.starts[k], q1 = A.starts[k + 1];
+    for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
+        uint32_t key[4];
+        TO w[4];
+        bool live[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t idx = q + u * nthr;
+            live[u] = idx < q1;
+            uint32_t v = 0;
+            if (A.pairs) {
+                const uint2 pv = live[u] ? A.pairs[idx] : make_uint2(0u, 0u);
+                key[u] = pv.x;
+                v = pv.y;
+            } else {
+                key[u] = live[u] ? A.keys[idx] : 0u;
+            }
+            if (A.table) w[u] = (live[u] && v < A.table_n) ? (TO)A.table[v] : (TO)0;    // the reads in flight together
+            else w[u] = 1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!live[u] || w[u] == 0) continue;
+            const uint64_t off = uint64_t(key[u]) - base;
+            if (key[u] >= A.domain || off >= span) { atomicExch(A.err, 1u); continue; }
+            atomicAdd(&acc[off], w[u]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < span; j += nthr) A.out[base + j] = acc[j];
+}
+
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_range_deg(RangeAccArgs<uint32_t, uint32_t> A) {
+    extern __shared__ uint32_t acc32[];
+    range_accumulate(A, acc32);
+}
+
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_range_w(RangeAccArgs<uint32_t, unsigned long long> A) {
+    extern __shared__ unsigned long long acc64w[];
+    range_accumulate(A, acc64w);
+}
+
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_range_count(RangeAccArgs<unsigned long long, unsigned long long> A) {
+    extern __shared__ unsigned long long acc64c[];
+    range_accumulate(A, acc64c);
+}
+
+__global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err) {
+    if (*err == 0) return;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = ~0ull;
+}
+
 }  // namespace mj

@@ -211,6 +211,28 @@ static_assert(CELL_CAP % CELL_THREADS == 0, "rehash takes CELL_CAP / CELL_THREAD
 constexpr int COUNT_THREADS = 512;
 constexpr uint32_t ACELL_MAX_SHIFT = 12;     // at most 4096 A values (32 KB of LDS) per range
 
+// Direct-indexed tables (keys in a small dense domain).  Per range of keys,
+// one workgroup: out[key] = sum over the range's tuples of weight(v), summed
+// in LDS and written once (zeros included); weight(v) = 1 without a table,
+// else table[v] (0 for v >= table_n).  A key outside [0, domain) sets err.
+template <class TW, class TO>
+struct RangeAccArgs {
+    const uint2* pairs;          // (key, v) by range of key; null: keys only
+    const uint32_t* keys;        // keys by range (when pairs is null)
+    const uint32_t* starts;      // [ranges + 1]
+    uint32_t shift;              // range k holds keys [k << shift, (k + 1) << shift)
+    uint32_t domain;
+    const TW* table;             // null: weight 1
+    uint32_t table_n;
+    TO* out;                     // [domain]
+    uint32_t* err;
+};
+__global__ void k_range_deg(RangeAccArgs<uint32_t, uint32_t> A);                  // keys, weight 1
+__global__ void k_range_w(RangeAccArgs<uint32_t, unsigned long long> A);          // W[b] += deg[c]
+__global__ void k_range_count(RangeAccArgs<unsigned long long, unsigned long long> A); // count[a] += W[b]
+// every entry of out set to all ones when *err is set (a certified key bound broken)
+__global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err);
+
 struct CountArgs {
     const uint2* R;              // partitioned (a, b) by range of a
     const uint32_t* rstarts;     // [number of ranges + 1]

@@ -226,10 +226,11 @@ k_part_scatter(PartLaunch L) {
         }
     } else {
         // single-column payloads are only used with a one-column bucket id
-        // computed from that same column
+        // (bits1 = 0) computed from that same column, so the staged value
+        // alone gives its bucket, hashed or by range as when it was staged
         for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
             const uint32_t v = stage[p];
-            const uint32_t d = top_bits(mix32(v, J.seed0), J.bits0);
+            const uint32_t d = part_bucket(J, v, v);
             part_store(v, J.out_single + gbase[d] + (p - lcount[d]));
         }
     }

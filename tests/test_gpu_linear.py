@@ -196,3 +196,74 @@ def test_linear_a_domain_extremes(mj, ctx, a_domain):
     untouched = np.ones(a_domain, dtype=bool)
     untouched[a_u] = False
     assert not got[untouched].any()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_linear_dense_and_hashed_tables_agree(mj, ctx, seed):
+    """Small B and C domains: the planner takes direct-indexed tables; a
+    fixed plan asking for the hashed tables gives the same, exact counts."""
+    banner(f"linear dense vs hashed tables seed={seed}")
+    rng = np.random.default_rng(400 + seed)
+    dom_b, dom_c, a_dom = [(3000, 5000, 700), (1, 1, 5), (70000, 100, 4096), (50000, 50000, 1 << 16)][seed]
+    n = [20000, 500, 60000, 200000][seed]
+    R = np.stack([rng.integers(0, a_dom, n), rng.integers(0, dom_b, n)], 1).astype(np.uint32)
+    S = np.stack([rng.integers(0, dom_b, n), rng.integers(0, dom_c, n)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, dom_c, n), rng.integers(0, 1 << 31, n)], 1).astype(np.uint32)
+    R[:7, 1] = dom_b - 1                         # the largest keys in use
+    S[:3, 1] = dom_c - 1
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    want = oracle.linear3_count(R, S, T, a_dom)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, a_dom)
+    assert p.flags & mj.PLAN_DENSE_KEYS and p.b_domain == dom_b and p.c_domain == dom_c
+    np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Rd, Sd, Td, a_dom, plan=p)), want)
+    h = fixed_plan(mj, ctx, mj.LINEAR, Rd, Sd, Td, a_dom, log2_nb=7, log2_nc=5, seed=9, flags=mj.PLAN_NO_DENSE)
+    assert not (h.flags & mj.PLAN_DENSE_KEYS)
+    np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Rd, Sd, Td, a_dom, plan=h)), want)
+
+
+def test_linear_sparse_keys_stay_hashed(mj, ctx):
+    banner("linear sparse keys: hashed tables")
+    rng = np.random.default_rng(8)
+    n = 30000
+    R = np.stack([rng.integers(0, 1000, n), rng.integers(0, 1 << 31, n)], 1).astype(np.uint32)
+    S = np.stack([R[rng.integers(0, n, n), 1], rng.integers(0, 300, n)], 1).astype(np.uint32)
+    T = rng.integers(0, 300, size=(n, 2)).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 1000)
+    assert not (p.flags & mj.PLAN_DENSE_KEYS)
+    np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 1000, plan=p)),
+                                  oracle.linear3_count(R, S, T, 1000))
+    Fd = dev(np.array([[0, 0xFFFFFFFF], [1, 2]], dtype=np.uint32))      # the all-ones key: domain 2^32
+    assert not (ctx.plan(mj.LINEAR, Fd, Fd, Fd, 2).flags & mj.PLAN_DENSE_KEYS)
+
+
+@pytest.mark.parametrize("change", ["S.b", "T.c"])
+def test_linear_dense_bound_broken_after_planning(mj, ctx, change):
+    banner(f"linear dense plan on changed data: {change}")
+    F = G.linear_small()[:20000]
+    Rd, Sd, Td = dev(F), dev(F), dev(F)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 4096)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    if change == "S.b":
+        Sd[5, 0] = 1 << 20
+    else:
+        Td[5, 0] = 1 << 20
+    got = mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 4096, plan=p))
+    assert (got == np.uint64(2 ** 64 - 1)).all()
+
+
+def test_linear_powerlaw_full_hashed_tables(mj, ctx):
+    """The full-size input through the hashed tables too (the planner takes
+    the direct-indexed ones): the sum equals the closed form and sampled A
+    values the oracle's counts."""
+    banner("linear power-law full size 2^24 edges, hashed tables")
+    F = G.linear_powerlaw()
+    Fd = dev(F)
+    p = fixed_plan(mj, ctx, mj.LINEAR, Fd, Fd, Fd, 1 << 20, log2_nb=10, log2_nc=9, seed=0x2545F491,
+                   flags=mj.PLAN_NO_DENSE)
+    got = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 1 << 20, plan=p))
+    assert int(got.sum(dtype=np.uint64)) == brute.linear_closed_total(F, F, F)
+    rng = np.random.default_rng(1)
+    sample = rng.integers(0, 1 << 20, 200).astype(np.uint32)
+    al, want = oracle.linear3_count_sampled(F, F, F, sample)
+    np.testing.assert_array_equal(got[al], want)
