@@ -29,9 +29,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain):
+def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain, b_domain=0, c_domain=0):
     """Algorithmic HBM bytes of one launch of the named kernel."""
     table = {
+        # direct-indexed tables: T.c, S and R partitioned by range in one launch group
+        "dense:k_part_hist": 4 * (n_r + n_s + n_t),     # read the key columns
+        "dense:k_part_scatter": 16 * (n_r + n_s) + 8 * n_t,   # read + write S, R pairs and T's C column
+        "k_range_deg": 4 * n_t + 4 * c_domain,          # T's C column, deg[] written once
+        # S pairs, one 4-byte deg[c] read per tuple, W[] written once
+        "k_range_w": 12 * n_s + 8 * b_domain,
+        # R pairs, one 8-byte W[b] read per tuple, the counts written once
+        "k_range_count": 16 * n_r + 8 * a_domain,
         "rs:k_part_hist": 4 * (n_r + n_s),              # read the bucketed columns
         "rs:k_part_scatter": 16 * (n_r + n_s),          # read + write 8-byte tuples
         "tab:k_part_hist": 4 * n_t,                     # read the C column
@@ -171,7 +179,7 @@ def main():
     distinct_t = int(np.unique(F[:, 0]).size)       # T.c and S.b are both F's first column
     dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
     avg_ms = kern[dom][0]
-    nbytes = kernel_bytes(dom, n, n, n, distinct_t, distinct_t, a_domain)
+    nbytes = kernel_bytes(dom, n, n, n, distinct_t, distinct_t, a_domain, plan.b_domain, plan.c_domain)
     roof = None
     if nbytes:
         ach = nbytes / (avg_ms * 1e-3) / 1e9
@@ -196,6 +204,8 @@ def main():
                                "2^24 int32 edges, 2^20 vertices, Zipf(1.1) out-degrees capped "
                                "at 4096, preferential-attachment destinations, seed 2001",
                    "a_domain": a_domain, "log2_nb": plan.log2_nb, "log2_nc": plan.log2_nc,
+                   "tables": "direct-indexed" if plan.flags & mj.PLAN_DENSE_KEYS else "hashed",
+                   "b_domain": plan.b_domain, "c_domain": plan.c_domain,
                    "plan_ms": round(plan_ms, 2), "exact_sum_check": exact,
                    "ms_per_step_with_kernel_events": round(ms_profiled, 4),
                    "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kern.items()}},

@@ -1025,27 +1025,45 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
 
 // ------------------------------------------ linear join, direct-indexed tables
 // T by range of C, S by range of B and R by range of A in one partition
-// launch group; then deg[c] over T, W[b] = sum of deg[s.c] over S, and
-// count[a] = sum of W[r.b] over R, each one range per workgroup in LDS.
+// launch group (identical partitions made once); then deg[c] over T,
+// W[b] = sum of deg[s.c] over S, and count[a] = sum of W[r.b] over R, each
+// one range per workgroup in LDS.
 int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, const mj_plan_t& p,
               unsigned long long* count, void* ws, hipStream_t s) {
     DenseLayout L = dense_layout(ws, p);
     MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    // S by range of B, R by range of A, T by range of C: each on its first
+    // column.  A partition identical to an earlier one (same columns,
+    // stride, size and ranges: R = S = T in a self-join) is not made again;
+    // its pairs and starts serve both (T then reads the keys of the pairs).
+    auto same = [](const mj_rel& x, uint32_t xb, uint32_t xs, const mj_rel& y, uint32_t yb, uint32_t ys) {
+        return same_rel(x, y) && xb == yb && xs == ys;
+    };
     PartLaunch P{};
-    P.njobs = 3;
-    P.job[0] = make_job(T, L.T.hist, L.T.counts, L.T.starts, 0, 0, L.c_bits, 0, 0, 0);
-    P.job[0].range_on = 1; P.job[0].range_shift = L.c_shift;
-    P.job[0].out_single = L.tkeys; P.job[0].single_col = 0;
-    P.job[1] = make_job(S, L.S.hist, L.S.counts, L.S.starts, 0, 0, L.b_bits, 0, 0, 0);
-    P.job[1].range_on = 1; P.job[1].range_shift = L.b_shift;
-    P.job[1].out_pair = L.S.pairs;
-    P.job[2] = make_job(R, L.R.hist, L.R.counts, L.R.starts, 0, 0, L.a_bits, 0, 0, 0);
-    P.job[2].range_on = 1; P.job[2].range_shift = L.a_shift;
-    P.job[2].out_pair = L.R.pairs;
+    P.njobs = 0;
+    P.job[P.njobs] = make_job(S, L.S.hist, L.S.counts, L.S.starts, 0, 0, L.b_bits, 0, 0, 0);
+    P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.b_shift;
+    P.job[P.njobs++].out_pair = L.S.pairs;
+    const bool r_is_s = same(R, L.a_bits, L.a_shift, S, L.b_bits, L.b_shift);
+    if (!r_is_s) {
+        P.job[P.njobs] = make_job(R, L.R.hist, L.R.counts, L.R.starts, 0, 0, L.a_bits, 0, 0, 0);
+        P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.a_shift;
+        P.job[P.njobs++].out_pair = L.R.pairs;
+    }
+    const bool t_is_s = same(T, L.c_bits, L.c_shift, S, L.b_bits, L.b_shift);
+    const bool t_is_r = !t_is_s && same(T, L.c_bits, L.c_shift, R, L.a_bits, L.a_shift);
+    if (!t_is_s && !t_is_r) {
+        P.job[P.njobs] = make_job(T, L.T.hist, L.T.counts, L.T.starts, 0, 0, L.c_bits, 0, 0, 0);
+        P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.c_shift;
+        P.job[P.njobs].out_single = L.tkeys; P.job[P.njobs++].single_col = 0;
+    }
     int st = launch_partition(prof, "dense", P, s);
     if (st) return st;
+    const RelPart& Rp = r_is_s ? L.S : L.R;
+    const RelPart* Tp = t_is_s ? &L.S : (t_is_r ? &Rp : nullptr);
     RangeAccArgs<uint32_t, uint32_t> Ad;
-    Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.T.starts; Ad.shift = L.c_shift;
+    Ad.pairs = Tp ? Tp->pairs : nullptr; Ad.keys = Tp ? nullptr : L.tkeys;
+    Ad.starts = Tp ? Tp->starts : L.T.starts; Ad.shift = L.c_shift;
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
     MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
               size_t(4) << L.c_shift, s, Ad);
@@ -1055,7 +1073,7 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(COUNT_THREADS),
               size_t(8) << L.b_shift, s, Aw);
     RangeAccArgs<unsigned long long, unsigned long long> Ac;
-    Ac.pairs = L.R.pairs; Ac.keys = nullptr; Ac.starts = L.R.starts; Ac.shift = L.a_shift;
+    Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
     MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
               size_t(8) << L.a_shift, s, Ac);

@@ -267,3 +267,22 @@ def test_linear_powerlaw_full_hashed_tables(mj, ctx):
     sample = rng.integers(0, 1 << 20, 200).astype(np.uint32)
     al, want = oracle.linear3_count_sampled(F, F, F, sample)
     np.testing.assert_array_equal(got[al], want)
+
+
+def test_linear_dense_shared_partitions(mj, ctx):
+    """Direct-indexed tables with partitions shared between relations: R = T
+    as one tensor with another S (T's partition is R's), and R = S = T with
+    a larger A domain (R's ranges differ; T's partition is S's)."""
+    banner("linear dense tables, shared partitions")
+    rng = np.random.default_rng(31)
+    F = rng.integers(0, 4096, size=(50000, 2)).astype(np.uint32)
+    Gs = rng.integers(0, 4096, size=(40000, 2)).astype(np.uint32)
+    Fd, Gd = dev(F), dev(Gs)
+    p = ctx.plan(mj.LINEAR, Fd, Gd, Fd, 4096)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Fd, Gd, Fd, 4096, plan=p)),
+                                  oracle.linear3_count(F, Gs, F, 4096))
+    q = ctx.plan(mj.LINEAR, Fd, Fd, Fd, 1 << 16)
+    assert q.flags & mj.PLAN_DENSE_KEYS
+    np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 1 << 16, plan=q)),
+                                  oracle.linear3_count(F, F, F, 1 << 16))
