@@ -236,7 +236,8 @@ struct DenseLayout {                  // the linear join with direct-indexed tab
     uint32_t* tkeys;
     uint32_t* deg;                    // [c_domain] multiplicity of each C value in T
     unsigned long long* w;            // [b_domain] W[b]
-    uint32_t* err;
+    uint32_t* w32;                    // [b_domain] low words of W[b]
+    uint32_t* err;                    // [0]: a key out of its bound; [1]: some W[b] >= 2^32
     uint32_t c_bits, c_shift, b_bits, b_shift, a_bits, a_shift;
     size_t bytes;
 };
@@ -266,7 +267,8 @@ DenseLayout dense_layout(void* ws, const mj_plan_t& p) {
     part(L.R, p.n_r, L.a_bits, true);
     L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
     L.w = B.take<unsigned long long>(std::max<uint32_t>(p.b_domain, 1));
-    L.err = B.take<uint32_t>(1);
+    L.w32 = B.take<uint32_t>(std::max<uint32_t>(p.b_domain, 1));
+    L.err = B.take<uint32_t>(2);
     L.bytes = B.off + 256;
     return L;
 }
@@ -1031,7 +1033,7 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
 int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, const mj_plan_t& p,
               unsigned long long* count, void* ws, hipStream_t s) {
     DenseLayout L = dense_layout(ws, p);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)2, 0u);
     // S by range of B, R by range of A, T by range of C: each on its first
     // column.  A partition identical to an earlier one (same columns,
     // stride, size and ranges: R = S = T in a self-join) is not made again;
@@ -1065,16 +1067,20 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     Ad.pairs = Tp ? Tp->pairs : nullptr; Ad.keys = Tp ? nullptr : L.tkeys;
     Ad.starts = Tp ? Tp->starts : L.T.starts; Ad.shift = L.c_shift;
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
+    Ad.out_narrow = nullptr; Ad.wide = nullptr; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
     MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
               size_t(4) << L.c_shift, s, Ad);
     RangeAccArgs<uint32_t, unsigned long long> Aw;
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
     Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
+    Aw.out_narrow = L.w32; Aw.wide = L.err + 1; Aw.table_narrow = nullptr; Aw.use_wide = nullptr;
     MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(COUNT_THREADS),
               size_t(8) << L.b_shift, s, Aw);
     RangeAccArgs<unsigned long long, unsigned long long> Ac;
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
+    // W's 4-byte copy unless some W[b] needs 64 bits
+    Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w32; Ac.use_wide = L.err + 1;
     MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
               size_t(8) << L.a_shift, s, Ac);
     MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,

@@ -565,6 +565,7 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, 
     const int nthr = blockDim.x;
     for (uint32_t j = threadIdx.x; j < span; j += nthr) acc[j] = 0;
     __syncthreads();
+    const bool narrow = A.table_narrow && *A.use_wide == 0;       // uniform over the launch
     const uint32_t q0 = A.starts[k], q1 = A.starts[k + 1];
     for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
         uint32_t key[4];
@@ -582,8 +583,12 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, 
             } else {
                 key[u] = live[u] ? A.keys[idx] : 0u;
             }
-            if (A.table) w[u] = (live[u] && v < A.table_n) ? (TO)A.table[v] : (TO)0;    // the reads in flight together
-            else w[u] = 1;
+            if (A.table) {                                           // the reads in flight together
+                const bool in = live[u] && v < A.table_n;
+                w[u] = !in ? (TO)0 : (narrow ? (TO)A.table_narrow[v] : (TO)A.table[v]);
+            } else {
+                w[u] = 1;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -594,7 +599,16 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, 
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < span; j += nthr) A.out[base + j] = acc[j];
+    bool big = false;
+    for (uint32_t j = threadIdx.x; j < span; j += nthr) {
+        const TO v = acc[j];
+        A.out[base + j] = v;
+        if (A.out_narrow) {
+            A.out_narrow[base + j] = (uint32_t)v;
+            big = big || (uint64_t(v) >> 32) != 0;
+        }
+    }
+    if (big) atomicOr(A.wide, 1u);
 }
 
 __global__ void __launch_bounds__(COUNT_THREADS)

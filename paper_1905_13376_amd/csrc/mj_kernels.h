@@ -226,6 +226,13 @@ struct RangeAccArgs {
     uint32_t table_n;
     TO* out;                     // [domain]
     uint32_t* err;
+    // optional 4-byte forms: out_narrow receives the low words of out and
+    // `wide` is set when some entry needs more; table_narrow is read instead
+    // of table while `use_wide` is clear (half the bytes per lookup)
+    uint32_t* out_narrow;
+    uint32_t* wide;
+    const uint32_t* table_narrow;
+    const uint32_t* use_wide;
 };
 __global__ void k_range_deg(RangeAccArgs<uint32_t, uint32_t> A);                  // keys, weight 1
 __global__ void k_range_w(RangeAccArgs<uint32_t, unsigned long long> A);          // W[b] += deg[c]

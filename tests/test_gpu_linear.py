@@ -286,3 +286,20 @@ def test_linear_dense_shared_partitions(mj, ctx):
     assert q.flags & mj.PLAN_DENSE_KEYS
     np.testing.assert_array_equal(mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, 1 << 16, plan=q)),
                                   oracle.linear3_count(F, F, F, 1 << 16))
+
+
+def test_linear_dense_w_beyond_32_bits(mj, ctx):
+    """A per-B sum W[b] of 70000 x 70000 > 2^32: the direct-indexed path
+    must read the 8-byte W, not its 4-byte copy."""
+    banner("linear dense tables, W beyond 32 bits")
+    n = 70000
+    R = np.stack([np.arange(5) % 3, np.zeros(5)], 1).astype(np.uint32)
+    S = np.stack([np.zeros(n), np.zeros(n)], 1).astype(np.uint32)
+    T = np.stack([np.zeros(n), np.arange(n)], 1).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 3)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    got = mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 3, plan=p))
+    want = oracle.linear3_count(R, S, T, 3)
+    assert int(want.max()) > 2 ** 32
+    np.testing.assert_array_equal(got, want)
