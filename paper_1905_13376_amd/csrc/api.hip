@@ -235,9 +235,11 @@ struct DenseLayout {                  // the linear join with direct-indexed tab
     RelPart T, S, R;                  // T.c by range of C (keys in T.pairs' space), S by B, R by A
     uint32_t* tkeys;
     uint32_t* deg;                    // [c_domain] multiplicity of each C value in T
+    uint16_t* deg16;                  // [c_domain] the same, cut to 16 bits
     unsigned long long* w;            // [b_domain] W[b]
     uint32_t* w32;                    // [b_domain] low words of W[b]
-    uint32_t* err;                    // [0]: a key out of its bound; [1]: some W[b] >= 2^32
+    uint32_t* err;                    // [0]: a key out of its bound; [1]: some W[b] >= 2^32;
+                                      // [2]: some deg[c] >= 2^16
     uint32_t c_bits, c_shift, b_bits, b_shift, a_bits, a_shift;
     size_t bytes;
 };
@@ -266,9 +268,10 @@ DenseLayout dense_layout(void* ws, const mj_plan_t& p) {
     part(L.S, p.n_s, L.b_bits, true);
     part(L.R, p.n_r, L.a_bits, true);
     L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
+    L.deg16 = B.take<uint16_t>(std::max<uint32_t>(p.c_domain, 1));
     L.w = B.take<unsigned long long>(std::max<uint32_t>(p.b_domain, 1));
     L.w32 = B.take<uint32_t>(std::max<uint32_t>(p.b_domain, 1));
-    L.err = B.take<uint32_t>(2);
+    L.err = B.take<uint32_t>(3);
     L.bytes = B.off + 256;
     return L;
 }
@@ -1033,7 +1036,7 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
 int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, const mj_plan_t& p,
               unsigned long long* count, void* ws, hipStream_t s) {
     DenseLayout L = dense_layout(ws, p);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)2, 0u);
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)3, 0u);
     // S by range of B, R by range of A, T by range of C: each on its first
     // column.  A partition identical to an earlier one (same columns,
     // stride, size and ranges: R = S = T in a self-join) is not made again;
@@ -1063,20 +1066,21 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     if (st) return st;
     const RelPart& Rp = r_is_s ? L.S : L.R;
     const RelPart* Tp = t_is_s ? &L.S : (t_is_r ? &Rp : nullptr);
-    RangeAccArgs<uint32_t, uint32_t> Ad;
+    RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad;
     Ad.pairs = Tp ? Tp->pairs : nullptr; Ad.keys = Tp ? nullptr : L.tkeys;
     Ad.starts = Tp ? Tp->starts : L.T.starts; Ad.shift = L.c_shift;
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
-    Ad.out_narrow = nullptr; Ad.wide = nullptr; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
+    Ad.out_narrow = L.deg16; Ad.wide = L.err + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
     MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
               size_t(4) << L.c_shift, s, Ad);
-    RangeAccArgs<uint32_t, unsigned long long> Aw;
+    RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> Aw;
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
     Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
-    Aw.out_narrow = L.w32; Aw.wide = L.err + 1; Aw.table_narrow = nullptr; Aw.use_wide = nullptr;
+    // deg's 2-byte copy unless some deg[c] needs more
+    Aw.out_narrow = L.w32; Aw.wide = L.err + 1; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
     MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(COUNT_THREADS),
               size_t(8) << L.b_shift, s, Aw);
-    RangeAccArgs<unsigned long long, unsigned long long> Ac;
+    RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> Ac;
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
     // W's 4-byte copy unless some W[b] needs 64 bits

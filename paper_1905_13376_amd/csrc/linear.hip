@@ -557,8 +557,8 @@ k_count(CountArgs A) {
 // workgroup owns one range of keys (the relation partitioned by range), sums
 // its weights in LDS and writes the range once; the weight of a tuple is one
 // read of the previous array.
-template <class TW, class TO>
-__device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, TO* acc) {
+template <class TW, class TWN, class TO, class TON>
+__device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO, TON>& A, TO* acc) {
     const uint32_t k = blockIdx.x;
     const uint64_t base = uint64_t(k) << A.shift;
     const uint32_t span = base < A.domain ? (uint32_t)min<uint64_t>(uint64_t(1) << A.shift, A.domain - base) : 0u;
@@ -604,27 +604,27 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TO>& A, 
         const TO v = acc[j];
         A.out[base + j] = v;
         if (A.out_narrow) {
-            A.out_narrow[base + j] = (uint32_t)v;
-            big = big || (uint64_t(v) >> 32) != 0;
+            A.out_narrow[base + j] = (TON)v;
+            big = big || uint64_t(v) > uint64_t(TON(~TON(0)));
         }
     }
     if (big) atomicOr(A.wide, 1u);
 }
 
 __global__ void __launch_bounds__(COUNT_THREADS)
-k_range_deg(RangeAccArgs<uint32_t, uint32_t> A) {
+k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A) {
     extern __shared__ uint32_t acc32[];
     range_accumulate(A, acc32);
 }
 
 __global__ void __launch_bounds__(COUNT_THREADS)
-k_range_w(RangeAccArgs<uint32_t, unsigned long long> A) {
+k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> A) {
     extern __shared__ unsigned long long acc64w[];
     range_accumulate(A, acc64w);
 }
 
 __global__ void __launch_bounds__(COUNT_THREADS)
-k_range_count(RangeAccArgs<unsigned long long, unsigned long long> A) {
+k_range_count(RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> A) {
     extern __shared__ unsigned long long acc64c[];
     range_accumulate(A, acc64c);
 }

@@ -215,7 +215,7 @@ constexpr uint32_t ACELL_MAX_SHIFT = 12;     // at most 4096 A values (32 KB of 
 // one workgroup: out[key] = sum over the range's tuples of weight(v), summed
 // in LDS and written once (zeros included); weight(v) = 1 without a table,
 // else table[v] (0 for v >= table_n).  A key outside [0, domain) sets err.
-template <class TW, class TO>
+template <class TW, class TWN, class TO, class TON>
 struct RangeAccArgs {
     const uint2* pairs;          // (key, v) by range of key; null: keys only
     const uint32_t* keys;        // keys by range (when pairs is null)
@@ -226,17 +226,20 @@ struct RangeAccArgs {
     uint32_t table_n;
     TO* out;                     // [domain]
     uint32_t* err;
-    // optional 4-byte forms: out_narrow receives the low words of out and
-    // `wide` is set when some entry needs more; table_narrow is read instead
-    // of table while `use_wide` is clear (half the bytes per lookup)
-    uint32_t* out_narrow;
+    // optional narrow forms: out_narrow receives out cut to TON and `wide` is
+    // set when some entry does not fit; table_narrow (the previous array's
+    // narrow form) is read instead of table while `use_wide` is clear
+    TON* out_narrow;
     uint32_t* wide;
-    const uint32_t* table_narrow;
+    const TWN* table_narrow;
     const uint32_t* use_wide;
 };
-__global__ void k_range_deg(RangeAccArgs<uint32_t, uint32_t> A);                  // keys, weight 1
-__global__ void k_range_w(RangeAccArgs<uint32_t, unsigned long long> A);          // W[b] += deg[c]
-__global__ void k_range_count(RangeAccArgs<unsigned long long, unsigned long long> A); // count[a] += W[b]
+// deg[c]: keys only, weight 1 (narrow copy: 16 bits)
+__global__ void k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A);
+// W[b] += deg[s.c] (narrow copy: 32 bits)
+__global__ void k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> A);
+// count[a] += W[r.b]
+__global__ void k_range_count(RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> A);
 // every entry of out set to all ones when *err is set (a certified key bound broken)
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err);
 
