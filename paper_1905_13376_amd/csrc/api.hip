@@ -336,11 +336,12 @@ CascadeLayout cascade_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
     take_part(B, L.R, p.n_r, p.log2_nb);
     take_part(B, L.S, p.n_s, p.log2_nb);
     take_table(B, L.T, p.n_t, p.log2_nc);
-    L.Rgrp = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
-    L.ecnt = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
-    L.elist = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
-    L.eoff = B.take<unsigned long long>(p.n_s + 1);
-    const uint64_t nblk = (p.n_s + SCAN_TILE - 1) / SCAN_TILE;
+    // join 1 groups S's C values by B and probes with R's tuples
+    L.Rgrp = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
+    L.ecnt = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+    L.elist = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
+    L.eoff = B.take<unsigned long long>(p.n_r + 1);
+    const uint64_t nblk = (p.n_r + SCAN_TILE - 1) / SCAN_TILE;
     L.partial = B.take<unsigned long long>(nblk + 1);
     L.I = B.take<uint2>(0);
     L.base_bytes = B.off + 256;
@@ -776,7 +777,7 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         const uint64_t hi = std::min<uint64_t>(totI, lo + L.i_cap);
         CasExpandArgs E;
         E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.S.pairs; E.ns = S->n;
-        E.lo = lo; E.hi = hi; E.I = L.I;
+        E.lo = lo; E.hi = hi; E.I = L.I; E.swap = 0;
         MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
                   dim3(EXP_THREADS), 0, s, E);
         CasProbeTriArgs Q;
@@ -1655,34 +1656,40 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     // join 2's build side: T partitioned by C, one multiplicity table per bucket
     st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
     if (st) return st;
-    // join 1: R and S partitioned by B
+    // join 1: R and S partitioned by B.  S is the build side (its C values
+    // grouped by B) and R the probe side, so the pairs of I come R tuple by R
+    // tuple and the second join can sum a run of one A value before its
+    // atomic.  The partitions store S as (c, b) and R as (b, a), the layout
+    // the grouping kernel reads (value, key) and (key, value) in.
     const uint32_t nb = 1u << p.log2_nb;
     PartLaunch P{};
     P.njobs = 2;
-    P.job[0] = make_job(*R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
-    P.job[0].out_pair = L.R.pairs;
-    P.job[1] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
-    P.job[1].out_pair = L.S.pairs;
+    P.job[0] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[0].out_pair = L.S.pairs;
+    P.job[0].swap_out = 1;
+    P.job[1] = make_job(*R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+    P.job[1].out_pair = L.R.pairs;
+    P.job[1].swap_out = 1;
     st = launch_partition(prof, "rs", P, s);
     if (st) return st;
     CasIndexArgs X;
-    X.R = L.R.pairs; X.rstarts = L.R.starts; X.S = L.S.pairs; X.sstarts = L.S.starts;
+    X.R = L.S.pairs; X.rstarts = L.S.starts; X.S = L.R.pairs; X.sstarts = L.R.starts;
     X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
     MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
-    const uint32_t nblk = (uint32_t)((S->n + SCAN_TILE - 1) / SCAN_TILE);
+    const uint32_t nblk = (uint32_t)((R->n + SCAN_TILE - 1) / SCAN_TILE);
     MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s,
-              L.ecnt, (uint64_t)S->n, L.partial);
+              L.ecnt, (uint64_t)R->n, L.partial);
     MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s,
               L.partial, nblk);
     MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s,
-              L.ecnt, (uint64_t)S->n, L.partial, L.eoff);
+              L.ecnt, (uint64_t)R->n, L.partial, L.eoff);
     // the intermediate, chunk by chunk: materialise, then join with T
     const uint64_t total = p.join2_size;
     for (uint64_t lo = 0; lo < total; lo += L.i_cap) {
         const uint64_t hi = std::min<uint64_t>(total, lo + L.i_cap);
         CasExpandArgs E;
-        E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.S.pairs; E.ns = S->n;
-        E.lo = lo; E.hi = hi; E.I = L.I;
+        E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.R.pairs; E.ns = R->n;
+        E.lo = lo; E.hi = hi; E.I = L.I; E.swap = 1;          // (a, c)
         MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
                   dim3(EXP_THREADS), 0, s, E);
         CasProbeArgs Q;

@@ -12,7 +12,8 @@
 //                  over many workgroups; writes I[p] = (a, c) coalesced
 //   k_cas_probe  : for every (a, c) of I, count[a] += mult_T(c), probing the
 //                  bucketed multiplicity tables of T (the paper's on-chip T
-//                  partitions of the second join)
+//                  partitions of the second join); a wave sums each run of
+//                  equal a before one atomic
 // I can be produced and consumed in chunks of the workspace.
 #include "mj_kernels.h"
 
@@ -264,15 +265,16 @@ k_cas_expand(CasExpandArgs A) {
             continue;
         }
         const uint32_t k = (uint32_t)(p - A.eoff[s]);
-        const uint32_t a = A.Rgrp[A.elist[s] + k];
-        const uint32_t c = A.S[s].y;
-        A.I[p - A.lo] = make_uint2(a, c);
+        const uint32_t g = A.Rgrp[A.elist[s] + k];
+        const uint32_t v = A.S[s].y;
+        A.I[p - A.lo] = A.swap ? make_uint2(v, g) : make_uint2(g, v);
     }
 }
 
 // ------------------------------------------------------------- second join
 __global__ void __launch_bounds__(256)
 k_cas_probe(CasProbeArgs A) {
+    const int lane = lane_id();
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
     for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
         uint2 iv[4];
@@ -282,15 +284,33 @@ k_cas_probe(CasProbeArgs A) {
         for (int u = 0; u < 4; ++u) {
             const uint64_t idx = q + uint64_t(u) * blockDim.x;
             live[u] = idx < A.n;
-            iv[u] = live[u] ? A.I[idx] : make_uint2(0u, 0u);
+            iv[u] = live[u] ? A.I[idx] : make_uint2(0xFFFFFFFFu, 0u);
             c[u] = iv[u].y;
         }
         dtab_lookup4(A.ddir, A.dpool, c, live, A.c_seed, A.c_bits, A.slot_seed, w);
+        // a wave holds 64 consecutive pairs per u: sum each run of equal a
+        // (segments by ballot, not by value, so two runs of one a stay apart)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (!w[u]) continue;
-            if (iv[u].x < A.a_domain) atomicAdd(&A.count[iv[u].x], (unsigned long long)w[u]);
-            else atomicExch(A.err, 1u);
+            const uint32_t a = iv[u].x;
+            unsigned long long v = live[u] ? (unsigned long long)w[u] : 0ull;
+            const uint32_t a_up = (uint32_t)__shfl_up((int)a, 1, WAVE);
+            const bool live_up = __shfl_up((int)live[u], 1, WAVE) != 0;
+            const bool head = lane == 0 || a_up != a || live_up != live[u];
+            const unsigned long long heads = __ballot(head);
+            const unsigned long long upto = lane == WAVE - 1 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+            const int seg = __popcll(heads & upto);
+#pragma unroll
+            for (int off = 1; off < WAVE; off <<= 1) {
+                const unsigned long long y = __shfl_up(v, off, WAVE);
+                const int sy = __shfl_up(seg, off, WAVE);
+                if (lane >= off && sy == seg) v += y;
+            }
+            const int seg_next = __shfl_down(seg, 1, WAVE);
+            const bool tail = lane == WAVE - 1 || seg_next != seg;
+            if (!tail || !live[u]) continue;
+            if (a >= A.a_domain) { atomicExch(A.err, 1u); continue; }
+            if (v) atomicAdd(&A.count[a], v);
         }
     }
 }

@@ -52,6 +52,7 @@ struct PartJob {
     uint32_t single_col;
     uint32_t range_on;   // bucket = min(key0 >> range_shift, 2^bits0 - 1) (no hash; pairs only)
     uint32_t range_shift;
+    uint32_t swap_out;   // pairs written as (col1, col0)
     uint32_t tile_begin; // first block of this job in the grid
     uint32_t ntiles;
 };
@@ -425,9 +426,13 @@ struct CasExpandArgs {
     uint64_t ns;
     unsigned long long lo, hi;        // chunk of I positions
     uint2* I;                         // [hi - lo]
+    uint32_t swap;                    // write (S value, grouped value) instead of (grouped value, S value)
 };
 __global__ void k_cas_expand(CasExpandArgs A);
 
+// I's pairs (a, c) come with the pairs of one A value consecutive (the
+// first join probes with R): each wave sums its runs of equal a before one
+// atomic per run
 struct CasProbeArgs {
     const uint2* I;
     uint64_t n;

@@ -221,7 +221,9 @@ k_part_scatter(PartLaunch L) {
         for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
             const uint2 v = st[p];
             const uint32_t d = part_bucket(J, v.x, v.y);
-            u32x2 w; w.x = v.x; w.y = v.y;
+            u32x2 w;
+            w.x = J.swap_out ? v.y : v.x;
+            w.y = J.swap_out ? v.x : v.y;
             part_store(w, reinterpret_cast<u32x2*>(J.out_pair) + gbase[d] + (p - lcount[d]));
         }
     } else {
