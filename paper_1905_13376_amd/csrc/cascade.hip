@@ -256,18 +256,46 @@ k_cas_expand(CasExpandArgs A) {
     }
     __syncthreads();
     const uint64_t sf = s_first, sl = s_last;
-    for (unsigned long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-        uint64_t lo = sf, hi = sl + 1;        // last s in [sf, sl] with eoff[s] <= p
-        while (hi - lo > 1) { uint64_t m = (lo + hi) >> 1; if (A.eoff[m] <= p) lo = m; else hi = m; }
-        const uint64_t s = lo;
-        if (p >= A.eoff[A.ns]) {              // only with a plan made for other data
-            A.I[p - A.lo] = make_uint2(EMPTY_KEY, EMPTY_KEY);
-            continue;
+    // the tile's list starts in LDS when they fit (the usual case)
+    __shared__ unsigned long long woff[EXP_WIN];
+    const bool win = sl - sf < EXP_WIN;
+    if (win)
+        for (uint64_t k = threadIdx.x; k <= sl - sf; k += blockDim.x) woff[k] = A.eoff[sf + k];
+    __syncthreads();
+    const unsigned long long total = A.eoff[A.ns];
+    // four positions per thread and step, their list reads in flight together
+    for (unsigned long long p00 = p0 + threadIdx.x; p00 < p1; p00 += 4ull * blockDim.x) {
+        uint64_t sidx[4];
+        unsigned long long base[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long p = min<unsigned long long>(p00 + uint64_t(u) * blockDim.x, p1 - 1);
+            uint64_t lo = 0, hi = sl - sf + 1;    // last s in [sf, sl] with eoff[s] <= p
+            if (win) {
+                while (hi - lo > 1) { uint64_t m = (lo + hi) >> 1; if (woff[m] <= p) lo = m; else hi = m; }
+                base[u] = woff[lo];
+            } else {
+                while (hi - lo > 1) { uint64_t m = (lo + hi) >> 1; if (A.eoff[sf + m] <= p) lo = m; else hi = m; }
+                base[u] = A.eoff[sf + lo];
+            }
+            sidx[u] = sf + lo;
         }
-        const uint32_t k = (uint32_t)(p - A.eoff[s]);
-        const uint32_t g = A.Rgrp[A.elist[s] + k];
-        const uint32_t v = A.S[s].y;
-        A.I[p - A.lo] = A.swap ? make_uint2(v, g) : make_uint2(g, v);
+        uint32_t g[4], v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long p = min<unsigned long long>(p00 + uint64_t(u) * blockDim.x, p1 - 1);
+            const bool ok = p < total;
+            g[u] = ok ? A.Rgrp[A.elist[sidx[u]] + (uint32_t)(p - base[u])] : EMPTY_KEY;
+            v[u] = ok ? A.S[sidx[u]].y : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long p = p00 + uint64_t(u) * blockDim.x;
+            if (p >= p1) continue;
+            // a position past the intermediate's end only comes with a plan
+            // made for other data: marked, not joined
+            A.I[p - A.lo] = A.swap ? make_uint2(v[u], g[u]) : make_uint2(g[u], v[u]);
+        }
     }
 }
 

@@ -405,6 +405,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_TILE = 4096;
 constexpr int EXP_THREADS = 256;
 constexpr int EXP_TILE = 4096;
+constexpr uint32_t EXP_WIN = 2048;        // list starts of one expansion tile held in LDS
 
 struct CasIndexArgs {
     const uint2* R;              // partitioned (a, b) by bucket of b
