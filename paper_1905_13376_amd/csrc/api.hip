@@ -318,6 +318,13 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
 struct CascadeLayout {
     RelPart R, S;
     TableLayout T;
+    // dense keys: T's C column by range and its multiplicities deg / deg16
+    RelPart Tr;
+    uint32_t* tkeys;
+    uint32_t* deg;
+    uint16_t* deg16;
+    uint32_t* dflags;                 // [0]: a C value out of its bound; [1]: unused; [2]: some deg >= 2^16
+    uint32_t c_bits, c_shift;
     uint32_t* Rgrp;
     uint32_t* ecnt;
     uint32_t* elist;
@@ -335,7 +342,21 @@ CascadeLayout cascade_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
     CascadeLayout L;
     take_part(B, L.R, p.n_r, p.log2_nb);
     take_part(B, L.S, p.n_s, p.log2_nb);
-    take_table(B, L.T, p.n_t, p.log2_nc);
+    L.Tr = RelPart{}; L.tkeys = nullptr; L.deg = nullptr; L.deg16 = nullptr; L.dflags = nullptr;
+    L.c_bits = L.c_shift = 0;
+    if (dense_plan(p)) {
+        key_ranges(p.n_t, p.c_domain, L.c_bits, L.c_shift);
+        const uint32_t nb = 1u << L.c_bits;
+        L.Tr.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(p.n_t));
+        L.Tr.counts = B.take<uint32_t>(nb);
+        L.Tr.starts = B.take<uint32_t>(nb + 1);
+        L.tkeys = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
+        L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
+        L.deg16 = B.take<uint16_t>(std::max<uint32_t>(p.c_domain, 1));
+        L.dflags = B.take<uint32_t>(3);
+    } else {
+        take_table(B, L.T, p.n_t, p.log2_nc);
+    }
     // join 1 groups S's C values by B and probes with R's tuples
     L.Rgrp = B.take<uint32_t>(std::max<uint64_t>(p.n_s, 1));
     L.ecnt = B.take<uint32_t>(std::max<uint64_t>(p.n_r, 1));
@@ -1653,9 +1674,27 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
                   count, (uint64_t)a_domain, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0 || p.join2_size == 0) return MJ_OK;
 
-    // join 2's build side: T partitioned by C, one multiplicity table per bucket
-    st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
-    if (st) return st;
+    // join 2's build side: T partitioned by C, one multiplicity table per
+    // bucket -- or, for dense keys, T by range of C and deg[c] directly
+    const bool dense = L.deg != nullptr;
+    if (dense) {
+        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.dflags, (uint64_t)3, 0u);
+        PartLaunch PT{};
+        PT.njobs = 1;
+        PT.job[0] = make_job(*T, L.Tr.hist, L.Tr.counts, L.Tr.starts, 0, 0, L.c_bits, 0, 0, 0);
+        PT.job[0].range_on = 1; PT.job[0].range_shift = L.c_shift;
+        PT.job[0].out_single = L.tkeys; PT.job[0].single_col = 0;
+        if ((st = launch_partition(prof, "tab", PT, s))) return st;
+        RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad;
+        Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.Tr.starts; Ad.shift = L.c_shift;
+        Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.dflags;
+        Ad.out_narrow = L.deg16; Ad.wide = L.dflags + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
+        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
+                  size_t(4) << L.c_shift, s, Ad);
+    } else {
+        st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
+        if (st) return st;
+    }
     // join 1: R and S partitioned by B.  S is the build side (its C values
     // grouped by B) and R the probe side, so the pairs of I come R tuple by R
     // tuple and the second join can sum a run of one A value before its
@@ -1693,11 +1732,16 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
                   dim3(EXP_THREADS), 0, s, E);
         CasProbeArgs Q;
-        Q.I = L.I; Q.n = hi - lo; Q.ddir = L.T.dir; Q.dpool = L.T.pool;
+        Q.I = L.I; Q.n = hi - lo; Q.ddir = dense ? nullptr : L.T.dir; Q.dpool = dense ? nullptr : L.T.pool;
         Q.c_seed = seed_c(p); Q.c_bits = p.log2_nc; Q.slot_seed = seed_slot(p);
-        Q.count = count; Q.a_domain = a_domain; Q.err = L.T.err;
+        Q.count = count; Q.a_domain = a_domain; Q.err = dense ? L.dflags : L.T.err;
+        Q.deg = L.deg; Q.deg16 = L.deg16; Q.c_domain = p.c_domain; Q.use_wide = dense ? L.dflags + 2 : nullptr;
         MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
     }
+    // dense keys: a key beyond its certified bound makes every count all ones
+    if (dense)
+        MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+                  count, (uint64_t)a_domain, L.dflags);
     return MJ_OK;
 }
 

@@ -303,6 +303,7 @@ k_cas_expand(CasExpandArgs A) {
 __global__ void __launch_bounds__(256)
 k_cas_probe(CasProbeArgs A) {
     const int lane = lane_id();
+    const bool wide = A.deg && *A.use_wide != 0;           // uniform over the launch
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
     for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
         uint2 iv[4];
@@ -315,7 +316,13 @@ k_cas_probe(CasProbeArgs A) {
             iv[u] = live[u] ? A.I[idx] : make_uint2(0xFFFFFFFFu, 0u);
             c[u] = iv[u].y;
         }
-        dtab_lookup4(A.ddir, A.dpool, c, live, A.c_seed, A.c_bits, A.slot_seed, w);
+        if (A.deg) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                w[u] = (live[u] && c[u] < A.c_domain) ? (wide ? A.deg[c[u]] : (uint32_t)A.deg16[c[u]]) : 0u;
+        } else {
+            dtab_lookup4(A.ddir, A.dpool, c, live, A.c_seed, A.c_bits, A.slot_seed, w);
+        }
         // a wave holds 64 consecutive pairs per u: sum each run of equal a
         // (segments by ballot, not by value, so two runs of one a stay apart)
 #pragma unroll

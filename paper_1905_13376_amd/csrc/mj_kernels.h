@@ -443,6 +443,12 @@ struct CasProbeArgs {
     unsigned long long* count;
     uint32_t a_domain;
     uint32_t* err;
+    // dense keys: mult_T(c) = deg[c] (its 2-byte copy while *use_wide is clear)
+    // for c < c_domain, instead of the bucketed tables
+    const uint32_t* deg;
+    const uint16_t* deg16;
+    uint32_t c_domain;
+    const uint32_t* use_wide;
 };
 __global__ void k_cas_probe(CasProbeArgs A);
 

@@ -126,3 +126,27 @@ def test_cascade_powerlaw_full(mj, ctx):
     three = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, A, plan=p))
     np.testing.assert_array_equal(got, three)
     assert int(got.sum(dtype=np.uint64)) == brute.linear_closed_total(F, F, F)
+
+
+def test_cascade_dense_and_hashed_agree(mj, ctx):
+    """The cascade's second join reads T's multiplicities from direct-indexed
+    arrays when the keys are dense, from the bucketed tables otherwise: the
+    same counts either way, and a C value beyond its bound at count time
+    sets every count to all ones."""
+    from tests.gpu_util import banner, dev, fixed_plan
+    banner("cascade dense vs hashed tables")
+    rng = np.random.default_rng(77)
+    R = np.stack([rng.integers(0, 900, 30000), rng.integers(0, 2000, 30000)], 1).astype(np.uint32)
+    S = np.stack([rng.integers(0, 2000, 30000), rng.integers(0, 3000, 30000)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, 3000, 30000), rng.integers(0, 10, 30000)], 1).astype(np.uint32)
+    T[:50, 0] = 7                                 # a C value with a high multiplicity
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    want = oracle.linear3_count(R, S, T, 900)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 900)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    np.testing.assert_array_equal(mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 900, plan=p)), want)
+    h = fixed_plan(mj, ctx, mj.LINEAR, Rd, Sd, Td, 900, log2_nb=6, log2_nc=6, seed=3, flags=mj.PLAN_NO_DENSE)
+    np.testing.assert_array_equal(mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 900, plan=h)), want)
+    Td[3, 0] = 1 << 20                            # beyond c_domain
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 900, plan=p))
+    assert (got == np.uint64(2 ** 64 - 1)).all()
