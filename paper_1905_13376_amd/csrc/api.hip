@@ -1093,21 +1093,21 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     Ad.starts = Tp ? Tp->starts : L.T.starts; Ad.shift = L.c_shift;
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
     Ad.out_narrow = L.deg16; Ad.wide = L.err + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
-    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
+    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
               size_t(4) << L.c_shift, s, Ad);
     RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> Aw;
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
     Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
     // deg's 2-byte copy unless some deg[c] needs more
     Aw.out_narrow = L.w32; Aw.wide = L.err + 1; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
-    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(COUNT_THREADS),
+    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(RANGE_THREADS),
               size_t(8) << L.b_shift, s, Aw);
     RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> Ac;
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
     // W's 4-byte copy unless some W[b] needs 64 bits
     Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w32; Ac.use_wide = L.err + 1;
-    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
+    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(RANGE_THREADS),
               size_t(8) << L.a_shift, s, Ac);
     MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)p.a_domain, L.err);
@@ -1689,7 +1689,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.Tr.starts; Ad.shift = L.c_shift;
         Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.dflags;
         Ad.out_narrow = L.deg16; Ad.wide = L.dflags + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
-        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(COUNT_THREADS),
+        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
                   size_t(4) << L.c_shift, s, Ad);
     } else {
         st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);

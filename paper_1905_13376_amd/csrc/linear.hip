@@ -611,19 +611,19 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
     if (big) atomicOr(A.wide, 1u);
 }
 
-__global__ void __launch_bounds__(COUNT_THREADS)
+__global__ void __launch_bounds__(RANGE_THREADS)
 k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A) {
     extern __shared__ uint32_t acc32[];
     range_accumulate(A, acc32);
 }
 
-__global__ void __launch_bounds__(COUNT_THREADS)
+__global__ void __launch_bounds__(RANGE_THREADS)
 k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> A) {
     extern __shared__ unsigned long long acc64w[];
     range_accumulate(A, acc64w);
 }
 
-__global__ void __launch_bounds__(COUNT_THREADS)
+__global__ void __launch_bounds__(RANGE_THREADS)
 k_range_count(RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> A) {
     extern __shared__ unsigned long long acc64c[];
     range_accumulate(A, acc64c);

@@ -212,6 +212,8 @@ static_assert(CELL_CAP % CELL_THREADS == 0, "rehash takes CELL_CAP / CELL_THREAD
 constexpr int COUNT_THREADS = 512;
 constexpr uint32_t ACELL_MAX_SHIFT = 12;     // at most 4096 A values (32 KB of LDS) per range
 
+constexpr int RANGE_THREADS = 1024;         // range sums: one workgroup per range of keys
+
 // Direct-indexed tables (keys in a small dense domain).  Per range of keys,
 // one workgroup: out[key] = sum over the range's tuples of weight(v), summed
 // in LDS and written once (zeros included); weight(v) = 1 without a table,
