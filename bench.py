@@ -81,7 +81,16 @@ def cpu_baseline(F, a_domain):
     oracle.linear3_count(Rs, F, F, a_domain)
     dt = time.perf_counter() - t0
     n_in = Rs.shape[0] + 2 * F.shape[0]
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n_in / dt, "unit": "input tuples/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_nproc": os.cpu_count(),
             "sample": f"R = every 16th tuple of F ({Rs.shape[0]} tuples), S = T = F "
                       f"({F.shape[0]} tuples); {dt:.2f} s single-threaded"}
 
