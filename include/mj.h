@@ -232,7 +232,12 @@ int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const 
  * carries its relations, its output (uint64[a_domain] or uint64[1], device)
  * and a plan from mj_plan (or the autotuner).  The preparation of every join
  * (partitions, multiplicity tables, sorts, work queues) is launched join by
- * join; then the cells of ALL linear joins run in one launch, and the groups
+ * join on four lanes, `stream` and three streams the context owns (default
+ * priority), each join on the lane with the least work so far; the
+ * context's streams start after everything queued on `stream` before the
+ * call and `stream` waits for all of them, so the call is ordered on
+ * `stream` like any other.  Then the cells of ALL linear
+ * joins run in one launch on `stream`, and the groups
  * of ALL cyclic joins in two persistent launches that pull work items from
  * device queues (so the many small joins share the chip instead of each
  * paying its own tail).  Items planned as cascades run their own path.

@@ -65,6 +65,9 @@ struct Prof {
     } while (0)
 
 // ------------------------------------------------------------------ context
+constexpr int BATCH_LANES = 3;   // a batch's own streams; with the caller's, the four hardware
+                                 // queues one process gets by default
+
 struct mj_ctx {
     int device = 0;
     int num_cu = 256;
@@ -79,6 +82,12 @@ struct mj_ctx {
     std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
     std::vector<void*> pinned;                  // batch argument tables (kept alive)
     const void* planner = nullptr;              // learned planner parameters (device)
+    // streams on which a batch prepares its joins side by side (default
+    // priority), the events that join each back to the caller's stream, and
+    // the one that forks them from it; made at the first batch call
+    hipStream_t lanes[BATCH_LANES] = {};
+    hipEvent_t lane_done[BATCH_LANES] = {};
+    hipEvent_t lane_fork = nullptr;
 };
 
 namespace {
@@ -575,6 +584,16 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
                       uint32_t first_pass = 0) {
     if (n <= 1) return MJ_OK;
     if (first_pass & 1) return MJ_ERR_INVALID_ARG;
+    if (first_pass >= 8) return MJ_OK;
+    if (n <= RS_SMALL) {                 // the whole sort in one workgroup
+        uint32_t P = 2;
+        while (P < n) P <<= 1;
+        const uint32_t shift = 8 * first_pass;
+        const size_t smem = size_t(shift ? 2 : 1) * P * sizeof(unsigned long long);
+        MJ_LAUNCH(prof, "k_rs_small", k_rs_small, dim3(1), dim3(RS_SMALL_THREADS), smem, s, keys, (uint32_t)n,
+                  shift);
+        return MJ_OK;
+    }
     const uint32_t ntiles = (uint32_t)((n + RS_TILE - 1) / RS_TILE);
     unsigned long long* src = keys;
     unsigned long long* dst = tmp;
@@ -583,13 +602,17 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
         A.in = src; A.out = dst; A.n = n; A.shift = 8 * pass; A.ntiles = ntiles;
         A.hist = hist; A.starts = starts;
         MJ_LAUNCH(prof, "k_rs_hist", k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
-        PartLaunch P{};
-        P.njobs = 1;
-        P.job[0].hist = hist; P.job[0].ntiles = ntiles; P.job[0].counts = counts;
-        P.job[0].starts = starts; P.job[0].bits0 = 8; P.job[0].bits1 = 0;
-        MJ_LAUNCH(prof, "k_part_rowscan", k_part_rowscan, dim3(256), dim3(PART_THREADS),
-                  PART_SCAN_CHUNK * 4, s, P);
-        MJ_LAUNCH(prof, "k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), 256 * 4, s, P);
+        if (ntiles <= RS_SCAN1_TILES) {
+            MJ_LAUNCH(prof, "k_rs_scan1", k_rs_scan1, dim3(1), dim3(256), 0, s, A, starts);
+        } else {
+            PartLaunch P{};
+            P.njobs = 1;
+            P.job[0].hist = hist; P.job[0].ntiles = ntiles; P.job[0].counts = counts;
+            P.job[0].starts = starts; P.job[0].bits0 = 8; P.job[0].bits1 = 0;
+            MJ_LAUNCH(prof, "k_part_rowscan", k_part_rowscan, dim3(256), dim3(PART_THREADS),
+                      PART_SCAN_CHUNK * 4, s, P);
+            MJ_LAUNCH(prof, "k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), 256 * 4, s, P);
+        }
         MJ_LAUNCH(prof, "k_rs_scatter", k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
         std::swap(src, dst);
     }
@@ -1302,6 +1325,9 @@ int mj_ctx_create(int device, mj_ctx** out) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_scatter),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)part_scatter_smem(PART_MAX_BITS));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rs_small),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2 * RS_SMALL * sizeof(unsigned long long)));
     (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
     e = hipMalloc(&c->stats, 4096);
     if (e != hipSuccess) { delete c; return MJ_ERR_HIP; }
@@ -1316,6 +1342,11 @@ int mj_ctx_destroy(mj_ctx* ctx) {
     if (ctx->stats) hipFree(ctx->stats);
     if (ctx->scratch) hipFree(ctx->scratch);
     for (void* h : ctx->pinned) (void)hipHostFree(h);
+    for (int j = 0; j < BATCH_LANES; ++j) {
+        if (ctx->lanes[j]) (void)hipStreamDestroy(ctx->lanes[j]);
+        if (ctx->lane_done[j]) (void)hipEventDestroy(ctx->lane_done[j]);
+    }
+    if (ctx->lane_fork) (void)hipEventDestroy(ctx->lane_fork);
     delete ctx;
     return MJ_OK;
 }
@@ -1986,6 +2017,26 @@ int mj_ctx_set_planner(mj_ctx* ctx, const void* params) {
 }
 
 // ------------------------------------------------------------------ batch
+// the batch's lanes, made on the context's device at the first batch call
+static int batch_lanes(mj_ctx* ctx) {
+    if (ctx->lane_fork) return MJ_OK;
+    int cur = 0;
+    MJ_HIP(hipGetDevice(&cur));
+    if (cur != ctx->device) MJ_HIP(hipSetDevice(ctx->device));
+    int st = MJ_OK;
+    for (int j = 0; j < BATCH_LANES && st == MJ_OK; ++j) {
+        if ((!ctx->lanes[j] && hipStreamCreateWithFlags(&ctx->lanes[j], hipStreamNonBlocking) != hipSuccess) ||
+            (!ctx->lane_done[j] && hipEventCreateWithFlags(&ctx->lane_done[j], hipEventDisableTiming) != hipSuccess))
+            st = MJ_ERR_HIP;
+    }
+    if (st == MJ_OK && hipEventCreateWithFlags(&ctx->lane_fork, hipEventDisableTiming) != hipSuccess) {
+        ctx->lane_fork = nullptr;
+        st = MJ_ERR_HIP;
+    }
+    if (cur != ctx->device) MJ_HIP(hipSetDevice(cur));
+    return st;
+}
+
 static size_t batch_item_bytes(const mj_batch_item& it) {
     if (it.plan.algo != MJ_ALGO_3WAY) return it.plan.workspace_bytes;
     if (it.kind == MJ_LINEAR) return linear_layout(nullptr, it.plan).bytes;
@@ -2033,33 +2084,46 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
     std::vector<LinearCellArgs> lin;
     std::vector<uint32_t> cell_base(1, 0);
     std::vector<TriJoinArgs> tri;
-    for (int i = 0; i < n; ++i) {
+    int st = batch_lanes(ctx);
+    if (st) return st;
+    // The joins' preparations are independent short strings of small
+    // launches: they go to four lanes (the caller's stream and the
+    // context's three), each join to the lane with the least estimated work
+    // so far; the context's lanes start after everything queued on the
+    // caller's stream.
+    MJ_HIP(hipEventRecord(ctx->lane_fork, s));
+    for (int j = 0; j < BATCH_LANES; ++j) MJ_HIP(hipStreamWaitEvent(ctx->lanes[j], ctx->lane_fork, 0));
+    constexpr int NL = BATCH_LANES + 1;
+    double load[NL] = {};
+    auto prepare = [&](int i) -> int {
         const mj_batch_item& it = items[i];
         const mj_plan_t& p = it.plan;
         void* wsi = base + off;
         const size_t bytes = batch_item_bytes(it);
         off += align256(bytes);
+        int lane = 0;
+        for (int j = 1; j < NL; ++j)
+            if (load[j] < load[lane]) lane = j;
+        load[lane] += 1.0 + double(it.R.n + it.S.n + it.T.n) / 65536.0;   // launches, then tuples
+        hipStream_t ls = lane ? ctx->lanes[lane - 1] : s;
         int st;
-        if (p.algo != MJ_ALGO_3WAY) {        // cascades and star plans run their own path
-            st = run_plan(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, p, wsi, bytes, stream);
-            if (st) return st;
-            continue;
-        }
+        if (p.algo != MJ_ALGO_3WAY)          // cascades, star and oriented plans run their own path
+            return run_plan(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, p, wsi, bytes, ls);
         if (it.kind == MJ_LINEAR) {
             LinearLayout L = linear_layout(wsi, p);
             unsigned long long* count = reinterpret_cast<unsigned long long*>(it.out);
             if (it.a_domain)
-                MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(it.a_domain, 256, 4096)), dim3(256), 0, s,
+                MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(it.a_domain, 256, 4096)), dim3(256), 0, ls,
                           count, (uint64_t)it.a_domain, 0ull);
-            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) continue;
-            if ((st = launch_tables(prof, L.T, it.T, 0, p.log2_nc, seed_c(p), seed_slot(p), s))) return st;
+            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
+            if ((st = launch_tables(prof, L.T, it.T, 0, p.log2_nc, seed_c(p), seed_slot(p), ls))) return st;
             PartLaunch P{};
             P.njobs = 2;
             P.job[0] = make_job(it.R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
             P.job[0].out_pair = L.R.pairs;
             P.job[1] = make_job(it.S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
             P.job[1].out_pair = L.S.pairs;
-            if ((st = launch_partition(prof, "rs", P, s))) return st;
+            if ((st = launch_partition(prof, "rs", P, ls))) return st;
             LinearCellArgs C;
             C.R = L.R.pairs; C.rstarts = L.R.starts; C.S = L.S.pairs; C.sstarts = L.S.starts;
             C.ddir = L.T.dir; C.dpool = L.T.pool;
@@ -2070,13 +2134,22 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         } else {
             TriLayout L = tri_layout(wsi, p);
             unsigned long long* out = reinterpret_cast<unsigned long long*>(it.out);
-            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
-            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) continue;
-            if ((st = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, s))) return st;
+            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, ls, out, (uint64_t)1, 0ull);
+            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
+            if ((st = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, ls))) return st;
             tri.push_back(tri_join_args(L, p, out, 0));
             tri.push_back(tri_join_args(L, p, out, 1));
         }
+        return MJ_OK;
+    };
+    for (int i = 0; i < n && st == MJ_OK; ++i) st = prepare(i);
+    // every lane joins back to the caller's stream, also after an error, so
+    // that no lane is left outside a capture of this call
+    for (int j = 0; j < BATCH_LANES; ++j) {
+        MJ_HIP(hipEventRecord(ctx->lane_done[j], ctx->lanes[j]));
+        MJ_HIP(hipStreamWaitEvent(s, ctx->lane_done[j], 0));
     }
+    if (st) return st;
     // device argument tables, staged through a pinned buffer kept by the context
     const size_t nl = lin.size(), nt = tri.size();
     const size_t a_lin = align256(nl * sizeof(LinearCellArgs)), a_cb = align256((nl + 1) * 4);

@@ -9,6 +9,9 @@
 //                  key among equal digits is its position among the wave's
 //                  matching lanes (found with eight ballots) plus the counts
 //                  of earlier waves and earlier rounds.
+//   k_rs_scan1   : with few tiles, one workgroup does both scans of a pass
+//   k_rs_small   : arrays of at most RS_SMALL keys are sorted whole in one
+//                  workgroup's LDS, in one launch instead of four per pass.
 #include "mj_kernels.h"
 
 namespace mj {
@@ -81,6 +84,81 @@ k_rs_scatter(RsArgs A) {
         if (leader) wcnt[w][d] = 0;
         __syncthreads();
     }
+}
+
+// One workgroup, at most RS_SCAN1_TILES tiles: every digit's row of the
+// histogram becomes its exclusive prefix over tiles (in place), and the
+// digits' totals their exclusive prefix (starts, with starts[256] = n):
+// what k_part_rowscan and k_part_scan write, in one launch.
+__global__ void __launch_bounds__(256)
+k_rs_scan1(RsArgs A, uint32_t* starts) {
+    __shared__ uint32_t h[256 * RS_SCAN1_TILES];
+    __shared__ uint32_t tot[256];
+    __shared__ uint32_t wave_tmp[256 / WAVE + 1];
+    const uint32_t nt = A.ntiles, m = 256 * nt;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) h[i] = A.hist[i];
+    __syncthreads();
+    {
+        const uint32_t d = threadIdx.x;          // one digit per thread
+        uint32_t run = 0;
+        for (uint32_t t = 0; t < nt; ++t) {
+            const uint32_t c = h[d * nt + t];
+            h[d * nt + t] = run;
+            run += c;
+        }
+        tot[d] = run;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) A.hist[i] = h[i];
+    const uint32_t total = block_exclusive_scan(tot, 256, wave_tmp);
+    starts[threadIdx.x] = tot[threadIdx.x];
+    if (threadIdx.x == 0) starts[256] = total;
+}
+
+// The keys ordered on their bits from `shift` up, ties in input order: the
+// order the passes from `shift` up produce.  With shift = 0 the keys are
+// sorted as they are (equal keys cannot be told apart).  Otherwise each key's
+// digits are packed above its index, which makes every composite distinct,
+// the composites are sorted, and each position takes the key its index names
+// (kept in LDS beside them).  A bitonic network over the next power of two,
+// padded with the largest value; pads sort after every real entry.
+__global__ void __launch_bounds__(RS_SMALL_THREADS)
+k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift) {
+    extern __shared__ unsigned long long rs_lds[];
+    uint32_t P = 2;
+    while (P < n) P <<= 1;
+    unsigned long long* v = rs_lds;
+    unsigned long long* orig = rs_lds + P;   // written only when shift > 0
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        unsigned long long x = ~0ull;
+        if (i < n) {
+            const unsigned long long k = keys[i];
+            if (shift) {
+                orig[i] = k;
+                x = ((k >> shift) << RS_SMALL_BITS) | i;
+            } else {
+                x = k;
+            }
+        }
+        v[i] = x;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const uint32_t lo = 2 * t - (t & (j - 1));   // t with a 0 bit inserted at j
+                const uint32_t hi = lo + j;
+                const unsigned long long a = v[lo], b = v[hi];
+                if ((a > b) == ((lo & k) == 0)) {
+                    v[lo] = b;
+                    v[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+        keys[i] = shift ? orig[uint32_t(v[i]) & (RS_SMALL - 1u)] : v[i];
 }
 
 }  // namespace mj

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import banner, dev
+from tests.gpu_util import banner, dev, fixed_plan
 from workloads import generators as G
 
 pytestmark = pytest.mark.gpu
@@ -92,3 +92,41 @@ def test_batch_graph_replay(mj, ctx):
         # eager work between replays on the default stream
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
+
+
+def test_batch_ordered_on_callers_stream(mj, ctx):
+    """The joins are prepared on the context's own streams, side by side.
+    They must start after the work queued on the caller's stream before the
+    call (here the copy that writes their inputs, queued behind a long
+    product) and end before the work queued after it (the copy of their
+    outputs).  Cascade and oriented items run on those streams too."""
+    import torch
+    banner("batch ordered on the caller's stream")
+    joins, want, keep = make_joins(mj, 40, 3.0, 4.5, 4300)
+    plans = [ctx.plan(k, R, S, T, a) for (k, R, S, T, a) in joins]
+    plans[3].algo = mj.ALGO_CASCADE
+    E = G.gnm_symmetric(3000, 30000, seed=14)
+    Ed = dev(E)
+    joins.append((mj.TRIANGLE, Ed, Ed, Ed, 0))
+    plans.append(fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED))
+    assert plans[-1].algo == mj.ALGO_ORIENTED
+    want.append(oracle.triangle3_count(E, E, E))
+    keep.append(Ed)
+    b = ctx.batch(joins, plans=plans)
+    staged = [x.clone() for x in keep]
+    res = [torch.full_like(o, -1) for o in b.outs]
+    for x in keep:
+        x.zero_()                        # wrong inputs until the caller's copy lands
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(6):
+            a = (a @ a) * 1e-3
+        for x, y in zip(keep, staged):
+            x.copy_(y)
+        b.run(stream=s)
+        for r, o in zip(res, b.outs):
+            r.copy_(o)
+    torch.cuda.synchronize()
+    check(mj, res, want)

@@ -107,6 +107,22 @@ def test_emit_hubs_sparse_r_and_empty_pairs(mj, ctx):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("n", [2, 8191, 8192, 8193, 131072, 131073])
+def test_emit_sort_sizes(mj, ctx, n):
+    """S and T of n tuples with long runs of equal B and of equal C, whose
+    order in the output is the relations' own order; n at the edges of the
+    one-workgroup sort (8192 keys) and of the one-launch scan (32 tiles)."""
+    banner(f"emit, S and T of {n} tuples")
+    rng = np.random.default_rng(n)
+    S = np.stack([rng.integers(0, 1000, n), rng.integers(0, 50000, n)], 1).astype(np.uint32)
+    T = np.stack([rng.integers(0, 50000, n), rng.integers(0, 1 << 32, n)], 1).astype(np.uint32)
+    R = np.stack([rng.integers(0, 1 << 32, 50), rng.integers(0, 1000, 50)], 1).astype(np.uint32)
+    want, wtotal = oracle.linear3_materialize(R, S, T)
+    got, total = emit(ctx, R, S, T)
+    assert total == wtotal
+    np.testing.assert_array_equal(got, want)
+
+
 def test_emit_empty_and_sizing(mj, ctx):
     banner("emit empty inputs and sizing")
     e = np.zeros((0, 2), dtype=np.uint32)
