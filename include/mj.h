@@ -77,7 +77,10 @@ enum {
                                  /* duplicate tuples and without loops (a, a)          */
     MJ_PLAN_DENSE_KEYS = 2,      /* linear: every B value of R and S is < b_domain and */
                                  /* every C value of S and T is < c_domain, both small */
-                                 /* enough for direct-indexed tables (see below)       */
+                                 /* enough for direct-indexed tables (see below);      */
+                                 /* cyclic, with MJ_PLAN_SYMMETRIC_SIMPLE: every       */
+                                 /* vertex id is < b_domain (the oriented join's       */
+                                 /* degrees by direct index)                           */
     MJ_PLAN_NO_DENSE = 0x100     /* request: keep the hashed tables even when the keys */
                                  /* are dense                                          */
 };
@@ -113,7 +116,8 @@ typedef struct {
     double pred_log2_out;      /* learned planner: predicted log2(1 + |output|)  */
     double est_ms_star;        /* linear: star three-way estimate (0 = not eligible) */
     double est_ms_star_cascade;/* linear: star cascade estimate (0 = not eligible)   */
-    uint32_t b_domain;         /* linear, MJ_PLAN_DENSE_KEYS: 1 + largest B value    */
+    uint32_t b_domain;         /* MJ_PLAN_DENSE_KEYS: 1 + largest B value (linear),  */
+                               /* 1 + largest vertex id (cyclic)                    */
     uint32_t c_domain;         /* linear, MJ_PLAN_DENSE_KEYS: 1 + largest C value    */
 } mj_plan_t;
 
@@ -171,10 +175,12 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
  * found MJ_PLAN_SYMMETRIC_SIMPLE, keeps every edge in one direction (from
  * the end of lower degree, ties broken by a hash of the id) and counts each
  * triangle once by intersecting the out-lists of an edge's ends; total is
- * six times that, the same value.  The plan certifies the property for the
- * data it was made on: if at count time the kept edges are not exactly
- * half of them, or a loop or an end without edges of its own appears,
- * total is set to all ones (UINT64_MAX).                                 */
+ * six times that, the same value.  The degrees come from a sort of the
+ * first ends, or, when the plan has MJ_PLAN_DENSE_KEYS, from an array
+ * indexed by id.  The plan certifies the property for the data it was made
+ * on: if at count time the kept edges are not exactly half of them, or a
+ * loop, an end without edges of its own or (dense ids) an id at or above
+ * b_domain appears, total is set to all ones (UINT64_MAX).               */
 int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                        uint64_t* total, const mj_plan_t* plan,
                        void* workspace, uint64_t workspace_bytes, void* stream);

@@ -1139,31 +1139,52 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
 
 // --------------------------------------------- degree-oriented cyclic join
 struct OrientLayout {
-    unsigned long long *K, *K2, *tmp;
+    unsigned long long *K, *K2, *tmp;  // sorted degrees: the keys (m(u), m(v)) and the sort's buffers
     uint32_t *rs_hist, *rs_counts, *rs_starts;
+    RunBuf U;
+    RelPart V;                         // dense ids: the first ends by range of id ...
+    uint32_t* vkeys;
+    uint32_t* deg;                     // ... and each vertex's degree, [vdom]
+    uint32_t v_bits, v_shift;
     uint32_t* flags;
     unsigned long long *ridx, *partial;
-    RunBuf U;
     uint2* E;                          // kept edges (at most n)
     uint32_t* err;
     size_t bytes;
 };
 
-// with_check: the second key array of the planner's symmetry check
-OrientLayout orient_layout(void* ws, uint64_t n, bool with_check) {
+// Vertex ids below a small bound found by the planner: degrees from a
+// direct-indexed array instead of a sort.
+bool orient_dense(const mj_plan_t& p, uint32_t& bits, uint32_t& shift) {
+    return (p.flags & MJ_PLAN_DENSE_KEYS) && (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) && p.b_domain &&
+           key_ranges(p.n_r, p.b_domain, bits, shift);
+}
+
+// with_check: the second key array of the planner's symmetry check;
+// vdom > 0: the dense form (degrees by range of id, no sort)
+OrientLayout orient_layout(void* ws, uint64_t n, bool with_check, uint32_t vdom = 0) {
     Bump B(ws);
     OrientLayout L{};
     const uint64_t m = std::max<uint64_t>(n, 1);
-    L.K = B.take<unsigned long long>(m);
-    L.K2 = with_check ? B.take<unsigned long long>(m) : nullptr;
-    L.tmp = B.take<unsigned long long>(m);
-    L.rs_hist = B.take<uint32_t>(256 * ((m + RS_TILE - 1) / RS_TILE));
-    L.rs_counts = B.take<uint32_t>(256);
-    L.rs_starts = B.take<uint32_t>(257);
+    if (vdom && key_ranges(n, vdom, L.v_bits, L.v_shift)) {
+        const uint32_t nb = 1u << L.v_bits;
+        L.V.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(n));
+        L.V.counts = B.take<uint32_t>(nb);
+        L.V.starts = B.take<uint32_t>(nb + 1);
+        L.vkeys = B.take<uint32_t>(m);
+        L.deg = B.take<uint32_t>(vdom);
+    } else {
+        L.K = B.take<unsigned long long>(m);
+        L.K2 = with_check ? B.take<unsigned long long>(m) : nullptr;
+        L.tmp = B.take<unsigned long long>(m);
+        L.rs_hist = B.take<uint32_t>(256 * ((m + RS_TILE - 1) / RS_TILE));
+        L.rs_counts = B.take<uint32_t>(256);
+        L.rs_starts = B.take<uint32_t>(257);
+        take_runs(B, L.U, n, true);
+    }
     L.flags = B.take<uint32_t>(m);
     L.ridx = B.take<unsigned long long>(m + 1);
     L.partial = B.take<unsigned long long>((m + SCAN_TILE - 1) / SCAN_TILE + 1);
-    take_runs(B, L.U, n, true);
     L.E = B.take<uint2>(m);
     L.err = B.take<uint32_t>(1);
     L.bytes = (B.off + 511) & ~size_t(255);      // a multiple of 256: the cyclic join's layout follows
@@ -1178,8 +1199,14 @@ mj_plan_t oriented_inner(const mj_plan_t& p) {
     return q;
 }
 
+uint32_t oriented_vdom(const mj_plan_t& p) {
+    uint32_t bits, shift;
+    return orient_dense(p, bits, shift) ? p.b_domain : 0u;
+}
+
 size_t oriented_bytes(const mj_plan_t& p) {
-    return orient_layout(nullptr, p.n_r, false).bytes + tri_layout(nullptr, oriented_inner(p)).bytes;
+    return orient_layout(nullptr, p.n_r, false, oriented_vdom(p)).bytes +
+           tri_layout(nullptr, oriented_inner(p)).bytes;
 }
 
 // Is R = S = T one symmetric relation without duplicates or loops?  Sorts
@@ -1203,23 +1230,46 @@ int symmetric_simple(Prof* prof, const mj_rel& E, uint32_t seed, void* ws, bool&
 
 int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p, unsigned long long* out,
                  void* ws, hipStream_t s) {
-    OrientLayout O = orient_layout(ws, Erel.n, false);
+    const uint32_t vdom = oriented_vdom(p);
+    OrientLayout O = orient_layout(ws, Erel.n, false, vdom);
     const mj_plan_t q = oriented_inner(p);
     TriLayout L = tri_layout(static_cast<char*>(ws) + O.bytes, q);
     int st;
-    // degrees: runs of m(u) over the relation (grouped on the high word)
-    if ((st = tri_keys(prof, Erel, 0, O.K, p.seed, s))) return st;
-    if ((st = launch_radix_sort(prof, O.K, O.tmp, Erel.n, O.rs_hist, O.rs_counts, O.rs_starts, s, 4))) return st;
-    TriLayout TL{};
-    TL.flags = O.flags; TL.ridx = O.ridx; TL.partial = O.partial;
-    if ((st = launch_runs(prof, TL, O.K, Erel.n, O.U, nullptr, s))) return st;
     MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, O.err, (uint64_t)1, 0u);
-    OrientArgs A;
+    OrientArgs A{};
     A.c0 = Erel.col0; A.c1 = Erel.col1; A.stride = Erel.stride; A.n = Erel.n;
-    A.U = run_index(O.U); A.seed = p.seed;
+    A.seed = p.seed;
     A.flags = O.flags; A.ridx = O.ridx; A.E = O.E; A.err = O.err; A.total = out;
-    MJ_LAUNCH(prof, "k_orient_flags", k_orient_flags, dim3(grid_for((Erel.n + 1) / 2, 256, 16384)), dim3(256),
-              0, s, A);
+    if (vdom) {
+        // degrees: the first ends partitioned by range of id, counted per
+        // range in LDS (an id at or above vdom raises err)
+        PartLaunch P{};
+        P.njobs = 1;
+        P.job[0] = make_job(Erel, O.V.hist, O.V.counts, O.V.starts, 0, 0, O.v_bits, 0, 0, 0);
+        P.job[0].range_on = 1; P.job[0].range_shift = O.v_shift;
+        P.job[0].out_single = O.vkeys; P.job[0].single_col = 0;
+        if ((st = launch_partition(prof, "orient", P, s))) return st;
+        RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad{};
+        Ad.pairs = nullptr; Ad.keys = O.vkeys; Ad.starts = O.V.starts; Ad.shift = O.v_shift;
+        Ad.domain = vdom; Ad.table = nullptr; Ad.table_n = 0; Ad.out = O.deg; Ad.err = O.err;
+        Ad.out_narrow = nullptr; Ad.wide = nullptr; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
+        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << O.v_bits), dim3(RANGE_THREADS),
+                  size_t(4) << O.v_shift, s, Ad);
+        A.deg = O.deg; A.vdom = vdom;
+        MJ_LAUNCH(prof, "k_orient_flags_dense", k_orient_flags_dense,
+                  dim3(grid_for((Erel.n + 3) / 4, 256, 16384)), dim3(256), 0, s, A);
+    } else {
+        // degrees: runs of m(u) over the relation (grouped on the high word)
+        if ((st = tri_keys(prof, Erel, 0, O.K, p.seed, s))) return st;
+        if ((st = launch_radix_sort(prof, O.K, O.tmp, Erel.n, O.rs_hist, O.rs_counts, O.rs_starts, s, 4)))
+            return st;
+        TriLayout TL{};
+        TL.flags = O.flags; TL.ridx = O.ridx; TL.partial = O.partial;
+        if ((st = launch_runs(prof, TL, O.K, Erel.n, O.U, nullptr, s))) return st;
+        A.U = run_index(O.U);
+        MJ_LAUNCH(prof, "k_orient_flags", k_orient_flags, dim3(grid_for((Erel.n + 1) / 2, 256, 16384)),
+                  dim3(256), 0, s, A);
+    }
     if ((st = launch_scan_u32(prof, O.flags, Erel.n, O.partial, O.ridx, s))) return st;
     MJ_LAUNCH(prof, "k_orient_compact", k_orient_compact, dim3(grid_for(Erel.n, 256, 16384)), dim3(256), 0, s, A);
     // R' = the kept edges reversed, S' = T' = the kept edges
@@ -1490,6 +1540,24 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         bool yes = false;
         if ((st = symmetric_simple(&ctx->prof, *R, 0x1B873593u, ctx->scratch, yes, s))) return st;
         if (yes) p.flags |= MJ_PLAN_SYMMETRIC_SIMPLE;
+        // vertex ids in a small dense domain: the oriented join's degrees by
+        // direct index (the relation is symmetric: its first column holds
+        // every id)
+        if (yes && !(requests & MJ_PLAN_NO_DENSE)) {
+            uint32_t* d = static_cast<uint32_t*>(ctx->stats);
+            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
+            MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(R->n, 256, 2048)), dim3(256), 0, s,
+                      R->col0, R->stride, R->n, d);
+            uint32_t mx = 0;
+            MJ_HIP(hipMemcpyAsync(&mx, d, 4, hipMemcpyDeviceToHost, s));
+            MJ_HIP(hipStreamSynchronize(s));
+            const uint64_t vdom = uint64_t(mx) + 1;
+            uint32_t bits, shift;
+            if (dense_ok(vdom, R->n) && key_ranges(R->n, (uint32_t)vdom, bits, shift)) {
+                p.b_domain = (uint32_t)vdom;
+                p.flags |= MJ_PLAN_DENSE_KEYS;
+            }
+        }
     }
     if (planner != MJ_PLANNER_FIXED) {
         st = analytic_plan(kind, p, ctx->num_cu, ctx->model);

@@ -765,8 +765,11 @@ struct OrientArgs {
     uint2* E;                      // [n] kept edges, compacted in input order
     uint32_t* err;                 // set when the relation is not symmetric and simple
     unsigned long long* total;
+    const uint32_t* deg;           // dense ids: [vdom] degree of each vertex (else unused)
+    uint32_t vdom;
 };
 __global__ void k_orient_flags(OrientArgs A);
+__global__ void k_orient_flags_dense(OrientArgs A);
 __global__ void k_orient_compact(OrientArgs A);
 __global__ void k_orient_finish(OrientArgs A, uint64_t expect);
 __global__ void k_sym_check(const unsigned long long* K1, const unsigned long long* K2, uint64_t n, uint32_t* bad);

@@ -48,6 +48,44 @@ k_orient_flags(OrientArgs A) {
     }
 }
 
+// The same rule with vertex ids below vdom: the degrees are read from a
+// direct-indexed array.  An id at or above vdom, a loop, or a v of degree 0
+// (never an edge's first end) means the relation is not what the plan
+// certified.
+__global__ void __launch_bounds__(256)
+k_orient_flags_dense(OrientArgs A) {
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
+    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
+        uint32_t u[4], v[4], du[4], dv[4];
+        bool ok[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = q + uint64_t(k) * blockDim.x;
+            const bool live = i < A.n;
+            u[k] = live ? ld_col(A.c0, i, A.stride) : 0u;
+            v[k] = live ? ld_col(A.c1, i, A.stride) : 0u;
+            ok[k] = live && u[k] != v[k] && u[k] < A.vdom && v[k] < A.vdom;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {                 // the reads in flight together
+            du[k] = ok[k] ? A.deg[u[k]] : 0u;
+            dv[k] = ok[k] ? A.deg[v[k]] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = q + uint64_t(k) * blockDim.x;
+            if (i >= A.n) continue;
+            if (!ok[k] || dv[k] == 0) {
+                atomicOr(A.err, 1u);
+                A.flags[i] = 0;
+                continue;
+            }
+            const uint32_t mu = mix32(u[k], A.seed), mv = mix32(v[k], A.seed);
+            A.flags[i] = (du[k] < dv[k] || (du[k] == dv[k] && mu < mv)) ? 1u : 0u;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_orient_compact(OrientArgs A) {
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;

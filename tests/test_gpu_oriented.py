@@ -50,16 +50,41 @@ CASES = {
 }
 
 
+def oriented_plan(mj, ctx, Ed, dense, **fields):
+    """A fixed oriented plan; dense=False asks for the sorted degrees."""
+    flags = {} if dense else {"flags": mj.PLAN_NO_DENSE}
+    return fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED,
+                      **flags, **fields)
+
+
+@pytest.mark.parametrize("dense", [True, False], ids=["dense_ids", "sorted_degrees"])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_oriented_matches_oracle(mj, ctx, case):
-    banner(f"oriented cyclic join, {case}")
+def test_oriented_matches_oracle(mj, ctx, case, dense):
+    banner(f"oriented cyclic join, {case}, dense={dense}")
     E = CASES[case]()
     Ed = dev(E)
-    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED)
+    p = oriented_plan(mj, ctx, Ed, dense)
     assert p.flags & mj.PLAN_SYMMETRIC_SIMPLE and p.algo == mj.ALGO_ORIENTED
+    # ids below 2n + 4096 are dense, unless the plan asked for the sort
+    small_ids = int(E.max()) + 1 <= 2 * E.shape[0] + 4096
+    assert bool(p.flags & mj.PLAN_DENSE_KEYS) == (dense and small_ids)
+    if p.flags & mj.PLAN_DENSE_KEYS:
+        assert p.b_domain == int(E.max()) + 1
     got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
     assert got == oracle.triangle3_count(E, E, E)
     assert got % 6 == 0
+
+
+def test_oriented_dense_ids_with_gaps(mj, ctx):
+    """Dense ids with most of the domain unused (degree 0): ids spread over
+    [0, 2n) for a graph of n tuples."""
+    banner("oriented cyclic join, dense ids with gaps")
+    E = G.gnm_symmetric(3000, 20000, seed=21).astype(np.uint64)
+    E = (E * 13 + 5).astype(np.uint32)                 # ids up to about 39,000 for 40,000 tuples
+    Ed = dev(E)
+    p = oriented_plan(mj, ctx, Ed, True)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    assert int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0]) == oracle.triangle3_count(E, E, E)
 
 
 def test_oriented_complete_graph_closed_form(mj, ctx):
@@ -131,19 +156,32 @@ def test_unaliased_copies_not_checked(mj, ctx):
     assert int(mj.as_u64(ctx.triangle3_count(R, S, T, plan=p))[0]) == oracle.triangle3_count(E, E, E)
 
 
-@pytest.mark.parametrize("change", ["loop", "unknown_end"])
-def test_data_changed_after_planning(mj, ctx, change):
-    banner(f"oriented plan on changed data: {change}")
+@pytest.mark.parametrize("dense", [True, False], ids=["dense_ids", "sorted_degrees"])
+@pytest.mark.parametrize("change", ["loop", "unknown_end", "id_above_domain"])
+def test_data_changed_after_planning(mj, ctx, change, dense):
+    banner(f"oriented plan on changed data: {change}, dense={dense}")
     E = G.gnm_symmetric(2000, 20000, seed=9)
     Ed = dev(E)
-    p = fixed_plan(mj, ctx, mj.TRIANGLE, Ed, Ed, Ed, seed=0x1B873593, algo=mj.ALGO_ORIENTED)
-    assert p.algo == mj.ALGO_ORIENTED
+    p = oriented_plan(mj, ctx, Ed, dense)
+    assert p.algo == mj.ALGO_ORIENTED and bool(p.flags & mj.PLAN_DENSE_KEYS) == dense
     if change == "loop":
         Ed[0, 1] = Ed[0, 0]
-    else:
+    elif change == "unknown_end":
         Ed[0, 1] = 1_000_000_000                  # a vertex with no edges of its own
+    else:
+        # both directions of one edge move to a new id above the planned
+        # domain: still symmetric and simple, but outside the dense array
+        u, v = E[0]
+        j = int(np.nonzero((E[:, 0] == v) & (E[:, 1] == u))[0][0])
+        Ed[0, 1] = 5000
+        Ed[j, 0] = 5000
     got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
-    assert got == 2 ** 64 - 1
+    if change == "id_above_domain" and not dense:
+        # the sorted degrees are not bound to a domain: the new edge is valid
+        Eh = Ed.cpu().numpy().view(np.uint32)
+        assert got == oracle.triangle3_count(Eh, Eh, Eh)
+    else:
+        assert got == 2 ** 64 - 1
 
 
 def test_oriented_rmat22_full_golden(mj, ctx):
@@ -155,6 +193,10 @@ def test_oriented_rmat22_full_golden(mj, ctx):
     E = G.triangle_rmat()
     Ed = dev(E)
     p = ctx.plan(mj.TRIANGLE, Ed, Ed, Ed)
-    assert p.algo == mj.ALGO_ORIENTED
+    assert p.algo == mj.ALGO_ORIENTED and p.flags & mj.PLAN_DENSE_KEYS
     got = int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=p))[0])
     assert got == gold["total"]
+    # the same plan with the degrees from the sort
+    q = oriented_plan(mj, ctx, Ed, False)
+    assert not (q.flags & mj.PLAN_DENSE_KEYS)
+    assert int(mj.as_u64(ctx.triangle3_count(Ed, Ed, Ed, plan=q))[0]) == gold["total"]
