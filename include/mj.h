@@ -247,10 +247,13 @@ int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const 
  * of ALL cyclic joins in two persistent launches that pull work items from
  * device queues (so the many small joins share the chip instead of each
  * paying its own tail).  Items planned as cascades run their own path.
- * Nothing is synchronised with the host, so the whole call can be captured
- * in a HIP graph and replayed; the device argument tables are copied from
- * pinned buffers the context keeps until mj_ctx_destroy.  Workspace: at
- * least mj_batch_workspace() bytes; each join gets its own slice.        */
+ * The device argument tables are copied from pinned host memory.  An
+ * eager call reuses the context's buffer, and first waits (on the host)
+ * until the previous call's copy out of it has run.  A call under stream
+ * capture synchronises nothing with the host: its tables get a buffer of
+ * their own, kept until mj_ctx_destroy because every replay reads it, so
+ * the whole call can be captured in a HIP graph and replayed.  Workspace:
+ * at least mj_batch_workspace() bytes; each join gets its own slice.     */
 typedef struct {
     int32_t kind;
     uint32_t a_domain;

@@ -80,7 +80,10 @@ struct mj_ctx {
     Prof prof;
     DeviceModel model = default_model();
     std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
-    std::vector<void*> pinned;                  // batch argument tables (kept alive)
+    std::vector<void*> pinned;                  // captured batches' argument tables (kept alive)
+    char* stage = nullptr;                      // eager batches' argument tables (pinned, reused)
+    size_t stage_bytes = 0;
+    hipEvent_t stage_read = nullptr;            // recorded after the last copy out of `stage`
     const void* planner = nullptr;              // learned planner parameters (device)
     // streams on which a batch prepares its joins side by side (default
     // priority), the events that join each back to the caller's stream, and
@@ -1392,6 +1395,8 @@ int mj_ctx_destroy(mj_ctx* ctx) {
     if (ctx->stats) hipFree(ctx->stats);
     if (ctx->scratch) hipFree(ctx->scratch);
     for (void* h : ctx->pinned) (void)hipHostFree(h);
+    if (ctx->stage) (void)hipHostFree(ctx->stage);
+    if (ctx->stage_read) (void)hipEventDestroy(ctx->stage_read);
     for (int j = 0; j < BATCH_LANES; ++j) {
         if (ctx->lanes[j]) (void)hipStreamDestroy(ctx->lanes[j]);
         if (ctx->lane_done[j]) (void)hipEventDestroy(ctx->lane_done[j]);
@@ -2218,19 +2223,40 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         MJ_HIP(hipStreamWaitEvent(s, ctx->lane_done[j], 0));
     }
     if (st) return st;
-    // device argument tables, staged through a pinned buffer kept by the context
+    // device argument tables, staged through pinned memory.  An eager call
+    // reuses the context's buffer once the previous copy out of it has run;
+    // a captured copy is read again at every replay, so its buffer is its
+    // own and lives as long as the context.
     const size_t nl = lin.size(), nt = tri.size();
     const size_t a_lin = align256(nl * sizeof(LinearCellArgs)), a_cb = align256((nl + 1) * 4);
     const size_t a_tri = align256(nt * sizeof(TriJoinArgs));
     const size_t stage = a_lin + a_cb + a_tri;
+    const size_t want = std::max<size_t>(stage, 256);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    MJ_HIP(hipStreamIsCapturing(s, &cap));
+    const bool captured = cap != hipStreamCaptureStatusNone;
     char* host = nullptr;
-    MJ_HIP(hipHostMalloc(reinterpret_cast<void**>(&host), std::max<size_t>(stage, 256)));
-    ctx->pinned.push_back(host);
+    if (captured) {
+        MJ_HIP(hipHostMalloc(reinterpret_cast<void**>(&host), want));
+        ctx->pinned.push_back(host);
+    } else {
+        if (!ctx->stage_read) MJ_HIP(hipEventCreateWithFlags(&ctx->stage_read, hipEventDisableTiming));
+        else MJ_HIP(hipEventSynchronize(ctx->stage_read));
+        if (ctx->stage_bytes < want) {
+            if (ctx->stage) MJ_HIP(hipHostFree(ctx->stage));
+            ctx->stage = nullptr;
+            ctx->stage_bytes = 0;
+            MJ_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->stage), want));
+            ctx->stage_bytes = want;
+        }
+        host = ctx->stage;
+    }
     if (nl) std::memcpy(host, lin.data(), nl * sizeof(LinearCellArgs));
     std::memcpy(host + a_lin, cell_base.data(), (nl + 1) * 4);
     if (nt) std::memcpy(host + a_lin + a_cb, tri.data(), nt * sizeof(TriJoinArgs));
     char* dev = base + off;
     MJ_HIP(hipMemcpyAsync(dev, host, stage, hipMemcpyHostToDevice, s));
+    if (!captured) MJ_HIP(hipEventRecord(ctx->stage_read, s));
     if (nl) {
         LinearBatchArgs B;
         B.joins = reinterpret_cast<const LinearCellArgs*>(dev);

@@ -130,3 +130,19 @@ def test_batch_ordered_on_callers_stream(mj, ctx):
             r.copy_(o)
     torch.cuda.synchronize()
     check(mj, res, want)
+
+
+def test_batch_staging_reused(mj, ctx):
+    """Eager calls share one staging buffer for their argument tables: two
+    batches of different sizes run back to back without a synchronisation
+    between them (the second call must not overwrite tables the first
+    one's copy has not read), alternately, each result checked."""
+    banner("batch staging buffer reused across calls")
+    j1, w1, k1 = make_joins(mj, 6, 3.0, 3.5, 4400)
+    j2, w2, k2 = make_joins(mj, 30, 3.0, 4.0, 4500)
+    b1, b2 = ctx.batch(j1), ctx.batch(j2)
+    for _ in range(2):
+        o1 = [o.clone() for o in b1.run()]
+        o2 = [o.clone() for o in b2.run()]
+        check(mj, o1, w1)
+        check(mj, o2, w2)
