@@ -37,10 +37,11 @@ def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain, b_domain
         "dense:k_part_scatter": 16 * (n_r + n_s) + 8 * n_t,   # read + write S, R pairs and T's C column
         # T's pairs (the shared partition), deg[] and its 2-byte copy written once
         "k_range_deg": 8 * n_t + 6 * c_domain,
-        # S pairs, one 2-byte deg[c] read per tuple, W[] and its 4-byte copy written once
-        "k_range_w": 10 * n_s + 12 * b_domain,
-        # R pairs, one 4-byte W[b] read per tuple, the counts written once
-        "k_range_count": 12 * n_r + 8 * a_domain,
+        # S pairs, one 2-byte deg[c] read per tuple, W[] and its 2-byte copy written once
+        "k_range_w": 10 * n_s + 10 * b_domain,
+        # R pairs, one 2-byte W[b] read per tuple (the full W only where the copy
+        # saturates: 0.03 % of the reads here, not counted), the counts written once
+        "k_range_count": 10 * n_r + 8 * a_domain,
         "rs:k_part_hist": 4 * (n_r + n_s),              # read the bucketed columns
         "rs:k_part_scatter": 16 * (n_r + n_s),          # read + write 8-byte tuples
         "tab:k_part_hist": 4 * n_t,                     # read the C column

@@ -249,8 +249,8 @@ struct DenseLayout {                  // the linear join with direct-indexed tab
     uint32_t* deg;                    // [c_domain] multiplicity of each C value in T
     uint16_t* deg16;                  // [c_domain] the same, cut to 16 bits
     unsigned long long* w;            // [b_domain] W[b]
-    uint32_t* w32;                    // [b_domain] low words of W[b]
-    uint32_t* err;                    // [0]: a key out of its bound; [1]: some W[b] >= 2^32;
+    uint16_t* w16;                    // [b_domain] W[b], or 0xFFFF where W[b] >= 0xFFFF (then read w)
+    uint32_t* err;                    // [0]: a key out of its bound; [1]: unused;
                                       // [2]: some deg[c] >= 2^16
     uint32_t c_bits, c_shift, b_bits, b_shift, a_bits, a_shift;
     size_t bytes;
@@ -282,7 +282,7 @@ DenseLayout dense_layout(void* ws, const mj_plan_t& p) {
     L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
     L.deg16 = B.take<uint16_t>(std::max<uint32_t>(p.c_domain, 1));
     L.w = B.take<unsigned long long>(std::max<uint32_t>(p.b_domain, 1));
-    L.w32 = B.take<uint32_t>(std::max<uint32_t>(p.b_domain, 1));
+    L.w16 = B.take<uint16_t>(std::max<uint32_t>(p.b_domain, 1));
     L.err = B.take<uint32_t>(3);
     L.bytes = B.off + 256;
     return L;
@@ -1121,18 +1121,18 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     Ad.out_narrow = L.deg16; Ad.wide = L.err + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
     MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
               size_t(4) << L.c_shift, s, Ad);
-    RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> Aw;
+    RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> Aw;
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
     Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
-    // deg's 2-byte copy unless some deg[c] needs more
-    Aw.out_narrow = L.w32; Aw.wide = L.err + 1; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
+    // deg's 2-byte copy unless some deg[c] needs more; W's saturating 2-byte copy
+    Aw.out_narrow = L.w16; Aw.wide = nullptr; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
     MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(RANGE_THREADS),
               size_t(8) << L.b_shift, s, Aw);
-    RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> Ac;
+    RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> Ac;
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
-    // W's 4-byte copy unless some W[b] needs 64 bits
-    Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w32; Ac.use_wide = L.err + 1;
+    // W's saturating 2-byte copy; the full W where it reads 0xFFFF
+    Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w16; Ac.use_wide = nullptr;
     MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(RANGE_THREADS),
               size_t(8) << L.a_shift, s, Ac);
     MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,

@@ -557,7 +557,8 @@ k_count(CountArgs A) {
 // workgroup owns one range of keys (the relation partitioned by range), sums
 // its weights in LDS and writes the range once; the weight of a tuple is one
 // read of the previous array.
-template <class TW, class TWN, class TO, class TON>
+// SAT_IN: table_narrow is a saturating copy; SAT_OUT: out_narrow is one.
+template <bool SAT_IN, bool SAT_OUT, class TW, class TWN, class TO, class TON>
 __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO, TON>& A, TO* acc) {
     const uint32_t k = blockIdx.x;
     const uint64_t base = uint64_t(k) << A.shift;
@@ -565,7 +566,8 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
     const int nthr = blockDim.x;
     for (uint32_t j = threadIdx.x; j < span; j += nthr) acc[j] = 0;
     __syncthreads();
-    const bool narrow = A.table_narrow && *A.use_wide == 0;       // uniform over the launch
+    bool narrow = false;                                            // uniform over the launch
+    if constexpr (!SAT_IN) narrow = A.table_narrow && *A.use_wide == 0;
     const uint32_t q0 = A.starts[k], q1 = A.starts[k + 1];
     for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
         uint32_t key[4];
@@ -585,7 +587,12 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
             }
             if (A.table) {                                           // the reads in flight together
                 const bool in = live[u] && v < A.table_n;
-                w[u] = !in ? (TO)0 : (narrow ? (TO)A.table_narrow[v] : (TO)A.table[v]);
+                if constexpr (SAT_IN) {
+                    const TWN x = in ? A.table_narrow[v] : TWN(0);
+                    w[u] = x == TWN(~TWN(0)) ? (TO)A.table[v] : (TO)x;
+                } else {
+                    w[u] = !in ? (TO)0 : (narrow ? (TO)A.table_narrow[v] : (TO)A.table[v]);
+                }
             } else {
                 w[u] = 1;
             }
@@ -604,8 +611,13 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
         const TO v = acc[j];
         A.out[base + j] = v;
         if (A.out_narrow) {
-            A.out_narrow[base + j] = (TON)v;
-            big = big || uint64_t(v) > uint64_t(TON(~TON(0)));
+            constexpr uint64_t top = uint64_t(TON(~TON(0)));
+            if constexpr (SAT_OUT) {
+                A.out_narrow[base + j] = uint64_t(v) >= top ? TON(~TON(0)) : (TON)v;
+            } else {
+                A.out_narrow[base + j] = (TON)v;
+                big = big || uint64_t(v) > top;
+            }
         }
     }
     if (big) atomicOr(A.wide, 1u);
@@ -614,19 +626,19 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
 __global__ void __launch_bounds__(RANGE_THREADS)
 k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A) {
     extern __shared__ uint32_t acc32[];
-    range_accumulate(A, acc32);
+    range_accumulate<false, false>(A, acc32);
 }
 
 __global__ void __launch_bounds__(RANGE_THREADS)
-k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> A) {
+k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> A) {
     extern __shared__ unsigned long long acc64w[];
-    range_accumulate(A, acc64w);
+    range_accumulate<false, true>(A, acc64w);
 }
 
 __global__ void __launch_bounds__(RANGE_THREADS)
-k_range_count(RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> A) {
+k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> A) {
     extern __shared__ unsigned long long acc64c[];
-    range_accumulate(A, acc64c);
+    range_accumulate<true, false>(A, acc64c);
 }
 
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err) {

@@ -229,20 +229,23 @@ struct RangeAccArgs {
     uint32_t table_n;
     TO* out;                     // [domain]
     uint32_t* err;
-    // optional narrow forms: out_narrow receives out cut to TON and `wide` is
-    // set when some entry does not fit; table_narrow (the previous array's
-    // narrow form) is read instead of table while `use_wide` is clear
+    // optional narrow forms, read by the next kernel instead of the full
+    // array.  Flagged (deg): out_narrow receives out cut to TON and `wide` is
+    // set when some entry does not fit; table_narrow is read instead of
+    // table while `use_wide` is clear.  Saturating (W): an entry that does
+    // not fit is stored as TON's largest value, and a reader that finds that
+    // value reads the entry from table instead (wide and use_wide unused).
     TON* out_narrow;
     uint32_t* wide;
     const TWN* table_narrow;
     const uint32_t* use_wide;
 };
-// deg[c]: keys only, weight 1 (narrow copy: 16 bits)
+// deg[c]: keys only, weight 1 (flagged 16-bit copy)
 __global__ void k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A);
-// W[b] += deg[s.c] (narrow copy: 32 bits)
-__global__ void k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint32_t> A);
-// count[a] += W[r.b]
-__global__ void k_range_count(RangeAccArgs<unsigned long long, uint32_t, unsigned long long, uint32_t> A);
+// W[b] += deg[s.c] (reads deg's flagged copy; writes a saturating 16-bit copy)
+__global__ void k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> A);
+// count[a] += W[r.b] (reads W's saturating copy)
+__global__ void k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> A);
 // every entry of out set to all ones when *err is set (a certified key bound broken)
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err);
 

@@ -288,9 +288,27 @@ def test_linear_dense_shared_partitions(mj, ctx):
                                   oracle.linear3_count(F, F, F, 1 << 16))
 
 
+def test_linear_dense_w_at_16_bit_boundary(mj, ctx):
+    """Per-B sums W[b] of 65534, 65535 and 65536 around the saturating
+    2-byte copy's escape value (65535 is stored as the escape itself, so
+    its reader must take the full W), and a few small ones."""
+    banner("linear dense tables, W at the 2-byte copy's boundary")
+    ws = [65534, 65535, 65536, 1, 700]
+    S = np.concatenate([np.stack([np.full(w, b), np.zeros(w)], 1) for b, w in enumerate(ws)]).astype(np.uint32)
+    T = np.array([[0, 9]], dtype=np.uint32)                       # deg[0] = 1
+    R = np.stack([np.arange(10) % 7, np.arange(10) % len(ws)], 1).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 7)
+    assert p.flags & mj.PLAN_DENSE_KEYS
+    got = mj.as_u64(ctx.linear3_count(Rd, Sd, Td, 7, plan=p))
+    want = oracle.linear3_count(R, S, T, 7)
+    assert set(ws[:3]) <= set(int(x) for x in want)               # each boundary value is some a's count
+    np.testing.assert_array_equal(got, want)
+
+
 def test_linear_dense_w_beyond_32_bits(mj, ctx):
     """A per-B sum W[b] of 70000 x 70000 > 2^32: the direct-indexed path
-    must read the 8-byte W, not its 4-byte copy."""
+    must read the 8-byte W, not its narrow copy."""
     banner("linear dense tables, W beyond 32 bits")
     n = 70000
     R = np.stack([np.arange(5) % 3, np.zeros(5)], 1).astype(np.uint32)
