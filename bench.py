@@ -463,9 +463,16 @@ def linear_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
     return out
 
 
+CASCADE_FULL_OFF = ("the cascade on the full 2^24-edge input faulted the GPU once, run after the "
+                    "three-way join in this program; its cause is not found yet, so it stays off")
+
+
 def cascade_path(mj, ctx, Fd, n, a_domain, plan, ms_3way):
     """The cascade of binary joins on the benchmarked input (Sec. 6.3)."""
     import torch
+    if CASCADE_FULL_OFF:
+        log(f"cascade on the power-law graph: skipped ({CASCADE_FULL_OFF})")
+        return {"skipped": CASCADE_FULL_OFF, "intermediate_pairs": plan.join2_size}
     log("cascade on the power-law graph")
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
     cnt = torch.empty(a_domain, dtype=torch.int64, device="cuda")
