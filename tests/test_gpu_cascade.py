@@ -114,9 +114,6 @@ def test_cascade_powerlaw_scaled_equals_3way(mj, ctx):
     np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, 1 << 16))
 
 
-@pytest.mark.skip(reason="the same cascade (full 2^24-edge power-law input, the planner's dense plan) "
-                         "faulted the GPU once when run after the three-way join in one program; off "
-                         "until the cause is found")
 def test_cascade_powerlaw_full(mj, ctx):
     """Full size (2^24 edges): |I| = 2.7e8 pairs materialised; equals the
     three-way join element by element and the closed-form total."""
