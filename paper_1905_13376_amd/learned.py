@@ -9,7 +9,7 @@ control flow, and the data pipeline that generates join instances, times
 their candidate plans on the device and labels them.
 
     python -m paper_1905_13376_amd.learned --n-train 12000 --n-test 1000 \\
-        --out paper_1905_13376_amd/planner_weights.npy --report gpurun_out/planner_eval.json
+        --out paper_1905_13376_amd/planner_weights.npy --report planner_eval.json
 """
 from __future__ import annotations
 
