@@ -96,3 +96,65 @@ def test_star_footnote_terms():
     I = cm.join2_size_uniform(R, S, d)
     assert cm.star_cascade_comparisons(R, S, T, d, h, g) == pytest.approx(
         R * S / h + cm.cascade_join2_comparisons(I, T, g))
+
+
+def _simulated_hash_join(probe_keys, build_keys, nbuckets, bucket_of):
+    """A literal bucketed hash join, counted: every tuple is loaded once into
+    its bucket, every pair of one bucket is compared, equal keys match.
+    Returns (tuples loaded, comparisons, matches)."""
+    pb, bb = bucket_of[probe_keys], bucket_of[build_keys]
+    loaded = comparisons = matches = 0
+    for q in range(nbuckets):
+        p, b = probe_keys[pb == q], build_keys[bb == q]
+        loaded += p.size + b.size
+        comparisons += p.size * b.size
+        matches += int((p[:, None] == b[None, :]).sum())
+    return loaded, comparisons, matches
+
+
+def test_cascade_second_join_counts_simulated():
+    # Sec. 6.3: the second join loads |R join S| + |T| tuples; with g buckets
+    # on C it makes |I||T|/g comparisons, of which |I||T|/d match (App. A's
+    # hit probability g/d).  Counted on a materialised I under uniform keys.
+    import oracle
+    rng = np.random.default_rng(5)
+    d, g = 320, 16
+    R = rng.integers(0, d, size=(3000, 2)).astype(np.uint32)
+    S = rng.integers(0, d, size=(3000, 2)).astype(np.uint32)
+    T = rng.integers(0, d, size=(4000, 2)).astype(np.uint32)
+    # I = R join S on B, as (a, c) pairs
+    by_b = {}
+    for b, c in S:
+        by_b.setdefault(int(b), []).append(int(c))
+    I_c = np.array([c for a, b in R for c in by_b.get(int(b), [])], dtype=np.int64)
+    bucket_of = np.arange(d) % g                     # a radix digit of C: balanced buckets
+    loaded, comparisons, matches = _simulated_hash_join(I_c, T[:, 0].astype(np.int64), g, bucket_of)
+    assert loaded == cm.cascade_join2_loaded(I_c.size, T.shape[0])
+    assert comparisons == pytest.approx(cm.cascade_join2_comparisons(I_c.size, T.shape[0], g), rel=0.05)
+    assert matches == pytest.approx(cm.cascade_join2_matches(I_c.size, T.shape[0], d), rel=0.05)
+    # the matches are the three-way join's result tuples
+    assert matches == int(oracle.linear3_count(R, S, T, d).sum())
+
+
+def test_star_cascade_comparisons_simulated():
+    # Sec. 6.5's footnote: the binary cascade of the star join compares
+    # |R||S|/h pairs in its first join (h buckets on B) and |R||S||T|/(dg)
+    # in its second (g buckets on C, |I| = |R||S|/d), counted here.
+    rng = np.random.default_rng(8)
+    d, h, g = 384, 32, 32
+    R = rng.integers(0, d, size=(2000, 2)).astype(np.int64)      # (a, b)
+    S = rng.integers(0, d, size=(40000, 2)).astype(np.int64)     # (b, c)
+    T = rng.integers(0, d, size=(2000, 2)).astype(np.int64)      # (c, d)
+    hb = np.arange(d) % h                            # radix digits: balanced buckets
+    hc = (np.arange(d) // 3) % g
+    _, cmp1, m1 = _simulated_hash_join(S[:, 0], R[:, 1], h, hb)
+    # I = R join S as the C value of each match
+    deg_r = np.bincount(R[:, 1], minlength=d)
+    I_c = np.repeat(S[:, 1], deg_r[S[:, 0]])
+    assert I_c.size == m1
+    _, cmp2, _ = _simulated_hash_join(I_c, T[:, 0], g, hc)
+    want = cm.star_cascade_comparisons(R.shape[0], S.shape[0], T.shape[0], d, h, g)
+    assert cmp1 + cmp2 == pytest.approx(want, rel=0.05)
+    # each term on its own
+    assert cmp1 == pytest.approx(R.shape[0] * S.shape[0] / h, rel=0.05)
+    assert cmp2 == pytest.approx(R.shape[0] * S.shape[0] * T.shape[0] / (d * g), rel=0.08)
