@@ -305,7 +305,10 @@ k_cas_probe(CasProbeArgs A) {
     const int lane = lane_id();
     const bool wide = A.deg && *A.use_wide != 0;           // uniform over the launch
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
-    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
+    // the loop runs on the block's base so that every lane of a wave takes
+    // part in the cross-lane steps of every round, the tail round included
+    for (uint64_t q0 = uint64_t(blockIdx.x) * blockDim.x * 4; q0 < A.n; q0 += stride) {
+        const uint64_t q = q0 + threadIdx.x;
         uint2 iv[4];
         uint32_t c[4], w[4];
         bool live[4];

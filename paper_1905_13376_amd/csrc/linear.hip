@@ -475,6 +475,17 @@ k_wbuild(WBuildArgs A) {
     }
 }
 
+// The rest of a W-table probe whose first slot `s` has been read as `v`
+// (scalar arguments, so that four probes in flight stay in registers).
+__device__ __forceinline__ unsigned long long wprobe_from(const WSlot* __restrict__ base, uint32_t mask,
+                                                          uint32_t key, WSlot v, uint32_t s) {
+    while (v.key != key && v.key != EMPTY_KEY) {
+        s = (s + 1u) & mask;
+        v = base[s];
+    }
+    return v.key == key ? v.w : 0ull;
+}
+
 // Four independent W lookups (directory loads, then first slots, in flight
 // together; only keys that collide walk further); 0 when absent.
 __device__ __forceinline__ void wtab_lookup4(const WDirEntry* __restrict__ dir,
@@ -499,14 +510,7 @@ __device__ __forceinline__ void wtab_lookup4(const WDirEntry* __restrict__ dir,
     for (int u = 0; u < 4; ++u) {
         if (!live[u]) { out[u] = 0; continue; }
         if (key[u] == EMPTY_KEY) { out[u] = e[u].special; continue; }
-        const uint32_t mask = (1u << e[u].log2cap) - 1u;
-        WSlot v = kv[u];
-        uint32_t t = s[u];
-        while (v.key != key[u] && v.key != EMPTY_KEY) {
-            t = (t + 1u) & mask;
-            v = pool[e[u].offset + t];
-        }
-        out[u] = v.key == key[u] ? v.w : 0ull;
+        out[u] = wprobe_from(pool + e[u].offset, (1u << e[u].log2cap) - 1u, key[u], kv[u], s[u]);
     }
 }
 

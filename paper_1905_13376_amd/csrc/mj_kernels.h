@@ -121,6 +121,19 @@ __device__ __forceinline__ uint32_t dtab_lookup(const DirEntry* __restrict__ dir
 // Four independent lookups: the directory loads, then the first slot loads
 // are issued together so that four table reads are in flight per lane;
 // only keys that collide walk further.
+// The rest of an open-addressing probe whose first slot `s` has been read
+// as `v`: walk on until the key or an empty slot; `none` when absent.
+// (A function of scalars, so that callers holding several probes in
+// flight keep them in registers.)
+__device__ __forceinline__ uint32_t probe_from(const uint2* __restrict__ base, uint32_t mask, uint32_t key,
+                                               uint2 v, uint32_t s, uint32_t none) {
+    while (v.x != key && v.x != EMPTY_KEY) {
+        s = (s + 1u) & mask;
+        v = base[s];
+    }
+    return v.x == key ? v.y : none;
+}
+
 __device__ __forceinline__ void dtab_lookup4(const DirEntry* __restrict__ dir,
                                              const uint2* __restrict__ pool,
                                              const uint32_t (&key)[4], const bool (&live)[4],
@@ -143,14 +156,7 @@ __device__ __forceinline__ void dtab_lookup4(const DirEntry* __restrict__ dir,
     for (int u = 0; u < 4; ++u) {
         if (!live[u]) { out[u] = 0u; continue; }
         if (key[u] == EMPTY_KEY) { out[u] = e[u].special; continue; }
-        const uint32_t mask = (1u << e[u].log2cap) - 1u;
-        uint2 v = kv[u];
-        uint32_t t = s[u];
-        while (v.x != key[u] && v.x != EMPTY_KEY) {
-            t = (t + 1u) & mask;
-            v = pool[e[u].offset + t];
-        }
-        out[u] = v.x == key[u] ? v.y : 0u;
+        out[u] = probe_from(pool + e[u].offset, (1u << e[u].log2cap) - 1u, key[u], kv[u], s[u], 0u);
     }
 }
 

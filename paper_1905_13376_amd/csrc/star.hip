@@ -94,13 +94,7 @@ __device__ __forceinline__ void star_lookup4(const DirEntry& e, const uint2* __r
     for (int u = 0; u < STAR_U; ++u) {
         if (!live[u]) { out[u] = none; continue; }
         if (key[u] == EMPTY_KEY) { out[u] = special; continue; }
-        uint2 v = kv[u];
-        uint32_t t = s[u];
-        while (v.x != key[u] && v.x != EMPTY_KEY) {
-            t = (t + 1u) & mask;
-            v = base[t];
-        }
-        out[u] = v.x == key[u] ? v.y : none;
+        out[u] = probe_from(base, mask, key[u], kv[u], s[u], none);
     }
 }
 
@@ -143,10 +137,7 @@ __device__ __forceinline__ void lds_get4(const uint2* tab, const uint32_t (&key)
     for (int u = 0; u < STAR_U; ++u) {
         if (!live[u]) { out[u] = none; continue; }
         if (key[u] == EMPTY_KEY) { out[u] = special; continue; }
-        uint2 v = kv[u];
-        uint32_t t = h[u];
-        while (v.x != key[u] && v.x != EMPTY_KEY) { t = (t + 1u) & mask; v = tab[t]; }
-        out[u] = v.x == key[u] ? v.y : none;
+        out[u] = probe_from(tab, mask, key[u], kv[u], h[u], none);
     }
 }
 
