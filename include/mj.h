@@ -19,7 +19,8 @@
  *   - Every pointer passed to a count call is DEVICE memory owned by the
  *     caller; the library allocates no device memory and keeps no pointer
  *     after a call returns.  The caller supplies a workspace of at least
- *     mj_plan_t.workspace_bytes bytes (256-byte aligned).
+ *     mj_plan_t.workspace_bytes bytes (256-byte aligned), and mj_plan a
+ *     planning workspace of mj_plan_workspace() bytes.
  *   - Count calls are asynchronous on the given HIP stream (a hipStream_t
  *     passed as void*; NULL = the default stream); results are valid after
  *     the stream synchronises.  Calls on one context from one host thread
@@ -119,6 +120,9 @@ typedef struct {
     uint32_t b_domain;         /* MJ_PLAN_DENSE_KEYS: 1 + largest B value (linear),  */
                                /* 1 + largest vertex id (cyclic)                    */
     uint32_t c_domain;         /* linear, MJ_PLAN_DENSE_KEYS: 1 + largest C value    */
+    uint64_t input_fingerprint;/* hash of the three relations' column pointers,     */
+                               /* strides and sizes; a count call given other       */
+                               /* relations returns MJ_ERR_PLAN_MISMATCH            */
 } mj_plan_t;
 
 /* Context: binds the library to a device (the current one if device < 0). */
@@ -137,14 +141,24 @@ int mj_ctx_profile_read(mj_ctx* ctx, int max_entries, char* names, double* total
 /* Human-readable name of a status code (static string). */
 const char* mj_status_str(int status);
 
-/* Plan a join (synchronous on `stream`: it may launch statistics kernels
+/* Plan a join (synchronous on `stream`: it launches statistics kernels
  * over the inputs and waits for them).  Fills *plan (host memory).  With
  * MJ_PLANNER_FIXED the caller's log2_nb / log2_nc / log2_share / seed / algo
  * are kept and only the sizes and workspace are filled in.  For the linear
  * kind it checks that every A value is < a_domain (MJ_ERR_KEY_RANGE).
- * Sec. 4.2 and Sec. 5.2 give the costs the analytic planner compares. */
+ * Sec. 4.2 and Sec. 5.2 give the costs the analytic planner compares.
+ * plan_ws: device scratch of at least mj_plan_workspace(kind, |R|, |S|, |T|)
+ * bytes, owned by the caller and free again when mj_plan returns
+ * (MJ_ERR_WORKSPACE when smaller; checked before any launch).  The plan
+ * records a fingerprint of R, S and T (pointers, strides, sizes): count
+ * calls accept it for those relations only.  The properties it certifies
+ * (MJ_PLAN_DENSE_KEYS, MJ_PLAN_SYMMETRIC_SIMPLE) are facts about the data
+ * at planning time; a count call that finds them broken on the device
+ * writes all ones (UINT64_MAX) to its output instead of a count.        */
+uint64_t mj_plan_workspace(int kind, uint64_t n_r, uint64_t n_s, uint64_t n_t);
 int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
-            uint32_t a_domain, int planner, mj_plan_t* plan, void* stream);
+            uint32_t a_domain, int planner, mj_plan_t* plan, void* plan_ws,
+            uint64_t plan_ws_bytes, void* stream);
 
 /* Linear three-way join with per-A count (Sec. 4, Algorithm 1; Example 1):
  *   count_per_a[a] = #{ (r,s,t) in R x S x T : r.a = a, r.b = s.b, s.c = t.c }

@@ -53,7 +53,8 @@ class Plan(ctypes.Structure):
                 ("est_ms_3way", ctypes.c_double), ("est_ms_cascade", ctypes.c_double),
                 ("pred_log2_join2", ctypes.c_double), ("pred_log2_out", ctypes.c_double),
                 ("est_ms_star", ctypes.c_double), ("est_ms_star_cascade", ctypes.c_double),
-                ("b_domain", ctypes.c_uint32), ("c_domain", ctypes.c_uint32)]
+                ("b_domain", ctypes.c_uint32), ("c_domain", ctypes.c_uint32),
+                ("input_fingerprint", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,7 +78,8 @@ _SIGS = {
     "mj_ctx_create": ([_i32, ctypes.POINTER(_vp)], _i32),
     "mj_ctx_destroy": ([_vp], _i32),
     "mj_status_str": ([_i32], ctypes.c_char_p),
-    "mj_plan": ([_vp, _i32, _RP, _RP, _RP, _u32, _i32, _PP, _vp], _i32),
+    "mj_plan_workspace": ([_i32, _u64, _u64, _u64], _u64),
+    "mj_plan": ([_vp, _i32, _RP, _RP, _RP, _u32, _i32, _PP, _vp, _u64, _vp], _i32),
     "mj_linear3_count": ([_vp, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_triangle3_count": ([_vp, _RP, _RP, _RP, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_cascade2_count": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
@@ -161,6 +163,7 @@ class Context:
                "mj_ctx_create")
         self._h = h
         self._ws = None
+        self._pws = None        # planning workspace (mj_plan allocates nothing)
 
     def close(self):
         if self._h:
@@ -208,8 +211,12 @@ class Context:
              stream=None) -> Plan:
         p = fixed.copy() if fixed is not None else Plan()
         r, s, t = rel(R), rel(S), rel(T)
-        _check(_lib.mj_plan(self._h, kind, r, s, t, a_domain, PLANNERS[planner],
-                            ctypes.byref(p), _stream_ptr(stream)), "mj_plan")
+        need = _lib.mj_plan_workspace(kind, R.shape[0], S.shape[0], T.shape[0])
+        if self._pws is None or self._pws.numel() < need or self._pws.device != R.device:
+            self._pws = torch.empty(max(int(need), 256), dtype=torch.uint8, device=R.device)
+        _check(_lib.mj_plan(self._h, kind, r, s, t, a_domain, PLANNERS[planner], ctypes.byref(p),
+                            ctypes.c_void_p(self._pws.data_ptr()), self._pws.numel(),
+                            _stream_ptr(stream)), "mj_plan")
         return p
 
     def linear3_count(self, R, S, T, a_domain, plan: Plan | None = None, out=None,

@@ -71,12 +71,6 @@ constexpr int BATCH_LANES = 3;   // a batch's own streams; with the caller's, th
 struct mj_ctx {
     int device = 0;
     int num_cu = 256;
-    // small statistics buffer owned by the context (planning only)
-    void* stats = nullptr;
-    size_t stats_bytes = 0;
-    // grown on demand by mj_plan for degree statistics
-    void* scratch = nullptr;
-    size_t scratch_bytes = 0;
     Prof prof;
     DeviceModel model = default_model();
     std::map<std::string, mj_plan_t> tuned;     // autotuner cache per size class
@@ -115,20 +109,6 @@ namespace {
         }                                                              \
     } while (0)
 
-int ensure_scratch(mj_ctx* ctx, size_t bytes) {
-    if (ctx->scratch_bytes >= bytes) return MJ_OK;
-    if (ctx->scratch) {
-        MJ_HIP(hipDeviceSynchronize());
-        MJ_HIP(hipFree(ctx->scratch));
-        ctx->scratch = nullptr;
-        ctx->scratch_bytes = 0;
-    }
-    size_t want = std::max<size_t>(bytes, size_t(1) << 20);
-    MJ_HIP(hipMalloc(&ctx->scratch, want));
-    ctx->scratch_bytes = want;
-    return MJ_OK;
-}
-
 }  // namespace
 
 // ============================================================ validation
@@ -143,6 +123,22 @@ int check_rel(const mj_rel* r) {
 
 bool same_rel(const mj_rel& x, const mj_rel& y) {
     return x.col0 == y.col0 && x.col1 == y.col1 && x.n == y.n && x.stride == y.stride;
+}
+
+// FNV-1a over the three relations' pointers, strides and sizes: the plan's
+// fingerprint of the inputs it was made for.
+uint64_t fingerprint(const mj_rel& R, const mj_rel& S, const mj_rel& T) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) { h ^= (v >> (8 * i)) & 0xFF; h *= 1099511628211ull; }
+    };
+    for (const mj_rel* r : {&R, &S, &T}) {
+        mix(reinterpret_cast<uintptr_t>(r->col0));
+        mix(reinterpret_cast<uintptr_t>(r->col1));
+        mix(r->n);
+        mix(static_cast<uint64_t>(r->stride));
+    }
+    return h;
 }
 
 uint32_t ceil_log2(uint64_t x) {
@@ -1382,9 +1378,6 @@ int mj_ctx_create(int device, mj_ctx** out) {
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(2 * RS_SMALL * sizeof(unsigned long long)));
     (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
-    e = hipMalloc(&c->stats, 4096);
-    if (e != hipSuccess) { delete c; return MJ_ERR_HIP; }
-    c->stats_bytes = 4096;
     *out = c;
     return MJ_OK;
 }
@@ -1392,8 +1385,6 @@ int mj_ctx_create(int device, mj_ctx** out) {
 int mj_ctx_destroy(mj_ctx* ctx) {
     if (!ctx) return MJ_ERR_INVALID_ARG;
     hipDeviceSynchronize();
-    if (ctx->stats) hipFree(ctx->stats);
-    if (ctx->scratch) hipFree(ctx->scratch);
     for (void* h : ctx->pinned) (void)hipHostFree(h);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->stage_read) (void)hipEventDestroy(ctx->stage_read);
@@ -1478,13 +1469,46 @@ int mj_join2_size(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, uint64_t* out,
     return MJ_OK;
 }
 
+// The planning workspace: a few statistics words, the learned planner's
+// features and outputs, then one scratch region for the largest of the
+// planning steps (the |R join S| tables, the symmetry check of a cyclic
+// relation, the degree sketch).
+struct PlanLayout {
+    uint32_t* stats;
+    float* feat;                      // [MLP_IN] features, then [MLP_OUT] outputs
+    void* scratch;
+    size_t scratch_bytes;
+    size_t bytes;
+};
+
+static PlanLayout plan_layout(void* ws, int kind, uint64_t n_r, uint64_t n_s, uint64_t n_t) {
+    Bump B(ws);
+    PlanLayout L;
+    L.stats = B.take<uint32_t>(64);
+    L.feat = B.take<float>(MLP_IN + MLP_OUT);
+    size_t need = mj_join2_size_workspace(n_r, n_s);
+    if (kind == MJ_TRIANGLE && n_r >= 2) need = std::max<size_t>(need, orient_layout(nullptr, n_r, true).bytes);
+    need = std::max<size_t>(need, mj_sketch_workspace(n_r, n_s, n_t));
+    L.scratch = B.take<char>(need);
+    L.scratch_bytes = need;
+    L.bytes = B.off + 256;
+    return L;
+}
+
+uint64_t mj_plan_workspace(int kind, uint64_t n_r, uint64_t n_s, uint64_t n_t) {
+    return plan_layout(nullptr, kind, n_r, n_s, n_t).bytes;
+}
+
 int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
-            uint32_t a_domain, int planner, mj_plan_t* plan, void* stream) {
+            uint32_t a_domain, int planner, mj_plan_t* plan, void* plan_ws, uint64_t plan_ws_bytes,
+            void* stream) {
     if (!ctx || !plan) return MJ_ERR_INVALID_ARG;
     int st;
     if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
     if (kind != MJ_LINEAR && kind != MJ_TRIANGLE) return MJ_ERR_INVALID_ARG;
     if (planner < MJ_PLANNER_ANALYTIC || planner > MJ_PLANNER_FIXED) return MJ_ERR_INVALID_ARG;
+    if (!plan_ws || plan_ws_bytes < plan_layout(nullptr, kind, R->n, S->n, T->n).bytes) return MJ_ERR_WORKSPACE;
+    const PlanLayout PL = plan_layout(plan_ws, kind, R->n, S->n, T->n);
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     mj_plan_t p = planner == MJ_PLANNER_FIXED ? *plan : mj_plan_t{};
@@ -1494,11 +1518,12 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     p.b_domain = p.c_domain = 0;
     p.n_r = R->n; p.n_s = S->n; p.n_t = T->n;
     p.a_domain = kind == MJ_LINEAR ? a_domain : 0;
+    p.input_fingerprint = fingerprint(*R, *S, *T);
 
     if (kind == MJ_LINEAR) {
         if (a_domain == 0 && R->n) return MJ_ERR_KEY_RANGE;
         if (R->n) {
-            uint32_t* d = static_cast<uint32_t*>(ctx->stats);
+            uint32_t* d = PL.stats;
             MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
             MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(R->n, 256, 2048)), dim3(256), 0, s,
                                R->col0, R->stride, R->n, d);
@@ -1509,7 +1534,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         }
         // B and C in small dense domains: direct-indexed tables
         if (!(requests & MJ_PLAN_NO_DENSE) && R->n && S->n && T->n) {
-            uint32_t* d = static_cast<uint32_t*>(ctx->stats);
+            uint32_t* d = PL.stats;
             MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)2, 0u);
             const mj_rel* src[4] = {R, S, S, T};
             const int col[4] = {1, 0, 1, 0};          // B of R and S, C of S and T
@@ -1531,25 +1556,22 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     }
     // exact size of the binary intermediate (cascade workspace, cost model)
     {
-        size_t need = mj_join2_size_workspace(R->n, S->n);
-        if ((st = ensure_scratch(ctx, need))) return st;
         uint64_t I = 0;
-        st = mj_join2_size(ctx, R, S, &I, ctx->scratch, ctx->scratch_bytes, stream);
+        st = mj_join2_size(ctx, R, S, &I, PL.scratch, PL.scratch_bytes, stream);
         if (st) return st;
         p.join2_size = I;
     }
     // one symmetric relation without duplicates or loops: the degree-oriented
     // cyclic join applies
     if (kind == MJ_TRIANGLE && R->n >= 2 && same_rel(*R, *S) && same_rel(*R, *T)) {
-        if ((st = ensure_scratch(ctx, orient_layout(nullptr, R->n, true).bytes))) return st;
         bool yes = false;
-        if ((st = symmetric_simple(&ctx->prof, *R, 0x1B873593u, ctx->scratch, yes, s))) return st;
+        if ((st = symmetric_simple(&ctx->prof, *R, 0x1B873593u, PL.scratch, yes, s))) return st;
         if (yes) p.flags |= MJ_PLAN_SYMMETRIC_SIMPLE;
         // vertex ids in a small dense domain: the oriented join's degrees by
         // direct index (the relation is symmetric: its first column holds
         // every id)
         if (yes && !(requests & MJ_PLAN_NO_DENSE)) {
-            uint32_t* d = static_cast<uint32_t*>(ctx->stats);
+            uint32_t* d = PL.stats;
             MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
             MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(R->n, 256, 2048)), dim3(256), 0, s,
                       R->col0, R->stride, R->n, d);
@@ -1570,11 +1592,9 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         if (planner == MJ_PLANNER_LEARNED && ctx->planner) {
             // the network's choice replaces the analytic one; the analytic
             // estimates stay in the plan as its judge
-            const size_t need = mj_sketch_workspace(R->n, S->n, T->n) + 512;
-            if ((st = ensure_scratch(ctx, need))) return st;
-            float* feat = reinterpret_cast<float*>(static_cast<char*>(ctx->stats) + 256);
+            float* feat = PL.feat;
             float* y = feat + MLP_IN;
-            if ((st = mj_sketch(ctx, kind, R, S, T, feat, ctx->scratch, ctx->scratch_bytes, stream))) return st;
+            if ((st = mj_sketch(ctx, kind, R, S, T, feat, PL.scratch, PL.scratch_bytes, stream))) return st;
             if ((st = mj_mlp_forward(ctx, ctx->planner, feat, 1, y, stream))) return st;
             float h[MLP_OUT];
             MJ_HIP(hipMemcpyAsync(h, y, sizeof h, hipMemcpyDeviceToHost, s));
@@ -1626,7 +1646,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
     const mj_plan_t& p = *plan;
     if (p.kind != MJ_LINEAR || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n ||
-        p.a_domain != a_domain)
+        p.a_domain != a_domain || p.input_fingerprint != fingerprint(*R, *S, *T))
         return MJ_ERR_PLAN_MISMATCH;
     if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
     if (p.algo == MJ_ALGO_STAR)
@@ -1720,7 +1740,8 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
     int st;
     if ((st = check_rel(R)) || (st = check_rel(S)) || (st = check_rel(T))) return st;
     const mj_plan_t& p = *plan;
-    if (p.kind != MJ_TRIANGLE || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n)
+    if (p.kind != MJ_TRIANGLE || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n ||
+        p.input_fingerprint != fingerprint(*R, *S, *T))
         return MJ_ERR_PLAN_MISMATCH;
     if (p.log2_share > 16) return MJ_ERR_INVALID_ARG;
     if (p.algo == MJ_ALGO_ORIENTED) {
@@ -1760,7 +1781,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     if (kind != MJ_LINEAR && kind != MJ_TRIANGLE) return MJ_ERR_INVALID_ARG;
     const mj_plan_t& p = *plan;
     if (p.kind != kind || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n ||
-        (kind == MJ_LINEAR && p.a_domain != a_domain))
+        (kind == MJ_LINEAR && p.a_domain != a_domain) || p.input_fingerprint != fingerprint(*R, *S, *T))
         return MJ_ERR_PLAN_MISMATCH;
     if (kind == MJ_TRIANGLE) return cascade_triangle(ctx, R, S, T, out, p, ws, ws_bytes, stream);
     if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
@@ -2145,7 +2166,8 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         if (!it.out) return MJ_ERR_INVALID_ARG;
         const mj_plan_t& p = it.plan;
         if (p.kind != it.kind || p.n_r != it.R.n || p.n_s != it.S.n || p.n_t != it.T.n ||
-            (it.kind == MJ_LINEAR && p.a_domain != it.a_domain))
+            (it.kind == MJ_LINEAR && p.a_domain != it.a_domain) ||
+            p.input_fingerprint != fingerprint(it.R, it.S, it.T))
             return MJ_ERR_PLAN_MISMATCH;
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 16)
             return MJ_ERR_INVALID_ARG;

@@ -58,8 +58,20 @@ def test_null_arguments_rejected_without_device(lib):
     f.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, vp, vp, vp, ctypes.c_uint64, vp]
     assert f(None, None, None, None, 0, None, None, None, 0, None) == INVALID
     g = lib.mj_plan
-    g.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_uint32, ctypes.c_int, vp, vp]
-    assert g(None, 0, None, None, None, 0, 0, None, None) == INVALID
+    g.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_uint32, ctypes.c_int, vp, vp, ctypes.c_uint64, vp]
+    assert g(None, 0, None, None, None, 0, 0, None, None, 0, None) == INVALID
+
+
+def test_planning_workspace_size(lib):
+    """mj_plan's workspace (the library allocates none): it grows with the
+    relations and covers the cyclic kind's symmetry check."""
+    f = lib.mj_plan_workspace
+    f.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    f.restype = ctypes.c_uint64
+    small, big = f(0, 1000, 1000, 1000), f(0, 1 << 24, 1 << 24, 1 << 24)
+    assert 0 < small < big
+    assert f(1, 1 << 20, 1 << 20, 1 << 20) >= f(0, 1 << 20, 1 << 20, 1 << 20)
+    assert f(0, 0, 0, 0) > 0
 
 
 def test_struct_layouts_match_the_header(tmp_path):
