@@ -1,0 +1,56 @@
+// Host-build checks of the C ABI that need a context (test infrastructure
+// only): planning with a too-small planning workspace, a plan given other
+// relations of the same sizes, and a too-small count workspace.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "mj.h"
+
+static int fails = 0;
+static void expect(bool ok, const char* what) {
+    std::printf("[abi] %-64s %s\n", what, ok ? "ok" : "FAILED");
+    if (!ok) ++fails;
+}
+
+int main() {
+    mj_ctx* ctx = nullptr;
+    if (mj_ctx_create(0, &ctx) != MJ_OK) { std::printf("[abi] no context\n"); return 2; }
+    const uint64_t n = 5000;
+    std::vector<uint32_t> F(2 * n), G(2 * n);
+    for (uint64_t i = 0; i < n; ++i) {
+        F[2 * i] = (uint32_t)((i * 7919u) % 600u);
+        F[2 * i + 1] = (uint32_t)((i * 104729u) % 600u);
+        G[2 * i] = F[2 * i];
+        G[2 * i + 1] = F[2 * i + 1];
+    }
+    mj_rel R{F.data(), F.data() + 1, n, 2};
+    mj_rel R2{G.data(), G.data() + 1, n, 2};
+    const uint64_t need = mj_plan_workspace(MJ_LINEAR, n, n, n);
+    std::vector<unsigned char> pws(need);
+    mj_plan_t p;
+    std::memset(&p, 0, sizeof p);
+    expect(mj_plan(ctx, MJ_LINEAR, &R, &R, &R, 600, MJ_PLANNER_ANALYTIC, &p, pws.data(), need - 1, nullptr) ==
+               MJ_ERR_WORKSPACE, "planning workspace one byte short: MJ_ERR_WORKSPACE");
+    expect(mj_plan(ctx, MJ_LINEAR, &R, &R, &R, 600, MJ_PLANNER_ANALYTIC, &p, nullptr, need, nullptr) ==
+               MJ_ERR_WORKSPACE, "no planning workspace: MJ_ERR_WORKSPACE");
+    expect(mj_plan(ctx, MJ_LINEAR, &R, &R, &R, 600, MJ_PLANNER_ANALYTIC, &p, pws.data(), need, nullptr) == MJ_OK,
+           "planning workspace of mj_plan_workspace() bytes: MJ_OK");
+    std::vector<unsigned char> ws(p.workspace_bytes);
+    std::vector<uint64_t> out(600);
+    expect(mj_linear3_count(ctx, &R, &R, &R, 600, out.data(), &p, ws.data(), ws.size(), nullptr) == MJ_OK,
+           "count on the planned relations: MJ_OK");
+    uint64_t total = 0;
+    for (uint64_t v : out) total += v;
+    expect(total > 0, "count on the planned relations: a nonzero total");
+    expect(mj_linear3_count(ctx, &R2, &R2, &R2, 600, out.data(), &p, ws.data(), ws.size(), nullptr) ==
+               MJ_ERR_PLAN_MISMATCH, "same sizes, other relations: MJ_ERR_PLAN_MISMATCH");
+    expect(mj_cascade2_count(ctx, MJ_LINEAR, &R2, &R, &R, 600, out.data(), &p, ws.data(), ws.size(), nullptr) ==
+               MJ_ERR_PLAN_MISMATCH, "cascade, other R: MJ_ERR_PLAN_MISMATCH");
+    expect(mj_linear3_count(ctx, &R, &R, &R, 600, out.data(), &p, ws.data(), 64, nullptr) == MJ_ERR_WORKSPACE,
+           "count workspace too small: MJ_ERR_WORKSPACE");
+    mj_ctx_destroy(ctx);
+    std::printf("[abi] %s\n", fails ? "FAILED" : "all checks passed");
+    return fails ? 1 : 0;
+}

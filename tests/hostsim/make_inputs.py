@@ -1,0 +1,82 @@
+"""Inputs for the host-build replay (tests/hostsim/replay.cpp): the seeded
+workloads written as raw little-endian uint32 [n, 2] files, with their
+closed-form totals in meta.json.
+
+    python tests/hostsim/make_inputs.py OUT_DIR [--full | --tiny]
+
+Without --full the power-law graph is scaled down (2^20 edges over 2^16
+vertices, --tiny: 2^16 over 2^12) and the star schema's fact relation to
+2^22 tuples (--tiny: 2^18).
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from workloads import generators as G  # noqa: E402
+
+
+def closed_total(R, S, T):
+    """Sum over S of deg_R(s.b) * deg_T(s.c): the linear join's total."""
+    keys_r, cnt_r = np.unique(R[:, 1], return_counts=True)
+    keys_t, cnt_t = np.unique(T[:, 0], return_counts=True)
+    ir = np.searchsorted(keys_r, S[:, 0])
+    it = np.searchsorted(keys_t, S[:, 1])
+    ir_ok = (ir < keys_r.size) & (keys_r[np.minimum(ir, keys_r.size - 1)] == S[:, 0])
+    it_ok = (it < keys_t.size) & (keys_t[np.minimum(it, keys_t.size - 1)] == S[:, 1])
+    dr = np.where(ir_ok, cnt_r[np.minimum(ir, keys_r.size - 1)], 0).astype(np.uint64)
+    dt = np.where(it_ok, cnt_t[np.minimum(it, keys_t.size - 1)], 0).astype(np.uint64)
+    return int((dr * dt).sum(dtype=np.uint64))
+
+
+def main():
+    out = sys.argv[1]
+    full = "--full" in sys.argv
+    tiny = "--tiny" in sys.argv
+    os.makedirs(out, exist_ok=True)
+    meta = {}
+
+    def put(name, arr, a_domain=None, R=None, S=None, T=None):
+        arr = np.ascontiguousarray(np.asarray(arr).view(np.uint32).reshape(-1, 2))
+        arr.tofile(os.path.join(out, name + ".bin"))
+        meta[name] = {"n": int(arr.shape[0])}
+        if a_domain is not None:
+            meta[name]["a_domain"] = int(a_domain)
+
+    if full:
+        F = G.linear_powerlaw()
+        a_dom = 1 << 20
+    elif tiny:
+        F = G.linear_powerlaw(seed=2001, n_vertices=1 << 12, m=1 << 16)
+        a_dom = 1 << 12
+    else:
+        F = G.linear_powerlaw(seed=2001, n_vertices=1 << 16, m=1 << 20)
+        a_dom = 1 << 16
+    F = F.view(np.uint32)
+    put("F", F, a_dom)
+    meta["F"]["closed_total"] = closed_total(F, F, F)
+    Fs = G.linear_small().view(np.uint32)
+    put("Fs", Fs, 4096)
+    meta["Fs"]["closed_total"] = closed_total(Fs, Fs, Fs)
+    R, S, T = G.star_schema() if full else G.star_schema(n_fact=1 << (18 if tiny else 22))
+    R, S, T = (x.view(np.uint32) for x in (R, S, T))
+    put("starR", R, G.STAR["a_domain"])
+    put("starS", S)
+    put("starT", T)
+    meta["starR"]["closed_total"] = closed_total(R, S, T)
+    with open(os.path.join(out, "meta.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    with open(os.path.join(out, "meta.txt"), "w") as f:          # name n a_domain closed_total
+        for k, v in meta.items():
+            f.write(f"{k} {v['n']} {v.get('a_domain', 0)} {v.get('closed_total', 0)}\n")
+    print(json.dumps(meta))
+
+
+if __name__ == "__main__":
+    main()
