@@ -671,6 +671,7 @@ struct CasTriLayout {
     uint32_t* flags;
     unsigned long long* ridx;
     RunBuf Trun;
+    uint32_t* err;                    // set when |I| on the device is not the plan's
     uint2* I;
     uint64_t i_cap;
     size_t base_bytes;
@@ -695,6 +696,7 @@ CasTriLayout cas_tri_layout(void* ws, const mj_plan_t& p, uint64_t ws_bytes) {
     L.flags = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
     L.ridx = B.take<unsigned long long>(p.n_t + 1);
     take_runs(B, L.Trun, p.n_t, true);
+    L.err = B.take<uint32_t>(1);
     L.I = B.take<uint2>(0);
     L.base_bytes = B.off + 256;
     if (ws) {
@@ -815,6 +817,9 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
     MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
     if ((st = launch_scan_u32(prof, L.ecnt, S->n, L.partial, L.eoff, s))) return st;
+    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + S->n,
+              (unsigned long long)p.join2_size, L.err);
     const uint64_t totI = p.join2_size;
     for (uint64_t lo = 0; lo < totI; lo += L.i_cap) {
         const uint64_t hi = std::min<uint64_t>(totI, lo + L.i_cap);
@@ -827,6 +832,8 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         Q.I = L.I; Q.n = hi - lo; Q.T = run_index(L.Trun); Q.Tk = L.Tk; Q.seed = p.seed; Q.total = total;
         MJ_LAUNCH(prof, "k_cas_probe_tri", k_cas_probe_tri, dim3(grid_for(hi - lo, 256, 16384)), dim3(256), 0, s, Q);
     }
+    // an intermediate of another size than the plan's: the total is all ones
+    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, L.err);
     return MJ_OK;
 }
 
@@ -965,6 +972,9 @@ int run_star3(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, ui
     C.R = star_table(L.Rt, seed_b(p), seed_slot(p)); C.rid = L.rid; C.W = L.W;
     C.count = count; C.a_domain = a_domain; C.err = L.Rt.err;
     MJ_LAUNCH(prof, "k_star_count", k_star_count, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, C);
+    // an A value out of range or a table overflow: every count all ones
+    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+              count, (uint64_t)a_domain, L.Rt.err);
     return MJ_OK;
 }
 
@@ -1008,10 +1018,18 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     MJ_LAUNCH(prof, "k_star_icount", k_star_icount, dim3(g1), dim3(STAR_THREADS), 0, s, E);
     if ((st = launch_scan_u32(prof, L.icnt, S->n, L.scan_part, L.ioff, s))) return st;
     MJ_LAUNCH(prof, "k_star_expand", k_star_expand, dim3(g1), dim3(STAR_THREADS), 0, s, E);
+    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.ioff + S->n,
+              (unsigned long long)p.join2_size, L.Rt.err);
     // join 2: I streamed past T, grouped by A
     const uint32_t* icol = reinterpret_cast<const uint32_t*>(L.I);
-    return star_group(prof, "k_star_group_i", icol, icol + 1, 2, std::min<uint64_t>(p.join2_size, L.i_cap),
-                      false, a_domain, ctx->num_cu, p, L, count, a_domain, s);
+    if ((st = star_group(prof, "k_star_group_i", icol, icol + 1, 2, std::min<uint64_t>(p.join2_size, L.i_cap),
+                         false, a_domain, ctx->num_cu, p, L, count, a_domain, s)))
+        return st;
+    // an intermediate of another size than the plan's, or an A value out of
+    // range: every count all ones
+    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+              count, (uint64_t)a_domain, L.Rt.err);
+    return MJ_OK;
 }
 
 // ---------------------------------------------- FM distinct count per A
@@ -1709,6 +1727,9 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         Cn.err = L.T.err;
         MJ_LAUNCH(&ctx->prof, "k_count", k_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
                   (size_t(8) << L.a_shift), s, Cn);
+        // an A value out of range or a table overflow: every count all ones
+        MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+                  Cn.count, (uint64_t)a_domain, L.T.err);
         return MJ_OK;
     }
     // R and S: partition by the bucket of B (one group of launches for both)
@@ -1730,6 +1751,8 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     C.a_domain = a_domain;
     C.err = L.T.err;
     MJ_LAUNCH(&ctx->prof, "k_linear_cell", k_linear_cell, dim3(nb), dim3(CELL_THREADS), 0, s, C);
+    MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+              C.count, (uint64_t)a_domain, L.T.err);
     return MJ_OK;
 }
 
@@ -1847,6 +1870,11 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
               L.partial, nblk);
     MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s,
               L.ecnt, (uint64_t)R->n, L.partial, L.eoff);
+    // the chunks below cover the plan's |I|: an intermediate of another size
+    // (same relations, other contents) makes every count all ones
+    uint32_t* verr = dense ? L.dflags : L.T.err;
+    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + R->n,
+              (unsigned long long)p.join2_size, verr);
     // the intermediate, chunk by chunk: materialise, then join with T
     const uint64_t total = p.join2_size;
     for (uint64_t lo = 0; lo < total; lo += L.i_cap) {
@@ -1863,10 +1891,10 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         Q.deg = L.deg; Q.deg16 = L.deg16; Q.c_domain = p.c_domain; Q.use_wide = dense ? L.dflags + 2 : nullptr;
         MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
     }
-    // dense keys: a key beyond its certified bound makes every count all ones
-    if (dense)
-        MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
-                  count, (uint64_t)a_domain, L.dflags);
+    // a key beyond its certified bound, an A value out of range, a table
+    // overflow or an intermediate of another size: every count all ones
+    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+              count, (uint64_t)a_domain, verr);
     return MJ_OK;
 }
 

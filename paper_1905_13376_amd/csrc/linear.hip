@@ -645,6 +645,10 @@ k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uin
     range_accumulate<true, false>(A, acc64c);
 }
 
+__global__ void k_check_size(const unsigned long long* got, unsigned long long want, uint32_t* err) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *got != want) atomicExch(err, 1u);
+}
+
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err) {
     if (*err == 0) return;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)

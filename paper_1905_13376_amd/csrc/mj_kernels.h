@@ -254,6 +254,9 @@ __global__ void k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, u
 __global__ void k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> A);
 // every entry of out set to all ones when *err is set (a certified key bound broken)
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err);
+// *err set when a size found on the device (*got) is not the one the plan
+// was made with (a plan reused on data of the same sizes but other contents)
+__global__ void k_check_size(const unsigned long long* got, unsigned long long want, uint32_t* err);
 
 struct CountArgs {
     const uint2* R;              // partitioned (a, b) by range of a

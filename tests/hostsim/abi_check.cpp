@@ -3,6 +3,7 @@
 // relations of the same sizes, and a too-small count workspace.
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -50,6 +51,35 @@ int main() {
                MJ_ERR_PLAN_MISMATCH, "cascade, other R: MJ_ERR_PLAN_MISMATCH");
     expect(mj_linear3_count(ctx, &R, &R, &R, 600, out.data(), &p, ws.data(), 64, nullptr) == MJ_ERR_WORKSPACE,
            "count workspace too small: MJ_ERR_WORKSPACE");
+    // a plan reused on the same relations after their contents changed so
+    // that |R join S| grew: the cascade's chunks cover the planned |I| only,
+    // so every count must come out all ones, with direct-indexed and with
+    // hashed tables
+    for (int hashed = 0; hashed < 2; ++hashed) {
+        for (uint64_t i = 0; i < n; ++i) G[2 * i + 1] = F[2 * i + 1];
+        mj_plan_t q;
+        std::memset(&q, 0, sizeof q);
+        if (hashed) { q.log2_nb = 3; q.log2_nc = 3; q.seed = 7; q.flags = MJ_PLAN_NO_DENSE; q.algo = MJ_ALGO_CASCADE; }
+        const int planner = hashed ? MJ_PLANNER_FIXED : MJ_PLANNER_ANALYTIC;
+        if (mj_plan(ctx, MJ_LINEAR, &R2, &R, &R, 600, planner, &q, pws.data(), need, nullptr) != MJ_OK) {
+            expect(false, "plan for the changed-data check");
+            continue;
+        }
+        std::vector<unsigned char> wq(q.workspace_bytes);
+        std::fill(out.begin(), out.end(), 0);
+        expect(mj_cascade2_count(ctx, MJ_LINEAR, &R2, &R, &R, 600, out.data(), &q, wq.data(), wq.size(), nullptr) ==
+                   MJ_OK, "cascade on the planned data: MJ_OK");
+        bool ones = true;
+        for (uint64_t v : out) ones = ones && v == ~0ull;
+        expect(!ones, "cascade on the planned data: counts");
+        for (uint64_t i = 0; i < n; i += 3) G[2 * i + 1] = 5;     // B = 5 joins many more S tuples
+        expect(mj_cascade2_count(ctx, MJ_LINEAR, &R2, &R, &R, 600, out.data(), &q, wq.data(), wq.size(), nullptr) ==
+                   MJ_OK, "cascade after R changed in place: MJ_OK (checked on the device)");
+        ones = true;
+        for (uint64_t v : out) ones = ones && v == ~0ull;
+        expect(ones, hashed ? "larger intermediate than planned (hashed tables): all ones"
+                            : "larger intermediate than planned (direct-indexed): all ones");
+    }
     mj_ctx_destroy(ctx);
     std::printf("[abi] %s\n", fails ? "FAILED" : "all checks passed");
     return fails ? 1 : 0;

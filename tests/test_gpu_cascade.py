@@ -153,3 +153,38 @@ def test_cascade_dense_and_hashed_agree(mj, ctx):
     Td[3, 0] = 1 << 20                            # beyond c_domain
     got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 900, plan=p))
     assert (got == np.uint64(2 ** 64 - 1)).all()
+
+
+@pytest.mark.parametrize("tables", ["dense", "hashed"])
+def test_cascade_plan_reused_on_larger_intermediate(mj, ctx, tables):
+    """A plan reused on the same tensors after their contents changed so that
+    |R |x| S| grew: the intermediate's chunks cover the planned size only,
+    so the device finds the sizes differ and every count is all ones."""
+    banner(f"cascade plan reused on a larger intermediate ({tables})")
+    rng = np.random.default_rng(12)
+    R = rng.integers(0, 600, size=(20000, 2)).astype(np.uint32)
+    S = rng.integers(0, 600, size=(20000, 2)).astype(np.uint32)
+    T = rng.integers(0, 600, size=(20000, 2)).astype(np.uint32)
+    Rd, Sd, Td = dev(R), dev(S), dev(T)
+    if tables == "dense":
+        p = ctx.plan(mj.LINEAR, Rd, Sd, Td, 600)
+        assert p.flags & mj.PLAN_DENSE_KEYS
+    else:
+        p = fixed_plan(mj, ctx, mj.LINEAR, Rd, Sd, Td, 600, log2_nb=4, log2_nc=4, seed=9, algo=1,
+                       flags=mj.PLAN_NO_DENSE)
+    np.testing.assert_array_equal(mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 600, plan=p)),
+                                  oracle.linear3_count(R, S, T, 600))
+    Rd[::3, 1] = 5                                  # B = 5 for a third of R: more (r, s) pairs
+    got = mj.as_u64(ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, 600, plan=p))
+    assert (got == np.uint64(2 ** 64 - 1)).all()
+
+
+def test_plan_rejects_other_relations_of_the_same_sizes(mj, ctx):
+    """The plan's fingerprint: other tensors of the same sizes are refused."""
+    banner("plan fingerprint")
+    F = G.linear_small()[:5000]
+    Fd, Fd2 = dev(F), dev(F)
+    p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, 4096)
+    with pytest.raises(mj.MJError) as e:
+        ctx.cascade2_count(mj.LINEAR, Fd2, Fd, Fd, 4096, plan=p)
+    assert "PLAN_MISMATCH" in str(e.value)
