@@ -181,6 +181,22 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
                      uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan,
                      void* workspace, uint64_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * linear three-way join exactly as mj_linear3_count, with the library's own
+ * workspace -- one array of mj_linear3_count_static_max_bytes() bytes
+ * (128 MiB) per device, part of the library's code object, held by each
+ * device the library runs on until the process ends.  The call allocates
+ * nothing.  It returns MJ_ERR_WORKSPACE before any launch when the plan's
+ * path needs more than that array (the direct-indexed path of about 2^22
+ * tuples per relation fits).  Every call on one device uses the same
+ * array: calls that overlap on a device (other streams, other host
+ * threads, other contexts) race and must be ordered by the caller.       */
+uint64_t mj_linear3_count_static_max_bytes(void);
+int mj_linear3_count_static(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                            uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan,
+                            void* stream);
+
 /* Cyclic three-way join, total count (Sec. 5):
  *   total[0] = #{ (r,s,t) : r.b = s.b, s.c = t.c, t.a = r.a }
  * With R = S = T = the symmetric edge relation of a simple graph this is

@@ -82,6 +82,8 @@ _SIGS = {
     "mj_plan": ([_vp, _i32, _RP, _RP, _RP, _u32, _i32, _PP, _vp, _u64, _vp], _i32),
     "mj_linear3_count": ([_vp, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_triangle3_count": ([_vp, _RP, _RP, _RP, _vp, _PP, _vp, _u64, _vp], _i32),
+    "mj_linear3_count_static_max_bytes": ([], _u64),
+    "mj_linear3_count_static": ([_vp, _RP, _RP, _RP, _u32, _vp, _PP, _vp], _i32),
     "mj_cascade2_count": ([_vp, _i32, _RP, _RP, _RP, _u32, _vp, _PP, _vp, _u64, _vp], _i32),
     "mj_join2_size_workspace": ([_u64, _u64], _u64),
     "mj_linear3_distinct_workspace": ([_u64, _u64, _u64, _u32], _u64),
@@ -231,6 +233,17 @@ class Context:
                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream_ptr(stream)), "mj_linear3_count")
+        return out[:a_domain]
+
+    def linear3_count_static(self, R, S, T, a_domain, plan: Plan, out=None, stream=None) -> torch.Tensor:
+        """mj_linear3_count with the library's per-device scratch array as
+        its workspace (no allocation in the call; ``out`` must be given for
+        an allocation-free call)."""
+        if out is None:
+            out = torch.empty(max(a_domain, 1), dtype=torch.int64, device=R.device)
+        _check(_lib.mj_linear3_count_static(self._h, rel(R), rel(S), rel(T), a_domain,
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(plan),
+                                            _stream_ptr(stream)), "mj_linear3_count_static")
         return out[:a_domain]
 
     def linear3_distinct(self, R, S, T, a_domain, seed=0x9E3779B9, sketch=None, est=None,

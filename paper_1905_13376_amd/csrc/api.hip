@@ -85,7 +85,16 @@ struct mj_ctx {
     hipStream_t lanes[BATCH_LANES] = {};
     hipEvent_t lane_done[BATCH_LANES] = {};
     hipEvent_t lane_fork = nullptr;
+    // this device's copy of the file-scope scratch array (device address),
+    // found once at context creation
+    void* static_scratch = nullptr;
 };
+
+// Workspace of mj_linear3_count_static: one array per device, part of the
+// library's code object, so that the call allocates nothing.  Every call on
+// a device shares it (and finds what the last call left there).
+constexpr size_t MJ_STATIC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[MJ_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1396,6 +1405,9 @@ int mj_ctx_create(int device, mj_ctx** out) {
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(2 * RS_SMALL * sizeof(unsigned long long)));
     (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
+    // the scratch array's address on this device (the device is current here)
+    e = hipGetSymbolAddress(&c->static_scratch, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !c->static_scratch) { delete c; return MJ_ERR_HIP; }
     *out = c;
     return MJ_OK;
 }
@@ -1754,6 +1766,17 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
               C.count, (uint64_t)a_domain, L.T.err);
     return MJ_OK;
+}
+
+uint64_t mj_linear3_count_static_max_bytes(void) { return MJ_STATIC_SCRATCH_BYTES; }
+
+int mj_linear3_count_static(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,
+                            uint32_t a_domain, uint64_t* count_per_a, const mj_plan_t* plan, void* stream) {
+    if (!ctx || !ctx->static_scratch) return MJ_ERR_INVALID_ARG;
+    // the same call with the device's scratch array as its workspace: it
+    // returns MJ_ERR_WORKSPACE before any launch when the plan's path needs more
+    return mj_linear3_count(ctx, R, S, T, a_domain, count_per_a, plan, ctx->static_scratch,
+                            MJ_STATIC_SCRATCH_BYTES, stream);
 }
 
 int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T,

@@ -80,6 +80,36 @@ int main() {
         expect(ones, hashed ? "larger intermediate than planned (hashed tables): all ones"
                             : "larger intermediate than planned (direct-indexed): all ones");
     }
+    // the allocation-free entry point: the same counts as the workspace call,
+    // twice in a row (the second on a smaller input), and a refusal before
+    // any launch when the plan's path needs more than the static array
+    for (uint64_t m : {uint64_t(5000), uint64_t(1234)}) {
+        mj_rel Rm{F.data(), F.data() + 1, m, 2};
+        mj_plan_t q;
+        std::memset(&q, 0, sizeof q);
+        expect(mj_plan(ctx, MJ_LINEAR, &Rm, &Rm, &Rm, 600, MJ_PLANNER_ANALYTIC, &q, pws.data(), need, nullptr) == MJ_OK,
+               "plan for the allocation-free call");
+        std::vector<unsigned char> wq(q.workspace_bytes);
+        std::vector<uint64_t> a(600, 7), b(600, 9);
+        expect(mj_linear3_count(ctx, &Rm, &Rm, &Rm, 600, a.data(), &q, wq.data(), wq.size(), nullptr) == MJ_OK &&
+                   mj_linear3_count_static(ctx, &Rm, &Rm, &Rm, 600, b.data(), &q, nullptr) == MJ_OK && a == b,
+               m == 5000 ? "static scratch: equals the workspace call" : "static scratch, smaller input next: equal");
+    }
+    {
+        const uint64_t big = uint64_t(1) << 23;
+        std::vector<uint32_t> H(2 * big);
+        for (uint64_t i = 0; i < 2 * big; ++i) H[i] = (uint32_t)(((i * 2654435761u) >> 8) & 0xFFFFFFu);   // sparse keys below 2^24
+        mj_rel Rb{H.data(), H.data() + 1, big, 2};
+        mj_plan_t q;
+        std::memset(&q, 0, sizeof q);
+        q.log2_nb = 10; q.log2_nc = 10; q.seed = 1; q.flags = MJ_PLAN_NO_DENSE;
+        const uint64_t nb = mj_plan_workspace(MJ_LINEAR, big, big, big);
+        std::vector<unsigned char> pb(nb);
+        std::vector<uint64_t> o(1u << 24);
+        expect(mj_plan(ctx, MJ_LINEAR, &Rb, &Rb, &Rb, 1u << 24, MJ_PLANNER_FIXED, &q, pb.data(), nb, nullptr) == MJ_OK &&
+                   mj_linear3_count_static(ctx, &Rb, &Rb, &Rb, 1u << 24, o.data(), &q, nullptr) == MJ_ERR_WORKSPACE,
+               "static scratch too small for the plan: MJ_ERR_WORKSPACE");
+    }
     mj_ctx_destroy(ctx);
     std::printf("[abi] %s\n", fails ? "FAILED" : "all checks passed");
     return fails ? 1 : 0;

@@ -229,6 +229,8 @@ hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned flags);
 hipError_t hipStreamDestroy(hipStream_t s);
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags);
 hipError_t hipStreamIsCapturing(hipStream_t s, hipStreamCaptureStatus* st);
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol);
+#define HIP_SYMBOL(x) reinterpret_cast<const void*>(&(x))
 
 #define hipLaunchKernelGGL(kern, grid, block, smem, stream, ...) \
     ::hipsim::launch(#kern, dim3(grid), dim3(block), (size_t)(smem), [&]() { kern(__VA_ARGS__); })

@@ -449,3 +449,7 @@ hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus* st) {
     *st = hipStreamCaptureStatusNone;
     return hipSuccess;
 }
+hipError_t hipGetSymbolAddress(void** ptr, const void* symbol) {
+    *ptr = const_cast<void*>(symbol);
+    return hipSuccess;
+}
