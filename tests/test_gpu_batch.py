@@ -146,3 +146,46 @@ def test_batch_staging_reused(mj, ctx):
         o2 = [o.clone() for o in b2.run()]
         check(mj, o1, w1)
         check(mj, o2, w2)
+
+
+def _check_golden(mj, outs, gold):
+    import hashlib
+    for o, g in zip(outs, gold):
+        got = mj.as_u64(o)
+        if g["kind"] == "linear":
+            got = got[:g["a_domain"]].astype("<u8")
+            assert int(got.sum(dtype=np.uint64)) == g["sum"], g["k"]
+            assert hashlib.sha256(got.tobytes()).hexdigest() == g["sha256_u64_le"], g["k"]
+        else:
+            assert int(got[0]) == g["total"], g["k"]
+
+
+def test_batch_512_full_golden(mj, ctx):
+    """The full 512-join batch (seeds 4000 + k, 10^3..10^6 edges, half linear
+    and half cyclic) under the planner's plans: every join's result equals
+    the oracle's, stored by tests/golden/make_batch_golden.py, for the eager
+    call and for three replays of its HIP-graph capture."""
+    import json
+    import os
+    import torch
+    banner("batch of 512 joins, full size, against the oracle's results")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch512.json")))["joins"]
+    joins, keep = [], []
+    for k in range(512):
+        x = G.batch_instance(k)
+        Fd = dev(x["F"])
+        keep.append(Fd)
+        joins.append((mj.LINEAR, Fd, Fd, Fd, x["n"]) if x["kind"] == "linear" else (mj.TRIANGLE, Fd, Fd, Fd, 0))
+    b = ctx.batch(joins)
+    _check_golden(mj, b.run(), gold)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
+        b.run(stream=s)
+    for _ in range(3):
+        for o in b.outs:
+            o.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        _check_golden(mj, b.outs, gold)

@@ -139,6 +139,38 @@ def test_linear_powerlaw_full_sampled(mj, ctx):
     np.testing.assert_array_equal(got[al], want)
 
 
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+@pytest.mark.parametrize("tables", ["dense", "hashed"])
+def test_linear_powerlaw_full_golden(mj, ctx, tables):
+    """Full-size power-law input (2^24 edges, 2^20 vertices): all 2^20 per-A
+    counts equal the oracle's, stored by tests/golden/make_linear_golden.py
+    (SHA-256 of the whole vector, plus 4096 entries that name a difference),
+    with the planner's direct-indexed tables (the benchmarked plan) and with
+    the hashed tables."""
+    import hashlib
+    banner(f"linear power-law full size 2^24 edges against the oracle's vector ({tables})")
+    gold = _golden("linear_powerlaw_2e24.json")
+    F = G.linear_powerlaw()
+    Fd = dev(F)
+    A = gold["a_domain"]
+    if tables == "dense":
+        p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, A)
+        assert p.flags & mj.PLAN_DENSE_KEYS
+    else:
+        p = fixed_plan(mj, ctx, mj.LINEAR, Fd, Fd, Fd, A, log2_nb=10, log2_nc=9, seed=0x2545F491,
+                       flags=mj.PLAN_NO_DENSE)
+    got = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, A, plan=p)).astype("<u8")
+    sa = np.array(gold["sample_a"])
+    np.testing.assert_array_equal(got[sa], np.array(gold["sample_count"], dtype=np.uint64))
+    assert int(got.sum(dtype=np.uint64)) == gold["sum"]
+    assert hashlib.sha256(got.tobytes()).hexdigest() == gold["sha256_u64_le"]
+
+
 def test_join2_size(mj, ctx):
     banner("join2 size")
     F = G.linear_powerlaw(seed=3, n_vertices=1 << 14, m=1 << 18)

@@ -310,22 +310,25 @@ def batch_instances(count: int = 512, base_seed: int = 4000,
     uniform degrees, odd ones Zipf(1.1) degrees capped at min(4096, n-1).
     Yields dicts with ``kind`` ('linear' | 'triangle'), ``F`` (the relation
     used for R, S and T), ``n`` and ``seed``."""
-    out = []
-    for k in range(count):
-        seed = base_seed + k
-        g = _rng(seed)
-        m = int(round(10 ** g.uniform(lo_exp, hi_exp)))
-        n = max(64, m // 16)
-        kind = "linear" if k < count // 2 else "triangle"
-        if kind == "linear":
-            if k % 2 == 0:
-                F = uniform_pairs(m, n, seed, dtype=np.int32)
-            else:
-                F = powerlaw_friends(n, m, seed, cap=min(4096, n - 1))
+    return [batch_instance(k, count, base_seed, lo_exp, hi_exp) for k in range(count)]
+
+
+def batch_instance(k: int, count: int = 512, base_seed: int = 4000,
+                   lo_exp: float = 3.0, hi_exp: float = 6.0):
+    """Instance k of batch_instances (generated alone)."""
+    seed = base_seed + k
+    g = _rng(seed)
+    m = int(round(10 ** g.uniform(lo_exp, hi_exp)))
+    n = max(64, m // 16)
+    kind = "linear" if k < count // 2 else "triangle"
+    if kind == "linear":
+        if k % 2 == 0:
+            F = uniform_pairs(m, n, seed, dtype=np.int32)
         else:
-            if k % 2 == 0:
-                F = gnm_symmetric(n, m, seed)
-            else:
-                F = chung_lu_symmetric(n, m, seed, cap=min(4096, n - 1))
-        out.append(dict(kind=kind, F=F, n=n, seed=seed, m=m))
-    return out
+            F = powerlaw_friends(n, m, seed, cap=min(4096, n - 1))
+    else:
+        if k % 2 == 0:
+            F = gnm_symmetric(n, m, seed)
+        else:
+            F = chung_lu_symmetric(n, m, seed, cap=min(4096, n - 1))
+    return dict(kind=kind, F=F, n=n, seed=seed, m=m)
