@@ -66,8 +66,14 @@ typedef enum {
     MJ_ALGO_STAR = 2,          /* linear only: star three-way join, R and T         */
                                /* resident, S streamed once (Sec. 6, star join)     */
     MJ_ALGO_STAR_CASCADE = 3,  /* linear only: cascade of two binary star joins     */
-    MJ_ALGO_ORIENTED = 4       /* cyclic only: one symmetric simple relation, each  */
+    MJ_ALGO_ORIENTED = 4,      /* cyclic only: one symmetric simple relation, each  */
                                /* triangle counted once along degree-ordered edges  */
+    MJ_ALGO_SLARGE = 5         /* linear only, S the largest relation (Sec. 4, the  */
+                               /* paragraph after Algorithm 1): R split into        */
+                               /* 2^log2_nb parts by a hash of B, T into 2^log2_nc  */
+                               /* by a hash of C, S into the pairs of parts; each   */
+                               /* pair (R_i's per-B sums, T_j's multiplicities in   */
+                               /* LDS) meets its partition S_ij once                */
 } mj_algo;
 
 /* mj_plan_t.flags bits.  mj_plan sets the properties it finds; the
@@ -123,6 +129,7 @@ typedef struct {
     uint64_t input_fingerprint;/* hash of the three relations' column pointers,     */
                                /* strides and sizes; a count call given other       */
                                /* relations returns MJ_ERR_PLAN_MISMATCH            */
+    double est_ms_slarge;      /* linear: S-largest estimate (0 = not eligible)      */
 } mj_plan_t;
 
 /* Context: binds the library to a device (the current one if device < 0). */
@@ -164,6 +171,8 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
  *   count_per_a[a] = #{ (r,s,t) in R x S x T : r.a = a, r.b = s.b, s.c = t.c }
  * for a in [0, a_domain); T's second column (D) takes no part.
  * count_per_a: device uint64[a_domain], fully overwritten.
+ * A plan with algo MJ_ALGO_SLARGE runs the S-largest form of the
+ * three-way join (needs a_domain <= 2^24 and log2_nb + log2_nc <= 12).
  * A plan with algo MJ_ALGO_STAR runs the star three-way join (Sec. 6,
  * linear star join: R and T small dimension relations held resident, the
  * fact relation S streamed once and grouped by B); any other algo runs the

@@ -25,7 +25,7 @@ STATUS = {0: "MJ_OK", -1: "MJ_ERR_INVALID_ARG", -2: "MJ_ERR_KEY_RANGE", -3: "MJ_
           -4: "MJ_ERR_PLAN_MISMATCH", -5: "MJ_ERR_HIP", -6: "MJ_ERR_OVERFLOW",
           -7: "MJ_ERR_UNSUPPORTED"}
 LINEAR, TRIANGLE = 0, 1
-ALGO_3WAY, ALGO_CASCADE, ALGO_STAR, ALGO_STAR_CASCADE, ALGO_ORIENTED = 0, 1, 2, 3, 4
+ALGO_3WAY, ALGO_CASCADE, ALGO_STAR, ALGO_STAR_CASCADE, ALGO_ORIENTED, ALGO_SLARGE = 0, 1, 2, 3, 4, 5
 PLAN_SYMMETRIC_SIMPLE = 1          # mj_plan_t.flags: R = S = T, symmetric, no duplicates or loops
 PLAN_DENSE_KEYS = 2                # mj_plan_t.flags: B and C values small enough for direct-indexed tables
 PLAN_NO_DENSE = 0x100              # request (fixed plans): keep the hashed tables
@@ -54,7 +54,7 @@ class Plan(ctypes.Structure):
                 ("pred_log2_join2", ctypes.c_double), ("pred_log2_out", ctypes.c_double),
                 ("est_ms_star", ctypes.c_double), ("est_ms_star_cascade", ctypes.c_double),
                 ("b_domain", ctypes.c_uint32), ("c_domain", ctypes.c_uint32),
-                ("input_fingerprint", ctypes.c_uint64)]
+                ("input_fingerprint", ctypes.c_uint64), ("est_ms_slarge", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

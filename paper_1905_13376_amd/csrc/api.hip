@@ -306,11 +306,16 @@ struct LinearLayout {
     size_t bytes;
 };
 
+// S-largest plans partition S by (bucket of B, bucket of C)
+uint32_t s_part_bits(const mj_plan_t& p) {
+    return p.log2_nb + (p.algo == MJ_ALGO_SLARGE ? p.log2_nc : 0u);
+}
+
 LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
     Bump B(ws);
     LinearLayout L;
     take_part(B, L.R, p.n_r, p.log2_nb);
-    take_part(B, L.S, p.n_s, p.log2_nb);
+    take_part(B, L.S, p.n_s, s_part_bits(p));
     take_table(B, L.T, p.n_t, p.log2_nc);
     L.by_range = a_ranges(p, L.a_bits, L.a_shift);
     L.wdir = nullptr; L.wpool = nullptr; L.wcursor = nullptr; L.wslots = 0;
@@ -1636,6 +1641,11 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
             // relations are small and the model rates them faster
             if (p.algo == MJ_ALGO_3WAY && p.est_ms_star > 0.0 && p.est_ms_star < p.est_ms_3way)
                 p.algo = MJ_ALGO_STAR;
+            // so does the S-largest form (its bucket counts are in the plan
+            // when the analytic planner chose it)
+            if (p.algo == MJ_ALGO_3WAY && p.est_ms_slarge > 0.0 && p.est_ms_slarge < p.est_ms_3way &&
+                p.log2_nb + p.log2_nc <= PART_MAX_BITS)
+                p.algo = MJ_ALGO_SLARGE;
             if (p.algo == MJ_ALGO_CASCADE && p.est_ms_star_cascade > 0.0 &&
                 p.est_ms_star_cascade < p.est_ms_cascade)
                 p.algo = MJ_ALGO_STAR_CASCADE;
@@ -1656,10 +1666,12 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;
-        const bool ok = kind == MJ_LINEAR ? (p.algo >= MJ_ALGO_3WAY && p.algo <= MJ_ALGO_STAR_CASCADE)
+        const bool ok = kind == MJ_LINEAR ? ((p.algo >= MJ_ALGO_3WAY && p.algo <= MJ_ALGO_STAR_CASCADE) ||
+                                             p.algo == MJ_ALGO_SLARGE)
                                           : (p.algo == MJ_ALGO_3WAY || p.algo == MJ_ALGO_CASCADE ||
                                              p.algo == MJ_ALGO_ORIENTED);
         if (!ok) return MJ_ERR_INVALID_ARG;
+        if (p.algo == MJ_ALGO_SLARGE && p.log2_nb + p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
         if (p.algo == MJ_ALGO_ORIENTED && !(p.flags & MJ_PLAN_SYMMETRIC_SIMPLE)) return MJ_ERR_UNSUPPORTED;
     }
     st = plan_workspace(p);
@@ -1678,10 +1690,16 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     if (p.kind != MJ_LINEAR || p.n_r != R->n || p.n_s != S->n || p.n_t != T->n ||
         p.a_domain != a_domain || p.input_fingerprint != fingerprint(*R, *S, *T))
         return MJ_ERR_PLAN_MISMATCH;
-    if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS) return MJ_ERR_INVALID_ARG;
+    if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || s_part_bits(p) > PART_MAX_BITS)
+        return MJ_ERR_INVALID_ARG;
     if (p.algo == MJ_ALGO_STAR)
         return run_star3(ctx, R, S, T, a_domain, count, p, ws, ws_bytes, static_cast<hipStream_t>(stream));
-    if (dense_plan(p)) {
+    const bool slarge = p.algo == MJ_ALGO_SLARGE;
+    if (slarge) {
+        uint32_t ab, as;
+        if (!a_ranges(p, ab, as)) return MJ_ERR_UNSUPPORTED;       // needs per-A ranges in LDS
+    }
+    if (!slarge && dense_plan(p)) {
         if (!ws || ws_bytes < dense_layout(nullptr, p).bytes) return MJ_ERR_WORKSPACE;
         hipStream_t sd = static_cast<hipStream_t>(stream);
         unsigned long long* cnt = reinterpret_cast<unsigned long long*>(count);
@@ -1712,7 +1730,11 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         // S by bucket of B, R by range of A (one group of launches)
         PartLaunch P{};
         P.njobs = 2;
-        P.job[0] = make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+        // S by bucket of B -- and, for the S-largest form, by bucket of C
+        // within it (the digit T's tables are bucketed by)
+        P.job[0] = slarge ? make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb,
+                                     1, seed_c(p), p.log2_nc)
+                          : make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
         P.job[0].out_pair = L.S.pairs;
         P.job[1] = make_job(*R, L.Ra.hist, L.Ra.counts, L.Ra.starts, 0, 0, L.a_bits, 0, 0, 0);
         P.job[1].range_on = 1;
@@ -1729,7 +1751,10 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         Wb.c_seed = seed_c(p); Wb.c_bits = p.log2_nc; Wb.slot_seed = seed_slot(p); Wb.w_seed = seed_w(p);
         Wb.wdir = L.wdir; Wb.wpool = L.wpool; Wb.wcursor = L.wcursor; Wb.wcap = L.wslots;
         Wb.err = L.T.err;
-        MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
+        if (slarge)
+            MJ_LAUNCH(&ctx->prof, "k_wbuild_staged", k_wbuild_staged, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
+        else
+            MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
         // per range of A: count[a] = sum of W[r.b], written once
         CountArgs Cn;
         Cn.R = L.Ra.pairs; Cn.rstarts = L.Ra.starts; Cn.wdir = L.wdir; Cn.wpool = L.wpool;
@@ -2404,6 +2429,13 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
             cand.push_back(c);
         }
         if (base.est_ms_star > 0.0) { mj_plan_t c = base; c.algo = MJ_ALGO_STAR; cand.push_back(c); }
+        if (base.est_ms_slarge > 0.0) {
+            mj_plan_t c = base;
+            c.algo = MJ_ALGO_SLARGE;
+            c.log2_nb = ceil_log2((base.n_r + 2047) / 2048);
+            c.log2_nc = ceil_log2((base.n_t + 2047) / 2048);
+            if (c.log2_nb + c.log2_nc <= PART_MAX_BITS) cand.push_back(c);
+        }
         if (base.est_ms_star_cascade > 0.0) { mj_plan_t c = base; c.algo = MJ_ALGO_STAR_CASCADE; cand.push_back(c); }
     } else {
         for (uint32_t k = 0; k <= 4; k += 2) {

@@ -211,8 +211,18 @@ struct WBuildArgs {
     unsigned long long* wcursor;
     unsigned long long wcap;
     uint32_t* err;               // set to 1 if the pool is exhausted
+    // k_wbuild_staged: S is partitioned by (bucket of b, bucket of c) with
+    // 2^c_bits c-buckets per b-bucket, sstarts has nb * 2^c_bits + 1
+    // entries, and each c-bucket's multiplicity table is staged in LDS
+    // before its sub-bucket of S is streamed past it
 };
 __global__ void k_wbuild(WBuildArgs A);
+// the S-largest form (Sec. 4, the paragraph after Algorithm 1): per
+// b-bucket i of R, the c-buckets j of T one after another, each staged in
+// LDS (when its table has at most WSTAGE_SLOTS slots) while S_ij streams past
+constexpr uint32_t WSTAGE_LOG2 = 13;
+constexpr uint32_t WSTAGE_SLOTS = 1u << WSTAGE_LOG2;
+__global__ void k_wbuild_staged(WBuildArgs A);
 
 static_assert(CELL_CAP % CELL_THREADS == 0, "rehash takes CELL_CAP / CELL_THREADS slots per thread");
 constexpr int COUNT_THREADS = 512;

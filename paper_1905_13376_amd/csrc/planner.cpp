@@ -99,6 +99,17 @@ double model_star_cascade_ms(const DeviceModel& m, double R, double S, double T,
     return t * 1e3;
 }
 
+// S-largest form of the linear join: the partitions of the three-way join
+// (S by two digits), T's tables staged into LDS once per part of R (L_R
+// parts: |R||T|/M of Sec. 4.2 with M the part of R one workgroup holds),
+// one LDS probe per S tuple, one table probe per R tuple.
+double model_slarge_ms(const DeviceModel& m, double R, double S, double T, double L_R) {
+    const double bytes = 24.0 * (R + S) + 16.0 * T + 16.0 * (R + S) + 16.0 * L_R * T;
+    const double t = bytes / (m.stream_gbs * 1e9) + (S * m.lds_ps + R * m.probe_ps) * 1e-12 +
+                     20.0 * m.launch_us * 1e-6;
+    return t * 1e3;
+}
+
 // Cyclic join: three sorts (8 passes of 24 B/tuple), the run indexes, and
 // the intersection work, bounded by the wedges the cascade would
 // materialise (I); `share` slices hub lists and adds a list search per
@@ -155,7 +166,25 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
         // the star plans (when eligible) compete with the one chosen so far
         double best = std::min(p.est_ms_3way, p.est_ms_cascade);
         if (p.est_ms_star > 0.0 && p.est_ms_star < best) { p.algo = MJ_ALGO_STAR; best = p.est_ms_star; }
-        if (p.est_ms_star_cascade > 0.0 && p.est_ms_star_cascade < best) p.algo = MJ_ALGO_STAR_CASCADE;
+        if (p.est_ms_star_cascade > 0.0 && p.est_ms_star_cascade < best) {
+            p.algo = MJ_ALGO_STAR_CASCADE;
+            best = p.est_ms_star_cascade;
+        }
+        // S the largest relation and R, T too large for the star plans
+        // (Sec. 4, after Algorithm 1): R in parts of about 2048 tuples (the
+        // per-B sums of one workgroup), T in parts of about 2048 tuples (a
+        // multiplicity table of at most 8192 slots in LDS).  Hashed tables
+        // only: with dense keys the direct-indexed path is cheaper still.
+        const uint32_t lr = ceil_log2((p.n_r + 2047) / 2048), lt = ceil_log2((p.n_t + 2047) / 2048);
+        const bool eligible = !(p.flags & MJ_PLAN_DENSE_KEYS) && p.n_r > STAR_PLAN_MAX_R &&
+                              p.n_s >= 4 * std::max(p.n_r, p.n_t) && lr + lt <= 12 && p.a_domain > 0 &&
+                              p.a_domain <= (1u << 24);
+        p.est_ms_slarge = eligible ? model_slarge_ms(m, R, S, T, double(1u << lr)) : 0.0;
+        if (eligible && p.est_ms_slarge < best) {
+            p.algo = MJ_ALGO_SLARGE;
+            p.log2_nb = lr;
+            p.log2_nc = lt;
+        }
     }
     return MJ_OK;
 }

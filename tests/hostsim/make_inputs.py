@@ -70,6 +70,15 @@ def main():
     put("starS", S)
     put("starT", T)
     meta["starR"]["closed_total"] = closed_total(R, S, T)
+    # the S-largest shape: dimension relations too large for the star plans
+    k = 1 << (13 if tiny else 16)
+    R, S, T = G.star_schema(n_fact=1 << (18 if tiny else (26 if full else 22)), k_r=k, k_t=k,
+                            a_domain=1 << 14, seed=5002)
+    R, S, T = (x.view(np.uint32) for x in (R, S, T))
+    put("slR", R, 1 << 14)
+    put("slS", S)
+    put("slT", T)
+    meta["slR"]["closed_total"] = closed_total(R, S, T)
     with open(os.path.join(out, "meta.json"), "w") as f:
         json.dump(meta, f, indent=1)
     with open(os.path.join(out, "meta.txt"), "w") as f:          # name n a_domain closed_total

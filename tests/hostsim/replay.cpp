@@ -6,7 +6,7 @@
 // any access outside those buffers; the checks below report results that
 // differ from the closed forms or between algorithms.
 //
-//   replay DATA_DIR [legs...]     legs: main cascade small fm emit star (default: all)
+//   replay DATA_DIR [legs...]     legs: main cascade small fm emit star slarge (default: all)
 //   environment: HIPSIM_STEPS (timed steps of the main leg, default 2)
 #include <cinttypes>
 #include <cstdio>
@@ -251,6 +251,36 @@ int main(int argc, char** argv) {
             expect(sum(c, mr.a_domain) == mr.closed, what);
         }
         std::free(wst); std::free(c);
+        std::free(const_cast<uint32_t*>(R)); std::free(const_cast<uint32_t*>(S)); std::free(const_cast<uint32_t*>(T));
+    }
+    if (want("slarge")) {
+        leg("slarge");
+        const Meta& mr = g_meta.at("slR");
+        const uint32_t* R = load("slR");
+        const uint32_t* S = load("slS");
+        const uint32_t* T = load("slT");
+        const mj_rel rR = rel_of(R, mr.n), rS = rel_of(S, g_meta.at("slS").n), rT = rel_of(T, g_meta.at("slT").n);
+        mj_plan_t p;
+        std::memset(&p, 0, sizeof p);
+        check(make_plan(ctx, MJ_LINEAR, &rR, &rS, &rT, mr.a_domain, &p), "mj_plan S-largest");
+        expect(p.algo == MJ_ALGO_SLARGE, "slarge: the planner picks the S-largest form");
+        void* wst = alloc(p.workspace_bytes);
+        const uint64_t na = mr.a_domain;
+        uint64_t* c0 = static_cast<uint64_t*>(alloc(na * 8));
+        uint64_t* c1 = static_cast<uint64_t*>(alloc(na * 8));
+        for (int i = 0; i < 2; ++i)
+            check(mj_linear3_count(ctx, &rR, &rS, &rT, mr.a_domain, c0, &p, wst, p.workspace_bytes, nullptr),
+                  "S-largest");
+        expect(sum(c0, na) == mr.closed, "slarge: sum equals the closed form");
+        mj_plan_t q = p;
+        q.algo = MJ_ALGO_3WAY;
+        check(mj_linear3_count(ctx, &rR, &rS, &rT, mr.a_domain, c1, &q, wst, p.workspace_bytes, nullptr), "3-way");
+        expect(std::memcmp(c0, c1, na * 8) == 0, "slarge: equals the partitioned three-way join");
+        q.algo = MJ_ALGO_CASCADE;
+        check(mj_cascade2_count(ctx, MJ_LINEAR, &rR, &rS, &rT, mr.a_domain, c1, &q, wst, p.workspace_bytes, nullptr),
+              "cascade");
+        expect(std::memcmp(c0, c1, na * 8) == 0, "slarge: equals the cascade");
+        std::free(wst); std::free(c0); std::free(c1);
         std::free(const_cast<uint32_t*>(R)); std::free(const_cast<uint32_t*>(S)); std::free(const_cast<uint32_t*>(T));
     }
     check(mj_ctx_destroy(ctx), "mj_ctx_destroy");
