@@ -33,12 +33,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain, b_domain=0, c_domain=0):
-    """Algorithmic HBM bytes of one launch of the named kernel."""
+def kernel_bytes(name, n_r, n_s, n_t, distinct_t, distinct_b, a_domain, b_domain=0, c_domain=0,
+                 shared_partition=False):
+    """Algorithmic HBM bytes of one launch of the named kernel.  With
+    ``shared_partition`` (R = S = T one relation, whose partitions by range of
+    its first column are one and the same) the partition launches move one
+    relation, not three."""
+    part_hist = 4 * n_s if shared_partition else 4 * (n_r + n_s + n_t)
+    part_scatter = 16 * n_s if shared_partition else 16 * (n_r + n_s) + 8 * n_t
     table = {
         # direct-indexed tables: T.c, S and R partitioned by range in one launch group
-        "dense:k_part_hist": 4 * (n_r + n_s + n_t),     # read the key columns
-        "dense:k_part_scatter": 16 * (n_r + n_s) + 8 * n_t,   # read + write S, R pairs and T's C column
+        "dense:k_part_hist": part_hist,                 # read the key columns
+        "dense:k_part_scatter": part_scatter,           # read + write the pairs (T: its C column)
         # T's pairs (the shared partition), deg[] and its 2-byte copy written once
         "k_range_deg": 8 * n_t + 6 * c_domain,
         # S pairs, one 2-byte deg[c] read per tuple, W[] and its 2-byte copy written once
@@ -109,10 +115,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (to scale HBM byte counters)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="time only the main workload (the default; kept for old command lines)")
+                    help="time only the main workload (no child legs)")
     ap.add_argument("--paths", action="store_true",
-                    help="after the main workload, run every other path, each in a child process "
-                         "of its own (bench.py --only LEG), and add their JSON")
+                    help="after the main workload, run every other path (not only the default "
+                         "legs), each in a child process of its own (bench.py --only LEG)")
     ap.add_argument("--only", choices=LEGS, default=None,
                     help="run one of the other paths alone and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -127,6 +133,12 @@ def main():
     import paper_1905_13376_amd as mj
     from workloads import generators as G
 
+    if args.only in OWN_WORKLOAD_LEGS:
+        # a leg on a workload of its own: the power-law graph is not needed
+        ctx = mj.Context()
+        print(json.dumps({args.only: extra_paths(mj, ctx, None, None, 1 << 20, None, None, only=args.only)}),
+              flush=True)
+        return
     log("generating the power-law friends graph (2^24 edges, 2^20 vertices)")
     F = G.linear_powerlaw()
     a_domain = 1 << 20
@@ -134,14 +146,24 @@ def main():
     Fd = torch.from_numpy(F).to("cuda")
     torch.cuda.synchronize()
 
-    if args.calib_copy:
-        # a plain copy of known size: 1 GiB read + 1 GiB written
-        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # a plain device copy of known size (1 GiB read + 1 GiB written): the
+    # measured bandwidth beside the 8 TB/s peak, and the calibration of the
+    # byte counters (--calib-copy only adds the run to a profile)
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     ctx = mj.Context()
     t0 = time.perf_counter()
     plan = ctx.plan(mj.LINEAR, Fd, Fd, Fd, a_domain)
@@ -197,14 +219,27 @@ def main():
     distinct_t = int(np.unique(F[:, 0]).size)       # T.c and S.b are both F's first column
     dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
     avg_ms = kern[dom][0]
-    nbytes = kernel_bytes(dom, n, n, n, distinct_t, distinct_t, a_domain, plan.b_domain, plan.c_domain)
+    nbytes = kernel_bytes(dom, n, n, n, distinct_t, distinct_t, a_domain, plan.b_domain, plan.c_domain,
+                          shared_partition=True)
     roof = None
     if nbytes:
         ach = nbytes / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom),
-                "algorithmic_bytes": nbytes, "avg_launch_us": round(avg_ms * 1e3, 2)}
+                "algorithmic_bytes": nbytes, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "measured_copy_gbs": round(copy_gbs, 1)}
+    # every kernel of the step on its own algorithmic bytes
+    per_kernel = {}
+    for k, (avg, per) in kern.items():
+        kb = kernel_bytes(k, n, n, n, distinct_t, distinct_t, a_domain, plan.b_domain, plan.c_domain,
+                          shared_partition=True)
+        if kb:
+            per_kernel[k] = {"us": round(avg * 1e3, 2), "algorithmic_bytes": kb,
+                             "frac_of_peak": round(kb / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # algorithmic probes of the step: one table read per S tuple (W) and per R
+    # tuple (counts), one key counted per T tuple (multiplicities)
+    probes = 3 * n
     result = {
         "metric": "join input tuples/s (linear 3-way, per-A count)",
         "value": 3 * n / (ms * 1e-3),
@@ -226,22 +261,58 @@ def main():
                    "b_domain": plan.b_domain, "c_domain": plan.c_domain,
                    "plan_ms": round(plan_ms, 2), "exact_sum_check": exact,
                    "ms_per_step_with_kernel_events": round(ms_profiled, 4),
-                   "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kern.items()}},
+                   "probes_per_s": probes / (ms * 1e-3),
+                   "measured_copy_gbs": round(copy_gbs, 1),
+                   "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kern.items()},
+                   "kernels_roofline": per_kernel},
         "roofline": roof,
     }
     # The other paths never run in this process after the timed workload:
     # that sequence faulted the GPU (the first call after it), while each
-    # path alone and the timed workload alone run cleanly.
-    if args.paths and not args.no_extra:
+    # path alone and the timed workload alone run cleanly.  By default the
+    # other configurations (the small linear workload, the cyclic join, the
+    # 512-join batch, the planners) and the gather-locality measurement run
+    # after it, each as a child process of its own; --paths runs every leg.
+    if not args.no_extra:
         del ws, out
         ctx.close()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        result["paths"] = child_paths()
+        result["paths"] = child_paths(LEGS if args.paths else DEFAULT_LEGS)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(F, a_domain)
+        result["cpu_baseline"]["per_config"] = oracle_per_config()
     print(json.dumps(result), flush=True)
+
+
+def oracle_per_config():
+    """The oracle's time on every configuration: the small linear workload
+    timed here (median of 5 runs, one thread), the others from the CPU
+    seconds the oracle-only golden scripts recorded (one thread per slice
+    or join, summed)."""
+    import numpy as np
+    import oracle
+    from workloads import generators as G
+    Fs = G.linear_small().view(np.uint32)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.linear3_count(Fs, Fs, Fs, 4096)
+        ts.append(time.perf_counter() - t0)
+    out = {"linear_small_65536": {"seconds": round(float(np.median(ts)), 4), "runs": 5,
+                                  "input_tuples_per_s": 3 * Fs.shape[0] / float(np.median(ts)),
+                                  "where": "this host, one thread"}}
+    gdir = os.path.join(ROOT, "tests", "golden")
+    for key, fname, what in (("linear_powerlaw_2e24", "linear_powerlaw_2e24.json", "all 2^20 per-A counts"),
+                             ("cyclic_rmat22", "triangle_rmat22.json", "the cyclic total"),
+                             ("batch_512", "batch512.json", "every join of the batch")):
+        path = os.path.join(gdir, fname)
+        if os.path.exists(path):
+            g = json.load(open(path))
+            out[key] = {"cpu_seconds": g.get("oracle_cpu_seconds"), "computes": what,
+                        "where": "recorded by " + g.get("command", fname) + " (one thread per task)"}
+    return out
 
 
 def time_call(fn, steps, warmup=1):
@@ -323,6 +394,73 @@ def star_path(mj, ctx):
     res["speedup_star_over_star_cascade"] = round(res["star_cascade"]["ms"] / res["star"]["ms"], 2)
     res["speedup_star_over_partitioned"] = round(res["partitioned_3way"]["ms"] / res["star"]["ms"], 2)
     del ws, Rd, Sd, Td
+    return res
+
+
+def slarge_path(mj, ctx):
+    """The S-largest form of the linear join (Sec. 4, after Algorithm 1): a
+    2^26-tuple S with R and T of 2^16 tuples each (beyond the star plans),
+    under the planner's S-largest plan and, on the same bucket counts, the
+    partitioned three-way join and the cascade."""
+    import numpy as np
+    import torch
+    from workloads import generators as G
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import brute
+    log("generating the S-largest workload (2^26 S tuples, 2^16-tuple R and T)")
+    R, S, T = G.star_schema(n_fact=1 << 26, k_r=1 << 16, k_t=1 << 16, a_domain=1 << 14, seed=5002)
+    a_dom = 1 << 14
+    Rd, Sd, Td = (torch.from_numpy(x).to("cuda") for x in (R, S, T))
+    closed = brute.linear_closed_total(R, S, T)
+    plan = ctx.plan(mj.LINEAR, Rd, Sd, Td, a_dom)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    cnt = torch.empty(a_dom, dtype=torch.int64, device="cuda")
+    n_in = R.shape[0] + S.shape[0] + T.shape[0]
+    res = {"planned_algo": int(plan.algo), "log2_nb": int(plan.log2_nb), "log2_nc": int(plan.log2_nc),
+           "est_ms": {"slarge": round(plan.est_ms_slarge, 3), "3way": round(plan.est_ms_3way, 3),
+                      "cascade": round(plan.est_ms_cascade, 3)}}
+    for name, algo in (("s_largest", mj.ALGO_SLARGE), ("partitioned_3way", mj.ALGO_3WAY),
+                       ("cascade", mj.ALGO_CASCADE)):
+        p = plan.copy()
+        p.algo = algo
+        if algo == mj.ALGO_CASCADE:
+            fn = lambda: ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
+        else:
+            fn = lambda: ctx.linear3_count(Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
+        ms, kp = time_and_profile(ctx, fn, 5)
+        ok = int(mj.as_u64(cnt).sum(dtype=np.uint64)) == closed
+        res[name] = {"ms": round(ms, 4), "tuples_per_s": n_in / (ms * 1e-3), "sum_equals_closed_form": ok,
+                     "kernels_us": {k: round(v[0] / max(v[1], 1) * 1e3, 1)
+                                    for k, v in sorted(kp.items(), key=lambda kv: -kv[1][0])[:5]}}
+        log(f"S-largest workload, {name}: {ms:.3f} ms, sum ok {ok}")
+    res["speedup_over_partitioned"] = round(res["partitioned_3way"]["ms"] / res["s_largest"]["ms"], 2)
+    return res
+
+
+def gather_path(mj, ctx, F, a_domain):
+    """What bounds the per-range sums: the benchmark step on its input, and
+    on the same edges sorted by (source, destination) -- the same join, with
+    each range's gathered keys in order, so that consecutive lanes read
+    neighbouring entries.  The kernels' times on the two orders show what
+    locality of the random table reads is worth."""
+    import numpy as np
+    import torch
+    res = {}
+    for name, E in (("benchmark_order", F), ("sorted_by_source_destination",
+                                              F[np.lexsort((F[:, 1], F[:, 0]))])):
+        Ed = torch.from_numpy(np.ascontiguousarray(E)).to("cuda")
+        p = ctx.plan(mj.LINEAR, Ed, Ed, Ed, a_domain)
+        ws = torch.empty(p.workspace_bytes, dtype=torch.uint8, device="cuda")
+        out = torch.empty(a_domain, dtype=torch.int64, device="cuda")
+        ms, kp = time_and_profile(ctx, lambda: ctx.linear3_count(Ed, Ed, Ed, a_domain, plan=p, out=out,
+                                                                   workspace=ws), 20, 3)
+        res[name] = {"ms_per_step": round(ms, 4),
+                     "kernels_us": {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in kp.items()
+                                    if k.startswith("k_range") or "scatter" in k},
+                     "sum": int(mj.as_u64(out).sum(dtype=np.uint64))}
+        del ws, Ed
+        log(f"gather locality, {name}: {ms:.4f} ms")
+    res["same_counts"] = res["benchmark_order"]["sum"] == res["sorted_by_source_destination"]["sum"]
     return res
 
 
@@ -427,14 +565,16 @@ def emit_path(mj, ctx, F, Fd):
     return res
 
 
-LEGS = ("cascade", "small", "fm", "emit", "star", "triangle", "batch", "planner")
+LEGS = ("cascade", "small", "fm", "emit", "star", "slarge", "triangle", "batch", "planner", "gather")
+DEFAULT_LEGS = ("small", "triangle", "batch", "planner", "gather")
+OWN_WORKLOAD_LEGS = ("small", "star", "slarge", "triangle", "batch", "planner")
 
 
-def child_paths():
-    """Every other path, each as `bench.py --only LEG` in a child process."""
+def child_paths(legs):
+    """The named paths, each as `bench.py --only LEG` in a child process."""
     import subprocess
     out = {}
-    for leg in LEGS:
+    for leg in legs:
         log(f"path {leg} (child process)")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--only", leg, "--no-cpu"],
                            capture_output=True, text=True, timeout=1200)
@@ -458,6 +598,10 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
         out["materialised"] = emit_path(mj, ctx, F, Fd)
     if only in (None, "star"):
         out["star"] = star_path(mj, ctx)
+    if only in (None, "slarge"):
+        out["s_largest"] = slarge_path(mj, ctx)
+    if only in (None, "gather"):
+        out["gather_locality"] = gather_path(mj, ctx, F, a_domain)
     if only in (None, "triangle"):
         out["triangle_rmat22"] = triangle_path(mj, ctx)
     if only in (None, "batch"):
@@ -473,9 +617,8 @@ def linear_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
     import torch
     from workloads import generators as G
     out = {}
-    n = F.shape[0]
     if only in (None, "cascade"):
-        out["cascade_linear"] = cascade_path(mj, ctx, Fd, n, a_domain, plan, ms_3way)
+        out["cascade_linear"] = cascade_path(mj, ctx, Fd, F.shape[0], a_domain, plan, ms_3way)
     if only == "cascade":
         return out
     # small uniform linear workload (65,536 tuples, keys in [0, 4096))
@@ -487,8 +630,16 @@ def linear_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
     ms_s = time_call(lambda: ctx.linear3_count(Fsd, Fsd, Fsd, 4096, plan=ps, out=cs, workspace=ws), 20, 3)
     ms_sc = time_call(lambda: ctx.cascade2_count(mj.LINEAR, Fsd, Fsd, Fsd, 4096, plan=ps, out=cs,
                                                  workspace=ws), 20, 3)
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import brute
+    closed = brute.linear_closed_total(Fs, Fs, Fs)
+    got_c = int(mj.as_u64(cs).sum(dtype=np.uint64))
+    ctx.linear3_count(Fsd, Fsd, Fsd, 4096, plan=ps, out=cs, workspace=ws)
+    got_3 = int(mj.as_u64(cs).sum(dtype=np.uint64))
     out["linear_small"] = {"ms_3way": round(ms_s, 4), "ms_cascade": round(ms_sc, 4),
-                           "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3)}
+                           "tuples_per_s_3way": 3 * Fs.shape[0] / (ms_s * 1e-3),
+                           "tuples_per_s_cascade": 3 * Fs.shape[0] / (ms_sc * 1e-3),
+                           "sums_equal_closed_form": got_3 == closed and got_c == closed}
     del ws
     return out
 

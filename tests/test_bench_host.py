@@ -31,7 +31,7 @@ def test_child_paths_runs_every_leg_alone(monkeypatch):
         return subprocess.CompletedProcess(cmd, 0, stdout="noise\n" + json.dumps(body) + "\n", stderr="")
 
     monkeypatch.setattr(subprocess, "run", fake_run)
-    out = bench.child_paths()
+    out = bench.child_paths(bench.LEGS)
     assert [c[c.index("--only") + 1] for c in calls] == list(bench.LEGS)
     for c in calls:
         assert c[0] == sys.executable and c[1].endswith("bench.py") and "--no-cpu" in c
@@ -39,6 +39,20 @@ def test_child_paths_runs_every_leg_alone(monkeypatch):
     for leg in bench.LEGS:
         if leg != "emit":
             assert out[f"{leg}_result"] == {"ms": 1.0}
+
+
+def test_default_legs_are_configurations_other_than_the_main_one():
+    assert set(bench.DEFAULT_LEGS) <= set(bench.LEGS)
+    assert {"small", "triangle", "batch", "planner"} <= set(bench.DEFAULT_LEGS)
+
+
+def test_shared_partition_bytes():
+    """R = S = T one relation: its partition by range of its first column is
+    made once, so the partition launches move one relation."""
+    n = 1 << 24
+    assert bench.kernel_bytes("dense:k_part_scatter", n, n, n, 0, 0, 0, shared_partition=True) == 16 * n
+    assert bench.kernel_bytes("dense:k_part_scatter", n, n, n, 0, 0, 0) == 40 * n
+    assert bench.kernel_bytes("dense:k_part_hist", n, n, n, 0, 0, 0, shared_partition=True) == 4 * n
 
 
 def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
