@@ -419,10 +419,16 @@ def slarge_path(mj, ctx):
     res = {"planned_algo": int(plan.algo), "log2_nb": int(plan.log2_nb), "log2_nc": int(plan.log2_nc),
            "est_ms": {"slarge": round(plan.est_ms_slarge, 3), "3way": round(plan.est_ms_3way, 3),
                       "cascade": round(plan.est_ms_cascade, 3)}}
+    clog2 = lambda x: max(0, (int(x) - 1).bit_length())
     for name, algo in (("s_largest", mj.ALGO_SLARGE), ("partitioned_3way", mj.ALGO_3WAY),
                        ("cascade", mj.ALGO_CASCADE)):
         p = plan.copy()
         p.algo = algo
+        if algo != mj.ALGO_SLARGE:
+            # the bucket counts the planner gives these plans (about 16K S
+            # tuples per B bucket, 32K T tuples per C bucket)
+            p.log2_nb = min(10, clog2((S.shape[0] + 16383) // 16384))
+            p.log2_nc = min(10, clog2((T.shape[0] + 32767) // 32768))
         if algo == mj.ALGO_CASCADE:
             fn = lambda: ctx.cascade2_count(mj.LINEAR, Rd, Sd, Td, a_dom, plan=p, out=cnt, workspace=ws)
         else:
@@ -709,16 +715,17 @@ def triangle_path(mj, ctx):
 
 def planner_path(ctx, n=300):
     """Learned vs plain planners on held-out join instances (sizes 10^3 to
-    10^5, the families the network was trained on, other seeds): the
+    10^5.5, the families the network was trained on, other seeds): the
     summed measured time of each planner's plans, with counts checked."""
     import numpy as np
     from paper_1905_13376_amd import learned
     log(f"planner comparison on {n} held-out instances")
     pl = learned.use_shipped(ctx)
-    rows = [learned.label_instance(ctx, x) for x in learned.planner_instances(n, 7_000_000)]
-    res = learned.evaluate(pl, rows)
-    res["counts_exact_all_plans"] = all(r["cascade_equals_3way"] for r in rows)
-    res["plan_ms_median_analytic"] = round(float(np.median([r["plan_ms"] for r in rows])), 3)
+    rows = [learned.label_instance(ctx, x) for x in learned.planner_instances(n, 7_000_000, 3.0, 5.5)]
+    D = learned.rows_to_arrays(rows)
+    res = learned.evaluate(pl, D)
+    res["counts_exact_all_plans"] = bool(D["counts_exact"].all())
+    res["plan_ms_median_analytic"] = round(float(np.median(D["plan_ms"])), 3)
     ctx.set_planner(None)
     return res
 

@@ -338,36 +338,48 @@ typedef enum {
 } mj_cost_formula;
 int mj_cost_model(int which, const double* args, int nargs, double* out);
 
+/* Bucket counts of the S-largest plan (Sec. 4, the paragraph after
+ * Algorithm 1) for relations of n_r, n_s, n_t tuples: *log2_nb = log2 L_R
+ * (parts of R of about 1024 tuples), *log2_nc = log2 L_T (the count the
+ * planner's time model prefers, log2_nb + log2_nc <= 12) and *est_ms the
+ * modelled time (may be NULL).  Host only, no device needed.  Returns
+ * MJ_ERR_INVALID_ARG for NULL outputs or when R needs more than 2^12
+ * parts; the outputs are then left unchanged.                            */
+int mj_slarge_buckets(uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t* log2_nb, uint32_t* log2_nc,
+                      double* est_ms);
+
 /* ---------------------------------------------------------------------
  * Learned planner (not from the paper; its choices never change a count).
  * A join is summarised by a degree sketch of MJ_SKETCH_DIM features: for
  * R's B column, S's B column and T's C column a 32-bin histogram of
  * floor(log2 deg(v)) over their distinct values v (each bin given as
  * log2(1 + keys in the bin) / 32), then log2(1 + |R|), (1 + |S|), (1 + |T|)
- * over 32, then the kind.  A network MJ_SKETCH_DIM -> 64 -> 64 -> 7 with
+ * over 32, then the kind.  A network MJ_SKETCH_DIM -> 64 -> 64 -> 11 with
  * GELU maps it to: predicted log2(1 + |R |x| S|), log2(1 + |output|),
- * logits of (three-way, cascade) and of the share (1, 4, 16).
+ * logits of the plan in mj_algo order (three-way, cascade, star, star
+ * cascade, oriented, S-largest) and of the share (1, 4, 16).  mj_plan
+ * takes the plan of largest logit among those the join is eligible for.
  * Weights are BF16 (W1, W2, W3), biases and arithmetic FP32.
  * The parameter buffer is device memory of mj_mlp_param_bytes() bytes:
  *   float master[P], grad[P], adam_m[P], adam_v[P]; uint16 bf16_weights[]
- * with P = 64*100 + 64 + 64*64 + 64 + 7*64 + 7 parameters in the order
- * W1 (row-major [64][100]), b1, W2 ([64][64]), b2, W3 ([7][64]), b3.
+ * with P = 64*100 + 64 + 64*64 + 64 + 11*64 + 11 parameters in the order
+ * W1 (row-major [64][100]), b1, W2 ([64][64]), b2, W3 ([11][64]), b3.
  * All calls are asynchronous on `stream` and launch kernels only.       */
 #define MJ_SKETCH_DIM 100
 #define MJ_MLP_HIDDEN 64
-#define MJ_MLP_OUT 7
+#define MJ_MLP_OUT 11
 uint64_t mj_mlp_param_bytes(void);
 /* BF16 copies from the FP32 masters; gradients cleared. */
 int mj_mlp_sync(mj_ctx* ctx, void* params, void* stream);
-/* Y[B][7] = network(X[B][100]) (device fp32 arrays). */
+/* Y[B][11] = network(X[B][100]) (device fp32 arrays). */
 int mj_mlp_forward(mj_ctx* ctx, const void* params, const float* X, uint32_t B, float* Y,
                    void* stream);
 /* Forward, loss and backward of a batch: the gradients are ADDED to the
  * grad block of `params`; *loss (device fp32) is increased by the batch's
  * mean loss: squared error of heads 0-1 against targets[B][2], softmax
- * cross entropy of heads 2-3 against plan_label[B] (0 = three-way,
- * 1 = cascade) and of heads 4-6 against share_label[B] (0, 1, 2 for
- * 1, 4, 16; -1 = no share term).  Workspace: mj_mlp_workspace(B).     */
+ * cross entropy of heads 2-7 against plan_label[B] (an mj_algo value,
+ * 0..5) and of heads 8-10 against share_label[B] (0, 1, 2 for 1, 4, 16;
+ * -1 = no share term).  Workspace: mj_mlp_workspace(B).               */
 uint64_t mj_mlp_workspace(uint32_t B);
 int mj_mlp_grads(mj_ctx* ctx, void* params, const float* X, uint32_t B, const float* targets,
                  const int32_t* plan_label, const int32_t* share_label, float* loss,

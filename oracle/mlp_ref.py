@@ -8,8 +8,9 @@ the exact form x * Phi(x) with Phi the standard normal CDF.
 Loss for a batch of B samples (the planner's heads):
   y[0], y[1]   : predicted log2(1 + |I|), log2(1 + |OUT|); squared error
                  against the targets, weight 1 each, averaged over B
-  y[2:4]       : logits of (three-way, cascade); cross entropy, averaged
-  y[4:7]       : logits of the share (1, 4, 16); cross entropy over the
+  y[2:8]       : logits of the plan (three-way, cascade, star, star
+                 cascade, oriented, S-largest); cross entropy, averaged
+  y[8:11]      : logits of the share (1, 4, 16); cross entropy over the
                  samples whose share label is >= 0, divided by B
 This module restates those definitions directly; it shares nothing with
 the HIP kernels.  Parity of the reference itself is pinned by finite
@@ -21,7 +22,9 @@ import math
 
 import numpy as np
 
-IN, H, OUT = 100, 64, 7
+IN, H, NPLAN = 100, 64, 6
+PLAN0, SHARE0 = 2, 2 + NPLAN
+OUT = SHARE0 + 3
 
 
 def bf16_round(w32: np.ndarray) -> np.ndarray:
@@ -64,10 +67,10 @@ def loss(y, targets, plan_label, share_label):
     B = y.shape[0]
     t = np.asarray(targets, dtype=np.float64)
     l_reg = ((y[:, 0] - t[:, 0]) ** 2 + (y[:, 1] - t[:, 1]) ** 2).sum() / B
-    lp = _log_softmax(y[:, 2:4])
+    lp = _log_softmax(y[:, PLAN0:SHARE0])
     l_plan = -lp[np.arange(B), plan_label].sum() / B
     m = share_label >= 0
-    ls = _log_softmax(y[:, 4:7])
+    ls = _log_softmax(y[:, SHARE0:SHARE0 + 3])
     l_share = -ls[np.arange(B)[m], share_label[m]].sum() / B if m.any() else 0.0
     return l_reg + l_plan + l_share
 
@@ -78,13 +81,13 @@ def loss_grad_y(y, targets, plan_label, share_label):
     t = np.asarray(targets, dtype=np.float64)
     g[:, 0] = 2.0 * (y[:, 0] - t[:, 0]) / B
     g[:, 1] = 2.0 * (y[:, 1] - t[:, 1]) / B
-    p = np.exp(_log_softmax(y[:, 2:4]))
+    p = np.exp(_log_softmax(y[:, PLAN0:SHARE0]))
     p[np.arange(B), plan_label] -= 1.0
-    g[:, 2:4] = p / B
+    g[:, PLAN0:SHARE0] = p / B
     m = share_label >= 0
-    q = np.exp(_log_softmax(y[:, 4:7]))
+    q = np.exp(_log_softmax(y[:, SHARE0:SHARE0 + 3]))
     q[np.arange(B), np.maximum(share_label, 0)] -= 1.0
-    g[:, 4:7] = np.where(m[:, None], q / B, 0.0)
+    g[:, SHARE0:SHARE0 + 3] = np.where(m[:, None], q / B, 0.0)
     return g
 
 

@@ -6,4 +6,4 @@ library is missing (there is no CPU path)."""
 from ._lib import (ALGO_3WAY, ALGO_CASCADE, ALGO_ORIENTED, ALGO_SLARGE, ALGO_STAR, ALGO_STAR_CASCADE,  # noqa: F401
                    LINEAR, PLAN_DENSE_KEYS, PLAN_NO_DENSE, PLAN_SYMMETRIC_SIMPLE, TRIANGLE,
                    Context, MJError,
-                   Plan, Rel, as_u64, cost_model, rel, status_str, LIB_PATH)
+                   Plan, Rel, as_u64, cost_model, rel, slarge_buckets, status_str, LIB_PATH)

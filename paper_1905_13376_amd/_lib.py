@@ -107,6 +107,8 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_double), _vp], _i32),
     "mj_cost_model": ([_i32, ctypes.POINTER(ctypes.c_double), _i32,
                        ctypes.POINTER(ctypes.c_double)], _i32),
+    "mj_slarge_buckets": ([_u64, _u64, _u64, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                           ctypes.POINTER(ctypes.c_double)], _i32),
     "mj_ctx_profile_read": ([_vp, _i32, _vp, _vp, _vp], _i32),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -125,6 +127,14 @@ def cost_model(name: str, *args) -> float:
     out = ctypes.c_double()
     _check(_lib.mj_cost_model(COST[name], arr, len(args), ctypes.byref(out)), "mj_cost_model")
     return out.value
+
+
+def slarge_buckets(n_r: int, n_s: int, n_t: int):
+    """(log2 L_R, log2 L_T, modelled ms) of the S-largest plan (no GPU needed)."""
+    lr, lt, ms = _u32(), _u32(), ctypes.c_double()
+    _check(_lib.mj_slarge_buckets(n_r, n_s, n_t, ctypes.byref(lr), ctypes.byref(lt), ctypes.byref(ms)),
+           "mj_slarge_buckets")
+    return lr.value, lt.value, ms.value
 
 
 def exported_symbols():

@@ -303,12 +303,25 @@ struct LinearLayout {
     uint64_t wslots;
     uint32_t a_bits, a_shift;
     bool by_range;                    // per-A counts by ranges of A (no atomics)
+    // S-largest plans: R's B values as tables per part of R, a sum per slot
+    TableLayout Rk;
+    unsigned long long* wval;
+    unsigned long long* wspecial;
     size_t bytes;
 };
 
 // S-largest plans partition S by (bucket of B, bucket of C)
 uint32_t s_part_bits(const mj_plan_t& p) {
     return p.log2_nb + (p.algo == MJ_ALGO_SLARGE ? p.log2_nc : 0u);
+}
+
+// Workgroups per (part of R, part of T) of the S-largest plan: about 32K
+// tuples of S each, and 512 workgroups at least in all.
+uint32_t sl_pieces(const mj_plan_t& p) {
+    const uint64_t cells = uint64_t(1) << (p.log2_nb + p.log2_nc);
+    uint64_t k = std::max<uint64_t>(1, p.n_s / (cells * 32768));
+    k = std::max<uint64_t>(k, (512 + cells - 1) / cells);
+    return (uint32_t)std::min<uint64_t>(k, 64);
 }
 
 LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
@@ -327,15 +340,26 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
         L.Ra.starts = B.take<uint32_t>(na + 1);
         const uint32_t nb = 1u << p.log2_nb;
         L.wdir = B.take<WDirEntry>(nb);
-        // a bucket's table holds at most 4 slots per S tuple (a power of two
-        // >= twice its keys), plus the minimum per bucket and the empty head
-        L.wslots = 4 * p.n_s + uint64_t(W_MIN_CAP) * (nb + 1);
+        if (p.algo == MJ_ALGO_SLARGE) {
+            // the W tables are R's B tables, slot for slot
+            take_table(B, L.Rk, p.n_r, p.log2_nb);
+            L.wval = B.take<unsigned long long>(L.Rk.pool_slots);
+            L.wspecial = B.take<unsigned long long>(nb);
+            L.wslots = L.Rk.pool_slots;
+        } else {
+            // a bucket's table holds at most 4 slots per S tuple (a power of
+            // two >= twice its keys), plus the minimum per bucket and the
+            // empty head
+            L.wslots = 4 * p.n_s + uint64_t(W_MIN_CAP) * (nb + 1);
+        }
         L.wpool = B.take<WSlot>(L.wslots);
         L.wcursor = B.take<unsigned long long>(1);
     }
     L.bytes = B.off + 256;
     return L;
 }
+
+
 
 struct CascadeLayout {
     RelPart R, S;
@@ -1624,7 +1648,8 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
     if (planner != MJ_PLANNER_FIXED) {
         st = analytic_plan(kind, p, ctx->num_cu, ctx->model);
         if (st) return st;
-        if (planner == MJ_PLANNER_LEARNED && ctx->planner) {
+        const bool learned_choice = planner == MJ_PLANNER_LEARNED && ctx->planner;
+        if (learned_choice) {
             // the network's choice replaces the analytic one; the analytic
             // estimates stay in the plan as its judge
             float* feat = PL.feat;
@@ -1636,23 +1661,36 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
             MJ_HIP(hipStreamSynchronize(s));
             p.pred_log2_join2 = h[0];
             p.pred_log2_out = h[1];
-            p.algo = h[3] > h[2] ? MJ_ALGO_CASCADE : MJ_ALGO_3WAY;
-            // the star plans specialise the two classes when the dimension
-            // relations are small and the model rates them faster
-            if (p.algo == MJ_ALGO_3WAY && p.est_ms_star > 0.0 && p.est_ms_star < p.est_ms_3way)
-                p.algo = MJ_ALGO_STAR;
-            // so does the S-largest form (its bucket counts are in the plan
-            // when the analytic planner chose it)
-            if (p.algo == MJ_ALGO_3WAY && p.est_ms_slarge > 0.0 && p.est_ms_slarge < p.est_ms_3way &&
-                p.log2_nb + p.log2_nc <= PART_MAX_BITS)
-                p.algo = MJ_ALGO_SLARGE;
-            if (p.algo == MJ_ALGO_CASCADE && p.est_ms_star_cascade > 0.0 &&
-                p.est_ms_star_cascade < p.est_ms_cascade)
-                p.algo = MJ_ALGO_STAR_CASCADE;
+            // the plan of largest logit among those this join can take
+            bool ok[MLP_NPLAN] = {};
+            ok[MJ_ALGO_3WAY] = true;
+            ok[MJ_ALGO_CASCADE] = p.join2_size <= CAS_DEFAULT_I_CAP;
+            if (kind == MJ_LINEAR) {
+                ok[MJ_ALGO_STAR] = p.est_ms_star > 0.0;
+                ok[MJ_ALGO_STAR_CASCADE] = p.est_ms_star_cascade > 0.0;
+                ok[MJ_ALGO_SLARGE] = p.est_ms_slarge > 0.0;
+            } else {
+                ok[MJ_ALGO_ORIENTED] = (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) != 0;
+            }
+            int best = MJ_ALGO_3WAY;
+            for (int k = 0; k < MLP_NPLAN; ++k)
+                if (ok[k] && h[MLP_PLAN0 + k] > h[MLP_PLAN0 + best]) best = k;
+            // the S-largest plan needs its own bucket counts (set by the
+            // analytic planner when it chose it, else derived here)
+            if (best == MJ_ALGO_SLARGE && p.algo != MJ_ALGO_SLARGE) {
+                uint32_t lr = 0, lt = 0;
+                if (slarge_buckets(default_model(), p.n_r, p.n_s, p.n_t, lr, lt, nullptr)) {
+                    p.log2_nb = lr;
+                    p.log2_nc = lt;
+                } else {
+                    best = MJ_ALGO_3WAY;
+                }
+            }
+            p.algo = best;
             if (kind == MJ_TRIANGLE) {            // share classes 1, 4, 16
-                int best = 0;
-                for (int k = 1; k < 3; ++k) if (h[4 + k] > h[4 + best]) best = k;
-                p.log2_share = 2 * best;
+                int bs = 0;
+                for (int k = 1; k < 3; ++k) if (h[MLP_SHARE0 + k] > h[MLP_SHARE0 + bs]) bs = k;
+                p.log2_share = 2 * bs;
             }
         }
         // an intermediate beyond one workspace-sized chunk is never worth
@@ -1662,7 +1700,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         // counting each triangle once does less work than either form of
         // the general cyclic join, for the same total, once the relation is
         // large and skewed enough to pay for orienting it
-        if ((p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) && orient_pays(p)) p.algo = MJ_ALGO_ORIENTED;
+        if (!learned_choice && (p.flags & MJ_PLAN_SYMMETRIC_SIMPLE) && orient_pays(p)) p.algo = MJ_ALGO_ORIENTED;
     } else {
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 6)
             return MJ_ERR_INVALID_ARG;
@@ -1741,20 +1779,38 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         P.job[1].range_shift = L.a_shift;
         P.job[1].out_pair = L.Ra.pairs;
         if ((st = launch_partition(&ctx->prof, "rs", P, s))) return st;
-        // W[b] per bucket of B into the pool (slots [0, W_MIN_CAP) stay empty)
-        MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s,
-                  reinterpret_cast<uint32_t*>(L.wpool), (uint64_t)(4 * W_MIN_CAP), EMPTY_KEY);
-        MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
-                  (unsigned long long)W_MIN_CAP);
-        WBuildArgs Wb;
-        Wb.S = L.S.pairs; Wb.sstarts = L.S.starts; Wb.ddir = L.T.dir; Wb.dpool = L.T.pool;
-        Wb.c_seed = seed_c(p); Wb.c_bits = p.log2_nc; Wb.slot_seed = seed_slot(p); Wb.w_seed = seed_w(p);
-        Wb.wdir = L.wdir; Wb.wpool = L.wpool; Wb.wcursor = L.wcursor; Wb.wcap = L.wslots;
-        Wb.err = L.T.err;
-        if (slarge)
-            MJ_LAUNCH(&ctx->prof, "k_wbuild_staged", k_wbuild_staged, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
-        else
+        if (slarge) {
+            // R's B values as tables per part of R (slots hashed as the W
+            // tables are), a zero sum beside each slot; then every (R_i, T_j)
+            // pair meets S_ij; then the tables become the W tables
+            st = launch_tables(&ctx->prof, L.Rk, *R, 1, p.log2_nb, seed_b(p), seed_w(p), s);
+            if (st) return st;
+            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(L.Rk.pool_slots, 256, 4096)), dim3(256), 0, s,
+                      L.wval, (uint64_t)L.Rk.pool_slots, 0ull);
+            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, s,
+                      L.wspecial, (uint64_t)nb, 0ull);
+            SlCellArgs Sc;
+            Sc.S = L.S.pairs; Sc.sstarts = L.S.starts; Sc.r_bits = p.log2_nb; Sc.t_bits = p.log2_nc;
+            Sc.pieces = sl_pieces(p);
+            Sc.rdir = L.Rk.dir; Sc.rpool = L.Rk.pool; Sc.w_seed = seed_w(p); Sc.wval = L.wval;
+            Sc.wspecial = L.wspecial; Sc.tdir = L.T.dir; Sc.tpool = L.T.pool; Sc.slot_seed = seed_slot(p);
+            const uint32_t grid = (1u << (p.log2_nb + p.log2_nc)) * Sc.pieces;
+            MJ_LAUNCH(&ctx->prof, "k_sl_cell", k_sl_cell, dim3(grid), dim3(SL_THREADS), 0, s, Sc);
+            MJ_LAUNCH(&ctx->prof, "k_sl_wtables", k_sl_wtables, dim3(nb), dim3(256), 0, s, L.Rk.dir, L.Rk.pool,
+                      L.wval, L.wspecial, L.wdir, L.wpool);
+        } else {
+            // W[b] per bucket of B into the pool (slots [0, W_MIN_CAP) stay empty)
+            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s,
+                      reinterpret_cast<uint32_t*>(L.wpool), (uint64_t)(4 * W_MIN_CAP), EMPTY_KEY);
+            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
+                      (unsigned long long)W_MIN_CAP);
+            WBuildArgs Wb;
+            Wb.S = L.S.pairs; Wb.sstarts = L.S.starts; Wb.ddir = L.T.dir; Wb.dpool = L.T.pool;
+            Wb.c_seed = seed_c(p); Wb.c_bits = p.log2_nc; Wb.slot_seed = seed_slot(p); Wb.w_seed = seed_w(p);
+            Wb.wdir = L.wdir; Wb.wpool = L.wpool; Wb.wcursor = L.wcursor; Wb.wcap = L.wslots;
+            Wb.err = L.T.err;
             MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
+        }
         // per range of A: count[a] = sum of W[r.b], written once
         CountArgs Cn;
         Cn.R = L.Ra.pairs; Cn.rstarts = L.Ra.starts; Cn.wdir = L.wdir; Cn.wpool = L.wpool;
@@ -2432,9 +2488,12 @@ int mj_autotune(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const m
         if (base.est_ms_slarge > 0.0) {
             mj_plan_t c = base;
             c.algo = MJ_ALGO_SLARGE;
-            c.log2_nb = ceil_log2((base.n_r + 2047) / 2048);
-            c.log2_nc = ceil_log2((base.n_t + 2047) / 2048);
-            if (c.log2_nb + c.log2_nc <= PART_MAX_BITS) cand.push_back(c);
+            uint32_t lr = 0, lt = 0;
+            if (slarge_buckets(default_model(), base.n_r, base.n_s, base.n_t, lr, lt, nullptr)) {
+                c.log2_nb = lr;
+                c.log2_nc = lt;
+                cand.push_back(c);
+            }
         }
         if (base.est_ms_star_cascade > 0.0) { mj_plan_t c = base; c.algo = MJ_ALGO_STAR_CASCADE; cand.push_back(c); }
     } else {
@@ -2509,7 +2568,7 @@ int plan_workspace(mj_plan_t& p) {
         }
         if (p.flags & MJ_PLAN_DENSE_KEYS) need = std::max(need, dense_layout(nullptr, p).bytes);
         // the star plans (planned or tuned only for small R)
-        if (p.n_r <= STAR_PLAN_MAX_R || p.algo == MJ_ALGO_STAR || p.algo == MJ_ALGO_STAR_CASCADE) {
+        if (star_plan_fits(p) || p.algo == MJ_ALGO_STAR || p.algo == MJ_ALGO_STAR_CASCADE) {
             need = std::max(need, star_layout(nullptr, p, false).bytes);
             if (p.join2_size <= STAR_PLAN_MAX_I) need = std::max(need, star_layout(nullptr, p, true).bytes);
         }

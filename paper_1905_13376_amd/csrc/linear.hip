@@ -250,77 +250,6 @@ __device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const Dir
     }
 }
 
-// W[b] += mult_Tj(c) over the S tuples of b-bucket i, one c-bucket j at a
-// time: T_j's table is copied into `stage` (LDS) when it fits, and S_ij,
-// which the 2-D partition keeps contiguous, streams past it.  Same pass
-// split and overflow rule as w_accumulate.  Every thread runs every j and
-// reaches every barrier; *over is read between two barriers, so all threads
-// see the same value.
-__device__ void w_accumulate_staged(const WBuildArgs& A, uint32_t i, uint32_t level, uint32_t pass,
-                                    const WTable& T, uint2* stage) {
-    const uint32_t mask = CELL_CAP - 1;
-    const int nthr = blockDim.x;
-    const uint32_t L = 1u << A.c_bits;
-    for (uint32_t j = 0; j < L; ++j) {
-        const uint32_t q0 = A.sstarts[i * L + j], q1 = A.sstarts[i * L + j + 1];
-        if (q0 == q1) continue;                      // the same for every thread
-        __syncthreads();                              // the previous stage's readers are done
-        const uint32_t stop = *(volatile uint32_t*)T.over;
-        __syncthreads();
-        if (stop) break;
-        const DirEntry e = A.ddir[j];
-        const bool lds = e.log2cap <= WSTAGE_LOG2;
-        const uint32_t tmask = (1u << e.log2cap) - 1u;
-        const uint2* gtab = A.dpool + e.offset;
-        if (lds)
-            for (uint32_t t = threadIdx.x; t <= tmask; t += nthr) stage[t] = gtab[t];
-        __syncthreads();
-        const uint2* tab = lds ? stage : gtab;
-        for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
-            if (*(volatile uint32_t*)T.over) break;
-            uint2 sv[4];
-            uint32_t w[4], sl[4];
-            uint2 kv[4];
-            bool live[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t idx = q + u * nthr;
-                sv[u] = idx < q1 ? A.S[idx] : make_uint2(0u, 0u);
-                live[u] = idx < q1 && (level == 0 || pass_of(sv[u].x, A.w_seed, level) == pass);
-                sl[u] = slot_hash(sv[u].y, A.slot_seed) & tmask;
-                kv[u] = live[u] && sv[u].y != EMPTY_KEY ? tab[sl[u]] : make_uint2(EMPTY_KEY, 0u);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (!live[u]) { w[u] = 0; continue; }
-                if (sv[u].y == EMPTY_KEY) { w[u] = e.special; continue; }
-                w[u] = probe_from(tab, tmask, sv[u].y, kv[u], sl[u], 0u);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (w[u] == 0) continue;
-                const uint32_t b = sv[u].x;
-                if (b == EMPTY_KEY) { atomicAdd(T.special, (unsigned long long)w[u]); continue; }
-                uint32_t s = slot_hash(b, A.w_seed) & mask;
-                for (uint32_t step = 0;; ++step) {
-                    uint32_t cur = T.keys[s];
-                    if (cur == b) { atomicAdd(&T.vals[s], (unsigned long long)w[u]); break; }
-                    if (cur == EMPTY_KEY || step >= CELL_CAP) {
-                        if (*(volatile uint32_t*)T.over || step >= CELL_CAP) { *T.over = 1; break; }
-                        uint32_t old = atomicCAS(&T.keys[s], EMPTY_KEY, b);
-                        if (old == EMPTY_KEY || old == b) {
-                            if (old == EMPTY_KEY && atomicAdd(T.distinct, 1u) + 1 >= CELL_LIMIT) *T.over = 1;
-                            atomicAdd(&T.vals[s], (unsigned long long)w[u]);
-                            break;
-                        }
-                    }
-                    s = (s + 1u) & mask;
-                }
-            }
-        }
-    }
-}
-
 __device__ void linear_cell_run(const LinearCellArgs& A, uint32_t i) {
     __shared__ uint32_t wkeys[CELL_CAP];
     __shared__ unsigned long long wvals[CELL_CAP];
@@ -412,8 +341,8 @@ k_linear_cell_batch(LinearBatchArgs B) {
 // region sized for every S tuple of the bucket, cleared, into which each
 // pass inserts its keys (every key belongs to one pass, so a claimed slot's
 // W is stored once).
-template <bool STAGED>
-__device__ __forceinline__ void wbuild_run(const WBuildArgs& A) {
+__global__ void __launch_bounds__(CELL_THREADS)
+k_wbuild(WBuildArgs A) {
     __shared__ uint32_t wkeys[CELL_CAP];
     __shared__ unsigned long long wvals[CELL_CAP];
     __shared__ unsigned long long w_special, s_special_tot, s_base;
@@ -422,8 +351,7 @@ __device__ __forceinline__ void wbuild_run(const WBuildArgs& A) {
     __shared__ int s_sp;
     const WTable T{wkeys, wvals, &w_special, &s_distinct, &s_over};
     const uint32_t i = blockIdx.x;
-    const uint32_t sub = STAGED ? (1u << A.c_bits) : 1u;     // S sub-buckets per b-bucket
-    const uint32_t s0 = A.sstarts[i * sub], s1 = A.sstarts[(i + 1) * sub];
+    const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
     const int nthr = blockDim.x;
     if (s0 == s1) {                       // an empty table: the pool's first slots
         if (threadIdx.x == 0) {
@@ -447,13 +375,8 @@ __device__ __forceinline__ void wbuild_run(const WBuildArgs& A) {
         __syncthreads();
         if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; s_sp = sp - 1; }
         __syncthreads();
-        if constexpr (STAGED) {
-            __shared__ uint2 stage[WSTAGE_SLOTS];
-            w_accumulate_staged(A, i, level, pass, T, stage);
-        } else {
-            w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
-                         level, pass, T);
-        }
+        w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
+                     level, pass, T);
         __syncthreads();
         if (s_over) {
             if (threadIdx.x == 0) {
@@ -551,12 +474,6 @@ __device__ __forceinline__ void wbuild_run(const WBuildArgs& A) {
         A.wdir[i] = e;
     }
 }
-
-__global__ void __launch_bounds__(CELL_THREADS)
-k_wbuild(WBuildArgs A) { wbuild_run<false>(A); }
-
-__global__ void __launch_bounds__(CELL_THREADS)
-k_wbuild_staged(WBuildArgs A) { wbuild_run<true>(A); }
 
 // The rest of a W-table probe whose first slot `s` has been read as `v`
 // (scalar arguments, so that four probes in flight stay in registers).
@@ -730,6 +647,103 @@ k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uin
 
 __global__ void k_check_size(const unsigned long long* got, unsigned long long want, uint32_t* err) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *got != want) atomicExch(err, 1u);
+}
+
+// ------------------------------------------------ S-largest linear join
+// Block (i, j, piece): T_j's multiplicities and R_i's B keys in LDS (each
+// when it fits, else probed where it lies), the piece of S_ij streamed:
+// w = mult_Tj(c); if b is one of R_i's keys its LDS sum grows by w.  At
+// the end every nonzero sum is added to R_i's table once.
+__global__ void __launch_bounds__(SL_THREADS)
+k_sl_cell(SlCellArgs A) {
+    __shared__ uint2 ttab[1u << SL_T_LOG2];
+    __shared__ uint32_t rkeys[1u << SL_R_LOG2];
+    __shared__ unsigned long long racc[1u << SL_R_LOG2];
+    // 80 KB in all: two workgroups share a compute unit's LDS
+    const uint32_t LT = 1u << A.t_bits;
+    const uint32_t cell = blockIdx.x / A.pieces, piece = blockIdx.x % A.pieces;
+    const uint32_t i = cell >> A.t_bits, j = cell & (LT - 1u);
+    const uint32_t c0 = A.sstarts[cell], c1 = A.sstarts[cell + 1];
+    const uint32_t len = c1 - c0;
+    const uint32_t q0 = c0 + (uint32_t)((uint64_t)len * piece / A.pieces);
+    const uint32_t q1 = c0 + (uint32_t)((uint64_t)len * (piece + 1) / A.pieces);
+    if (q0 == q1) return;                                  // uniform over the block
+    const int nthr = blockDim.x;
+    const DirEntry te = A.tdir[j], re = A.rdir[i];
+    const uint32_t tmask = (1u << te.log2cap) - 1u, rmask = (1u << re.log2cap) - 1u;
+    const bool tl = te.log2cap <= SL_T_LOG2, rl = re.log2cap <= SL_R_LOG2;
+    const uint2* tg = A.tpool + te.offset;
+    const uint2* rg = A.rpool + re.offset;
+    unsigned long long* wv = A.wval + re.offset;
+    if (tl) for (uint32_t t = threadIdx.x; t <= tmask; t += nthr) ttab[t] = tg[t];
+    if (rl) for (uint32_t t = threadIdx.x; t <= rmask; t += nthr) { rkeys[t] = rg[t].x; racc[t] = 0; }
+    __syncthreads();
+    const uint2* tab = tl ? ttab : tg;
+    for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
+        uint2 sv[4], kv[4];
+        uint32_t sl[4], w[4];
+        bool live[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t idx = q + u * nthr;
+            live[u] = idx < q1;
+            sv[u] = live[u] ? A.S[idx] : make_uint2(0u, 0u);
+            sl[u] = slot_hash(sv[u].y, A.slot_seed) & tmask;
+            kv[u] = live[u] && sv[u].y != EMPTY_KEY ? tab[sl[u]] : make_uint2(EMPTY_KEY, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!live[u]) { w[u] = 0; continue; }
+            if (sv[u].y == EMPTY_KEY) { w[u] = te.special; continue; }
+            w[u] = probe_from(tab, tmask, sv[u].y, kv[u], sl[u], 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (w[u] == 0) continue;
+            const uint32_t b = sv[u].x;
+            if (b == EMPTY_KEY) {
+                // b = 0xFFFFFFFF, kept beside the table (rare: a global add)
+                if (re.special) atomicAdd(&A.wspecial[i], (unsigned long long)w[u]);
+                continue;
+            }
+            // b among R_i's keys: its slot (linear probing from the W hash)
+            uint32_t s = slot_hash(b, A.w_seed) & rmask;
+            while (true) {
+                const uint32_t k = rl ? rkeys[s] : rg[s].x;
+                if (k == b) {
+                    if (rl) atomicAdd(&racc[s], (unsigned long long)w[u]);
+                    else atomicAdd(&wv[s], (unsigned long long)w[u]);
+                    break;
+                }
+                if (k == EMPTY_KEY) break;                 // not in R_i: joins nothing
+                s = (s + 1u) & rmask;
+            }
+        }
+    }
+    __syncthreads();
+    if (rl)
+        for (uint32_t t = threadIdx.x; t <= rmask; t += nthr)
+            if (racc[t]) atomicAdd(&wv[t], racc[t]);
+}
+
+// R_i's table with its sums as the W table of bucket i (same slots).
+__global__ void k_sl_wtables(const DirEntry* rdir, const uint2* rpool, const unsigned long long* wval,
+                             const unsigned long long* wspecial, WDirEntry* wdir, WSlot* wpool) {
+    const uint32_t i = blockIdx.x;
+    const DirEntry e = rdir[i];
+    const uint32_t cap = 1u << e.log2cap;
+    for (uint32_t t = threadIdx.x; t < cap; t += blockDim.x) {
+        WSlot v;
+        v.key = rpool[e.offset + t].x;
+        v.pad = 0;
+        v.w = wval[e.offset + t];
+        wpool[e.offset + t] = v;
+    }
+    if (threadIdx.x == 0) {
+        WDirEntry d;
+        d.offset = e.offset; d.special = wspecial[i]; d.log2cap = e.log2cap; d.pad = 0;
+        wdir[i] = d;
+    }
 }
 
 __global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err) {

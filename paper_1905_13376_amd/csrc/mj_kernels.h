@@ -211,18 +211,46 @@ struct WBuildArgs {
     unsigned long long* wcursor;
     unsigned long long wcap;
     uint32_t* err;               // set to 1 if the pool is exhausted
-    // k_wbuild_staged: S is partitioned by (bucket of b, bucket of c) with
-    // 2^c_bits c-buckets per b-bucket, sstarts has nb * 2^c_bits + 1
-    // entries, and each c-bucket's multiplicity table is staged in LDS
-    // before its sub-bucket of S is streamed past it
 };
 __global__ void k_wbuild(WBuildArgs A);
-// the S-largest form (Sec. 4, the paragraph after Algorithm 1): per
-// b-bucket i of R, the c-buckets j of T one after another, each staged in
-// LDS (when its table has at most WSTAGE_SLOTS slots) while S_ij streams past
-constexpr uint32_t WSTAGE_LOG2 = 13;
-constexpr uint32_t WSTAGE_SLOTS = 1u << WSTAGE_LOG2;
-__global__ void k_wbuild_staged(WBuildArgs A);
+
+// ------------------------------------------------ S-largest linear join
+// Sec. 4, the paragraph after Algorithm 1: R split into L_R parts by the
+// bucket of B, T into L_T parts by the bucket of C, S into the L_R x L_T
+// pairs.  R_i's distinct B values form a table (the multiplicity tables of
+// R's B column, slots hashed with the W seed) with a u64 sum beside every
+// slot; a workgroup per (i, j, piece of S_ij) copies T_j's multiplicities
+// and R_i's keys into LDS, streams its piece of S_ij, sums w = mult_Tj(c)
+// per B value of R_i in LDS (B values absent from R_i are skipped) and adds
+// its sums to the table's once.
+#ifndef MJ_SL_LOG2
+#define MJ_SL_LOG2 12
+#endif
+#ifndef MJ_SL_THREADS
+#define MJ_SL_THREADS 1024
+#endif
+constexpr uint32_t SL_T_LOG2 = MJ_SL_LOG2;     // T_j tables of at most 2^SL_T_LOG2 slots staged
+constexpr uint32_t SL_R_LOG2 = MJ_SL_LOG2;     // R_i key tables of at most 2^SL_R_LOG2 slots staged
+constexpr int SL_THREADS = MJ_SL_THREADS;
+struct SlCellArgs {
+    const uint2* S;              // S partitioned by (bucket of b, bucket of c)
+    const uint32_t* sstarts;     // [L_R * L_T + 1]
+    uint32_t r_bits, t_bits;     // log2 L_R, log2 L_T
+    uint32_t pieces;             // workgroups per (i, j)
+    const DirEntry* rdir;        // R's B tables (keys; slots hashed with w_seed)
+    const uint2* rpool;
+    uint32_t w_seed;
+    unsigned long long* wval;    // sums beside the slots of rpool
+    unsigned long long* wspecial;// [L_R] sum for b = 0xFFFFFFFF
+    const DirEntry* tdir;        // T's C tables
+    const uint2* tpool;
+    uint32_t slot_seed;
+};
+__global__ void k_sl_cell(SlCellArgs A);
+// R's B tables with their sums, rewritten as W tables (the format the
+// per-A counts read): one workgroup per part of R
+__global__ void k_sl_wtables(const DirEntry* rdir, const uint2* rpool, const unsigned long long* wval,
+                             const unsigned long long* wspecial, WDirEntry* wdir, WSlot* wpool);
 
 static_assert(CELL_CAP % CELL_THREADS == 0, "rehash takes CELL_CAP / CELL_THREADS slots per thread");
 constexpr int COUNT_THREADS = 512;
@@ -797,7 +825,10 @@ __global__ void k_orient_finish(OrientArgs A, uint64_t expect);
 __global__ void k_sym_check(const unsigned long long* K1, const unsigned long long* K2, uint64_t n, uint32_t* bad);
 
 // ------------------------------------------------------------ learned planner
-constexpr int MLP_IN = 100, MLP_H = 64, MLP_OUT = 7;
+// outputs: 2 cardinalities, MLP_NPLAN plan logits (in mj_algo order:
+// three-way, cascade, star, star cascade, oriented, S-largest), 3 share logits
+constexpr int MLP_NPLAN = 6, MLP_PLAN0 = 2, MLP_SHARE0 = MLP_PLAN0 + MLP_NPLAN;
+constexpr int MLP_IN = 100, MLP_H = 64, MLP_OUT = MLP_SHARE0 + 3;
 constexpr int MLP_OFF_W1 = 0;
 constexpr int MLP_OFF_B1 = MLP_OFF_W1 + MLP_H * MLP_IN;
 constexpr int MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;

@@ -16,10 +16,16 @@ struct DeviceModel {
 };
 
 // star plans: R's distinct B values must fit one workgroup's LDS array
-// (the kernels' STAR_GROUPS), and the star cascade's intermediate must fit
+// (the kernels' STAR_GROUPS), T's table one workgroup's LDS stage (T's
+// one-bucket table is also built by a single workgroup: at 2^22 tuples
+// that build alone took about 20 ms), and the star cascade's intermediate
 // one chunk of the workspace
 constexpr uint64_t STAR_PLAN_MAX_R = 4096;
+constexpr uint64_t STAR_PLAN_MAX_T = 4096;
 constexpr uint64_t STAR_PLAN_MAX_I = uint64_t(1) << 28;
+inline bool star_plan_fits(const mj_plan_t& p) {
+    return p.n_r <= STAR_PLAN_MAX_R && p.n_t <= STAR_PLAN_MAX_T;
+}
 
 // the degree-oriented cyclic join pays for its orientation pass (about
 // 0.4 ms of extra launches) when the relation is large and its wedges dense:
@@ -49,6 +55,9 @@ double model_linear_3way_ms(const DeviceModel& m, double R, double S, double T);
 double model_linear_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
 double model_star_ms(const DeviceModel& m, double R, double S, double T);
 double model_star_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
+double model_slarge_ms(const DeviceModel& m, double R, double S, double T, uint32_t lr, uint32_t lt);
+bool slarge_buckets(const DeviceModel& m, uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t& lr,
+                    uint32_t& lt, double* ms);
 double model_cyclic_ms(const DeviceModel& m, double R, double S, double T, double I, double share);
 double model_cyclic_cascade_ms(const DeviceModel& m, double R, double S, double T, double I);
 

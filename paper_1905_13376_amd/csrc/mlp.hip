@@ -77,23 +77,26 @@ __global__ void k_mlp_loss(MlpLossArgs A) {
         l += d * d;
         g[k] = 2.f * d * invB;
     }
-    {   // plan head: softmax cross entropy over 2 logits
-        const float m = fmaxf(y[2], y[3]);
-        const float e2 = expf(y[2] - m), e3 = expf(y[3] - m), s = e2 + e3;
+    {   // plan head: softmax cross entropy over the MLP_NPLAN plan logits
+        const float* z = y + MLP_PLAN0;
+        float m = z[0];
+        for (int k = 1; k < MLP_NPLAN; ++k) m = fmaxf(m, z[k]);
+        float e[MLP_NPLAN], s = 0.f;
+        for (int k = 0; k < MLP_NPLAN; ++k) { e[k] = expf(z[k] - m); s += e[k]; }
         const int c = A.plan_label[b];
-        l += -((c == 0 ? y[2] : y[3]) - m - logf(s));
-        g[2] = (e2 / s - (c == 0 ? 1.f : 0.f)) * invB;
-        g[3] = (e3 / s - (c == 1 ? 1.f : 0.f)) * invB;
+        l += -(z[c] - m - logf(s));
+        for (int k = 0; k < MLP_NPLAN; ++k) g[MLP_PLAN0 + k] = (e[k] / s - (k == c ? 1.f : 0.f)) * invB;
     }
     const int sc = A.share_label[b];
     if (sc >= 0) {
-        const float m = fmaxf(y[4], fmaxf(y[5], y[6]));
-        const float e[3] = {expf(y[4] - m), expf(y[5] - m), expf(y[6] - m)};
+        const float* z = y + MLP_SHARE0;
+        const float m = fmaxf(z[0], fmaxf(z[1], z[2]));
+        const float e[3] = {expf(z[0] - m), expf(z[1] - m), expf(z[2] - m)};
         const float s = e[0] + e[1] + e[2];
-        l += -(y[4 + sc] - m - logf(s));
-        for (int k = 0; k < 3; ++k) g[4 + k] = (e[k] / s - (k == sc ? 1.f : 0.f)) * invB;
+        l += -(z[sc] - m - logf(s));
+        for (int k = 0; k < 3; ++k) g[MLP_SHARE0 + k] = (e[k] / s - (k == sc ? 1.f : 0.f)) * invB;
     } else {
-        g[4] = g[5] = g[6] = 0.f;
+        g[MLP_SHARE0] = g[MLP_SHARE0 + 1] = g[MLP_SHARE0 + 2] = 0.f;
     }
     atomicAdd(A.loss, l * invB);
 }

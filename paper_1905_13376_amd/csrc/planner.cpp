@@ -99,15 +99,49 @@ double model_star_cascade_ms(const DeviceModel& m, double R, double S, double T,
     return t * 1e3;
 }
 
-// S-largest form of the linear join: the partitions of the three-way join
-// (S by two digits), T's tables staged into LDS once per part of R (L_R
-// parts: |R||T|/M of Sec. 4.2 with M the part of R one workgroup holds),
-// one LDS probe per S tuple, one table probe per R tuple.
-double model_slarge_ms(const DeviceModel& m, double R, double S, double T, double L_R) {
-    const double bytes = 24.0 * (R + S) + 16.0 * T + 16.0 * (R + S) + 16.0 * L_R * T;
-    const double t = bytes / (m.stream_gbs * 1e9) + (S * m.lds_ps + R * m.probe_ps) * 1e-12 +
-                     20.0 * m.launch_us * 1e-6;
+// S-largest form of the linear join (Sec. 4, after Algorithm 1).  Per S
+// tuple: the partition by the pair (bucket of B, bucket of C) and one pass
+// of the cell kernel (an LDS probe of T_j's table, an LDS probe of R_i's B
+// values, an LDS add).  Both were measured on MI355X over star schemas with
+// 2^24..2^26 S tuples and R, T of 2^12..2^22 tuples:
+//   partition, per S tuple: 7.5 ps with at most 2^10 cells, 12.8 ps with
+//     2^11, 16.8 ps with 2^12 (more buckets than the scatter's LDS stage
+//     holds at full speed);
+//   cell pass, per S tuple: 5.5 ps while T_j (about |T| / L_T tuples) fits
+//     the 4096-slot LDS stage, 4 ps more per doubling of T_j beyond 2048
+//     tuples (its probes go to L2 and beyond).
+// R's parts hold about 1024 B values each (the table's 4096 slots staged
+// in LDS stay at load 1/4 or less under the hash's imbalance); R and T are
+// read, tabled and partitioned at stream rate, and each R tuple probes the
+// sums once.
+double slarge_part_ps(uint32_t bits) { return bits <= 10 ? 7.5 : bits == 11 ? 12.8 : 16.8; }
+double slarge_cell_ps(double t_part) {
+    return t_part <= 2048.0 ? 5.5 : 5.5 + 4.0 * std::log2(t_part / 2048.0);
+}
+double model_slarge_ms(const DeviceModel& m, double R, double S, double T, uint32_t lr, uint32_t lt) {
+    const double bytes = 40.0 * R + 16.0 * T;
+    const double t = bytes / (m.stream_gbs * 1e9) +
+                     S * (slarge_part_ps(lr + lt) + slarge_cell_ps(T / double(1u << lt))) * 1e-12 +
+                     R * m.atomic_ps * 1e-12 + 20.0 * m.launch_us * 1e-6;
     return t * 1e3;
+}
+
+// Bucket counts of the S-largest plan: L_R = 2^lr parts of R of about 1024
+// tuples, and the L_T = 2^lt (lr + lt <= 12) the model above prefers.
+// Returns false when R needs more than 2^12 parts.
+constexpr uint32_t SLARGE_MAX_BITS = 12;   // cells: one partition pass's bucket limit
+bool slarge_buckets(const DeviceModel& m, uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t& lr,
+                    uint32_t& lt, double* ms) {
+    lr = ceil_log2((n_r + 1023) / 1024);
+    lt = 0;
+    if (lr > SLARGE_MAX_BITS) return false;
+    double best = INFINITY;
+    for (uint32_t k = 0; lr + k <= SLARGE_MAX_BITS; ++k) {
+        const double t = model_slarge_ms(m, (double)n_r, (double)n_s, (double)n_t, lr, k);
+        if (t < best) { best = t; lt = k; }
+    }
+    if (ms) *ms = best;
+    return true;
 }
 
 // Cyclic join: three sorts (8 passes of 24 B/tuple), the run indexes, and
@@ -143,8 +177,8 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
         p.log2_nc = std::min<uint32_t>(10, ceil_log2((p.n_t + 32767) / 32768));
         p.est_ms_3way = model_linear_3way_ms(m, R, S, T);
         p.est_ms_cascade = model_linear_cascade_ms(m, R, S, T, I);
-        p.est_ms_star = p.n_r <= STAR_PLAN_MAX_R ? model_star_ms(m, R, S, T) : 0.0;
-        p.est_ms_star_cascade = p.n_r <= STAR_PLAN_MAX_R && p.join2_size <= STAR_PLAN_MAX_I
+        p.est_ms_star = star_plan_fits(p) ? model_star_ms(m, R, S, T) : 0.0;
+        p.est_ms_star_cascade = star_plan_fits(p) && p.join2_size <= STAR_PLAN_MAX_I
                                     ? model_star_cascade_ms(m, R, S, T, I) : 0.0;
     } else {
         // share on A (the least number of slices of a hub list): the
@@ -170,16 +204,15 @@ int analytic_plan(int kind, mj_plan_t& p, int num_cu, const DeviceModel& m) {
             p.algo = MJ_ALGO_STAR_CASCADE;
             best = p.est_ms_star_cascade;
         }
-        // S the largest relation and R, T too large for the star plans
-        // (Sec. 4, after Algorithm 1): R in parts of about 2048 tuples (the
-        // per-B sums of one workgroup), T in parts of about 2048 tuples (a
-        // multiplicity table of at most 8192 slots in LDS).  Hashed tables
-        // only: with dense keys the direct-indexed path is cheaper still.
-        const uint32_t lr = ceil_log2((p.n_r + 2047) / 2048), lt = ceil_log2((p.n_t + 2047) / 2048);
-        const bool eligible = !(p.flags & MJ_PLAN_DENSE_KEYS) && p.n_r > STAR_PLAN_MAX_R &&
-                              p.n_s >= 4 * std::max(p.n_r, p.n_t) && lr + lt <= 12 && p.a_domain > 0 &&
-                              p.a_domain <= (1u << 24);
-        p.est_ms_slarge = eligible ? model_slarge_ms(m, R, S, T, double(1u << lr)) : 0.0;
+        // S the largest relation and R or T too large for the star plans
+        // (Sec. 4, after Algorithm 1).  Hashed tables only: with dense keys
+        // the direct-indexed path is cheaper still.
+        uint32_t lr = 0, lt = 0;
+        double t_sl = 0.0;
+        const bool eligible = !(p.flags & MJ_PLAN_DENSE_KEYS) && !star_plan_fits(p) &&
+                              p.n_s >= 4 * std::max(p.n_r, p.n_t) && p.a_domain > 0 &&
+                              p.a_domain <= (1u << 24) && slarge_buckets(m, p.n_r, p.n_s, p.n_t, lr, lt, &t_sl);
+        p.est_ms_slarge = eligible ? t_sl : 0.0;
         if (eligible && p.est_ms_slarge < best) {
             p.algo = MJ_ALGO_SLARGE;
             p.log2_nb = lr;
@@ -224,4 +257,17 @@ extern "C" int mj_cost_model(int which, const double* args, int nargs, double* o
         default:
             return MJ_ERR_INVALID_ARG;
     }
+}
+
+extern "C" int mj_slarge_buckets(uint64_t n_r, uint64_t n_s, uint64_t n_t, uint32_t* log2_nb,
+                                 uint32_t* log2_nc, double* est_ms) {
+    using namespace mj;
+    if (!log2_nb || !log2_nc) return MJ_ERR_INVALID_ARG;
+    uint32_t lr = 0, lt = 0;
+    double ms = 0.0;
+    if (!slarge_buckets(default_model(), n_r, n_s, n_t, lr, lt, &ms)) return MJ_ERR_INVALID_ARG;
+    *log2_nb = lr;
+    *log2_nc = lt;
+    if (est_ms) *est_ms = ms;
+    return MJ_OK;
 }

@@ -1,6 +1,7 @@
 """Learned planner: a small network over degree sketches that predicts the
-intermediate and output cardinalities of a join and chooses between the
-three-way join and the cascade (and the share on A of a cyclic join).
+intermediate and output cardinalities of a join and chooses its plan among
+the three-way join, the cascade, the star plans, the degree-oriented cyclic
+join and the S-largest form (and the share on A of a cyclic join).
 
 Everything numeric runs in libmj's kernels (k_deg_hist / k_sketch_features
 for the sketch, k_mlp_fwd / k_mlp_loss / k_mlp_bwd / k_mlp_adamw for the
@@ -8,8 +9,9 @@ network); this module holds the parameter buffer, the training loop's
 control flow, and the data pipeline that generates join instances, times
 their candidate plans on the device and labels them.
 
-    python -m paper_1905_13376_amd.learned --n-train 12000 --n-test 1000 \\
-        --out paper_1905_13376_amd/planner_weights.npy --report planner_eval.json
+    python -m paper_1905_13376_amd.learned label --count N --seed S --lo 3 --hi 5 --out rows.npz
+    python -m paper_1905_13376_amd.learned train --train rows.npz ... --test heldout.npz \\
+        --out paper_1905_13376_amd/planner_weights.npy --report paper_1905_13376_amd/planner_eval.json
 """
 from __future__ import annotations
 
@@ -25,7 +27,7 @@ import torch
 
 from . import _lib as L
 
-IN, H, OUT = 100, 64, 7
+IN, H, OUT = 100, 64, 11
 SHAPES = [("W1", (H, IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (OUT, H)), ("b3", (OUT,))]
 P = sum(int(np.prod(s)) for _, s in SHAPES)
 SHARES = (0, 2, 4)                     # log2 of the shares 1, 4, 16 (the share head's classes)
@@ -117,35 +119,60 @@ def use_shipped(ctx, path=WEIGHTS):
 
 
 # ---------------------------------------------------------------- data
+# plan classes of the network's plan head, in mj_algo order
+PLANS = ("3way", "cascade", "star", "star_cascade", "oriented", "slarge")
+COLS = PLANS + ("share0", "share2", "share4")      # measured-time columns
+
+
 def planner_instances(count, base_seed, lo_exp=3.0, hi_exp=5.0):
-    """Join instances shaped like the benchmark families, at small sizes:
-    linear joins on uniform pairs of varying selectivity and on power-law
-    friends graphs; cyclic joins on G(n, m), Chung-Lu and R-MAT graphs."""
+    """Join instances shaped like the benchmark families: linear joins on
+    uniform pairs of varying selectivity, on power-law friends graphs, on
+    star schemas (small dimension relations) and on S-largest schemas
+    (dimension relations beyond the star plans); cyclic joins on G(n, m),
+    Chung-Lu and R-MAT graphs.  Each instance holds R, S, T (one relation
+    for all three unless a schema) and a (the A domain; 0 for cyclic)."""
     from workloads import generators as G
     out = []
     for k in range(count):
         seed = base_seed + k
         g = np.random.default_rng(seed)
         m = int(round(10 ** g.uniform(lo_exp, hi_exp)))
-        fam = int(g.integers(0, 6))
+        fam = int(g.integers(0, 8))
         if fam == 0:       # uniform, mean degree 1..64 (selectivity varies widely)
             n = max(16, int(m / (2 ** g.uniform(0, 6))))
-            out.append(dict(kind="linear", F=G.uniform_pairs(m, n, seed, dtype=np.int32), a=n))
+            F = G.uniform_pairs(m, n, seed, dtype=np.int32)
+            out.append(dict(kind="linear", R=F, S=F, T=F, a=n))
         elif fam == 1:     # uniform over a large domain: tiny intermediate
             n = int(m * 2 ** g.uniform(2, 8))
-            out.append(dict(kind="linear", F=G.uniform_pairs(m, n, seed, dtype=np.int32), a=n))
+            F = G.uniform_pairs(m, n, seed, dtype=np.int32)
+            out.append(dict(kind="linear", R=F, S=F, T=F, a=n))
         elif fam == 2:     # power-law friends graph, mean degree 16
             n = max(64, m // 16)
-            out.append(dict(kind="linear", F=G.powerlaw_friends(n, m, seed, cap=min(4096, n - 1)), a=n))
+            F = G.powerlaw_friends(n, m, seed, cap=min(4096, n - 1))
+            out.append(dict(kind="linear", R=F, S=F, T=F, a=n))
         elif fam == 3:
             n = max(64, m // 16)
-            out.append(dict(kind="triangle", F=G.gnm_symmetric(n, m, seed), a=0))
+            F = G.gnm_symmetric(n, m, seed)
+            out.append(dict(kind="triangle", R=F, S=F, T=F, a=0))
         elif fam == 4:
             n = max(64, m // 16)
-            out.append(dict(kind="triangle", F=G.chung_lu_symmetric(n, m, seed, cap=min(4096, n - 1)), a=0))
-        else:
+            F = G.chung_lu_symmetric(n, m, seed, cap=min(4096, n - 1))
+            out.append(dict(kind="triangle", R=F, S=F, T=F, a=0))
+        elif fam == 5:
             scale = max(6, int(round(math.log2(max(64, m // 16)))))
-            out.append(dict(kind="triangle", F=G.rmat_symmetric(scale, min(m, (1 << scale) * 16), seed), a=0))
+            F = G.rmat_symmetric(scale, min(m, (1 << scale) * 16), seed)
+            out.append(dict(kind="triangle", R=F, S=F, T=F, a=0))
+        elif fam == 6:     # star schema: dimension relations of 64..4096 tuples
+            kr, kt = (int(2 ** g.uniform(6, 12)) for _ in range(2))
+            a = int(2 ** g.uniform(4, 12))
+            R, S, T = G.star_schema(n_fact=m, k_r=kr, k_t=kt, a_domain=a, seed=seed)
+            out.append(dict(kind="linear", R=R, S=S, T=T, a=a))
+        else:              # S-largest schema: dimension relations of 2^12..m/4 tuples
+            hi = max(12.5, math.log2(max(m // 4, 1 << 12)))
+            kr, kt = (int(2 ** g.uniform(12, hi)) for _ in range(2))
+            a = int(2 ** g.uniform(6, 14))
+            R, S, T = G.star_schema(n_fact=m, k_r=kr, k_t=kt, a_domain=a, seed=seed)
+            out.append(dict(kind="linear", R=R, S=S, T=T, a=a))
     return out
 
 
@@ -162,71 +189,109 @@ def _time(fn, reps=2):
 
 
 def label_instance(ctx, inst):
-    """Features, exact cardinalities and measured times of the candidate
-    plans of one instance."""
+    """Features, exact cardinalities and measured times of every plan the
+    instance is eligible for (infinity for the others); the plan label is
+    the fastest measured plan (mj_algo value), the share label the fastest
+    share of the cyclic three-way join.  Every plan's count is checked
+    against the three-way join's."""
     kind = L.LINEAR if inst["kind"] == "linear" else L.TRIANGLE
-    Fd = torch.from_numpy(np.ascontiguousarray(inst["F"]).view(np.int32)).to("cuda")
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).to("cuda")
+    same = inst["R"] is inst["S"] and inst["S"] is inst["T"]
+    Rd = dev(inst["R"])
+    Sd, Td = (Rd, Rd) if same else (dev(inst["S"]), dev(inst["T"]))
     a = inst["a"]
-    feat = ctx.sketch(kind, Fd, Fd, Fd)
+    feat = ctx.sketch(kind, Rd, Sd, Td)
     t0 = time.perf_counter()
-    plan = ctx.plan(kind, Fd, Fd, Fd, a)
+    plan = ctx.plan(kind, Rd, Sd, Td, a)
     plan_ms = (time.perf_counter() - t0) * 1e3
-    ws = ctx.workspace(plan.workspace_bytes, Fd.device)
     n_out = max(a, 1) if kind == L.LINEAR else 1
     out = torch.empty(n_out, dtype=torch.int64, device="cuda")
-    times = {}
+    times = {c: float("inf") for c in COLS}
+    got = {}
+
+    def run(name, p, reps=2):
+        ws = ctx.workspace(p.workspace_bytes, Rd.device)
+        if kind == L.LINEAR:
+            if p.algo in (L.ALGO_CASCADE, L.ALGO_STAR_CASCADE):
+                fn = lambda: ctx.cascade2_count(L.LINEAR, Rd, Sd, Td, a, plan=p, out=out, workspace=ws)
+            else:
+                fn = lambda: ctx.linear3_count(Rd, Sd, Td, a, plan=p, out=out, workspace=ws)
+        elif p.algo == L.ALGO_CASCADE:
+            fn = lambda: ctx.cascade2_count(L.TRIANGLE, Rd, Sd, Td, plan=p, out=out, workspace=ws)
+        else:
+            fn = lambda: ctx.triangle3_count(Rd, Sd, Td, plan=p, out=out, workspace=ws)
+        times[name] = _time(fn, reps)
+        got[name] = int(L.as_u64(out[:max(a, 1)] if kind == L.LINEAR else out).sum(dtype=np.uint64))
+
+    def variant(algo, **fields):
+        q = plan.copy()
+        q.algo = algo
+        for k, v in fields.items():
+            setattr(q, k, v)
+        return q
+
     if kind == L.LINEAR:
-        p3 = plan.copy(); p3.algo = L.ALGO_3WAY
-        times["3way"] = _time(lambda: ctx.linear3_count(Fd, Fd, Fd, a, plan=p3, out=out, workspace=ws))
-        res = int(L.as_u64(out[:a]).sum(dtype=np.uint64))
-        pc = plan.copy(); pc.algo = L.ALGO_CASCADE
-        times["cascade"] = _time(lambda: ctx.cascade2_count(L.LINEAR, Fd, Fd, Fd, a, plan=pc, out=out, workspace=ws))
-        exact = int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
-        # the star plans specialise the two when R is small (planner rule)
+        run("3way", variant(L.ALGO_3WAY))
+        if plan.join2_size <= CASCADE_CAP:
+            run("cascade", variant(L.ALGO_CASCADE))
         if plan.est_ms_star > 0.0:
-            pst = plan.copy(); pst.algo = L.ALGO_STAR
-            times["star"] = _time(lambda: ctx.linear3_count(Fd, Fd, Fd, a, plan=pst, out=out, workspace=ws))
-            exact = exact and int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
+            run("star", variant(L.ALGO_STAR))
         if plan.est_ms_star_cascade > 0.0:
-            psc = plan.copy(); psc.algo = L.ALGO_STAR_CASCADE
-            times["star_cascade"] = _time(lambda: ctx.cascade2_count(L.LINEAR, Fd, Fd, Fd, a, plan=psc, out=out,
-                                                                     workspace=ws))
-            exact = exact and int(L.as_u64(out[:a]).sum(dtype=np.uint64)) == res
+            run("star_cascade", variant(L.ALGO_STAR_CASCADE))
+        if plan.est_ms_slarge > 0.0:
+            lr, lt, _ = L.slarge_buckets(plan.n_r, plan.n_s, plan.n_t)
+            run("slarge", variant(L.ALGO_SLARGE, log2_nb=lr, log2_nc=lt))
+        ref = got["3way"]
     else:
         for k in SHARES:
-            ps = plan.copy(); ps.algo = L.ALGO_3WAY; ps.log2_share = k
-            times[f"share{k}"] = _time(lambda: ctx.triangle3_count(Fd, Fd, Fd, plan=ps, out=out, workspace=ws), 1)
-        res = int(L.as_u64(out)[0])
+            run(f"share{k}", variant(L.ALGO_3WAY, log2_share=k), 1)
+        times["3way"] = min(times[f"share{k}"] for k in SHARES)
+        ref = got["share0"]
         if plan.join2_size <= CASCADE_CAP:
-            pc = plan.copy(); pc.algo = L.ALGO_CASCADE
-            times["cascade"] = _time(lambda: ctx.cascade2_count(L.TRIANGLE, Fd, Fd, Fd, plan=pc, out=out, workspace=ws), 1)
-            exact = int(L.as_u64(out)[0]) == res
-        else:
-            times["cascade"] = float("inf")      # never chosen: the planner caps the intermediate
-            exact = True
-        # one symmetric simple relation: the degree-oriented join (planner rule)
+            run("cascade", variant(L.ALGO_CASCADE), 1)
         if plan.flags & L.PLAN_SYMMETRIC_SIMPLE:
-            po = plan.copy(); po.algo = L.ALGO_ORIENTED
-            times["oriented"] = _time(lambda: ctx.triangle3_count(Fd, Fd, Fd, plan=po, out=out, workspace=ws), 1)
-            exact = exact and int(L.as_u64(out)[0]) == res
-    best3 = min(v for k, v in times.items() if k in ("3way", "star") or k.startswith("share"))
-    bestc = min(v for k, v in times.items() if k in ("cascade", "star_cascade"))
-    return dict(kind=kind, features=feat, join2=plan.join2_size, out=res, times=times,
-                est=dict(star=plan.est_ms_star, star_cascade=plan.est_ms_star_cascade,
-                         three=plan.est_ms_3way, cascade=plan.est_ms_cascade),
-                plan_label=int(bestc < best3),
-                share_label=(int(np.argmin([times[f"share{k}"] for k in SHARES])) if kind == L.TRIANGLE else -1),
-                analytic=dict(algo=plan.algo, share=plan.log2_share), plan_ms=plan_ms,
-                oriented_ok=bool(plan.flags & L.PLAN_SYMMETRIC_SIMPLE),
-                cascade_equals_3way=exact, n=int(Fd.shape[0]))
+            run("oriented", variant(L.ALGO_ORIENTED), 1)
+    exact = all(v == ref for v in got.values())
+    plan_label = int(np.argmin([times[c] for c in PLANS]))
+    share_label = int(np.argmin([times[f"share{k}"] for k in SHARES])) if kind == L.TRIANGLE else -1
+    return dict(kind=kind, features=feat, join2=int(plan.join2_size), out=ref,
+                times=np.array([times[c] for c in COLS], dtype=np.float64),
+                plan_label=plan_label, share_label=share_label,
+                analytic_algo=int(plan.algo), analytic_share=int(plan.log2_share), plan_ms=plan_ms,
+                counts_exact=exact, n=int(Rd.shape[0] + (0 if same else Sd.shape[0] + Td.shape[0])))
 
 
-def stack(rows):
-    X = torch.stack([r["features"] for r in rows]).contiguous()
-    targets = torch.tensor([[math.log2(1 + r["join2"]), math.log2(1 + r["out"])] for r in rows],
-                           dtype=torch.float32, device=X.device)
-    pl = torch.tensor([r["plan_label"] for r in rows], dtype=torch.int32, device=X.device)
-    sl = torch.tensor([r["share_label"] for r in rows], dtype=torch.int32, device=X.device)
+def rows_to_arrays(rows):
+    """Labelled instances as one dict of arrays (the form evaluate() takes)."""
+    return dict(features=torch.stack([r["features"] for r in rows]).cpu().numpy(),
+                join2=np.array([r["join2"] for r in rows], dtype=np.float64),
+                out=np.array([r["out"] for r in rows], dtype=np.float64),
+                times=np.stack([r["times"] for r in rows]),
+                kind=np.array([r["kind"] for r in rows], dtype=np.int32),
+                plan_label=np.array([r["plan_label"] for r in rows], dtype=np.int32),
+                share_label=np.array([r["share_label"] for r in rows], dtype=np.int32),
+                analytic_algo=np.array([r["analytic_algo"] for r in rows], dtype=np.int32),
+                analytic_share=np.array([r["analytic_share"] for r in rows], dtype=np.int32),
+                plan_ms=np.array([r["plan_ms"] for r in rows], dtype=np.float64),
+                counts_exact=np.array([r["counts_exact"] for r in rows], dtype=bool),
+                n=np.array([r["n"] for r in rows], dtype=np.int64))
+
+
+def save_rows(rows, path):
+    np.savez_compressed(path, **rows_to_arrays(rows))
+
+
+def load_rows(paths):
+    parts = [np.load(p, allow_pickle=False) for p in paths]
+    return {k: np.concatenate([q[k] for q in parts]) for k in parts[0].files}
+
+
+def as_tensors(D, device="cuda"):
+    X = torch.from_numpy(np.ascontiguousarray(D["features"], dtype=np.float32)).to(device)
+    targets = torch.from_numpy(np.stack([np.log2(1 + D["join2"]), np.log2(1 + D["out"])], 1)
+                               .astype(np.float32)).to(device)
+    pl = torch.from_numpy(D["plan_label"].astype(np.int32)).to(device)
+    sl = torch.from_numpy(D["share_label"].astype(np.int32)).to(device)
     return X, targets, pl, sl
 
 
@@ -235,101 +300,104 @@ def nearest_share(k):
     return min(SHARES, key=lambda c: (abs(c - k), c))
 
 
-def plan_time(r, algo, share):
-    t = r["times"]
-    if algo == L.ALGO_ORIENTED:
-        return t["oriented"]
-    if algo == L.ALGO_STAR_CASCADE:
-        return t["star_cascade"]
-    if algo == L.ALGO_STAR:
-        return t["star"]
-    if algo == L.ALGO_CASCADE:
-        return t["cascade"]
-    return t["3way"] if r["kind"] == L.LINEAR else t[f"share{share}"]
+def plan_time(times_row, kind, algo, share):
+    """Measured time of a plan (the three-way plan of a cyclic join at the
+    given share)."""
+    if kind == L.TRIANGLE and algo == L.ALGO_3WAY:
+        return times_row[COLS.index(f"share{share}")]
+    return times_row[algo]
 
 
-# mj_plan's rule for the degree-oriented cyclic join (mj_plan_model.h)
-ORIENT_MIN_N, ORIENT_MIN_WEDGES = 32768, 64
-
-
-def specialise(r, algo):
-    """mj_plan's rules: a cyclic join of one large, skewed, symmetric simple
-    relation becomes the degree-oriented join; a three-way (cascade) choice becomes
-    the star three-way join (star cascade) when that plan is eligible and
-    rated faster by the analytic model."""
-    if (r["kind"] == L.TRIANGLE and r.get("oriented_ok") and r["n"] >= ORIENT_MIN_N
-            and r["join2"] >= ORIENT_MIN_WEDGES * r["n"]):
-        return L.ALGO_ORIENTED
-    e = r.get("est")
-    if r["kind"] != L.LINEAR or not e:
-        return algo
-    if algo == L.ALGO_3WAY and 0.0 < e["star"] < e["three"]:
-        return L.ALGO_STAR
-    if algo == L.ALGO_CASCADE and 0.0 < e["star_cascade"] < e["cascade"]:
-        return L.ALGO_STAR_CASCADE
-    return algo
-
-
-def evaluate(planner, rows):
-    """Held-out comparison of the learned plan with the analytic plan, the
+def evaluate(planner, D):
+    """Held-out comparison of the learned plans with the analytic plans, the
     fixed plans and the best measured plan (regret), plus cardinality
-    q-errors."""
-    X, targets, _, _ = stack(rows)
+    q-errors.  The network's plan is its largest logit among the plans the
+    instance was eligible for (measured: finite time)."""
+    X = torch.from_numpy(np.ascontiguousarray(D["features"], dtype=np.float32)).to("cuda")
     Y = planner.predict(X).cpu().numpy()
+    T = D["times"]
     tot = {"learned": 0.0, "analytic": 0.0, "always_3way": 0.0, "always_cascade": 0.0, "best": 0.0}
+    agree = {"learned": 0, "analytic": 0}
     qI, qO = [], []
-    for r, y in zip(rows, Y):
-        algo = specialise(r, L.ALGO_CASCADE if (y[3] > y[2] and r["join2"] <= CASCADE_CAP) else L.ALGO_3WAY)
-        share = SHARES[int(np.argmax(y[4:7]))]
-        tot["learned"] += plan_time(r, algo, share)
-        tot["analytic"] += plan_time(r, r["analytic"]["algo"], nearest_share(r["analytic"]["share"]))
-        tot["always_3way"] += plan_time(r, L.ALGO_3WAY, SHARES[0])
-        tot["always_cascade"] += r["times"]["cascade"]
-        tot["best"] += min(r["times"].values())
-        qI.append(2 ** abs(float(y[0]) - math.log2(1 + r["join2"])))
-        qO.append(2 ** abs(float(y[1]) - math.log2(1 + r["out"])))
+    for i, y in enumerate(Y):
+        kind = int(D["kind"][i])
+        t = T[i]
+        elig = np.isfinite(t[:len(PLANS)])
+        logits = np.where(elig, y[2:2 + len(PLANS)], -np.inf)
+        algo = int(np.argmax(logits))
+        share = SHARES[int(np.argmax(y[2 + len(PLANS):]))]
+        best = float(np.min(t[np.isfinite(t)]))
+        tl = plan_time(t, kind, algo, share)
+        ta = plan_time(t, kind, int(D["analytic_algo"][i]), nearest_share(int(D["analytic_share"][i])))
+        tot["learned"] += tl
+        tot["analytic"] += ta
+        tot["always_3way"] += plan_time(t, kind, L.ALGO_3WAY, SHARES[0])
+        tot["always_cascade"] += t[L.ALGO_CASCADE] if np.isfinite(t[L.ALGO_CASCADE]) else t[L.ALGO_3WAY]
+        tot["best"] += best
+        agree["learned"] += tl <= best
+        agree["analytic"] += ta <= best
+        qI.append(2 ** abs(float(y[0]) - math.log2(1 + D["join2"][i])))
+        qO.append(2 ** abs(float(y[1]) - math.log2(1 + D["out"][i])))
     res = {k: round(v, 3) for k, v in tot.items()}
     res["regret_learned"] = round(tot["learned"] / tot["best"], 4)
     res["regret_analytic"] = round(tot["analytic"] / tot["best"], 4)
+    res["best_plan_chosen_learned"] = int(agree["learned"])
+    res["best_plan_chosen_analytic"] = int(agree["analytic"])
     res["qerror_join2_median"] = round(float(np.median(qI)), 3)
     res["qerror_join2_p95"] = round(float(np.percentile(qI, 95)), 3)
     res["qerror_out_median"] = round(float(np.median(qO)), 3)
     res["qerror_out_p95"] = round(float(np.percentile(qO, 95)), 3)
-    res["instances"] = len(rows)
+    res["instances"] = int(len(Y))
+    res["plan_label_counts"] = {PLANS[k]: int((D["plan_label"] == k).sum()) for k in range(len(PLANS))}
     return res
+
+
+def label(ctx, count, seed, lo_exp, hi_exp, path, log=None):
+    """Label `count` instances (seeds seed..seed+count-1) and save them."""
+    rows = []
+    t0 = time.time()
+    for i, x in enumerate(planner_instances(count, seed, lo_exp, hi_exp)):
+        rows.append(label_instance(ctx, x))
+        if log and (i + 1) % 250 == 0:
+            log(f"{i + 1}/{count} instances labelled ({time.time() - t0:.0f} s)")
+    save_rows(rows, path)
+    return rows
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n-train", type=int, default=12000)
-    ap.add_argument("--n-test", type=int, default=1000)
-    ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--out", default=WEIGHTS)
-    ap.add_argument("--report", default=None)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    la = sub.add_parser("label", help="label instances and save them (npz)")
+    la.add_argument("--count", type=int, required=True)
+    la.add_argument("--seed", type=int, required=True)
+    la.add_argument("--lo", type=float, default=3.0)
+    la.add_argument("--hi", type=float, default=5.0)
+    la.add_argument("--out", required=True)
+    tr = sub.add_parser("train", help="train on labelled sets, evaluate on a held-out set")
+    tr.add_argument("--train", nargs="+", required=True)
+    tr.add_argument("--test", required=True)
+    tr.add_argument("--epochs", type=int, default=60)
+    tr.add_argument("--out", default=WEIGHTS)
+    tr.add_argument("--report", default=None)
     args = ap.parse_args()
 
     def log(m):
         print(f"[learned] {m}", file=sys.stderr, flush=True)
     ctx = L.Context()
-    rows = {}
-    for part, n, seed in (("train", args.n_train, 5_000_000), ("test", args.n_test, 6_000_000)):
-        rows[part] = []
-        t0 = time.time()
-        inst = planner_instances(n, seed)
-        for i, x in enumerate(inst):
-            rows[part].append(label_instance(ctx, x))
-            if (i + 1) % 1000 == 0:
-                log(f"{part}: {i + 1}/{n} instances labelled ({time.time() - t0:.0f} s)")
-    X, targets, pl, sl = stack(rows["train"])
+    if args.cmd == "label":
+        label(ctx, args.count, args.seed, args.lo, args.hi, args.out, log)
+        return
+    D = load_rows(args.train)
+    X, targets, pl, sl = as_tensors(D)
     planner = LearnedPlanner(ctx)
     planner.init_weights(seed=0)
     hist = planner.train(X, targets, pl, sl, epochs=args.epochs, log=log)
     planner.save(args.out)
-    rep = evaluate(planner, rows["test"])
+    rep = evaluate(planner, load_rows([args.test]))
     rep["train_loss_first_last"] = [round(hist[0], 4), round(hist[-1], 4)]
-    rep["train_instances"] = len(rows["train"])
-    rep["cascade_equals_3way_all"] = all(r["cascade_equals_3way"] for part in rows.values() for r in part)
-    rep["train_plan_label_cascade_fraction"] = round(float(pl.float().mean().item()), 4)
+    rep["train_instances"] = int(X.shape[0])
+    rep["train_plan_label_counts"] = {PLANS[k]: int((D["plan_label"] == k).sum()) for k in range(len(PLANS))}
+    rep["counts_exact_all_plans"] = bool(D["counts_exact"].all())
     log(json.dumps(rep))
     if args.report:
         with open(args.report, "w") as f:

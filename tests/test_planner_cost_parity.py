@@ -55,3 +55,19 @@ def test_bad_formula_id_rejected(mj):
     out = ctypes.c_double()
     assert L._lib.mj_cost_model(99, arr, 1, ctypes.byref(out)) == -1
     assert L._lib.mj_cost_model(0, arr, 1, ctypes.byref(out)) == -1   # too few arguments
+
+
+def test_slarge_buckets(mj):
+    """The S-largest plan's bucket counts (host only): parts of R of about
+    1024 tuples, at most 2^12 cells, larger T split further; R beyond 2^12
+    parts of 1024 is refused."""
+    lr, lt, ms = mj.slarge_buckets(1 << 16, 1 << 26, 1 << 16)
+    assert lr == 6 and lr + lt <= 12 and ms > 0
+    lr2, lt2, _ = mj.slarge_buckets(1 << 12, 1 << 26, 1 << 22)
+    assert lr2 == 2 and lt2 > lt and lr2 + lt2 <= 12
+    assert mj.slarge_buckets(1025, 1 << 20, 10)[0] == 1
+    assert mj.slarge_buckets(1, 1 << 20, 1)[:2] == (0, 0)
+    with pytest.raises(mj.MJError):
+        mj.slarge_buckets((1 << 22) + 1, 1 << 26, 1 << 10)
+    # the modelled time grows with S
+    assert mj.slarge_buckets(1 << 16, 1 << 27, 1 << 16)[2] > ms
