@@ -443,6 +443,46 @@ def slarge_path(mj, ctx):
     return res
 
 
+def skew_path(mj, ctx):
+    """Heavy keys (Sec. 1.2's skew): the power-law graph of the benchmark
+    (2^24 edges over 2^20 vertices) with its out-degree cap at 4096, 65536
+    and none (the largest vertex then holds about 1.2 million edges), under
+    the planner's plan (direct-indexed tables) and under hashed tables.  A
+    range or bucket crowded beyond one workgroup's share runs as several."""
+    import numpy as np
+    import torch
+    from workloads import generators as G
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import brute
+    n = 1 << 20
+    res = {}
+    for cap in (4096, 1 << 16, n - 1):
+        log(f"skew: power-law graph, out-degree cap {cap}")
+        F = G.powerlaw_friends(n, 1 << 24, 1234, cap=cap)
+        Fd = torch.from_numpy(F).to("cuda")
+        closed = brute.linear_closed_total(F, F, F)
+        cnt = torch.empty(n, dtype=torch.int64, device="cuda")
+        p = ctx.plan(mj.LINEAR, Fd, Fd, Fd, n)
+        q = p.copy()
+        q.algo = mj.ALGO_3WAY
+        q.flags = (q.flags & ~mj.PLAN_DENSE_KEYS) | mj.PLAN_NO_DENSE
+        q = ctx.plan(mj.LINEAR, Fd, Fd, Fd, n, planner="fixed", fixed=q)
+        row = {"max_out_degree": int(np.bincount(F[:, 0].astype(np.int64), minlength=n).max())}
+        for name, plan in (("direct_indexed", p), ("hashed", q)):
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+            ms, kp = time_and_profile(ctx, lambda: ctx.linear3_count(Fd, Fd, Fd, n, plan=plan, out=cnt,
+                                                                     workspace=ws), 5)
+            row[name] = {"ms": round(ms, 4), "tuples_per_s": 3 * F.shape[0] / (ms * 1e-3),
+                         "sum_equals_closed_form": int(mj.as_u64(cnt).sum(dtype=np.uint64)) == closed,
+                         "kernels_us": {k: round(v[0] / max(v[1], 1) * 1e3, 1)
+                                        for k, v in sorted(kp.items(), key=lambda kv: -kv[1][0])[:5]}}
+            log(f"skew cap {cap} {name}: {ms:.3f} ms")
+            del ws
+        res[f"cap_{cap}"] = row
+        del Fd
+    return res
+
+
 def gather_path(mj, ctx, F, a_domain):
     """What bounds the per-range sums: the benchmark step on its input, and
     on the same edges sorted by (source, destination) -- the same join, with
@@ -571,9 +611,9 @@ def emit_path(mj, ctx, F, Fd):
     return res
 
 
-LEGS = ("cascade", "small", "fm", "emit", "star", "slarge", "triangle", "batch", "planner", "gather")
-DEFAULT_LEGS = ("small", "triangle", "batch", "planner", "gather")
-OWN_WORKLOAD_LEGS = ("small", "star", "slarge", "triangle", "batch", "planner")
+LEGS = ("cascade", "small", "fm", "emit", "star", "slarge", "skew", "triangle", "batch", "planner", "gather")
+DEFAULT_LEGS = ("small", "skew", "triangle", "batch", "planner", "gather")
+OWN_WORKLOAD_LEGS = ("small", "star", "slarge", "skew", "triangle", "batch", "planner")
 
 
 def child_paths(legs):
@@ -606,6 +646,8 @@ def extra_paths(mj, ctx, F, Fd, a_domain, plan, ms_3way, only=None):
         out["star"] = star_path(mj, ctx)
     if only in (None, "slarge"):
         out["s_largest"] = slarge_path(mj, ctx)
+    if only in (None, "skew"):
+        out["skew"] = skew_path(mj, ctx)
     if only in (None, "gather"):
         out["gather_locality"] = gather_path(mj, ctx, F, a_domain)
     if only in (None, "triangle"):

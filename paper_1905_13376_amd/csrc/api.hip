@@ -212,6 +212,32 @@ struct RelPart {                     // one relation partitioned into 2^bits buc
     uint2* pairs;
 };
 
+// Skew split of a per-bucket kernel: a bucket of more than `chunk` tuples
+// (MJ_SPLIT_PCT percent of the mean bucket, at least SPLIT_MIN_CHUNK) runs
+// as several workgroups.  items: at most nb + n / chunk + 1 of them;
+// scratch rows: a split bucket has len > chunk, so its pieces number fewer
+// than 2 len / chunk, and all split buckets fewer than 2 n / chunk + 1.
+#ifndef MJ_SPLIT_PCT
+#define MJ_SPLIT_PCT 200
+#endif
+uint32_t split_chunk(uint64_t n, uint32_t bits) {
+    const uint64_t mean = (n + (uint64_t(1) << bits) - 1) >> bits;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(SPLIT_MIN_CHUNK, mean * MJ_SPLIT_PCT / 100),
+                                        uint64_t(1) << 31);
+}
+uint32_t split_grid(uint64_t n, uint32_t bits) { return (1u << bits) + (uint32_t)(n / split_chunk(n, bits)) + 1; }
+uint64_t split_rows(uint64_t n, uint32_t bits) { return 2 * (n / split_chunk(n, bits)) + 1; }
+BucketItems take_items(Bump& B, uint64_t n, uint32_t bits) {
+    BucketItems I{};
+    const uint32_t nb = 1u << bits;
+    I.chunk = split_chunk(n, bits);
+    I.items = B.take<uint32_t>(split_grid(n, bits));
+    I.nitems = B.take<uint32_t>(1);
+    I.hrow = B.take<uint32_t>(nb);
+    I.done = B.take<uint32_t>(nb);
+    return I;
+}
+
 void take_part(Bump& B, RelPart& P, uint64_t n, uint32_t bits) {
     const uint32_t nb = 1u << bits;
     P.hist = B.take<uint32_t>(uint64_t(nb) * ntiles_of(n));
@@ -258,6 +284,8 @@ struct DenseLayout {                  // the linear join with direct-indexed tab
     uint32_t* err;                    // [0]: a key out of its bound; [1]: unused;
                                       // [2]: some deg[c] >= 2^16
     uint32_t c_bits, c_shift, b_bits, b_shift, a_bits, a_shift;
+    BucketItems Tsplit, Ssplit, Rsplit;  // skew split of each partition's ranges
+    unsigned long long* rows;         // scratch rows of the split ranges (shared by the three sums)
     size_t bytes;
 };
 
@@ -284,6 +312,13 @@ DenseLayout dense_layout(void* ws, const mj_plan_t& p) {
     L.tkeys = B.take<uint32_t>(std::max<uint64_t>(p.n_t, 1));
     part(L.S, p.n_s, L.b_bits, true);
     part(L.R, p.n_r, L.a_bits, true);
+    L.Tsplit = take_items(B, p.n_t, L.c_bits);
+    L.Ssplit = take_items(B, p.n_s, L.b_bits);
+    L.Rsplit = take_items(B, p.n_r, L.a_bits);
+    const uint64_t row_words = std::max({split_rows(p.n_t, L.c_bits) << L.c_shift,
+                                         split_rows(p.n_s, L.b_bits) << L.b_shift,
+                                         split_rows(p.n_r, L.a_bits) << L.a_shift});
+    L.rows = B.take<unsigned long long>(row_words);
     L.deg = B.take<uint32_t>(std::max<uint32_t>(p.c_domain, 1));
     L.deg16 = B.take<uint16_t>(std::max<uint32_t>(p.c_domain, 1));
     L.w = B.take<unsigned long long>(std::max<uint32_t>(p.b_domain, 1));
@@ -303,6 +338,8 @@ struct LinearLayout {
     uint64_t wslots;
     uint32_t a_bits, a_shift;
     bool by_range;                    // per-A counts by ranges of A (no atomics)
+    BucketItems Rasplit;              // skew split of the ranges of A
+    unsigned long long* rows;         // scratch rows of its split ranges
     // S-largest plans: R's B values as tables per part of R, a sum per slot
     TableLayout Rk;
     unsigned long long* wval;
@@ -332,12 +369,15 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
     take_table(B, L.T, p.n_t, p.log2_nc);
     L.by_range = a_ranges(p, L.a_bits, L.a_shift);
     L.wdir = nullptr; L.wpool = nullptr; L.wcursor = nullptr; L.wslots = 0;
+    L.Rasplit = BucketItems{}; L.rows = nullptr;
     L.Ra = L.R;
     if (L.by_range) {
         const uint32_t na = 1u << L.a_bits;
         L.Ra.hist = B.take<uint32_t>(uint64_t(na) * ntiles_of(p.n_r));
         L.Ra.counts = B.take<uint32_t>(na);
         L.Ra.starts = B.take<uint32_t>(na + 1);
+        L.Rasplit = take_items(B, p.n_r, L.a_bits);
+        L.rows = B.take<unsigned long long>(split_rows(p.n_r, L.a_bits) << L.a_shift);
         const uint32_t nb = 1u << p.log2_nb;
         L.wdir = B.take<WDirEntry>(nb);
         if (p.algo == MJ_ALGO_SLARGE) {
@@ -1148,11 +1188,13 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     P.njobs = 0;
     P.job[P.njobs] = make_job(S, L.S.hist, L.S.counts, L.S.starts, 0, 0, L.b_bits, 0, 0, 0);
     P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.b_shift;
+    P.job[P.njobs].split = L.Ssplit;
     P.job[P.njobs++].out_pair = L.S.pairs;
     const bool r_is_s = same(R, L.a_bits, L.a_shift, S, L.b_bits, L.b_shift);
     if (!r_is_s) {
         P.job[P.njobs] = make_job(R, L.R.hist, L.R.counts, L.R.starts, 0, 0, L.a_bits, 0, 0, 0);
         P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.a_shift;
+        P.job[P.njobs].split = L.Rsplit;
         P.job[P.njobs++].out_pair = L.R.pairs;
     }
     const bool t_is_s = same(T, L.c_bits, L.c_shift, S, L.b_bits, L.b_shift);
@@ -1160,32 +1202,41 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     if (!t_is_s && !t_is_r) {
         P.job[P.njobs] = make_job(T, L.T.hist, L.T.counts, L.T.starts, 0, 0, L.c_bits, 0, 0, 0);
         P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.c_shift;
+        P.job[P.njobs].split = L.Tsplit;
         P.job[P.njobs].out_single = L.tkeys; P.job[P.njobs++].single_col = 0;
     }
     int st = launch_partition(prof, "dense", P, s);
     if (st) return st;
     const RelPart& Rp = r_is_s ? L.S : L.R;
     const RelPart* Tp = t_is_s ? &L.S : (t_is_r ? &Rp : nullptr);
-    RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad;
+    // the work items of each sum: those of the partition it reads
+    const BucketItems& Rsp = r_is_s ? L.Ssplit : L.Rsplit;
+    const BucketItems& Tsp = t_is_s ? L.Ssplit : (t_is_r ? Rsp : L.Tsplit);
+    const uint64_t n_rp = r_is_s ? S.n : R.n;
+    const uint64_t n_tp = t_is_s ? S.n : (t_is_r ? n_rp : T.n);
+    RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad{};
     Ad.pairs = Tp ? Tp->pairs : nullptr; Ad.keys = Tp ? nullptr : L.tkeys;
     Ad.starts = Tp ? Tp->starts : L.T.starts; Ad.shift = L.c_shift;
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
     Ad.out_narrow = L.deg16; Ad.wide = L.err + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
-    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
+    Ad.split = Tsp; Ad.rows = L.rows; Ad.row_len = 1u << L.c_shift;
+    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(split_grid(n_tp, L.c_bits)), dim3(RANGE_THREADS),
               size_t(4) << L.c_shift, s, Ad);
-    RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> Aw;
+    RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> Aw{};
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
     Aw.domain = p.b_domain; Aw.table = L.deg; Aw.table_n = p.c_domain; Aw.out = L.w; Aw.err = L.err;
     // deg's 2-byte copy unless some deg[c] needs more; W's saturating 2-byte copy
     Aw.out_narrow = L.w16; Aw.wide = nullptr; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
-    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(1u << L.b_bits), dim3(RANGE_THREADS),
+    Aw.split = L.Ssplit; Aw.rows = L.rows; Aw.row_len = 1u << L.b_shift;
+    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(split_grid(S.n, L.b_bits)), dim3(RANGE_THREADS),
               size_t(8) << L.b_shift, s, Aw);
-    RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> Ac;
+    RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> Ac{};
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
     Ac.domain = p.a_domain; Ac.table = L.w; Ac.table_n = p.b_domain; Ac.out = count; Ac.err = L.err;
     // W's saturating 2-byte copy; the full W where it reads 0xFFFF
     Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w16; Ac.use_wide = nullptr;
-    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(1u << L.a_bits), dim3(RANGE_THREADS),
+    Ac.split = Rsp; Ac.rows = L.rows; Ac.row_len = 1u << L.a_shift;
+    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(split_grid(n_rp, L.a_bits)), dim3(RANGE_THREADS),
               size_t(8) << L.a_shift, s, Ac);
     MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)p.a_domain, L.err);
@@ -1777,6 +1828,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         P.job[1] = make_job(*R, L.Ra.hist, L.Ra.counts, L.Ra.starts, 0, 0, L.a_bits, 0, 0, 0);
         P.job[1].range_on = 1;
         P.job[1].range_shift = L.a_shift;
+        P.job[1].split = L.Rasplit;
         P.job[1].out_pair = L.Ra.pairs;
         if ((st = launch_partition(&ctx->prof, "rs", P, s))) return st;
         if (slarge) {
@@ -1812,13 +1864,14 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
             MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
         }
         // per range of A: count[a] = sum of W[r.b], written once
-        CountArgs Cn;
+        CountArgs Cn{};
         Cn.R = L.Ra.pairs; Cn.rstarts = L.Ra.starts; Cn.wdir = L.wdir; Cn.wpool = L.wpool;
         Cn.b_seed = seed_b(p); Cn.b_bits = p.log2_nb; Cn.w_seed = seed_w(p);
         Cn.a_shift = L.a_shift; Cn.a_domain = a_domain;
         Cn.count = reinterpret_cast<unsigned long long*>(count);
         Cn.err = L.T.err;
-        MJ_LAUNCH(&ctx->prof, "k_count", k_count, dim3(1u << L.a_bits), dim3(COUNT_THREADS),
+        Cn.split = L.Rasplit; Cn.rows = L.rows;
+        MJ_LAUNCH(&ctx->prof, "k_count", k_count, dim3(split_grid(R->n, L.a_bits)), dim3(COUNT_THREADS),
                   (size_t(8) << L.a_shift), s, Cn);
         // an A value out of range or a table overflow: every count all ones
         MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
@@ -1937,7 +1990,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         PT.job[0].range_on = 1; PT.job[0].range_shift = L.c_shift;
         PT.job[0].out_single = L.tkeys; PT.job[0].single_col = 0;
         if ((st = launch_partition(prof, "tab", PT, s))) return st;
-        RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad;
+        RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> Ad{};
         Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.Tr.starts; Ad.shift = L.c_shift;
         Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.dflags;
         Ad.out_narrow = L.deg16; Ad.wide = L.dflags + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;

@@ -514,13 +514,45 @@ __device__ __forceinline__ void wtab_lookup4(const WDirEntry* __restrict__ dir,
     }
 }
 
+// A piece of a split bucket: its sums acc[0, span) go to its scratch row;
+// the last piece of the bucket to finish returns true with the bucket's
+// totals in acc (the other pieces return false).
+template <class TO>
+__device__ __forceinline__ bool split_merge(const BucketItems& B, uint32_t k, uint32_t piece, uint32_t pcs,
+                                            TO* rows, uint32_t row_len, TO* acc, uint32_t span) {
+    __shared__ uint32_t s_last;
+    TO* mine = rows + (uint64_t(B.hrow[k]) + piece) * row_len;
+    for (uint32_t j = threadIdx.x; j < span; j += blockDim.x) mine[j] = acc[j];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&B.done[k], 1u) == pcs - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return false;                                      // uniform over the block
+    __threadfence();
+    const TO* first = rows + uint64_t(B.hrow[k]) * row_len;
+    for (uint32_t j = threadIdx.x; j < span; j += blockDim.x) {
+        TO v = 0;
+        for (uint32_t r = 0; r < pcs; ++r) v += *(const volatile TO*)&first[uint64_t(r) * row_len + j];
+        acc[j] = v;
+    }
+    if (threadIdx.x == 0) B.done[k] = 0;                            // for the next kernel over these items
+    __syncthreads();
+    return true;
+}
+
 // ------------------------------------------------------------- counts
 // One workgroup per range of A values: count[a] = sum over r(a, b) of W[b]
 // in LDS, then the range is written out whole (zeros included).
 __global__ void __launch_bounds__(COUNT_THREADS)
 k_count(CountArgs A) {
     extern __shared__ unsigned long long cnt[];          // [1 << a_shift]
-    const uint32_t k = blockIdx.x;
+    uint32_t k = blockIdx.x, piece = 0;
+    if (A.split.items) {                                  // uniform over the block
+        if (blockIdx.x >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[blockIdx.x];
+        k = it & 0xFFFu;
+        piece = it >> 12;
+    }
     const uint64_t base = uint64_t(k) << A.a_shift;
     // ranges past a_domain only receive keys out of range (reported)
     const uint32_t span = base < A.a_domain
@@ -528,7 +560,10 @@ k_count(CountArgs A) {
     const int nthr = blockDim.x;
     for (uint32_t j = threadIdx.x; j < span; j += nthr) cnt[j] = 0;
     __syncthreads();
-    const uint32_t r0 = A.rstarts[k], r1 = A.rstarts[k + 1];
+    const uint32_t s0 = A.rstarts[k], len = A.rstarts[k + 1] - s0;
+    const uint32_t pcs = A.split.items ? split_pieces(len, A.split.chunk) : 1u;
+    const uint32_t r0 = s0 + (uint32_t)(uint64_t(len) * piece / pcs);
+    const uint32_t r1 = s0 + (uint32_t)(uint64_t(len) * (piece + 1) / pcs);
     for (uint32_t q = r0 + threadIdx.x; q < r1; q += 4 * nthr) {
         uint2 rv[4];
         uint32_t bb[4];
@@ -551,6 +586,7 @@ k_count(CountArgs A) {
         }
     }
     __syncthreads();
+    if (pcs > 1 && !split_merge(A.split, k, piece, pcs, A.rows, 1u << A.a_shift, cnt, span)) return;
     for (uint32_t j = threadIdx.x; j < span; j += nthr) A.count[base + j] = cnt[j];
 }
 
@@ -564,7 +600,13 @@ k_count(CountArgs A) {
 // SAT_IN: table_narrow is a saturating copy; SAT_OUT: out_narrow is one.
 template <bool SAT_IN, bool SAT_OUT, class TW, class TWN, class TO, class TON>
 __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO, TON>& A, TO* acc) {
-    const uint32_t k = blockIdx.x;
+    uint32_t k = blockIdx.x, piece = 0;
+    if (A.split.items) {                                            // uniform over the block
+        if (blockIdx.x >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[blockIdx.x];
+        k = it & 0xFFFu;
+        piece = it >> 12;
+    }
     const uint64_t base = uint64_t(k) << A.shift;
     const uint32_t span = base < A.domain ? (uint32_t)min<uint64_t>(uint64_t(1) << A.shift, A.domain - base) : 0u;
     const int nthr = blockDim.x;
@@ -572,7 +614,10 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
     __syncthreads();
     bool narrow = false;                                            // uniform over the launch
     if constexpr (!SAT_IN) narrow = A.table_narrow && *A.use_wide == 0;
-    const uint32_t q0 = A.starts[k], q1 = A.starts[k + 1];
+    const uint32_t s0 = A.starts[k], len = A.starts[k + 1] - s0;
+    const uint32_t pcs = A.split.items ? split_pieces(len, A.split.chunk) : 1u;
+    const uint32_t q0 = s0 + (uint32_t)(uint64_t(len) * piece / pcs);
+    const uint32_t q1 = s0 + (uint32_t)(uint64_t(len) * (piece + 1) / pcs);
     for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
         uint32_t key[4];
         TO w[4];
@@ -610,6 +655,8 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
         }
     }
     __syncthreads();
+    if (pcs > 1 && !split_merge(A.split, k, piece, pcs, reinterpret_cast<TO*>(A.rows), A.row_len, acc, span))
+        return;                                                     // another piece writes the range
     bool big = false;
     for (uint32_t j = threadIdx.x; j < span; j += nthr) {
         const TO v = acc[j];

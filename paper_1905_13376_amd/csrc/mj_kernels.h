@@ -34,6 +34,26 @@ static_assert((size_t(8) << PART_MAX_BITS) + size_t(8) * PART_TILE + 4 * (PART_S
 static_assert(PART_TILE <= 65536 && PART_TILE % (2 * PART_THREADS) == 0 &&
               PART_TILE % (2 * PART_SCATTER_THREADS) == 0, "partition tile shape");
 
+// Work items of a per-bucket kernel when a bucket holds too many tuples
+// for one workgroup (skew: a heavy key or a crowded range).  k_part_scan
+// writes them when the job asks: a bucket of more than `chunk` tuples is
+// split into split_pieces(len, chunk) pieces, each a workgroup of its own;
+// item g = bucket | piece << 12.  The pieces of a split bucket leave their
+// sums in scratch rows hrow[bucket] + piece, and the last piece to finish
+// (counted in done[bucket]) adds the rows and writes the bucket's outputs,
+// then sets done[bucket] back to 0 for the next kernel over the same items.
+struct BucketItems {     // null unless set, however the holder is declared
+    uint32_t* items = nullptr;   // [nb + n / chunk + 1]; null: one workgroup per bucket
+    uint32_t* nitems = nullptr;  // [1]
+    uint32_t* hrow = nullptr;    // [nb]
+    uint32_t* done = nullptr;    // [nb]
+    uint32_t chunk = 0;          // at least SPLIT_MIN_CHUNK
+};
+constexpr uint32_t SPLIT_MIN_CHUNK = 4096;   // pieces < 2^20 for any n < 2^32
+__host__ __device__ inline uint32_t split_pieces(uint32_t len, uint32_t chunk) {
+    return len > chunk ? (len - 1) / chunk + 1 : 1u;
+}
+
 struct PartJob {
     const uint32_t* col0;
     const uint32_t* col1;
@@ -55,6 +75,7 @@ struct PartJob {
     uint32_t swap_out;   // pairs written as (col1, col0)
     uint32_t tile_begin; // first block of this job in the grid
     uint32_t ntiles;
+    BucketItems split;   // optional work items of the buckets (k_part_scan)
 };
 
 struct PartLaunch {
@@ -283,6 +304,11 @@ struct RangeAccArgs {
     uint32_t* wide;
     const TWN* table_narrow;
     const uint32_t* use_wide;
+    // optional: ranges split into pieces (items.items null: one workgroup
+    // per range); rows: scratch of row_len entries of TO per piece
+    BucketItems split;
+    void* rows = nullptr;
+    uint32_t row_len = 0;
 };
 // deg[c]: keys only, weight 1 (flagged 16-bit copy)
 __global__ void k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A);
@@ -306,6 +332,8 @@ struct CountArgs {
     uint32_t a_domain;
     unsigned long long* count;   // [a_domain], every entry written
     uint32_t* err;               // set to 1 for an a >= a_domain
+    BucketItems split;           // optional: ranges split into pieces
+    unsigned long long* rows = nullptr;  // scratch rows of 2^a_shift entries
 };
 __global__ void k_count(CountArgs A);
 

@@ -166,6 +166,32 @@ k_part_scan(PartLaunch L) {
     uint32_t total = block_exclusive_scan(lds, nb, wave_tmp);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) J.starts[d] = lds[d];
     if (threadIdx.x == 0) J.starts[nb] = total;
+    if (!J.split.items) return;                      // uniform over the block
+    // work items: first the pieces of the split buckets (so the longest
+    // work starts first; piece p of bucket d is item and scratch row
+    // hrow[d] + p), then the other buckets in bucket order
+    const BucketItems& B = J.split;
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
+        const uint32_t pcs = split_pieces(J.counts[d], B.chunk);
+        lds[d] = pcs > 1 ? pcs : 0u;
+    }
+    __syncthreads();
+    const uint32_t heavy = block_exclusive_scan(lds, nb, wave_tmp);
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
+        const uint32_t pcs = split_pieces(J.counts[d], B.chunk);
+        if (pcs == 1) continue;
+        B.hrow[d] = lds[d];
+        B.done[d] = 0;
+        for (uint32_t p = 0; p < pcs; ++p) B.items[lds[d] + p] = d | (p << 12);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = split_pieces(J.counts[d], B.chunk) == 1 ? 1u : 0u;
+    __syncthreads();
+    const uint32_t light = block_exclusive_scan(lds, nb, wave_tmp);
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x)
+        if (split_pieces(J.counts[d], B.chunk) == 1) B.items[heavy + lds[d]] = d;
+    if (threadIdx.x == 0) *B.nitems = heavy + light;
 }
 
 __global__ void __launch_bounds__(PART_SCATTER_THREADS)

@@ -55,7 +55,10 @@ def build(sanitize: bool = True, jobs: int = 8, verbose: bool = False) -> str:
             units.append(dst)
     units += [os.path.join(HERE, "sim.cpp")]
     mains = [os.path.join(HERE, "replay.cpp"), os.path.join(HERE, "abi_check.cpp")]
+    # uninitialised locals (kernel argument structs among them) hold a
+    # non-zero pattern, so a field left unset reads as a wild value, not 0
     flags = ["-x", "c++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", "-pthread",
+             "-ftrivial-auto-var-init=pattern",
              "-I" + HERE, "-I" + src_dir, "-I" + INCLUDE, "-Wno-unused-command-line-argument",
              "-Wno-ignored-attributes", "-Wno-unknown-pragmas", "-Wno-pass-failed"]
     if sanitize:

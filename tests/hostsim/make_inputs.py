@@ -79,6 +79,16 @@ def main():
     put("slS", S)
     put("slT", T)
     meta["slR"]["closed_total"] = closed_total(R, S, T)
+    # skew: heavy first-column keys crowding two of the ranges (each range
+    # then runs as several workgroups)
+    g = np.random.default_rng(77)
+    n = 1 << (18 if tiny else 21)
+    K = g.integers(0, 4096, size=(n, 2)).astype(np.uint32)
+    K[: n // 4, 0] = 5
+    K[n // 4: (3 * n) // 5, 0] = 3000
+    g.shuffle(K)
+    put("K", K, 4096)
+    meta["K"]["closed_total"] = closed_total(K, K, K)
     with open(os.path.join(out, "meta.json"), "w") as f:
         json.dump(meta, f, indent=1)
     with open(os.path.join(out, "meta.txt"), "w") as f:          # name n a_domain closed_total

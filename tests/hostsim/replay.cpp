@@ -6,8 +6,9 @@
 // any access outside those buffers; the checks below report results that
 // differ from the closed forms or between algorithms.
 //
-//   replay DATA_DIR [legs...]     legs: main cascade small fm emit star slarge (default: all)
+//   replay DATA_DIR [legs...]     legs: main cascade skew small fm emit star slarge (default: all)
 //   environment: HIPSIM_STEPS (timed steps of the main leg, default 2)
+#include <algorithm>
 #include <cinttypes>
 #include <cstdio>
 #include <cstdlib>
@@ -169,6 +170,40 @@ int main(int argc, char** argv) {
         }
         std::free(ws2);
         std::free(cnt);
+    }
+    if (want("skew")) {
+        // heavy keys: the crowded ranges run as several workgroups each,
+        // with direct-indexed and with hashed tables, twice in a row
+        leg("skew");
+        const Meta& mk = g_meta.at("K");
+        const uint32_t* K = load("K");
+        const mj_rel RK = rel_of(K, mk.n);
+        const uint32_t AK = mk.a_domain;
+        mj_plan_t pk;
+        std::memset(&pk, 0, sizeof pk);
+        check(make_plan(ctx, MJ_LINEAR, &RK, &RK, &RK, AK, &pk), "mj_plan skew");
+        expect((pk.flags & MJ_PLAN_DENSE_KEYS) != 0, "skew: the planner takes direct-indexed tables");
+        mj_plan_t ph = pk;
+        ph.algo = MJ_ALGO_3WAY;
+        ph.flags = (ph.flags & ~uint32_t(MJ_PLAN_DENSE_KEYS)) | MJ_PLAN_NO_DENSE;
+        {
+            const uint64_t need = mj_plan_workspace(MJ_LINEAR, RK.n, RK.n, RK.n);
+            void* pws = alloc(need);
+            check(mj_plan(ctx, MJ_LINEAR, &RK, &RK, &RK, AK, MJ_PLANNER_FIXED, &ph, pws, need, nullptr),
+                  "mj_plan skew hashed");
+            std::free(pws);
+        }
+        uint64_t* cd = static_cast<uint64_t*>(alloc(uint64_t(AK) * 8));
+        uint64_t* ch = static_cast<uint64_t*>(alloc(uint64_t(AK) * 8));
+        void* wsk = alloc(std::max(pk.workspace_bytes, ph.workspace_bytes));
+        for (int i = 0; i < 2; ++i) {
+            check(mj_linear3_count(ctx, &RK, &RK, &RK, AK, cd, &pk, wsk, pk.workspace_bytes, nullptr), "skew dense");
+            expect(sum(cd, AK) == mk.closed, "skew: direct-indexed sum equals the closed form");
+            check(mj_linear3_count(ctx, &RK, &RK, &RK, AK, ch, &ph, wsk, ph.workspace_bytes, nullptr), "skew hashed");
+            expect(std::memcmp(cd, ch, uint64_t(AK) * 8) == 0, "skew: hashed tables give the same counts");
+        }
+        std::free(wsk); std::free(cd); std::free(ch);
+        std::free(const_cast<uint32_t*>(K));
     }
     if (want("small")) {
         leg("small");
