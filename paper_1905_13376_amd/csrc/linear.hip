@@ -79,27 +79,39 @@ k_dbuild(DBuildArgs A) {
     if (threadIdx.x == 0) { s_special = 0; s_distinct = 0; s_over = 0; }
     __syncthreads();
 
-    for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    // four keys per thread and round: their loads are in flight together
+    // (a bucket crowded by a heavy key is one workgroup's work)
+    for (uint32_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
         if (*(volatile uint32_t*)&s_over) break;
-        const uint32_t k = A.keys[i];
-        if (k == EMPTY_KEY) { atomicAdd(&s_special, 1u); continue; }
-        uint32_t s = slot_hash(k, A.slot_seed) & mask;
-        for (uint32_t step = 0;; ++step) {
-            uint32_t cur = tkeys[s];
-            if (cur == k) { atomicAdd(&tvals[s], 1u); break; }
-            if (cur == EMPTY_KEY || step >= DB_CAP) {
-                // no new key is claimed after the overflow flag (the bucket is
-                // rebuilt in global memory), so the LDS table never fills
-                if (*(volatile uint32_t*)&s_over || step >= DB_CAP) { s_over = 1; break; }
-                uint32_t old = atomicCAS(&tkeys[s], EMPTY_KEY, k);
-                if (old == EMPTY_KEY) {
-                    if (atomicAdd(&s_distinct, 1u) + 1 >= DB_LIMIT) s_over = 1;
-                    atomicAdd(&tvals[s], 1u);
-                    break;
+        uint32_t kk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            kk[u] = i < end ? A.keys[i] : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u * blockDim.x >= end) break;
+            const uint32_t k = kk[u];
+            if (k == EMPTY_KEY) { atomicAdd(&s_special, 1u); continue; }
+            uint32_t s = slot_hash(k, A.slot_seed) & mask;
+            for (uint32_t step = 0;; ++step) {
+                uint32_t cur = tkeys[s];
+                if (cur == k) { atomicAdd(&tvals[s], 1u); break; }
+                if (cur == EMPTY_KEY || step >= DB_CAP) {
+                    // no new key is claimed after the overflow flag (the bucket is
+                    // rebuilt in global memory), so the LDS table never fills
+                    if (*(volatile uint32_t*)&s_over || step >= DB_CAP) { s_over = 1; break; }
+                    uint32_t old = atomicCAS(&tkeys[s], EMPTY_KEY, k);
+                    if (old == EMPTY_KEY) {
+                        if (atomicAdd(&s_distinct, 1u) + 1 >= DB_LIMIT) s_over = 1;
+                        atomicAdd(&tvals[s], 1u);
+                        break;
+                    }
+                    if (old == k) { atomicAdd(&tvals[s], 1u); break; }
                 }
-                if (old == k) { atomicAdd(&tvals[s], 1u); break; }
+                s = (s + 1u) & mask;
             }
-            s = (s + 1u) & mask;
         }
     }
     __syncthreads();
@@ -225,13 +237,14 @@ __device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const Dir
         dtab_lookup4(ddir, dpool, cc, live, c_seed, c_bits, slot_seed, w);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (w[u] == 0) continue;
+            const unsigned long long v = w[u];
+            if (v == 0) continue;
             const uint32_t b = sv[u].x;
-            if (b == EMPTY_KEY) { atomicAdd(T.special, (unsigned long long)w[u]); continue; }
+            if (b == EMPTY_KEY) { atomicAdd(T.special, v); continue; }
             uint32_t s = slot_hash(b, w_seed) & mask;
             for (uint32_t step = 0;; ++step) {
                 uint32_t cur = T.keys[s];
-                if (cur == b) { atomicAdd(&T.vals[s], (unsigned long long)w[u]); break; }
+                if (cur == b) { atomicAdd(&T.vals[s], v); break; }
                 if (cur == EMPTY_KEY || step >= CELL_CAP) {
                     // a new key: once the pass has overflowed no new slot is
                     // claimed (the pass is redone split), so the table can
@@ -240,7 +253,7 @@ __device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const Dir
                     uint32_t old = atomicCAS(&T.keys[s], EMPTY_KEY, b);
                     if (old == EMPTY_KEY || old == b) {
                         if (old == EMPTY_KEY && atomicAdd(T.distinct, 1u) + 1 >= CELL_LIMIT) *T.over = 1;
-                        atomicAdd(&T.vals[s], (unsigned long long)w[u]);
+                        atomicAdd(&T.vals[s], v);
                         break;
                     }
                 }
@@ -564,7 +577,9 @@ k_count(CountArgs A) {
     const uint32_t pcs = A.split.items ? split_pieces(len, A.split.chunk) : 1u;
     const uint32_t r0 = s0 + (uint32_t)(uint64_t(len) * piece / pcs);
     const uint32_t r1 = s0 + (uint32_t)(uint64_t(len) * (piece + 1) / pcs);
-    for (uint32_t q = r0 + threadIdx.x; q < r1; q += 4 * nthr) {
+    const bool heavy = pcs > 1;                           // equal A values of a wave folded first
+    for (uint32_t qb = r0; qb < r1; qb += 4 * nthr) {     // every lane runs every round
+        const uint32_t q = qb + threadIdx.x;
         uint2 rv[4];
         uint32_t bb[4];
         bool live[4];
@@ -579,10 +594,13 @@ k_count(CountArgs A) {
         wtab_lookup4(A.wdir, A.wpool, bb, live, A.b_seed, A.b_bits, A.w_seed, w);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (!live[u] || w[u] == 0) continue;
+            unsigned long long v = w[u];
+            bool act = live[u] && v != 0;
+            if (heavy && wave_fold_first(rv[u].x, act, v)) act = false;
+            if (!act) continue;
             const uint64_t off = uint64_t(rv[u].x) - base;   // < span unless a >= a_domain
             if (rv[u].x >= A.a_domain || off >= span) { atomicExch(A.err, 1u); continue; }
-            atomicAdd(&cnt[off], w[u]);
+            atomicAdd(&cnt[off], v);
         }
     }
     __syncthreads();
@@ -618,7 +636,10 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
     const uint32_t pcs = A.split.items ? split_pieces(len, A.split.chunk) : 1u;
     const uint32_t q0 = s0 + (uint32_t)(uint64_t(len) * piece / pcs);
     const uint32_t q1 = s0 + (uint32_t)(uint64_t(len) * (piece + 1) / pcs);
-    for (uint32_t q = q0 + threadIdx.x; q < q1; q += 4 * nthr) {
+    // a split range is a heavy one: equal keys of a wave are folded first
+    const bool heavy = pcs > 1;
+    for (uint32_t qb = q0; qb < q1; qb += 4 * nthr) {               // every lane runs every round
+        const uint32_t q = qb + threadIdx.x;
         uint32_t key[4];
         TO w[4];
         bool live[4];
@@ -648,10 +669,13 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (!live[u] || w[u] == 0) continue;
+            TO v = w[u];
+            bool act = live[u] && v != 0;
+            if (heavy && wave_fold_first(key[u], act, v)) act = false;
+            if (!act) continue;
             const uint64_t off = uint64_t(key[u]) - base;
             if (key[u] >= A.domain || off >= span) { atomicExch(A.err, 1u); continue; }
-            atomicAdd(&acc[off], w[u]);
+            atomicAdd(&acc[off], v);
         }
     }
     __syncthreads();

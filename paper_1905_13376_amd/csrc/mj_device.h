@@ -51,7 +51,8 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
     return x < tall ? x * (per + 1) + local : tall * (per + 1) + (x - tall) * per + local;
 }
 
-// Wave-wide sum of a 64-bit value (DPP/permute based reduction via shuffles).
+// Wave-wide sum of a 64-bit value (a butterfly of cross-lane permutes,
+// __shfl_xor, six steps).
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
@@ -62,6 +63,29 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
     return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return wave_sum_u64(v); }
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_sum_u32(v); }
+
+// Heavy keys: the active lanes of the wave whose key equals the first
+// active lane's key fold their values into that lane, which then adds the
+// sum once (a hub's tuples cost one atomic per wave instead of one per
+// lane).  Every lane of the wave must call it.  Returns true for a lane
+// whose value was folded into another (it skips its own add); the first
+// lane's v becomes the sum.  With fewer than two such lanes nothing changes.
+template <class T>
+__device__ __forceinline__ bool wave_fold_first(uint32_t key, bool act, T& v) {
+    const unsigned long long live = __ballot(act);
+    if (live == 0) return false;                                   // uniform over the wave
+    const int first = __ffsll((long long)live) - 1;
+    const uint32_t k0 = __shfl(key, first, WAVE);
+    const bool same = act && key == k0;
+    if (__popcll(__ballot(same)) < 2) return false;                // uniform over the wave
+    const T sum = wave_sum(same ? v : T(0));
+    if (!same) return false;
+    if (lane_id() == first) { v = sum; return false; }
+    return true;
 }
 
 // Read tuple component from a strided column.
