@@ -340,6 +340,9 @@ struct LinearLayout {
     bool by_range;                    // per-A counts by ranges of A (no atomics)
     BucketItems Rasplit;              // skew split of the ranges of A
     unsigned long long* rows;         // scratch rows of its split ranges
+    BucketItems Ssplit;               // skew split of the buckets of S (W build)
+    WSlot* wrows;                     // the pieces' W tables
+    unsigned long long* wrow_special;
     // S-largest plans: R's B values as tables per part of R, a sum per slot
     TableLayout Rk;
     unsigned long long* wval;
@@ -370,6 +373,7 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
     L.by_range = a_ranges(p, L.a_bits, L.a_shift);
     L.wdir = nullptr; L.wpool = nullptr; L.wcursor = nullptr; L.wslots = 0;
     L.Rasplit = BucketItems{}; L.rows = nullptr;
+    L.Ssplit = BucketItems{}; L.wrows = nullptr; L.wrow_special = nullptr;
     L.Ra = L.R;
     if (L.by_range) {
         const uint32_t na = 1u << L.a_bits;
@@ -391,6 +395,10 @@ LinearLayout linear_layout(void* ws, const mj_plan_t& p) {
             // two >= twice its keys), plus the minimum per bucket and the
             // empty head
             L.wslots = 4 * p.n_s + uint64_t(W_MIN_CAP) * (nb + 1);
+            L.Ssplit = take_items(B, p.n_s, p.log2_nb);
+            const uint64_t nrows = split_rows(p.n_s, p.log2_nb);
+            L.wrows = B.take<WSlot>(nrows * CELL_CAP);
+            L.wrow_special = B.take<unsigned long long>(nrows);
         }
         L.wpool = B.take<WSlot>(L.wslots);
         L.wcursor = B.take<unsigned long long>(1);
@@ -1825,6 +1833,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
                                      1, seed_c(p), p.log2_nc)
                           : make_job(*S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
         P.job[0].out_pair = L.S.pairs;
+        if (!slarge) P.job[0].split = L.Ssplit;          // heavy buckets of B in pieces
         P.job[1] = make_job(*R, L.Ra.hist, L.Ra.counts, L.Ra.starts, 0, 0, L.a_bits, 0, 0, 0);
         P.job[1].range_on = 1;
         P.job[1].range_shift = L.a_shift;
@@ -1856,12 +1865,13 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
                       reinterpret_cast<uint32_t*>(L.wpool), (uint64_t)(4 * W_MIN_CAP), EMPTY_KEY);
             MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
                       (unsigned long long)W_MIN_CAP);
-            WBuildArgs Wb;
+            WBuildArgs Wb{};
             Wb.S = L.S.pairs; Wb.sstarts = L.S.starts; Wb.ddir = L.T.dir; Wb.dpool = L.T.pool;
             Wb.c_seed = seed_c(p); Wb.c_bits = p.log2_nc; Wb.slot_seed = seed_slot(p); Wb.w_seed = seed_w(p);
             Wb.wdir = L.wdir; Wb.wpool = L.wpool; Wb.wcursor = L.wcursor; Wb.wcap = L.wslots;
             Wb.err = L.T.err;
-            MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(nb), dim3(CELL_THREADS), 0, s, Wb);
+            Wb.split = L.Ssplit; Wb.rows = L.wrows; Wb.row_special = L.wrow_special;
+            MJ_LAUNCH(&ctx->prof, "k_wbuild", k_wbuild, dim3(split_grid(S->n, p.log2_nb)), dim3(CELL_THREADS), 0, s, Wb);
         }
         // per range of A: count[a] = sum of W[r.b], written once
         CountArgs Cn{};

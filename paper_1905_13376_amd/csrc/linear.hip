@@ -213,6 +213,30 @@ struct WTable {
     uint32_t* over;
 };
 
+// W[b] += v in the LDS table; sets *over when the distinct b exceed
+// CELL_LIMIT (no slot is claimed after that, so every probe still ends).
+__device__ __forceinline__ void w_table_add(const WTable& T, uint32_t b, unsigned long long v, uint32_t w_seed) {
+    const uint32_t mask = CELL_CAP - 1;
+    uint32_t s = slot_hash(b, w_seed) & mask;
+    for (uint32_t step = 0;; ++step) {
+        uint32_t cur = T.keys[s];
+        if (cur == b) { atomicAdd(&T.vals[s], v); break; }
+        if (cur == EMPTY_KEY || step >= CELL_CAP) {
+            // a new key: once the pass has overflowed no new slot is
+            // claimed (the pass is redone split), so the table can
+            // never fill up and every probe finds an empty slot
+            if (*(volatile uint32_t*)T.over || step >= CELL_CAP) { *T.over = 1; break; }
+            uint32_t old = atomicCAS(&T.keys[s], EMPTY_KEY, b);
+            if (old == EMPTY_KEY || old == b) {
+                if (old == EMPTY_KEY && atomicAdd(T.distinct, 1u) + 1 >= CELL_LIMIT) *T.over = 1;
+                atomicAdd(&T.vals[s], v);
+                break;
+            }
+        }
+        s = (s + 1u) & mask;
+    }
+}
+
 // W[b] += mult_T(c) over the S tuples of [s0, s1) whose b belongs to the
 // pass (level, pass); sets *over when the distinct b exceed CELL_LIMIT (no
 // slot is claimed after that, so every probe still ends).
@@ -220,7 +244,6 @@ __device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const Dir
                              const uint2* dpool, uint32_t c_seed, uint32_t c_bits,
                              uint32_t slot_seed, uint32_t w_seed, uint32_t level, uint32_t pass,
                              const WTable& T) {
-    const uint32_t mask = CELL_CAP - 1;
     const int nthr = blockDim.x;
     for (uint32_t q = s0 + threadIdx.x; q < s1; q += 4 * nthr) {
         if (*(volatile uint32_t*)T.over) break;
@@ -241,25 +264,27 @@ __device__ void w_accumulate(const uint2* S, uint32_t s0, uint32_t s1, const Dir
             if (v == 0) continue;
             const uint32_t b = sv[u].x;
             if (b == EMPTY_KEY) { atomicAdd(T.special, v); continue; }
-            uint32_t s = slot_hash(b, w_seed) & mask;
-            for (uint32_t step = 0;; ++step) {
-                uint32_t cur = T.keys[s];
-                if (cur == b) { atomicAdd(&T.vals[s], v); break; }
-                if (cur == EMPTY_KEY || step >= CELL_CAP) {
-                    // a new key: once the pass has overflowed no new slot is
-                    // claimed (the pass is redone split), so the table can
-                    // never fill up and every probe finds an empty slot
-                    if (*(volatile uint32_t*)T.over || step >= CELL_CAP) { *T.over = 1; break; }
-                    uint32_t old = atomicCAS(&T.keys[s], EMPTY_KEY, b);
-                    if (old == EMPTY_KEY || old == b) {
-                        if (old == EMPTY_KEY && atomicAdd(T.distinct, 1u) + 1 >= CELL_LIMIT) *T.over = 1;
-                        atomicAdd(&T.vals[s], v);
-                        break;
-                    }
-                }
-                s = (s + 1u) & mask;
-            }
+            w_table_add(T, b, v, w_seed);
         }
+    }
+}
+
+// The pieces' W tables of a split bucket added into the LDS table (and
+// their sums for b = 0xFFFFFFFF into T.special); sets *over as above.
+__device__ void w_merge_rows(const WSlot* rows, const unsigned long long* rspecial, uint32_t pcs,
+                             uint32_t w_seed, const WTable& T) {
+    for (uint32_t r = 0; r < pcs; ++r) {
+        const WSlot* row = rows + uint64_t(r) * CELL_CAP;
+        for (uint32_t t = threadIdx.x; t < CELL_CAP; t += blockDim.x) {
+            if (*(volatile uint32_t*)T.over) break;
+            const WSlot e = row[t];
+            if (e.key != EMPTY_KEY && e.w) w_table_add(T, e.key, e.w, w_seed);
+        }
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long sp = 0;
+        for (uint32_t r = 0; r < pcs; ++r) sp += rspecial[r];
+        if (sp) atomicAdd(T.special, sp);
     }
 }
 
@@ -353,7 +378,8 @@ k_linear_cell_batch(LinearBatchArgs B) {
 // two >= twice its keys when that is below CELL_CAP); a split bucket gets a
 // region sized for every S tuple of the bucket, cleared, into which each
 // pass inserts its keys (every key belongs to one pass, so a claimed slot's
-// W is stored once).
+// W is stored once).  A bucket crowded by heavy keys runs as pieces, one
+// workgroup each, and the last piece to finish adds up their tables.
 __global__ void __launch_bounds__(CELL_THREADS)
 k_wbuild(WBuildArgs A) {
     __shared__ uint32_t wkeys[CELL_CAP];
@@ -362,10 +388,57 @@ k_wbuild(WBuildArgs A) {
     __shared__ uint32_t s_distinct, s_over, s_log2, s_global;
     __shared__ uint32_t st_level[64], st_pass[64];
     __shared__ int s_sp;
+    __shared__ uint32_t s_last;
     const WTable T{wkeys, wvals, &w_special, &s_distinct, &s_over};
-    const uint32_t i = blockIdx.x;
+    // the block's work item: a bucket, or a piece of a split bucket (heavy
+    // keys; listed first so that they start first)
+    uint32_t i = blockIdx.x, piece = 0, pcs = 1;
+    if (A.split.items) {                                         // uniform over the block
+        if (blockIdx.x >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[blockIdx.x];
+        i = it & 0xFFFu;
+        piece = it >> 12;
+        pcs = split_pieces(A.sstarts[i + 1] - A.sstarts[i], A.split.chunk);
+    }
     const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
     const int nthr = blockDim.x;
+    bool merged = false;
+    if (pcs > 1) {
+        // a piece: its W table in LDS, written to its scratch row (or, when
+        // its keys overflow the table, a flag that sends the bucket back to
+        // its tuples); the last piece to finish builds the bucket's table
+        const uint32_t len = s1 - s0;
+        const uint32_t q0 = s0 + (uint32_t)(uint64_t(len) * piece / pcs);
+        const uint32_t q1 = s0 + (uint32_t)(uint64_t(len) * (piece + 1) / pcs);
+        for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) { wkeys[s] = EMPTY_KEY; wvals[s] = 0; }
+        if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; }
+        __syncthreads();
+        w_accumulate(A.S, q0, q1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed, 0, 0, T);
+        __syncthreads();
+        const bool ovf = s_over != 0;
+        const uint64_t r = uint64_t(A.split.hrow[i]) + piece;
+        if (!ovf) {
+            WSlot* row = A.rows + r * CELL_CAP;
+            for (uint32_t s = threadIdx.x; s < CELL_CAP; s += nthr) {
+                WSlot v;
+                v.key = wkeys[s]; v.pad = 0; v.w = wvals[s];
+                row[s] = v;
+            }
+            if (threadIdx.x == 0) A.row_special[r] = w_special;
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (ovf) atomicOr(&A.split.done[i], 0x80000000u);
+            const uint32_t old = atomicAdd(&A.split.done[i], 1u);
+            s_last = (old & 0x7FFFFFFFu) == pcs - 1 ? 1u : 0u;
+        }
+        __syncthreads();
+        if (!s_last) return;                                     // uniform over the block
+        __threadfence();
+        merged = (atomicAdd(&A.split.done[i], 0u) & 0x80000000u) == 0;
+        __syncthreads();
+    }
     if (s0 == s1) {                       // an empty table: the pool's first slots
         if (threadIdx.x == 0) {
             WDirEntry e;
@@ -378,6 +451,8 @@ k_wbuild(WBuildArgs A) {
         s_sp = 1; st_level[0] = 0; st_pass[0] = 0;
         s_global = 0; s_base = 0; s_log2 = 31 - __clz(W_MIN_CAP); s_special_tot = 0;
     }
+    // a split bucket whose pieces all fit their tables: the first pass adds
+    // up the pieces' tables instead of reading the tuples
     while (true) {
         __syncthreads();
         const int sp = s_sp;
@@ -388,8 +463,19 @@ k_wbuild(WBuildArgs A) {
         __syncthreads();
         if (threadIdx.x == 0) { w_special = 0; s_distinct = 0; s_over = 0; s_sp = sp - 1; }
         __syncthreads();
-        w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
-                     level, pass, T);
+        if (merged) {
+            const uint64_t r0 = A.split.hrow[i];
+            w_merge_rows(A.rows + r0 * CELL_CAP, A.row_special + r0, pcs, A.w_seed, T);
+            __syncthreads();
+            if (s_over) {                    // the union overflows: redo this pass from the tuples
+                merged = false;
+                if (threadIdx.x == 0) s_sp = sp;
+                continue;
+            }
+        } else {
+            w_accumulate(A.S, s0, s1, A.ddir, A.dpool, A.c_seed, A.c_bits, A.slot_seed, A.w_seed,
+                         level, pass, T);
+        }
         __syncthreads();
         if (s_over) {
             if (threadIdx.x == 0) {

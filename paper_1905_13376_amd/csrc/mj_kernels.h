@@ -232,6 +232,14 @@ struct WBuildArgs {
     unsigned long long* wcursor;
     unsigned long long wcap;
     uint32_t* err;               // set to 1 if the pool is exhausted
+    // optional (heavy keys): buckets of S split into pieces, one workgroup
+    // each; each piece's W table (CELL_CAP slots) and its sum for
+    // b = 0xFFFFFFFF by scratch row; split.done[bucket] counts finished
+    // pieces, its top bit set when a piece's table overflowed (the last
+    // piece then builds the bucket from its tuples)
+    BucketItems split;
+    WSlot* rows = nullptr;
+    unsigned long long* row_special = nullptr;
 };
 __global__ void k_wbuild(WBuildArgs A);
 

@@ -85,10 +85,20 @@ def main():
     n = 1 << (18 if tiny else 21)
     K = g.integers(0, 4096, size=(n, 2)).astype(np.uint32)
     K[: n // 4, 0] = 5
-    K[n // 4: (3 * n) // 5, 0] = 3000
+    K[n // 4: (4 * n) // 5, 0] = 3000
     g.shuffle(K)
     put("K", K, 4096)
     meta["K"]["closed_total"] = closed_total(K, K, K)
+    # a heavy key among many distinct ones, for hashed tables in four
+    # buckets: with keys below 2^16 a piece of the heavy bucket overflows
+    # its table (the bucket is read whole); below 19200 the pieces fit but
+    # their union does not (the pass is redone from the tuples)
+    for name, m, dom, heavy in (("K2", 131072, 1 << 16, 52428), ("K3", 86000, 19200, 40000)):
+        K2 = g.integers(0, dom, size=(m, 2)).astype(np.uint32)
+        K2[:heavy, 0] = 77
+        g.shuffle(K2)
+        put(name, K2, dom)
+        meta[name]["closed_total"] = closed_total(K2, K2, K2)
     with open(os.path.join(out, "meta.json"), "w") as f:
         json.dump(meta, f, indent=1)
     with open(os.path.join(out, "meta.txt"), "w") as f:          # name n a_domain closed_total

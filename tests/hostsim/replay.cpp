@@ -204,6 +204,34 @@ int main(int argc, char** argv) {
         }
         std::free(wsk); std::free(cd); std::free(ch);
         std::free(const_cast<uint32_t*>(K));
+        // a heavy key among many distinct keys, hashed tables in four
+        // buckets of B: a piece that overflows its table (K2) and pieces
+        // whose union does (K3)
+        for (const char* nm : {"K2", "K3"}) {
+            const Meta& m2 = g_meta.at(nm);
+            const uint32_t* K2 = load(nm);
+            const mj_rel R2 = rel_of(K2, m2.n);
+            mj_plan_t p2;
+            std::memset(&p2, 0, sizeof p2);
+            check(make_plan(ctx, MJ_LINEAR, &R2, &R2, &R2, m2.a_domain, &p2), "mj_plan skew wide");
+            p2.algo = MJ_ALGO_3WAY;
+            p2.log2_nb = 2;
+            p2.flags = (p2.flags & ~uint32_t(MJ_PLAN_DENSE_KEYS)) | MJ_PLAN_NO_DENSE;
+            const uint64_t need = mj_plan_workspace(MJ_LINEAR, R2.n, R2.n, R2.n);
+            void* pws = alloc(need);
+            check(mj_plan(ctx, MJ_LINEAR, &R2, &R2, &R2, m2.a_domain, MJ_PLANNER_FIXED, &p2, pws, need, nullptr),
+                  "mj_plan skew wide hashed");
+            std::free(pws);
+            void* ws2 = alloc(p2.workspace_bytes);
+            uint64_t* c2 = static_cast<uint64_t*>(alloc(uint64_t(m2.a_domain) * 8));
+            for (int i = 0; i < 2; ++i) {
+                check(mj_linear3_count(ctx, &R2, &R2, &R2, m2.a_domain, c2, &p2, ws2, p2.workspace_bytes, nullptr),
+                      "skew wide");
+                expect(sum(c2, m2.a_domain) == m2.closed, "skew wide: hashed sum equals the closed form");
+            }
+            std::free(ws2); std::free(c2);
+            std::free(const_cast<uint32_t*>(K2));
+        }
     }
     if (want("small")) {
         leg("small");

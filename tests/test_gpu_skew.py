@@ -116,3 +116,18 @@ def test_uncapped_powerlaw_full_size(mj, ctx):
     sample = np.unique(np.concatenate([np.argsort(deg)[-4:], rng.integers(0, n, 40)])).astype(np.uint32)
     al, want = oracle.linear3_count_sampled(F, F, F, sample)
     np.testing.assert_array_equal(got[al], want)
+
+
+@pytest.mark.parametrize("m,dom,heavy", [(131072, 1 << 16, 52428), (86000, 19200, 40000), (300000, 1 << 20, 120000)])
+def test_heavy_bucket_among_many_keys_hashed(mj, ctx, m, dom, heavy):
+    """Hashed tables in four buckets of B with one heavy key: the heavy
+    bucket runs as pieces; a piece whose table overflows sends the bucket
+    back to one workgroup (keys below 2^16), pieces whose union overflows
+    have the pass redone from the tuples (keys below 19200)."""
+    banner(f"skew: hashed, heavy bucket among {dom} keys")
+    F = heavy_relation(m, dom, [(77, heavy / m)], 31)
+    Fd = dev(F)
+    p = fixed_plan(mj, ctx, mj.LINEAR, Fd, Fd, Fd, dom, algo=mj.ALGO_3WAY, log2_nb=2, log2_nc=3,
+                   seed=0x1B873593, flags=mj.PLAN_NO_DENSE)
+    got = mj.as_u64(ctx.linear3_count(Fd, Fd, Fd, dom, plan=p))
+    np.testing.assert_array_equal(got, oracle.linear3_count(F, F, F, dom))
