@@ -174,6 +174,37 @@ struct Bump {
     }
 };
 
+// Skew split of a per-bucket kernel: a bucket of more than `chunk` tuples
+// (MJ_SPLIT_PCT percent of the mean bucket, at least SPLIT_MIN_CHUNK) runs
+// as several workgroups.  items: at most nb + n / chunk + 1 of them;
+// scratch rows: a split bucket has len > chunk, so its pieces number fewer
+// than 2 len / chunk, and all split buckets fewer than 2 n / chunk + 1.
+#ifndef MJ_SPLIT_PCT
+#define MJ_SPLIT_PCT 200
+#endif
+uint32_t split_chunk(uint64_t n, uint32_t bits) {
+    const uint64_t mean = (n + (uint64_t(1) << bits) - 1) >> bits;
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(SPLIT_MIN_CHUNK, mean * MJ_SPLIT_PCT / 100),
+                                        uint64_t(1) << 31);
+}
+uint32_t split_grid(uint64_t n, uint32_t bits) { return (1u << bits) + (uint32_t)(n / split_chunk(n, bits)) + 1; }
+// the work items of n tuples under a given split (its chunk may come from a
+// larger relation's layout: then they are fewer)
+uint32_t items_grid(const BucketItems& I, uint64_t n, uint32_t bits) {
+    return (1u << bits) + (uint32_t)(n / I.chunk) + 1;
+}
+uint64_t split_rows(uint64_t n, uint32_t bits) { return 2 * (n / split_chunk(n, bits)) + 1; }
+BucketItems take_items(Bump& B, uint64_t n, uint32_t bits) {
+    BucketItems I{};
+    const uint32_t nb = 1u << bits;
+    I.chunk = split_chunk(n, bits);
+    I.items = B.take<uint32_t>(split_grid(n, bits));
+    I.nitems = B.take<uint32_t>(1);
+    I.hrow = B.take<uint32_t>(nb);
+    I.done = B.take<uint32_t>(nb);
+    return I;
+}
+
 struct TableLayout {                 // bucketed multiplicity tables of one column
     uint32_t* hist;
     uint32_t* counts;
@@ -184,6 +215,9 @@ struct TableLayout {                 // bucketed multiplicity tables of one colu
     unsigned long long* pool_cursor;
     uint32_t* err;
     uint64_t pool_slots;
+    BucketItems split;               // heavy buckets in pieces: their items,
+    uint2* rows;                     // the pieces' (key, count) tables
+    uint32_t* row_special;
 };
 
 uint32_t ntiles_of(uint64_t n) { return (uint32_t)((n + PART_TILE - 1) / PART_TILE); }
@@ -203,6 +237,10 @@ void take_table(Bump& B, TableLayout& L, uint64_t n, uint32_t bits) {
     L.pool = B.take<uint2>(L.pool_slots);
     L.pool_cursor = B.take<unsigned long long>(1);
     L.err = B.take<uint32_t>(1);
+    L.split = take_items(B, n, bits);
+    const uint64_t nrows = split_rows(n, bits);
+    L.rows = B.take<uint2>(nrows * DB_CAP);
+    L.row_special = B.take<uint32_t>(nrows);
 }
 
 struct RelPart {                     // one relation partitioned into 2^bits buckets
@@ -211,32 +249,6 @@ struct RelPart {                     // one relation partitioned into 2^bits buc
     uint32_t* starts;
     uint2* pairs;
 };
-
-// Skew split of a per-bucket kernel: a bucket of more than `chunk` tuples
-// (MJ_SPLIT_PCT percent of the mean bucket, at least SPLIT_MIN_CHUNK) runs
-// as several workgroups.  items: at most nb + n / chunk + 1 of them;
-// scratch rows: a split bucket has len > chunk, so its pieces number fewer
-// than 2 len / chunk, and all split buckets fewer than 2 n / chunk + 1.
-#ifndef MJ_SPLIT_PCT
-#define MJ_SPLIT_PCT 200
-#endif
-uint32_t split_chunk(uint64_t n, uint32_t bits) {
-    const uint64_t mean = (n + (uint64_t(1) << bits) - 1) >> bits;
-    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(SPLIT_MIN_CHUNK, mean * MJ_SPLIT_PCT / 100),
-                                        uint64_t(1) << 31);
-}
-uint32_t split_grid(uint64_t n, uint32_t bits) { return (1u << bits) + (uint32_t)(n / split_chunk(n, bits)) + 1; }
-uint64_t split_rows(uint64_t n, uint32_t bits) { return 2 * (n / split_chunk(n, bits)) + 1; }
-BucketItems take_items(Bump& B, uint64_t n, uint32_t bits) {
-    BucketItems I{};
-    const uint32_t nb = 1u << bits;
-    I.chunk = split_chunk(n, bits);
-    I.items = B.take<uint32_t>(split_grid(n, bits));
-    I.nitems = B.take<uint32_t>(1);
-    I.hrow = B.take<uint32_t>(nb);
-    I.done = B.take<uint32_t>(nb);
-    return I;
-}
 
 void take_part(Bump& B, RelPart& P, uint64_t n, uint32_t bits) {
     const uint32_t nb = 1u << bits;
@@ -537,13 +549,15 @@ int launch_tables(Prof* prof, const TableLayout& L, const mj_rel& rel, int col, 
     P.job[0] = make_job(rel, L.hist, L.counts, L.starts, col, bseed, bits, 0, 0, 0);
     P.job[0].out_single = L.keys;
     P.job[0].single_col = col;
+    P.job[0].split = L.split;                    // heavy buckets in pieces
     int st2 = launch_partition(prof, "tab", P, st);
     if (st2) return st2;
-    DBuildArgs D;
+    DBuildArgs D{};
     D.keys = L.keys; D.starts = L.starts; D.nbkt = nb; D.slot_seed = sseed;
     D.dir = L.dir; D.pool = L.pool; D.pool_cursor = L.pool_cursor; D.pool_cap = L.pool_slots;
     D.err = L.err;
-    MJ_LAUNCH(prof, "tab:k_dbuild", k_dbuild, dim3(nb), dim3(DB_THREADS), 0, st, D);
+    D.split = L.split; D.rows = L.rows; D.row_special = L.row_special;
+    MJ_LAUNCH(prof, "tab:k_dbuild", k_dbuild, dim3(items_grid(L.split, rel.n, bits)), dim3(DB_THREADS), 0, st, D);
     return MJ_OK;
 }
 

@@ -64,53 +64,118 @@ __device__ __forceinline__ void gtab_add(uint2* base, uint32_t mask, uint32_t ke
 }
 
 // ------------------------------------------------ multiplicity tables (D)
-__global__ void __launch_bounds__(DB_THREADS)
-k_dbuild(DBuildArgs A) {
-    __shared__ uint32_t tkeys[DB_CAP];
-    __shared__ uint32_t tvals[DB_CAP];
-    __shared__ uint32_t s_special, s_distinct, s_over, s_log2;
-    __shared__ unsigned long long s_base;
-    const uint32_t j = blockIdx.x;
-    const uint32_t beg = A.starts[j], end = A.starts[j + 1];
-    const uint32_t n = end - beg;
+// count[k] += c in the LDS table; sets *over when the distinct keys reach
+// DB_LIMIT (no new key is claimed after the overflow flag -- the bucket is
+// then rebuilt in global memory -- so the LDS table never fills).
+__device__ __forceinline__ void db_add(uint32_t* tkeys, uint32_t* tvals, uint32_t* distinct, uint32_t* over,
+                                       uint32_t k, uint32_t c, uint32_t slot_seed) {
     const uint32_t mask = DB_CAP - 1;
+    uint32_t s = slot_hash(k, slot_seed) & mask;
+    for (uint32_t step = 0;; ++step) {
+        uint32_t cur = tkeys[s];
+        if (cur == k) { atomicAdd(&tvals[s], c); break; }
+        if (cur == EMPTY_KEY || step >= DB_CAP) {
+            if (*(volatile uint32_t*)over || step >= DB_CAP) { *over = 1; break; }
+            uint32_t old = atomicCAS(&tkeys[s], EMPTY_KEY, k);
+            if (old == EMPTY_KEY) {
+                if (atomicAdd(distinct, 1u) + 1 >= DB_LIMIT) *over = 1;
+                atomicAdd(&tvals[s], c);
+                break;
+            }
+            if (old == k) { atomicAdd(&tvals[s], c); break; }
+        }
+        s = (s + 1u) & mask;
+    }
+}
 
-    for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
-    if (threadIdx.x == 0) { s_special = 0; s_distinct = 0; s_over = 0; }
-    __syncthreads();
-
-    // four keys per thread and round: their loads are in flight together
-    // (a bucket crowded by a heavy key is one workgroup's work)
+// The keys of [beg, end) counted into the LDS table, four per thread and
+// round (their loads in flight together).
+__device__ __forceinline__ void db_count(const uint32_t* keys, uint32_t beg, uint32_t end, uint32_t* tkeys,
+                                         uint32_t* tvals, uint32_t* special, uint32_t* distinct, uint32_t* over,
+                                         uint32_t slot_seed) {
     for (uint32_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * blockDim.x) {
-        if (*(volatile uint32_t*)&s_over) break;
+        if (*(volatile uint32_t*)over) break;
         uint32_t kk[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t i = i0 + u * blockDim.x;
-            kk[u] = i < end ? A.keys[i] : EMPTY_KEY;
+            kk[u] = i < end ? keys[i] : EMPTY_KEY;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (i0 + u * blockDim.x >= end) break;
-            const uint32_t k = kk[u];
-            if (k == EMPTY_KEY) { atomicAdd(&s_special, 1u); continue; }
-            uint32_t s = slot_hash(k, A.slot_seed) & mask;
-            for (uint32_t step = 0;; ++step) {
-                uint32_t cur = tkeys[s];
-                if (cur == k) { atomicAdd(&tvals[s], 1u); break; }
-                if (cur == EMPTY_KEY || step >= DB_CAP) {
-                    // no new key is claimed after the overflow flag (the bucket is
-                    // rebuilt in global memory), so the LDS table never fills
-                    if (*(volatile uint32_t*)&s_over || step >= DB_CAP) { s_over = 1; break; }
-                    uint32_t old = atomicCAS(&tkeys[s], EMPTY_KEY, k);
-                    if (old == EMPTY_KEY) {
-                        if (atomicAdd(&s_distinct, 1u) + 1 >= DB_LIMIT) s_over = 1;
-                        atomicAdd(&tvals[s], 1u);
-                        break;
-                    }
-                    if (old == k) { atomicAdd(&tvals[s], 1u); break; }
+            if (kk[u] == EMPTY_KEY) { atomicAdd(special, 1u); continue; }
+            db_add(tkeys, tvals, distinct, over, kk[u], 1u, slot_seed);
+        }
+    }
+}
+
+// One workgroup per bucket: the (key, count) table in LDS, then one table
+// per bucket in the pool.  A bucket crowded by heavy keys runs as pieces,
+// one workgroup each, and the last piece to finish adds up their tables.
+__global__ void __launch_bounds__(DB_THREADS)
+k_dbuild(DBuildArgs A) {
+    __shared__ uint32_t tkeys[DB_CAP];
+    __shared__ uint32_t tvals[DB_CAP];
+    __shared__ uint32_t s_special, s_distinct, s_over, s_log2, s_last;
+    __shared__ unsigned long long s_base;
+    uint32_t j = blockIdx.x, piece = 0, pcs = 1;
+    if (A.split.items) {                                         // uniform over the block
+        if (blockIdx.x >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[blockIdx.x];
+        j = it & 0xFFFu;
+        piece = it >> 12;
+        pcs = split_pieces(A.starts[j + 1] - A.starts[j], A.split.chunk);
+    }
+    const uint32_t beg = A.starts[j], end = A.starts[j + 1];
+    const uint32_t n = end - beg;
+
+    for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
+    if (threadIdx.x == 0) { s_special = 0; s_distinct = 0; s_over = 0; }
+    __syncthreads();
+    if (pcs == 1) {
+        db_count(A.keys, beg, end, tkeys, tvals, &s_special, &s_distinct, &s_over, A.slot_seed);
+    } else {
+        // a piece: its counts to its scratch row (or, when its keys overflow
+        // the table, a flag); the last piece to finish builds the bucket
+        const uint32_t q0 = beg + (uint32_t)(uint64_t(n) * piece / pcs);
+        const uint32_t q1 = beg + (uint32_t)(uint64_t(n) * (piece + 1) / pcs);
+        db_count(A.keys, q0, q1, tkeys, tvals, &s_special, &s_distinct, &s_over, A.slot_seed);
+        __syncthreads();
+        const bool ovf = s_over != 0;
+        const uint64_t r = uint64_t(A.split.hrow[j]) + piece;
+        if (!ovf) {
+            uint2* row = A.rows + r * DB_CAP;
+            for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) row[s] = make_uint2(tkeys[s], tvals[s]);
+            if (threadIdx.x == 0) A.row_special[r] = s_special;
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (ovf) atomicOr(&A.split.done[j], 0x80000000u);
+            const uint32_t old = atomicAdd(&A.split.done[j], 1u);
+            s_last = (old & 0x7FFFFFFFu) == pcs - 1 ? 1u : 0u;
+        }
+        __syncthreads();
+        if (!s_last) return;                                     // uniform over the block
+        __threadfence();
+        const bool merged = (atomicAdd(&A.split.done[j], 0u) & 0x80000000u) == 0;
+        for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
+        __syncthreads();
+        if (threadIdx.x == 0) { s_special = 0; s_distinct = 0; s_over = merged ? 0u : 1u; }
+        __syncthreads();
+        if (merged) {                     // the pieces' tables added up (an overflow here spills too)
+            const uint2* first = A.rows + uint64_t(A.split.hrow[j]) * DB_CAP;
+            for (uint32_t p = 0; p < pcs; ++p)
+                for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) {
+                    if (*(volatile uint32_t*)&s_over) break;
+                    const uint2 e = first[uint64_t(p) * DB_CAP + s];
+                    if (e.x != EMPTY_KEY && e.y) db_add(tkeys, tvals, &s_distinct, &s_over, e.x, e.y, A.slot_seed);
                 }
-                s = (s + 1u) & mask;
+            if (threadIdx.x == 0) {
+                uint32_t sp = 0;
+                for (uint32_t p = 0; p < pcs; ++p) sp += A.row_special[A.split.hrow[j] + p];
+                s_special = sp;
             }
         }
     }

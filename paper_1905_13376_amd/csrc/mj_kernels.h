@@ -117,6 +117,13 @@ struct DBuildArgs {
     unsigned long long* pool_cursor;
     unsigned long long pool_cap;
     uint32_t* err;               // set to 1 if the pool is exhausted
+    // optional (heavy keys): buckets split into pieces, one workgroup each;
+    // each piece's counts (DB_CAP slots of (key, count)) and its count of
+    // key 0xFFFFFFFF by scratch row; split.done[bucket] counts finished
+    // pieces, its top bit set when a piece's table overflowed
+    BucketItems split;
+    uint2* rows = nullptr;
+    uint32_t* row_special = nullptr;
 };
 __global__ void k_dbuild(DBuildArgs A);
 
