@@ -720,7 +720,17 @@ def triangle_path(mj, ctx):
         golden = json.load(open(gp))["total"]
     tri = {}
     tot = torch.empty(1, dtype=torch.int64, device="cuda")
-    for share in (0, 2, 4):
+    # the general join's list work: each S tuple (b, c) is handled once, by
+    # the shorter of R's list of b and T's list of c, so it visits
+    # sum over S of min(deg b, deg c) list elements (R = S = T symmetric)
+    import numpy as np
+    deg = np.bincount(E[:, 0].astype(np.int64))
+    visits = int(np.minimum(deg[E[:, 0].astype(np.int64)], deg[E[:, 1].astype(np.int64)]).sum(dtype=np.int64))
+    del deg
+    tri["general_join_list_elements_visited"] = visits
+    # shares 1, 4, 16 and the menu 8, 16, 32 of the workload statement (the
+    # least number of A-slices of a hub list)
+    for share in (0, 2, 3, 4, 5):
         p = mj.Plan()
         p.log2_share = share
         p.seed = 0x1B873593
@@ -729,8 +739,10 @@ def triangle_path(mj, ctx):
         ms_t, kp = time_and_profile(ctx, lambda: ctx.triangle3_count(Ed, Ed, Ed, plan=pt, out=tot, workspace=ws),
                                     2, 1, 1)
         got = int(mj.as_u64(tot)[0])
+        join_ms = sum(v[0] for k, v in kp.items() if k.startswith("k_tri_light") or k.startswith("k_tri_heavy"))
         tri[f"share_{1 << share}"] = {
             "ms": round(ms_t, 2), "tuples_per_s": 3 * E.shape[0] / (ms_t * 1e-3),
+            "list_elements_per_s_in_join_kernels": visits / (join_ms * 1e-3) if join_ms else None,
             "total": got, "triangles": got // 6,
             "matches_oracle_total": (got == golden) if golden is not None else None,
             "kernels_ms_per_call": {k: round(v[0], 3) for k, v in sorted(kp.items(), key=lambda kv: -kv[1][0])[:8]}}
