@@ -520,9 +520,13 @@ int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st)
         maxbits = std::max(maxbits, bits);
     }
     const std::string t(tag);
-    if (tiles)
+    // k_part_hist clears the caller's words first
+    if (tiles) {
         MJ_LAUNCH(prof, t + ":k_part_hist", k_part_hist, dim3(tiles), dim3(PART_THREADS),
                   (size_t(1) << maxbits) * 4, st, P);
+    } else if (P.nclear) {
+        MJ_LAUNCH(prof, t + ":k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, P.clear, (uint64_t)P.nclear, 0u);
+    }
     MJ_LAUNCH(prof, t + ":k_part_rowscan", k_part_rowscan, dim3(rows), dim3(PART_THREADS),
               PART_SCAN_CHUNK * 4, st, P);
     MJ_LAUNCH(prof, t + ":k_part_scan", k_part_scan, dim3(P.njobs), dim3(PART_THREADS),
@@ -1198,7 +1202,6 @@ FmLayout fm_layout(void* ws, uint64_t nr, uint64_t ns, uint64_t nt, uint32_t a_d
 int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, const mj_plan_t& p,
               unsigned long long* count, void* ws, hipStream_t s) {
     DenseLayout L = dense_layout(ws, p);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)3, 0u);
     // S by range of B, R by range of A, T by range of C: each on its first
     // column.  A partition identical to an earlier one (same columns,
     // stride, size and ranges: R = S = T in a self-join) is not made again;
@@ -1208,6 +1211,7 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     };
     PartLaunch P{};
     P.njobs = 0;
+    P.clear = L.err; P.nclear = 3;                   // the flags, cleared by the first launch
     P.job[P.njobs] = make_job(S, L.S.hist, L.S.counts, L.S.starts, 0, 0, L.b_bits, 0, 0, 0);
     P.job[P.njobs].range_on = 1; P.job[P.njobs].range_shift = L.b_shift;
     P.job[P.njobs].split = L.Ssplit;
@@ -1260,6 +1264,7 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     Ac.split = Rsp; Ac.rows = L.rows; Ac.row_len = 1u << L.a_shift;
     MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(split_grid(n_rp, L.a_bits)), dim3(RANGE_THREADS),
               size_t(8) << L.a_shift, s, Ac);
+    // a key beyond its certified bound: every count all ones
     MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)p.a_domain, L.err);
     return MJ_OK;

@@ -81,6 +81,8 @@ struct PartJob {
 struct PartLaunch {
     PartJob job[MJ_PART_MAX_JOBS];
     int njobs;
+    uint32_t* clear = nullptr;   // words k_part_hist sets to 0 first (flags of the caller's kernels)
+    uint32_t nclear = 0;
 };
 
 __global__ void k_part_hist(PartLaunch L);

@@ -107,6 +107,9 @@ k_part_hist(PartLaunch L) {
     const int jid = find_job(L, blk);
     const PartJob& J = L.job[jid];
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
+    if (blockIdx.x == 0) {                           // before the next launches of the group
+        for (uint32_t w = threadIdx.x; w < L.nclear; w += blockDim.x) L.clear[w] = 0;
+    }
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lhist[d] = 0;
     __syncthreads();
     const uint32_t tile = blk - J.tile_begin;
@@ -154,44 +157,50 @@ k_part_rowscan(PartLaunch L) {
     if (threadIdx.x == 0) J.counts[row] = carry;
 }
 
-// One block per job: starts[d] = exclusive prefix of counts, starts[nb] = n.
-__global__ void __launch_bounds__(PART_THREADS)
-k_part_scan(PartLaunch L) {
-    extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
-    const PartJob& J = L.job[blockIdx.x];
+// Bucket starts of one job: starts[d] = exclusive prefix of counts,
+// starts[nb] = n; then, when the job asks, the work items of its buckets:
+// first the pieces of the split buckets (so the longest work starts first;
+// piece p of bucket d is item and scratch row hrow[d] + p), then the other
+// buckets in bucket order.  All threads of the block call it.
+__device__ void part_scan_job(const PartJob& J, uint32_t* lds, uint32_t* wave_tmp) {
+    const uint32_t* counts = J.counts;
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
-    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = J.counts[d];
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = counts[d];
     __syncthreads();
     uint32_t total = block_exclusive_scan(lds, nb, wave_tmp);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) J.starts[d] = lds[d];
     if (threadIdx.x == 0) J.starts[nb] = total;
     if (!J.split.items) return;                      // uniform over the block
-    // work items: first the pieces of the split buckets (so the longest
-    // work starts first; piece p of bucket d is item and scratch row
-    // hrow[d] + p), then the other buckets in bucket order
     const BucketItems& B = J.split;
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
-        const uint32_t pcs = split_pieces(J.counts[d], B.chunk);
+        const uint32_t pcs = split_pieces(counts[d], B.chunk);
         lds[d] = pcs > 1 ? pcs : 0u;
     }
     __syncthreads();
     const uint32_t heavy = block_exclusive_scan(lds, nb, wave_tmp);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) {
-        const uint32_t pcs = split_pieces(J.counts[d], B.chunk);
+        const uint32_t pcs = split_pieces(counts[d], B.chunk);
         if (pcs == 1) continue;
         B.hrow[d] = lds[d];
         B.done[d] = 0;
         for (uint32_t p = 0; p < pcs; ++p) B.items[lds[d] + p] = d | (p << 12);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = split_pieces(J.counts[d], B.chunk) == 1 ? 1u : 0u;
+    for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lds[d] = split_pieces(counts[d], B.chunk) == 1 ? 1u : 0u;
     __syncthreads();
     const uint32_t light = block_exclusive_scan(lds, nb, wave_tmp);
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x)
-        if (split_pieces(J.counts[d], B.chunk) == 1) B.items[heavy + lds[d]] = d;
+        if (split_pieces(counts[d], B.chunk) == 1) B.items[heavy + lds[d]] = d;
     if (threadIdx.x == 0) *B.nitems = heavy + light;
+}
+
+// One block per job.
+__global__ void __launch_bounds__(PART_THREADS)
+k_part_scan(PartLaunch L) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
+    part_scan_job(L.job[blockIdx.x], lds, wave_tmp);
 }
 
 __global__ void __launch_bounds__(PART_SCATTER_THREADS)
