@@ -149,7 +149,7 @@ k_dbuild(DBuildArgs A) {
             for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) row[s] = make_uint2(tkeys[s], tvals[s]);
             if (threadIdx.x == 0) A.row_special[r] = s_special;
         }
-        __threadfence();
+        handoff_release();
         __syncthreads();
         if (threadIdx.x == 0) {
             if (ovf) atomicOr(&A.split.done[j], 0x80000000u);
@@ -158,7 +158,7 @@ k_dbuild(DBuildArgs A) {
         }
         __syncthreads();
         if (!s_last) return;                                     // uniform over the block
-        __threadfence();
+        handoff_acquire();
         const bool merged = (atomicAdd(&A.split.done[j], 0u) & 0x80000000u) == 0;
         for (uint32_t s = threadIdx.x; s < DB_CAP; s += blockDim.x) { tkeys[s] = EMPTY_KEY; tvals[s] = 0; }
         __syncthreads();
@@ -491,7 +491,7 @@ k_wbuild(WBuildArgs A) {
             }
             if (threadIdx.x == 0) A.row_special[r] = w_special;
         }
-        __threadfence();
+        handoff_release();
         __syncthreads();
         if (threadIdx.x == 0) {
             if (ovf) atomicOr(&A.split.done[i], 0x80000000u);
@@ -500,7 +500,7 @@ k_wbuild(WBuildArgs A) {
         }
         __syncthreads();
         if (!s_last) return;                                     // uniform over the block
-        __threadfence();
+        handoff_acquire();
         merged = (atomicAdd(&A.split.done[i], 0u) & 0x80000000u) == 0;
         __syncthreads();
     }
@@ -687,12 +687,12 @@ __device__ __forceinline__ bool split_merge(const BucketItems& B, uint32_t k, ui
     __shared__ uint32_t s_last;
     TO* mine = rows + (uint64_t(B.hrow[k]) + piece) * row_len;
     for (uint32_t j = threadIdx.x; j < span; j += blockDim.x) mine[j] = acc[j];
-    __threadfence();
+    handoff_release();
     __syncthreads();
     if (threadIdx.x == 0) s_last = atomicAdd(&B.done[k], 1u) == pcs - 1 ? 1u : 0u;
     __syncthreads();
     if (!s_last) return false;                                      // uniform over the block
-    __threadfence();
+    handoff_acquire();
     const TO* first = rows + uint64_t(B.hrow[k]) * row_len;
     for (uint32_t j = threadIdx.x; j < span; j += blockDim.x) {
         TO v = 0;

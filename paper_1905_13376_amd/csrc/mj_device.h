@@ -88,6 +88,17 @@ __device__ __forceinline__ bool wave_fold_first(uint32_t key, bool act, T& v) {
     return true;
 }
 
+// Hand-off between workgroups through a ticket atomic (the last of a
+// bucket's pieces adds up the others' rows): the writers' release makes
+// their stores visible at device scope before their ticket add, and the
+// last workgroup's acquire after its ticket add makes them visible to its
+// loads.  Each XCD has its own L2: the release writes the XCD's dirty lines
+// back, the acquire invalidates the XCD's L2, so the writers do only the
+// former (a full fence in every piece also threw away the gathered arrays
+// the other workgroups of its XCD were reading).
+__device__ __forceinline__ void handoff_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void handoff_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Read tuple component from a strided column.
 __device__ __forceinline__ uint32_t ld_col(const uint32_t* __restrict__ col, uint64_t i,
                                            int64_t stride) {

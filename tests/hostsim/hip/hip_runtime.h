@@ -100,6 +100,8 @@ inline T from_bits(uint64_t b) {
 inline unsigned __lane_id() { return ::hipsim::lane(); }
 inline void __syncthreads() { ::hipsim::syncthreads(); }
 inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
+// the device's scoped fence builtin: a fence of the given order on the host
+#define __builtin_amdgcn_fence(order, scope) __atomic_thread_fence(order)
 #define __builtin_amdgcn_wave_barrier() ((void)0)
 #define __builtin_amdgcn_fence(...) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 
