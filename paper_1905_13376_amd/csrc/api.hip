@@ -692,7 +692,7 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
         uint32_t P = 2;
         while (P < n) P <<= 1;
         const uint32_t shift = 8 * first_pass;
-        const size_t smem = size_t(shift ? 2 : 1) * P * sizeof(unsigned long long);
+        const size_t smem = size_t(P) * sizeof(unsigned long long);
         MJ_LAUNCH(prof, "k_rs_small", k_rs_small, dim3(1), dim3(RS_SMALL_THREADS), smem, s, keys, (uint32_t)n,
                   shift);
         return MJ_OK;
@@ -1510,7 +1510,7 @@ int mj_ctx_create(int device, mj_ctx** out) {
                               (int)part_scatter_smem(PART_MAX_BITS));
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rs_small),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(2 * RS_SMALL * sizeof(unsigned long long)));
+                              (int)(RS_SMALL * sizeof(unsigned long long)));
     (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
     // the scratch array's address on this device (the device is current here)
     e = hipGetSymbolAddress(&c->static_scratch, HIP_SYMBOL(scratch));

@@ -573,11 +573,11 @@ struct RsArgs {
 __global__ void k_rs_hist(RsArgs A);
 __global__ void k_rs_scatter(RsArgs A);
 // small arrays: the whole sort in one workgroup, or one scan launch per pass
-constexpr uint32_t RS_SMALL_BITS = 13;
+constexpr uint32_t RS_SMALL_BITS = 14;
 constexpr uint32_t RS_SMALL = 1u << RS_SMALL_BITS;   // keys sorted whole in LDS
 constexpr int RS_SMALL_THREADS = 1024;
 constexpr uint32_t RS_SCAN1_TILES = 32;              // tiles scanned by one workgroup
-static_assert(2 * size_t(RS_SMALL) * 8 <= LDS_BYTES && RS_SMALL_BITS <= 16, "small sort shape");
+static_assert(size_t(RS_SMALL) * 8 <= LDS_BYTES && RS_SMALL_BITS <= 16, "small sort shape");
 __global__ void k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift);
 __global__ void k_rs_scan1(RsArgs A, uint32_t* starts);
 

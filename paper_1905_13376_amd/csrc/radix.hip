@@ -128,17 +128,13 @@ k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift) {
     uint32_t P = 2;
     while (P < n) P <<= 1;
     unsigned long long* v = rs_lds;
-    unsigned long long* orig = rs_lds + P;   // written only when shift > 0
+    // sorting on the bits above `shift` only: the sort key is those bits
+    // with the element's index below them, so equal keys keep their order
     for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
         unsigned long long x = ~0ull;
         if (i < n) {
             const unsigned long long k = keys[i];
-            if (shift) {
-                orig[i] = k;
-                x = ((k >> shift) << RS_SMALL_BITS) | i;
-            } else {
-                x = k;
-            }
+            x = shift ? (((k >> shift) << RS_SMALL_BITS) | i) : k;
         }
         v[i] = x;
     }
@@ -157,8 +153,11 @@ k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift) {
             __syncthreads();
         }
     }
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
-        keys[i] = shift ? orig[uint32_t(v[i]) & (RS_SMALL - 1u)] : v[i];
+    if (shift) {                      // the original keys, in sorted order, gathered before any is overwritten
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) v[i] = keys[uint32_t(v[i]) & (RS_SMALL - 1u)];
+        __syncthreads();
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) keys[i] = v[i];
 }
 
 }  // namespace mj

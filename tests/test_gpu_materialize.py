@@ -107,7 +107,7 @@ def test_emit_hubs_sparse_r_and_empty_pairs(mj, ctx):
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("n", [2, 8191, 8192, 8193, 131072, 131073])
+@pytest.mark.parametrize("n", [2, 8191, 8192, 8193, 16383, 16384, 16385, 131072, 131073])
 def test_emit_sort_sizes(mj, ctx, n):
     """S and T of n tuples with long runs of equal B and of equal C, whose
     order in the output is the relations' own order; n at the edges of the

@@ -47,10 +47,10 @@ def test_triangle_random_bags(mj, ctx, seed):
     assert tri(mj, ctx, R, S, T) == oracle.triangle3_count(R, S, T)
 
 
-@pytest.mark.parametrize("n", [8191, 8192, 8193, 131072, 131073])
+@pytest.mark.parametrize("n", [8191, 8192, 8193, 16383, 16384, 16385, 131072, 131073])
 def test_triangle_sort_sizes(mj, ctx, n):
-    """Relations of n tuples, at the edges of the one-workgroup sort (8192
-    keys) and of the one-launch scan (32 tiles of 4096 keys)."""
+    """Relations of n tuples, at the edges of the one-workgroup sort (16384
+    keys; 8192 before) and of the one-launch scan (32 tiles of 4096 keys)."""
     banner(f"triangle, relations of {n} tuples")
     rng = np.random.default_rng(n)
     R, S, T = (rng.integers(0, 3000, size=(n, 2)).astype(np.uint32) for _ in range(3))
