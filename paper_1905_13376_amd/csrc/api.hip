@@ -659,6 +659,10 @@ int launch_scan_u32(Prof* prof, const uint32_t* in, uint64_t n, unsigned long lo
         MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
         return MJ_OK;
     }
+    if (nblk == 1) {                         // one tile: one launch
+        MJ_LAUNCH(prof, "k_scan_one", k_scan_one, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, out);
+        return MJ_OK;
+    }
     MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
     MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, nblk);
     MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
@@ -670,6 +674,10 @@ int launch_scan_u64(Prof* prof, const unsigned long long* in, uint64_t n, unsign
     const uint32_t nblk = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
     if (nblk == 0) {
         MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+        return MJ_OK;
+    }
+    if (nblk == 1) {
+        MJ_LAUNCH(prof, "k_scan_one64", k_scan_one64, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, out);
         return MJ_OK;
     }
     MJ_LAUNCH(prof, "k_scan_reduce64", k_scan_reduce64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
@@ -2049,13 +2057,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     X.R = L.S.pairs; X.rstarts = L.S.starts; X.S = L.R.pairs; X.sstarts = L.R.starts;
     X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
     MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
-    const uint32_t nblk = (uint32_t)((R->n + SCAN_TILE - 1) / SCAN_TILE);
-    MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s,
-              L.ecnt, (uint64_t)R->n, L.partial);
-    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s,
-              L.partial, nblk);
-    MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s,
-              L.ecnt, (uint64_t)R->n, L.partial, L.eoff);
+    if ((st = launch_scan_u32(prof, L.ecnt, R->n, L.partial, L.eoff, s))) return st;
     // the chunks below cover the plan's |I|: an intermediate of another size
     // (same relations, other contents) makes every count all ones
     uint32_t* verr = dense ? L.dflags : L.T.err;

@@ -231,6 +231,43 @@ k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial, 
     scan_apply(in, n, partial, out);
 }
 
+// At most SCAN_TILE elements: the whole scan in one workgroup, one launch.
+template <class In>
+__device__ __forceinline__ void scan_one(const In* in, uint64_t n, unsigned long long* out) {
+    __shared__ unsigned long long ws[SCAN_THREADS / WAVE + 1];
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < n; c0 += SCAN_THREADS) {
+        const uint64_t i = c0 + threadIdx.x;
+        const unsigned long long x = i < n ? in[i] : 0ull;
+        unsigned long long v = x;
+        const int lane = lane_id();
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            unsigned long long y = __shfl_up(v, off, WAVE);
+            if (lane >= off) v += y;
+        }
+        const int w = threadIdx.x / WAVE;
+        if (lane == WAVE - 1) ws[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long run = 0;
+            for (int q = 0; q < SCAN_THREADS / WAVE; ++q) { unsigned long long t = ws[q]; ws[q] = run; run += t; }
+            ws[SCAN_THREADS / WAVE] = run;
+        }
+        __syncthreads();
+        if (i < n) out[i] = carry + ws[w] + v - x;
+        carry += ws[SCAN_THREADS / WAVE];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_one(const uint32_t* in, uint64_t n, unsigned long long* out) { scan_one(in, n, out); }
+
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_scan_one64(const unsigned long long* in, uint64_t n, unsigned long long* out) { scan_one(in, n, out); }
+
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_scan_apply64(const unsigned long long* in, uint64_t n, const unsigned long long* partial,
                unsigned long long* out) {

@@ -557,6 +557,9 @@ __global__ void k_scan_apply64(const unsigned long long* in, uint64_t n, const u
 __global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
 __global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
                              unsigned long long* out);
+// at most SCAN_TILE elements: out[i] = sum of in[0..i) for i in [0, n], one workgroup
+__global__ void k_scan_one(const uint32_t* in, uint64_t n, unsigned long long* out);
+__global__ void k_scan_one64(const unsigned long long* in, uint64_t n, unsigned long long* out);
 
 // ------------------------------------------------------------- radix sort
 constexpr int RS_THREADS = 256;
