@@ -273,26 +273,29 @@ int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const 
                            uint64_t first, uint64_t cap, uint32_t* out, uint64_t* total,
                            void* workspace, uint64_t workspace_bytes, void* stream);
 
-/* A batch of independent joins (many joins of uneven size).  Every item
- * carries its relations, its output (uint64[a_domain] or uint64[1], device)
- * and a plan from mj_plan (or the autotuner).  The preparation of every join
- * (partitions, multiplicity tables, sorts, work queues) is launched join by
- * join on four lanes, `stream` and three streams the context owns (default
- * priority), each join on the lane with the least work so far; the
- * context's streams start after everything queued on `stream` before the
- * call and `stream` waits for all of them, so the call is ordered on
- * `stream` like any other.  Then the cells of ALL linear
- * joins run in one launch on `stream`, and the groups
- * of ALL cyclic joins in two persistent launches that pull work items from
- * device queues (so the many small joins share the chip instead of each
- * paying its own tail).  Items planned as cascades run their own path.
- * The device argument tables are copied from pinned host memory.  An
- * eager call reuses the context's buffer, and first waits (on the host)
- * until the previous call's copy out of it has run.  A call under stream
- * capture synchronises nothing with the host: its tables get a buffer of
- * their own, kept until mj_ctx_destroy because every replay reads it, so
- * the whole call can be captured in a HIP graph and replayed.  Workspace:
- * at least mj_batch_workspace() bytes; each join gets its own slice.     */
+/* A batch of independent joins (many joins of uneven size; Sec. 5 runs the
+ * partition triples one after another on one chip, here the joins share
+ * it).  Every item carries its relations, its output (uint64[a_domain] or
+ * uint64[1], device) and a plan from mj_plan (or the autotuner).  The call
+ * first records each join's work as the ordered list of launches its own
+ * call would make (partitions, multiplicity tables, sorts, scans, work
+ * queues; cascades, star and oriented plans their whole path), then issues
+ * the lists together on `stream`: each step launches one kernel once for
+ * every join whose next launch it is, as one grid (per-join argument
+ * structs and block counts in a table on the device), so the number of
+ * launches follows the longest list rather than the number of joins.  The
+ * cells of ALL linear 3-way joins then run in one launch, and the groups of
+ * ALL cyclic 3-way joins in two persistent launches that pull work items
+ * from device queues.  The device argument tables are copied from pinned
+ * host memory.  An eager call reuses the context's buffer, and first waits
+ * (on the host) until the previous call's copy out of it has run.  A call
+ * under stream capture synchronises nothing with the host: its tables get
+ * a buffer of their own, kept until mj_ctx_destroy because every replay
+ * reads it, so the whole call can be captured in a HIP graph and replayed.
+ * Workspace: at least mj_batch_workspace() bytes (each join's own
+ * workspace, then the tables; the call fails with MJ_ERR_WORKSPACE when it
+ * is short).  mj_batch_workspace records the joins' work on the host to
+ * size the tables, allocating nothing on the device.                       */
 typedef struct {
     int32_t kind;
     uint32_t a_domain;

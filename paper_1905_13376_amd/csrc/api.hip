@@ -13,14 +13,35 @@
 #include "mj_host.h"
 #include "mj_plan_model.h"
 
+#include <functional>
 #include <map>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 using namespace mj;
 
+// One launch (or device copy) of a join's path, recorded instead of issued
+// while a batch gathers its joins' work.  A kernel with a merged form
+// (`multi`) runs in one grid with the same kernel's launches of other joins;
+// anything else is issued alone, in its join's order.
+struct LaunchRec {
+    std::string name;
+    const void* multi = nullptr;          // the kernel's merged form, or null
+    uint32_t grid = 0, block = 0, smem = 0;
+    uint32_t asz = 0;                     // bytes of its argument struct (merged form)
+    size_t aoff = 0;                      // where they sit in the chain's `args`
+    std::function<int(hipStream_t)> alone;
+};
+struct LaunchChain {                      // one join's work, in order
+    std::vector<LaunchRec> recs;
+    std::vector<unsigned char> args;
+};
+
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 struct Prof {
+    LaunchChain* rec = nullptr;           // set: launches are recorded here, not issued
     bool on = false;
     struct Rec { std::string name; hipEvent_t a, b; };
     std::vector<Rec> pending;
@@ -47,9 +68,52 @@ struct Prof {
     }
 };
 
-// Launch a kernel, bracketed by timing events when profiling is on.
+template <class... P, class... A>
+static void record_alone(LaunchChain* c, const std::string& name, void (*kern)(P...), dim3 g, dim3 b,
+                         uint32_t smem, A&&... a) {
+    LaunchRec r;
+    r.name = name;
+    r.grid = g.x * g.y * g.z;
+    r.block = b.x * b.y * b.z;
+    r.smem = smem;
+    std::tuple<typename std::decay<P>::type...> args(std::forward<A>(a)...);   // converted now
+    r.alone = [=](hipStream_t st) -> int {
+        std::apply([&](const auto&... x) { hipLaunchKernelGGL(kern, g, b, smem, st, x...); }, args);
+        return hipGetLastError() == hipSuccess ? MJ_OK : MJ_ERR_HIP;
+    };
+    c->recs.push_back(std::move(r));
+}
+
+template <class Args>
+static void record_merged(LaunchChain* c, const std::string& name, void (*multi)(MultiGrid), void (*kern)(Args),
+                          dim3 g, dim3 b, uint32_t smem, const Args& a) {
+    static_assert(std::is_trivially_copyable<Args>::value, "argument structs are copied as bytes");
+    LaunchRec r;
+    r.name = name;
+    r.multi = reinterpret_cast<const void*>(multi);
+    r.grid = g.x * g.y * g.z;
+    r.block = b.x * b.y * b.z;
+    r.smem = smem;
+    r.asz = (uint32_t)sizeof(Args);
+    r.aoff = c->args.size();
+    const unsigned char* bytes = reinterpret_cast<const unsigned char*>(&a);
+    c->args.insert(c->args.end(), bytes, bytes + sizeof(Args));
+    r.alone = [=](hipStream_t st) -> int {
+        hipLaunchKernelGGL(kern, g, b, smem, st, a);
+        return hipGetLastError() == hipSuccess ? MJ_OK : MJ_ERR_HIP;
+    };
+    c->recs.push_back(std::move(r));
+}
+
+// Launch a kernel, bracketed by timing events when profiling is on (or
+// record it, inside a batch).
 #define MJ_LAUNCH(prof, name, kern, grid, block, smem, st, ...)                       \
     do {                                                                           \
+        if ((prof) && (prof)->rec) {                                               \
+            record_alone((prof)->rec, std::string(name), kern, dim3(grid), dim3(block), \
+                         (uint32_t)(smem), __VA_ARGS__);                           \
+            break;                                                                 \
+        }                                                                          \
         hipEvent_t ea_ = nullptr, eb_ = nullptr;                                   \
         if ((prof) && (prof)->on) { ea_ = (prof)->ev(); eb_ = (prof)->ev();        \
                                     (void)hipEventRecord(ea_, st); }               \
@@ -64,10 +128,20 @@ struct Prof {
                    (prof)->pending.push_back({std::string(name), ea_, eb_}); }     \
     } while (0)
 
-// ------------------------------------------------------------------ context
-constexpr int BATCH_LANES = 3;   // a batch's own streams; with the caller's, the four hardware
-                                 // queues one process gets by default
+// Launch a kernel written with MJ_KERNEL; the arguments initialise its
+// argument struct.  Inside a batch the launch is recorded in its merged form.
+#define MJ_LAUNCHM(prof, name, kern, grid, block, smem, st, ...)                      \
+    do {                                                                           \
+        const kern##_args ma_{__VA_ARGS__};                                        \
+        if ((prof) && (prof)->rec) {                                               \
+            record_merged((prof)->rec, std::string(name), kern##_multi, kern, dim3(grid), \
+                          dim3(block), (uint32_t)(smem), ma_);                     \
+            break;                                                                 \
+        }                                                                          \
+        MJ_LAUNCH(prof, name, kern, grid, block, smem, st, ma_);                   \
+    } while (0)
 
+// ------------------------------------------------------------------ context
 struct mj_ctx {
     int device = 0;
     int num_cu = 256;
@@ -79,12 +153,6 @@ struct mj_ctx {
     size_t stage_bytes = 0;
     hipEvent_t stage_read = nullptr;            // recorded after the last copy out of `stage`
     const void* planner = nullptr;              // learned planner parameters (device)
-    // streams on which a batch prepares its joins side by side (default
-    // priority), the events that join each back to the caller's stream, and
-    // the one that forks them from it; made at the first batch call
-    hipStream_t lanes[BATCH_LANES] = {};
-    hipEvent_t lane_done[BATCH_LANES] = {};
-    hipEvent_t lane_fork = nullptr;
     // this device's copy of the file-scope scratch array (device address),
     // found once at context creation
     void* static_scratch = nullptr;
@@ -522,17 +590,17 @@ int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st)
     const std::string t(tag);
     // k_part_hist clears the caller's words first
     if (tiles) {
-        MJ_LAUNCH(prof, t + ":k_part_hist", k_part_hist, dim3(tiles), dim3(PART_THREADS),
+        MJ_LAUNCHM(prof, t + ":k_part_hist", k_part_hist, dim3(tiles), dim3(PART_THREADS),
                   (size_t(1) << maxbits) * 4, st, P);
     } else if (P.nclear) {
-        MJ_LAUNCH(prof, t + ":k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, P.clear, (uint64_t)P.nclear, 0u);
+        MJ_LAUNCHM(prof, t + ":k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, P.clear, (uint64_t)P.nclear, 0u);
     }
-    MJ_LAUNCH(prof, t + ":k_part_rowscan", k_part_rowscan, dim3(rows), dim3(PART_THREADS),
+    MJ_LAUNCHM(prof, t + ":k_part_rowscan", k_part_rowscan, dim3(rows), dim3(PART_THREADS),
               PART_SCAN_CHUNK * 4, st, P);
-    MJ_LAUNCH(prof, t + ":k_part_scan", k_part_scan, dim3(P.njobs), dim3(PART_THREADS),
+    MJ_LAUNCHM(prof, t + ":k_part_scan", k_part_scan, dim3(P.njobs), dim3(PART_THREADS),
               (size_t(1) << maxbits) * 4, st, P);
     if (tiles)
-        MJ_LAUNCH(prof, t + ":k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_SCATTER_THREADS),
+        MJ_LAUNCHM(prof, t + ":k_part_scatter", k_part_scatter, dim3(tiles), dim3(PART_SCATTER_THREADS),
                   part_scatter_smem(maxbits), st, P);
     return MJ_OK;
 }
@@ -541,12 +609,12 @@ int launch_partition(Prof* prof, const char* tag, PartLaunch& P, hipStream_t st)
 int launch_tables(Prof* prof, const TableLayout& L, const mj_rel& rel, int col, uint32_t bits,
                   uint32_t bseed, uint32_t sseed, hipStream_t st) {
     const uint32_t nb = 1u << bits;
-    MJ_LAUNCH(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.pool),
+    MJ_LAUNCHM(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(L.pool),
                        (uint64_t)(2 * DB_MIN_CAP), EMPTY_KEY);
     // pool[0..DB_MIN_CAP) stays empty (keys EMPTY); cursor = DB_MIN_CAP; err = 0
-    MJ_LAUNCH(prof, "tab:k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, st, L.pool_cursor, (uint64_t)1,
+    MJ_LAUNCHM(prof, "tab:k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, st, L.pool_cursor, (uint64_t)1,
                        (unsigned long long)DB_MIN_CAP);
-    MJ_LAUNCH(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCHM(prof, "tab:k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, st, L.err, (uint64_t)1, 0u);
 
     PartLaunch P{};
     P.njobs = 1;
@@ -561,7 +629,7 @@ int launch_tables(Prof* prof, const TableLayout& L, const mj_rel& rel, int col, 
     D.dir = L.dir; D.pool = L.pool; D.pool_cursor = L.pool_cursor; D.pool_cap = L.pool_slots;
     D.err = L.err;
     D.split = L.split; D.rows = L.rows; D.row_special = L.row_special;
-    MJ_LAUNCH(prof, "tab:k_dbuild", k_dbuild, dim3(items_grid(L.split, rel.n, bits)), dim3(DB_THREADS), 0, st, D);
+    MJ_LAUNCHM(prof, "tab:k_dbuild", k_dbuild, dim3(items_grid(L.split, rel.n, bits)), dim3(DB_THREADS), 0, st, D);
     return MJ_OK;
 }
 
@@ -656,16 +724,16 @@ int launch_scan_u32(Prof* prof, const uint32_t* in, uint64_t n, unsigned long lo
                     unsigned long long* out, hipStream_t s) {
     const uint32_t nblk = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
     if (nblk == 0) {
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
         return MJ_OK;
     }
     if (nblk == 1) {                         // one tile: one launch
-        MJ_LAUNCH(prof, "k_scan_one", k_scan_one, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, out);
+        MJ_LAUNCHM(prof, "k_scan_one", k_scan_one, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, partial, out, nblk);
         return MJ_OK;
     }
-    MJ_LAUNCH(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
-    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, nblk);
-    MJ_LAUNCH(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    MJ_LAUNCHM(prof, "k_scan_reduce", k_scan_reduce, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out, nblk);
+    MJ_LAUNCHM(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, partial, out, nblk);
+    MJ_LAUNCHM(prof, "k_scan_apply", k_scan_apply, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out, nblk);
     return MJ_OK;
 }
 
@@ -673,16 +741,19 @@ int launch_scan_u64(Prof* prof, const unsigned long long* in, uint64_t n, unsign
                     unsigned long long* out, hipStream_t s) {
     const uint32_t nblk = (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE);
     if (nblk == 0) {
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
         return MJ_OK;
     }
     if (nblk == 1) {
-        MJ_LAUNCH(prof, "k_scan_one64", k_scan_one64, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, out);
+        MJ_LAUNCHM(prof, "k_scan_one64", k_scan_one64, dim3(1), dim3(SCAN_THREADS), 0, s, in, n, partial, out, nblk);
         return MJ_OK;
     }
-    MJ_LAUNCH(prof, "k_scan_reduce64", k_scan_reduce64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial);
-    MJ_LAUNCH(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, partial, nblk);
-    MJ_LAUNCH(prof, "k_scan_apply64", k_scan_apply64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out);
+    MJ_LAUNCHM(prof, "k_scan_reduce64", k_scan_reduce64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out,
+               nblk);
+    MJ_LAUNCHM(prof, "k_scan_partials", k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, s, nullptr, n, partial,
+               out, nblk);
+    MJ_LAUNCHM(prof, "k_scan_apply64", k_scan_apply64, dim3(nblk), dim3(SCAN_THREADS), 0, s, in, n, partial, out,
+               nblk);
     return MJ_OK;
 }
 
@@ -701,7 +772,7 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
         while (P < n) P <<= 1;
         const uint32_t shift = 8 * first_pass;
         const size_t smem = size_t(P) * sizeof(unsigned long long);
-        MJ_LAUNCH(prof, "k_rs_small", k_rs_small, dim3(1), dim3(RS_SMALL_THREADS), smem, s, keys, (uint32_t)n,
+        MJ_LAUNCHM(prof, "k_rs_small", k_rs_small, dim3(1), dim3(RS_SMALL_THREADS), smem, s, keys, (uint32_t)n,
                   shift);
         return MJ_OK;
     }
@@ -712,19 +783,19 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
         RsArgs A;
         A.in = src; A.out = dst; A.n = n; A.shift = 8 * pass; A.ntiles = ntiles;
         A.hist = hist; A.starts = starts;
-        MJ_LAUNCH(prof, "k_rs_hist", k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
+        MJ_LAUNCHM(prof, "k_rs_hist", k_rs_hist, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
         if (ntiles <= RS_SCAN1_TILES) {
-            MJ_LAUNCH(prof, "k_rs_scan1", k_rs_scan1, dim3(1), dim3(256), 0, s, A, starts);
+            MJ_LAUNCHM(prof, "k_rs_scan1", k_rs_scan1, dim3(1), dim3(256), 0, s, A, starts);
         } else {
             PartLaunch P{};
             P.njobs = 1;
             P.job[0].hist = hist; P.job[0].ntiles = ntiles; P.job[0].counts = counts;
             P.job[0].starts = starts; P.job[0].bits0 = 8; P.job[0].bits1 = 0;
-            MJ_LAUNCH(prof, "k_part_rowscan", k_part_rowscan, dim3(256), dim3(PART_THREADS),
+            MJ_LAUNCHM(prof, "k_part_rowscan", k_part_rowscan, dim3(256), dim3(PART_THREADS),
                       PART_SCAN_CHUNK * 4, s, P);
-            MJ_LAUNCH(prof, "k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), 256 * 4, s, P);
+            MJ_LAUNCHM(prof, "k_part_scan", k_part_scan, dim3(1), dim3(PART_THREADS), 256 * 4, s, P);
         }
-        MJ_LAUNCH(prof, "k_rs_scatter", k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
+        MJ_LAUNCHM(prof, "k_rs_scatter", k_rs_scatter, dim3(ntiles), dim3(RS_THREADS), 0, s, A);
         std::swap(src, dst);
     }
     return MJ_OK;            // an even number of passes: the result is back in `keys`
@@ -733,18 +804,18 @@ int launch_radix_sort(Prof* prof, unsigned long long* keys, unsigned long long* 
 int launch_runs(Prof* prof, const TriLayout& L, const unsigned long long* keys, uint64_t n,
                 const RunBuf& X, uint32_t* low, hipStream_t s) {
     if (n == 0) {
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, X.nruns, (uint64_t)1, 0ull);
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, X.run_start, (uint64_t)1, 0u);
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, X.nruns, (uint64_t)1, 0ull);
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, X.run_start, (uint64_t)1, 0u);
     } else {
-        MJ_LAUNCH(prof, "k_run_flags", k_run_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_run_flags", k_run_flags, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
                   keys, n, L.flags, low);
         int st = launch_scan_u32(prof, L.flags, n, L.partial, L.ridx, s);
         if (st) return st;
-        MJ_LAUNCH(prof, "k_run_compact", k_run_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_run_compact", k_run_compact, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
                   keys, n, L.flags, L.ridx, X.run_key, X.run_start, X.nruns);
     }
     if (X.dir)
-        MJ_LAUNCH(prof, "k_run_dir", k_run_dir, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_run_dir", k_run_dir, dim3(grid_for(n + 1, 256, 16384)), dim3(256), 0, s,
                   X.run_key, X.nruns, X.bits, X.dir);
     return MJ_OK;
 }
@@ -764,7 +835,7 @@ int tri_keys(Prof* prof, const mj_rel& r, int key_col, unsigned long long* out, 
     K.key_col = key_col ? r.col1 : r.col0;
     K.val_col = key_col ? r.col0 : r.col1;
     K.stride = r.stride; K.n = r.n; K.seed = seed; K.raw_low = raw_low ? 1u : 0u; K.out = out;
-    MJ_LAUNCH(prof, "k_tri_keys", k_tri_keys, dim3(grid_for(r.n, 256, 16384)), dim3(256), 0, s, K);
+    MJ_LAUNCHM(prof, "k_tri_keys", k_tri_keys, dim3(grid_for(r.n, 256, 16384)), dim3(256), 0, s, K);
     return MJ_OK;
 }
 
@@ -846,9 +917,9 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
         }
         const uint64_t n = src[i].r->n;
         if (same >= 0) {
-            if (n && hipMemcpyAsync(src[i].dst, src[same].dst, n * sizeof(unsigned long long),
-                                    hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return MJ_ERR_HIP;
+            if (n)
+                MJ_LAUNCHM(prof, "k_copy_u64", k_copy_u64, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s,
+                           src[i].dst, src[same].dst, n);
             continue;
         }
         if ((st = tri_keys(prof, *src[i].r, src[i].key_col, src[i].dst, seed, s))) return st;
@@ -863,8 +934,8 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
     // work queues of the two passes
     for (int q = 0; q < 2; ++q) {
         const PassBuf& P = L.P[q];
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, P.ctr, (uint64_t)4, 0u);
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(P.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, P.ctr, (uint64_t)4, 0u);
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(P.n_heavy_cap, 256, 4096)), dim3(256), 0, s,
                   P.heavy_items, (uint64_t)P.n_heavy_cap, 0u);
         TriClassifyArgs C;
         C.Stg = run_index(q == 0 ? L.R : L.T);
@@ -872,7 +943,7 @@ int tri_prepare(Prof* prof, int num_cu, const mj_rel& R, const mj_rel& S, const 
         C.share = 1u << p.log2_share;
         C.nlight = P.ctr + 0; C.light = P.light;
         C.nheavy_groups = P.ctr + 2; C.heavy_group = P.heavy_group; C.heavy_items = P.heavy_items;
-        MJ_LAUNCH(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S.n, 256, 16384)), dim3(256), 0, s, C);
+        MJ_LAUNCHM(prof, "k_tri_classify", k_tri_classify, dim3(grid_for(S.n, 256, 16384)), dim3(256), 0, s, C);
         if ((st = launch_scan_u32(prof, P.heavy_items, P.n_heavy_cap, L.partial, P.heavy_off, s))) return st;
     }
     return MJ_OK;
@@ -906,7 +977,7 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     hipStream_t s = static_cast<hipStream_t>(stream);
     Prof* prof = &ctx->prof;
     unsigned long long* total = reinterpret_cast<unsigned long long*>(out);
-    MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0ull);
+    MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0 || p.join2_size == 0) return MJ_OK;
     // join 2's side: T as sorted (m(c), m(a)) keys with its lists per C
     int st = tri_keys(prof, *T, 0, L.Tk, p.seed, s);
@@ -927,10 +998,10 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     CasIndexArgs X;
     X.R = L.R.pairs; X.rstarts = L.R.starts; X.S = L.S.pairs; X.sstarts = L.S.starts;
     X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
-    MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
+    MJ_LAUNCHM(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
     if ((st = launch_scan_u32(prof, L.ecnt, S->n, L.partial, L.eoff, s))) return st;
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
-    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + S->n,
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCHM(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + S->n,
               (unsigned long long)p.join2_size, L.err);
     const uint64_t totI = p.join2_size;
     for (uint64_t lo = 0; lo < totI; lo += L.i_cap) {
@@ -938,14 +1009,14 @@ int cascade_triangle(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         CasExpandArgs E;
         E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.S.pairs; E.ns = S->n;
         E.lo = lo; E.hi = hi; E.I = L.I; E.swap = 0;
-        MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
+        MJ_LAUNCHM(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
                   dim3(EXP_THREADS), 0, s, E);
         CasProbeTriArgs Q;
         Q.I = L.I; Q.n = hi - lo; Q.T = run_index(L.Trun); Q.Tk = L.Tk; Q.seed = p.seed; Q.total = total;
-        MJ_LAUNCH(prof, "k_cas_probe_tri", k_cas_probe_tri, dim3(grid_for(hi - lo, 256, 16384)), dim3(256), 0, s, Q);
+        MJ_LAUNCHM(prof, "k_cas_probe_tri", k_cas_probe_tri, dim3(grid_for(hi - lo, 256, 16384)), dim3(256), 0, s, Q);
     }
     // an intermediate of another size than the plan's: the total is all ones
-    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, L.err);
+    MJ_LAUNCHM(prof, "k_poison_u64", k_poison_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, L.err);
     return MJ_OK;
 }
 
@@ -1022,11 +1093,11 @@ int star_prepare(Prof* prof, const mj_rel& R, const mj_rel& T, const mj_plan_t& 
     O.R = star_table(L.Rt, seed_b(p), seed_slot(p));
     O.cursor = L.Rt.pool_cursor; O.occ = L.occ;
     const uint64_t slots = L.Rt.pool_slots;
-    MJ_LAUNCH(prof, "k_star_occ", k_star_occ, dim3(grid_for(slots + 1, 256, 4096)), dim3(256), 0, s, O);
+    MJ_LAUNCHM(prof, "k_star_occ", k_star_occ, dim3(grid_for(slots + 1, 256, 4096)), dim3(256), 0, s, O);
     if ((st = launch_scan_u32(prof, L.occ, slots + 1, L.scan_part, L.rid, s))) return st;
     StarIdArgs I;
     I.R = O.R; I.rid = L.rid; I.idtab = L.idtab;
-    MJ_LAUNCH(prof, "k_star_ids", k_star_ids, dim3(grid_for(slots, 256, 4096)), dim3(256), 0, s, I);
+    MJ_LAUNCHM(prof, "k_star_ids", k_star_ids, dim3(grid_for(slots, 256, 4096)), dim3(256), 0, s, I);
     return MJ_OK;
 }
 
@@ -1042,7 +1113,7 @@ int star_group(Prof* prof, const char* name, const uint32_t* col0, const uint32_
                hipStream_t s) {
     // zeroed first: the LDS modes overwrite, the global modes add
     if (out_len)
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(out_len, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(out_len, 256, 4096)), dim3(256), 0, s,
                   out, out_len, 0ull);
     StarGroupArgs G;
     G.col0 = col0; G.col1 = col1; G.stride = stride; G.n = n;
@@ -1051,13 +1122,13 @@ int star_group(Prof* prof, const char* name, const uint32_t* col0, const uint32_
     G.idtab = L.idtab; G.rid = L.rid; G.ngroups_max = ngroups_max;
     G.partial = L.partial; G.out = out; G.err = L.Rt.err;
     const uint32_t grid = star_grid_cu(n, num_cu);
-    if (by_b) MJ_LAUNCH(prof, name, k_star_group_b, dim3(grid), dim3(STAR_THREADS), 0, s, G);
-    else MJ_LAUNCH(prof, name, k_star_group_a, dim3(grid), dim3(STAR_THREADS), 0, s, G);
+    if (by_b) MJ_LAUNCHM(prof, name, k_star_group_b, dim3(grid), dim3(STAR_THREADS), 0, s, G);
+    else MJ_LAUNCHM(prof, name, k_star_group_a, dim3(grid), dim3(STAR_THREADS), 0, s, G);
     StarReduceArgs Rd;
     Rd.partial = L.partial; Rd.nblocks = grid; Rd.by_b = by_b ? 1u : 0u;
     Rd.rdir = L.Rt.dir; Rd.tdir = L.Tt.dir; Rd.rid = L.rid; Rd.pool_slots = G.R.pool_slots;
     Rd.ngroups_max = ngroups_max; Rd.out = out;
-    MJ_LAUNCH(prof, "k_star_reduce", k_star_reduce, dim3((STAR_STRIDE + 63) / 64), dim3(STAR_REDUCE_THREADS),
+    MJ_LAUNCHM(prof, "k_star_reduce", k_star_reduce, dim3((STAR_STRIDE + 63) / 64), dim3(STAR_REDUCE_THREADS),
               0, s, Rd);
     return MJ_OK;
 }
@@ -1071,7 +1142,7 @@ int run_star3(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, ui
     Prof* prof = &ctx->prof;
     unsigned long long* count = reinterpret_cast<unsigned long long*>(count_out);
     if (a_domain)
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                   count, (uint64_t)a_domain, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0 || a_domain == 0) return MJ_OK;
     int st;
@@ -1083,9 +1154,9 @@ int run_star3(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel* T, ui
     C.col0 = R->col0; C.col1 = R->col1; C.stride = R->stride; C.n = R->n;
     C.R = star_table(L.Rt, seed_b(p), seed_slot(p)); C.rid = L.rid; C.W = L.W;
     C.count = count; C.a_domain = a_domain; C.err = L.Rt.err;
-    MJ_LAUNCH(prof, "k_star_count", k_star_count, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, C);
+    MJ_LAUNCHM(prof, "k_star_count", k_star_count, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, C);
     // an A value out of range or a table overflow: every count all ones
-    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)a_domain, L.Rt.err);
     return MJ_OK;
 }
@@ -1101,7 +1172,7 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     unsigned long long* count = reinterpret_cast<unsigned long long*>(count_out);
     if (R->n == 0 || S->n == 0 || T->n == 0 || a_domain == 0 || p.join2_size == 0) {
         if (a_domain)
-            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+            MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                       count, (uint64_t)a_domain, 0ull);
         return MJ_OK;
     }
@@ -1112,14 +1183,14 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     X.col0 = R->col0; X.col1 = R->col1; X.stride = R->stride; X.n = R->n;
     X.R = star_table(L.Rt, seed_b(p), seed_slot(p)); X.rid = L.rid; X.roff = L.roff;
     X.rcur = L.rcur; X.ra = L.ra;
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
               L.mult, p.n_r + 1, 0u);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(p.n_r + 1, 256, 4096)), dim3(256), 0, s,
               L.rcur, p.n_r + 1, 0u);
-    MJ_LAUNCH(prof, "k_star_rmult", k_star_rmult, dim3(grid_for(uint64_t(X.R.pool_slots) + 1, 256, 4096)),
+    MJ_LAUNCHM(prof, "k_star_rmult", k_star_rmult, dim3(grid_for(uint64_t(X.R.pool_slots) + 1, 256, 4096)),
               dim3(256), 0, s, X, L.mult);
     if ((st = launch_scan_u32(prof, L.mult, p.n_r + 1, L.scan_part, L.roff, s))) return st;
-    MJ_LAUNCH(prof, "k_star_rfill", k_star_rfill, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, X);
+    MJ_LAUNCHM(prof, "k_star_rfill", k_star_rfill, dim3(grid_for(R->n, 256, 4096)), dim3(256), 0, s, X);
     // join 1: S streamed, I = R |x| S written as (a, c) pairs
     StarExpandArgs E;
     E.col0 = S->col0; E.col1 = S->col1; E.stride = S->stride; E.n = S->n;
@@ -1127,10 +1198,10 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     E.ioff = L.ioff; E.I = L.I;
     E.i_cap = L.i_cap; E.err = L.Rt.err;
     const uint32_t g1 = star_grid_cu(S->n, ctx->num_cu);
-    MJ_LAUNCH(prof, "k_star_icount", k_star_icount, dim3(g1), dim3(STAR_THREADS), 0, s, E);
+    MJ_LAUNCHM(prof, "k_star_icount", k_star_icount, dim3(g1), dim3(STAR_THREADS), 0, s, E);
     if ((st = launch_scan_u32(prof, L.icnt, S->n, L.scan_part, L.ioff, s))) return st;
-    MJ_LAUNCH(prof, "k_star_expand", k_star_expand, dim3(g1), dim3(STAR_THREADS), 0, s, E);
-    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.ioff + S->n,
+    MJ_LAUNCHM(prof, "k_star_expand", k_star_expand, dim3(g1), dim3(STAR_THREADS), 0, s, E);
+    MJ_LAUNCHM(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.ioff + S->n,
               (unsigned long long)p.join2_size, L.Rt.err);
     // join 2: I streamed past T, grouped by A
     const uint32_t* icol = reinterpret_cast<const uint32_t*>(L.I);
@@ -1139,7 +1210,7 @@ int run_star_cascade(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         return st;
     // an intermediate of another size than the plan's, or an A value out of
     // range: every count all ones
-    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)a_domain, L.Rt.err);
     return MJ_OK;
 }
@@ -1254,7 +1325,7 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.err;
     Ad.out_narrow = L.deg16; Ad.wide = L.err + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
     Ad.split = Tsp; Ad.rows = L.rows; Ad.row_len = 1u << L.c_shift;
-    MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(split_grid(n_tp, L.c_bits)), dim3(RANGE_THREADS),
+    MJ_LAUNCHM(prof, "k_range_deg", k_range_deg, dim3(split_grid(n_tp, L.c_bits)), dim3(RANGE_THREADS),
               size_t(4) << L.c_shift, s, Ad);
     RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> Aw{};
     Aw.pairs = L.S.pairs; Aw.keys = nullptr; Aw.starts = L.S.starts; Aw.shift = L.b_shift;
@@ -1262,7 +1333,7 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     // deg's 2-byte copy unless some deg[c] needs more; W's saturating 2-byte copy
     Aw.out_narrow = L.w16; Aw.wide = nullptr; Aw.table_narrow = L.deg16; Aw.use_wide = L.err + 2;
     Aw.split = L.Ssplit; Aw.rows = L.rows; Aw.row_len = 1u << L.b_shift;
-    MJ_LAUNCH(prof, "k_range_w", k_range_w, dim3(split_grid(S.n, L.b_bits)), dim3(RANGE_THREADS),
+    MJ_LAUNCHM(prof, "k_range_w", k_range_w, dim3(split_grid(S.n, L.b_bits)), dim3(RANGE_THREADS),
               size_t(8) << L.b_shift, s, Aw);
     RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> Ac{};
     Ac.pairs = Rp.pairs; Ac.keys = nullptr; Ac.starts = Rp.starts; Ac.shift = L.a_shift;
@@ -1270,10 +1341,10 @@ int run_dense(Prof* prof, const mj_rel& R, const mj_rel& S, const mj_rel& T, con
     // W's saturating 2-byte copy; the full W where it reads 0xFFFF
     Ac.out_narrow = nullptr; Ac.wide = nullptr; Ac.table_narrow = L.w16; Ac.use_wide = nullptr;
     Ac.split = Rsp; Ac.rows = L.rows; Ac.row_len = 1u << L.a_shift;
-    MJ_LAUNCH(prof, "k_range_count", k_range_count, dim3(split_grid(n_rp, L.a_bits)), dim3(RANGE_THREADS),
+    MJ_LAUNCHM(prof, "k_range_count", k_range_count, dim3(split_grid(n_rp, L.a_bits)), dim3(RANGE_THREADS),
               size_t(8) << L.a_shift, s, Ac);
     // a key beyond its certified bound: every count all ones
-    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(p.a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)p.a_domain, L.err);
     return MJ_OK;
 }
@@ -1359,7 +1430,7 @@ int symmetric_simple(Prof* prof, const mj_rel& E, uint32_t seed, void* ws, bool&
     if ((st = tri_keys(prof, E, 1, L.K2, seed, s))) return st;
     if ((st = launch_radix_sort(prof, L.K, L.tmp, E.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
     if ((st = launch_radix_sort(prof, L.K2, L.tmp, E.n, L.rs_hist, L.rs_counts, L.rs_starts, s))) return st;
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.err, (uint64_t)1, 0u);
     MJ_LAUNCH(prof, "k_sym_check", k_sym_check, dim3(grid_for(E.n, 256, 8192)), dim3(256), 0, s, L.K, L.K2,
               E.n, L.err);
     uint32_t bad = 1;
@@ -1376,7 +1447,7 @@ int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p,
     const mj_plan_t q = oriented_inner(p);
     TriLayout L = tri_layout(static_cast<char*>(ws) + O.bytes, q);
     int st;
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, O.err, (uint64_t)1, 0u);
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, O.err, (uint64_t)1, 0u);
     OrientArgs A{};
     A.c0 = Erel.col0; A.c1 = Erel.col1; A.stride = Erel.stride; A.n = Erel.n;
     A.seed = p.seed;
@@ -1394,10 +1465,10 @@ int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p,
         Ad.pairs = nullptr; Ad.keys = O.vkeys; Ad.starts = O.V.starts; Ad.shift = O.v_shift;
         Ad.domain = vdom; Ad.table = nullptr; Ad.table_n = 0; Ad.out = O.deg; Ad.err = O.err;
         Ad.out_narrow = nullptr; Ad.wide = nullptr; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
-        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << O.v_bits), dim3(RANGE_THREADS),
+        MJ_LAUNCHM(prof, "k_range_deg", k_range_deg, dim3(1u << O.v_bits), dim3(RANGE_THREADS),
                   size_t(4) << O.v_shift, s, Ad);
         A.deg = O.deg; A.vdom = vdom;
-        MJ_LAUNCH(prof, "k_orient_flags_dense", k_orient_flags_dense,
+        MJ_LAUNCHM(prof, "k_orient_flags_dense", k_orient_flags_dense,
                   dim3(grid_for((Erel.n + 3) / 4, 256, 16384)), dim3(256), 0, s, A);
     } else {
         // degrees: runs of m(u) over the relation (grouped on the high word)
@@ -1408,11 +1479,11 @@ int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p,
         TL.flags = O.flags; TL.ridx = O.ridx; TL.partial = O.partial;
         if ((st = launch_runs(prof, TL, O.K, Erel.n, O.U, nullptr, s))) return st;
         A.U = run_index(O.U);
-        MJ_LAUNCH(prof, "k_orient_flags", k_orient_flags, dim3(grid_for((Erel.n + 1) / 2, 256, 16384)),
+        MJ_LAUNCHM(prof, "k_orient_flags", k_orient_flags, dim3(grid_for((Erel.n + 1) / 2, 256, 16384)),
                   dim3(256), 0, s, A);
     }
     if ((st = launch_scan_u32(prof, O.flags, Erel.n, O.partial, O.ridx, s))) return st;
-    MJ_LAUNCH(prof, "k_orient_compact", k_orient_compact, dim3(grid_for(Erel.n, 256, 16384)), dim3(256), 0, s, A);
+    MJ_LAUNCHM(prof, "k_orient_compact", k_orient_compact, dim3(grid_for(Erel.n, 256, 16384)), dim3(256), 0, s, A);
     // R' = the kept edges reversed, S' = T' = the kept edges
     mj_rel Rp, Sp;
     Sp.col0 = reinterpret_cast<const uint32_t*>(O.E);
@@ -1426,12 +1497,12 @@ int run_oriented(Prof* prof, int num_cu, const mj_rel& Erel, const mj_plan_t& p,
         const uint32_t persistent = (uint32_t)num_cu * 8;
         for (int pass = 0; pass < 2; ++pass) {
             TriJoinArgs J = tri_join_args(L, q, out, pass);
-            MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
-            MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s,
+            MJ_LAUNCHM(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
+            MJ_LAUNCHM(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s,
                       J);
         }
     }
-    MJ_LAUNCH(prof, "k_orient_finish", k_orient_finish, dim3(1), dim3(64), 0, s, A, q.n_s);
+    MJ_LAUNCHM(prof, "k_orient_finish", k_orient_finish, dim3(1), dim3(64), 0, s, A, q.n_s);
     return MJ_OK;
 }
 
@@ -1513,12 +1584,11 @@ int mj_ctx_create(int device, mj_ctx** out) {
     if (e != hipSuccess) { delete c; return MJ_ERR_HIP; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_scatter),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)part_scatter_smem(PART_MAX_BITS));
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rs_small),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(RS_SMALL * sizeof(unsigned long long)));
+    for (const void* f : {reinterpret_cast<const void*>(&k_part_scatter), reinterpret_cast<const void*>(&k_part_scatter_multi)})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)part_scatter_smem(PART_MAX_BITS));
+    for (const void* f : {reinterpret_cast<const void*>(&k_rs_small), reinterpret_cast<const void*>(&k_rs_small_multi)})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(RS_SMALL * sizeof(unsigned long long)));
     (void)hipGetLastError();   // an unsupported size only matters if a launch needs it
     // the scratch array's address on this device (the device is current here)
     e = hipGetSymbolAddress(&c->static_scratch, HIP_SYMBOL(scratch));
@@ -1533,11 +1603,6 @@ int mj_ctx_destroy(mj_ctx* ctx) {
     for (void* h : ctx->pinned) (void)hipHostFree(h);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     if (ctx->stage_read) (void)hipEventDestroy(ctx->stage_read);
-    for (int j = 0; j < BATCH_LANES; ++j) {
-        if (ctx->lanes[j]) (void)hipStreamDestroy(ctx->lanes[j]);
-        if (ctx->lane_done[j]) (void)hipEventDestroy(ctx->lane_done[j]);
-    }
-    if (ctx->lane_fork) (void)hipEventDestroy(ctx->lane_fork);
     delete ctx;
     return MJ_OK;
 }
@@ -1598,7 +1663,7 @@ int mj_join2_size(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, uint64_t* out,
     // degrees of R.b as a bucketed multiplicity table, then sum over S.b
     st = launch_tables(&ctx->prof, L, *R, 1, bits, bseed, sseed, s);
     if (st) return st;
-    MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0ull);
+    MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0ull);
     if (S->n) {
         ProbeSumArgs P;
         P.col = S->col0; P.stride = S->stride; P.n = S->n;
@@ -1669,7 +1734,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         if (a_domain == 0 && R->n) return MJ_ERR_KEY_RANGE;
         if (R->n) {
             uint32_t* d = PL.stats;
-            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
             MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(R->n, 256, 2048)), dim3(256), 0, s,
                                R->col0, R->stride, R->n, d);
             uint32_t mx = 0;
@@ -1680,7 +1745,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         // B and C in small dense domains: direct-indexed tables
         if (!(requests & MJ_PLAN_NO_DENSE) && R->n && S->n && T->n) {
             uint32_t* d = PL.stats;
-            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)2, 0u);
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)2, 0u);
             const mj_rel* src[4] = {R, S, S, T};
             const int col[4] = {1, 0, 1, 0};          // B of R and S, C of S and T
             for (int i = 0; i < 4; ++i) {
@@ -1717,7 +1782,7 @@ int mj_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_re
         // every id)
         if (yes && !(requests & MJ_PLAN_NO_DENSE)) {
             uint32_t* d = PL.stats;
-            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, d, (uint64_t)1, 0u);
             MJ_LAUNCH(&ctx->prof, "k_col_max", k_col_max, dim3(grid_for(R->n, 256, 2048)), dim3(256), 0, s,
                       R->col0, R->stride, R->n, d);
             uint32_t mx = 0;
@@ -1828,7 +1893,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         hipStream_t sd = static_cast<hipStream_t>(stream);
         unsigned long long* cnt = reinterpret_cast<unsigned long long*>(count);
         if (R->n == 0 || S->n == 0 || T->n == 0) {
-            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, sd,
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, sd,
                       cnt, (uint64_t)a_domain, 0ull);
             return MJ_OK;
         }
@@ -1841,7 +1906,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
 
     const bool empty = R->n == 0 || S->n == 0 || T->n == 0;
     if (a_domain && (empty || !L.by_range)) {
-        MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                            reinterpret_cast<unsigned long long*>(count), (uint64_t)a_domain, 0ull);
     }
     if (empty || a_domain == 0) return MJ_OK;
@@ -1873,9 +1938,9 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
             // pair meets S_ij; then the tables become the W tables
             st = launch_tables(&ctx->prof, L.Rk, *R, 1, p.log2_nb, seed_b(p), seed_w(p), s);
             if (st) return st;
-            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(L.Rk.pool_slots, 256, 4096)), dim3(256), 0, s,
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(L.Rk.pool_slots, 256, 4096)), dim3(256), 0, s,
                       L.wval, (uint64_t)L.Rk.pool_slots, 0ull);
-            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, s,
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(grid_for(nb, 256, 64)), dim3(256), 0, s,
                       L.wspecial, (uint64_t)nb, 0ull);
             SlCellArgs Sc;
             Sc.S = L.S.pairs; Sc.sstarts = L.S.starts; Sc.r_bits = p.log2_nb; Sc.t_bits = p.log2_nc;
@@ -1888,9 +1953,9 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
                       L.wval, L.wspecial, L.wdir, L.wpool);
         } else {
             // W[b] per bucket of B into the pool (slots [0, W_MIN_CAP) stay empty)
-            MJ_LAUNCH(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s,
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s,
                       reinterpret_cast<uint32_t*>(L.wpool), (uint64_t)(4 * W_MIN_CAP), EMPTY_KEY);
-            MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
+            MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, L.wcursor, (uint64_t)1,
                       (unsigned long long)W_MIN_CAP);
             WBuildArgs Wb{};
             Wb.S = L.S.pairs; Wb.sstarts = L.S.starts; Wb.ddir = L.T.dir; Wb.dpool = L.T.pool;
@@ -1911,7 +1976,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
         MJ_LAUNCH(&ctx->prof, "k_count", k_count, dim3(split_grid(R->n, L.a_bits)), dim3(COUNT_THREADS),
                   (size_t(8) << L.a_shift), s, Cn);
         // an A value out of range or a table overflow: every count all ones
-        MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+        MJ_LAUNCHM(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
                   Cn.count, (uint64_t)a_domain, L.T.err);
         return MJ_OK;
     }
@@ -1934,7 +1999,7 @@ int mj_linear3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_rel
     C.a_domain = a_domain;
     C.err = L.T.err;
     MJ_LAUNCH(&ctx->prof, "k_linear_cell", k_linear_cell, dim3(nb), dim3(CELL_THREADS), 0, s, C);
-    MJ_LAUNCH(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+    MJ_LAUNCHM(&ctx->prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
               C.count, (uint64_t)a_domain, L.T.err);
     return MJ_OK;
 }
@@ -1967,7 +2032,7 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
         if (!ws || ws_bytes < oriented_bytes(p)) return MJ_ERR_WORKSPACE;
         hipStream_t so = static_cast<hipStream_t>(stream);
         unsigned long long* o = reinterpret_cast<unsigned long long*>(total);
-        MJ_LAUNCH(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, so, o, (uint64_t)1, 0ull);
+        MJ_LAUNCHM(&ctx->prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, so, o, (uint64_t)1, 0ull);
         if (R->n == 0) return MJ_OK;
         return run_oriented(&ctx->prof, ctx->num_cu, *R, p, o, ws, so);
     }
@@ -1977,14 +2042,14 @@ int mj_triangle3_count(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_r
     hipStream_t s = static_cast<hipStream_t>(stream);
     Prof* prof = &ctx->prof;
     unsigned long long* out = reinterpret_cast<unsigned long long*>(total);
-    MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+    MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0) return MJ_OK;
     if ((st = tri_prepare(prof, ctx->num_cu, *R, *S, *T, p, L, out, s))) return st;
     const uint32_t persistent = (uint32_t)ctx->num_cu * 8;
     for (int pass = 0; pass < 2; ++pass) {
         TriJoinArgs J = tri_join_args(L, p, out, pass);
-        MJ_LAUNCH(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
-        MJ_LAUNCH(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s, J);
+        MJ_LAUNCHM(prof, "k_tri_light", k_tri_light, dim3(persistent), dim3(TRI_THREADS), 0, s, J);
+        MJ_LAUNCHM(prof, "k_tri_heavy", k_tri_heavy, dim3((uint32_t)ctx->num_cu * 2), dim3(TRI_HEAVY_THREADS), 0, s, J);
     }
     return MJ_OK;
 }
@@ -2012,7 +2077,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     unsigned long long* count = reinterpret_cast<unsigned long long*>(out);
 
     if (a_domain)
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                   count, (uint64_t)a_domain, 0ull);
     if (R->n == 0 || S->n == 0 || T->n == 0 || p.join2_size == 0) return MJ_OK;
 
@@ -2020,7 +2085,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     // bucket -- or, for dense keys, T by range of C and deg[c] directly
     const bool dense = L.deg != nullptr;
     if (dense) {
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.dflags, (uint64_t)3, 0u);
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, L.dflags, (uint64_t)3, 0u);
         PartLaunch PT{};
         PT.njobs = 1;
         PT.job[0] = make_job(*T, L.Tr.hist, L.Tr.counts, L.Tr.starts, 0, 0, L.c_bits, 0, 0, 0);
@@ -2031,7 +2096,7 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         Ad.pairs = nullptr; Ad.keys = L.tkeys; Ad.starts = L.Tr.starts; Ad.shift = L.c_shift;
         Ad.domain = p.c_domain; Ad.table = nullptr; Ad.table_n = 0; Ad.out = L.deg; Ad.err = L.dflags;
         Ad.out_narrow = L.deg16; Ad.wide = L.dflags + 2; Ad.table_narrow = nullptr; Ad.use_wide = nullptr;
-        MJ_LAUNCH(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
+        MJ_LAUNCHM(prof, "k_range_deg", k_range_deg, dim3(1u << L.c_bits), dim3(RANGE_THREADS),
                   size_t(4) << L.c_shift, s, Ad);
     } else {
         st = launch_tables(prof, L.T, *T, 0, p.log2_nc, seed_c(p), seed_slot(p), s);
@@ -2056,12 +2121,12 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
     CasIndexArgs X;
     X.R = L.S.pairs; X.rstarts = L.S.starts; X.S = L.R.pairs; X.sstarts = L.R.starts;
     X.Rgrp = L.Rgrp; X.ecnt = L.ecnt; X.elist = L.elist; X.seed = seed_w(p);
-    MJ_LAUNCH(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
+    MJ_LAUNCHM(prof, "k_cas_index", k_cas_index, dim3(nb), dim3(CAS_THREADS), 0, s, X);
     if ((st = launch_scan_u32(prof, L.ecnt, R->n, L.partial, L.eoff, s))) return st;
     // the chunks below cover the plan's |I|: an intermediate of another size
     // (same relations, other contents) makes every count all ones
     uint32_t* verr = dense ? L.dflags : L.T.err;
-    MJ_LAUNCH(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + R->n,
+    MJ_LAUNCHM(prof, "k_check_size", k_check_size, dim3(1), dim3(64), 0, s, L.eoff + R->n,
               (unsigned long long)p.join2_size, verr);
     // the intermediate, chunk by chunk: materialise, then join with T
     const uint64_t total = p.join2_size;
@@ -2070,18 +2135,18 @@ int mj_cascade2_count(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, c
         CasExpandArgs E;
         E.eoff = L.eoff; E.elist = L.elist; E.Rgrp = L.Rgrp; E.S = L.R.pairs; E.ns = R->n;
         E.lo = lo; E.hi = hi; E.I = L.I; E.swap = 1;          // (a, c)
-        MJ_LAUNCH(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
+        MJ_LAUNCHM(prof, "k_cas_expand", k_cas_expand, dim3((uint32_t)((hi - lo + EXP_TILE - 1) / EXP_TILE)),
                   dim3(EXP_THREADS), 0, s, E);
         CasProbeArgs Q;
         Q.I = L.I; Q.n = hi - lo; Q.ddir = dense ? nullptr : L.T.dir; Q.dpool = dense ? nullptr : L.T.pool;
         Q.c_seed = seed_c(p); Q.c_bits = p.log2_nc; Q.slot_seed = seed_slot(p);
         Q.count = count; Q.a_domain = a_domain; Q.err = dense ? L.dflags : L.T.err;
         Q.deg = L.deg; Q.deg16 = L.deg16; Q.c_domain = p.c_domain; Q.use_wide = dense ? L.dflags + 2 : nullptr;
-        MJ_LAUNCH(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
+        MJ_LAUNCHM(prof, "k_cas_probe", k_cas_probe, dim3(grid_for(hi - lo, 1024, 8192)), dim3(256), 0, s, Q);
     }
     // a key beyond its certified bound, an A value out of range, a table
     // overflow or an intermediate of another size: every count all ones
-    MJ_LAUNCH(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
+    MJ_LAUNCHM(prof, "k_poison_u64", k_poison_u64, dim3(grid_for(a_domain, 256, 1024)), dim3(256), 0, s,
               count, (uint64_t)a_domain, verr);
     return MJ_OK;
 }
@@ -2114,10 +2179,10 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
     if (a_domain == 0) return MJ_OK;
     const uint64_t words = uint64_t(a_domain) * FM_WORDS;
     if (R->n == 0 || S->n == 0 || T->n == 0) {
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
                   sketch, words, 0u);
         if (est)
-            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
+            MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(a_domain, 256, 4096)), dim3(256), 0, s,
                       reinterpret_cast<unsigned long long*>(est), (uint64_t)a_domain, 0ull);   // 0.0
         return MJ_OK;
     }
@@ -2160,7 +2225,7 @@ int mj_linear3_distinct(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const mj_
     if (L.by_range) {
         MJ_LAUNCH(prof, "k_fm_asketch", k_fm_asketch, dim3(1u << L.a_bits), dim3(FM_THREADS), 0, s, Fa);
     } else {
-        MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
+        MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(grid_for(words, 256, 4096)), dim3(256), 0, s,
                   sketch, words, 0u);
         MJ_LAUNCH(prof, "k_fm_asketch_global", k_fm_asketch_global, dim3(grid_for(R->n, 256, 16384)), dim3(256),
                   0, s, Fa);
@@ -2186,7 +2251,7 @@ int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const 
     Prof* prof = &ctx->prof;
     unsigned long long* tot = reinterpret_cast<unsigned long long*>(total);
     if (R->n == 0 || S->n == 0 || T->n == 0) {
-        MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, tot, (uint64_t)1, 0ull);
+        MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, tot, (uint64_t)1, 0ull);
         return MJ_OK;
     }
     // the seed only groups equal keys; the output order does not depend on it
@@ -2211,8 +2276,7 @@ int mj_linear3_materialize(mj_ctx* ctx, const mj_rel* R, const mj_rel* S, const 
     MJ_LAUNCH(prof, "k_emit_rdeg", k_emit_rdeg, dim3(grid_for((R->n + 3) / 4, 256, 16384)), dim3(256), 0, s, Er);
     if ((st = launch_scan_u32(prof, L.pdeg, R->n, L.partial, L.O_I, s))) return st;
     if ((st = launch_scan_u64(prof, L.wout, R->n, L.partial, L.O_R, s))) return st;
-    if (hipMemcpyAsync(tot, L.O_R + R->n, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return MJ_ERR_HIP;
+    MJ_LAUNCHM(prof, "k_copy_u64", k_copy_u64, dim3(1), dim3(64), 0, s, tot, L.O_R + R->n, (uint64_t)1);
     // the window, in chunks of EMIT_CHUNK_TILES tiles
     const uint64_t chunk_max = uint64_t(EMIT_CHUNK_TILES) * EMIT_TILE;
     for (uint64_t c0 = 0; c0 < cap; c0 += chunk_max) {
@@ -2306,7 +2370,7 @@ int mj_sketch(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_
     TableLayout L;
     take_table(B, L, n, bits);
     uint32_t* hist = B.take<uint32_t>(96);
-    MJ_LAUNCH(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(96), 0, s, hist, (uint64_t)96, 0u);
+    MJ_LAUNCHM(prof, "k_fill_u32", k_fill_u32, dim3(1), dim3(96), 0, s, hist, (uint64_t)96, 0u);
     const mj_rel* rels[3] = {R, S, T};
     const int cols[3] = {1, 0, 0};
     for (int h = 0; h < 3; ++h) {
@@ -2327,25 +2391,13 @@ int mj_ctx_set_planner(mj_ctx* ctx, const void* params) {
 }
 
 // ------------------------------------------------------------------ batch
-// the batch's lanes, made on the context's device at the first batch call
-static int batch_lanes(mj_ctx* ctx) {
-    if (ctx->lane_fork) return MJ_OK;
-    int cur = 0;
-    MJ_HIP(hipGetDevice(&cur));
-    if (cur != ctx->device) MJ_HIP(hipSetDevice(ctx->device));
-    int st = MJ_OK;
-    for (int j = 0; j < BATCH_LANES && st == MJ_OK; ++j) {
-        if ((!ctx->lanes[j] && hipStreamCreateWithFlags(&ctx->lanes[j], hipStreamNonBlocking) != hipSuccess) ||
-            (!ctx->lane_done[j] && hipEventCreateWithFlags(&ctx->lane_done[j], hipEventDisableTiming) != hipSuccess))
-            st = MJ_ERR_HIP;
-    }
-    if (st == MJ_OK && hipEventCreateWithFlags(&ctx->lane_fork, hipEventDisableTiming) != hipSuccess) {
-        ctx->lane_fork = nullptr;
-        st = MJ_ERR_HIP;
-    }
-    if (cur != ctx->device) MJ_HIP(hipSetDevice(cur));
-    return st;
-}
+// A batch records every join's work (its launches, in order: a chain) and
+// then issues the chains together.  Each step of the issue order is one
+// kernel's launches from several joins merged into one grid (their argument
+// structs and block counts in a table on the device), or one record that
+// has no merged form, issued alone; the chains' order is kept.  A 3-way
+// plan's cells are left out of its chain and run for all joins in one
+// launch at the end.
 
 static size_t batch_item_bytes(const mj_batch_item& it) {
     if (it.plan.algo != MJ_ALGO_3WAY) return it.plan.workspace_bytes;
@@ -2355,25 +2407,168 @@ static size_t batch_item_bytes(const mj_batch_item& it) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-uint64_t mj_batch_workspace(const mj_batch_item* items, int n) {
-    if (!items || n < 0) return 0;
-    size_t off = 0;
-    for (int i = 0; i < n; ++i) off += align256(batch_item_bytes(items[i]));
-    const size_t nn = (size_t)n;
-    off += align256(nn * sizeof(LinearCellArgs)) + align256((nn + 1) * 4) +
-           align256(2 * nn * sizeof(TriJoinArgs)) + 2 * align256((2 * nn + 1) * 8) + align256(16);
-    return off + 256;
-}
-
 static int run_plan(mj_ctx* ctx, int kind, const mj_rel* R, const mj_rel* S, const mj_rel* T,
                     uint32_t a_domain, uint64_t* out, const mj_plan_t& p, void* ws,
                     uint64_t ws_bytes, void* stream);
+
+struct BatchRecord {
+    std::vector<LaunchChain> chains;      // one per join
+    std::vector<LinearCellArgs> lin;      // the 3-way plans' cells
+    std::vector<uint32_t> cell_base{0};
+    std::vector<TriJoinArgs> tri;
+    size_t join_bytes = 0;                // the joins' workspaces
+};
+
+// Record every join's work; `base` is where the joins' workspaces start
+// (nothing is dereferenced on the host, so a stand-in serves for sizing).
+static int record_batch(mj_ctx* ctx, const mj_batch_item* items, int n, char* base, hipStream_t s,
+                        BatchRecord& B) {
+    Prof* prof = &ctx->prof;
+    B.chains.assign((size_t)n, LaunchChain());
+    size_t off = 0;
+    int st = MJ_OK;
+    for (int i = 0; i < n && st == MJ_OK; ++i) {
+        const mj_batch_item& it = items[i];
+        const mj_plan_t& p = it.plan;
+        void* wsi = base + off;
+        const size_t bytes = batch_item_bytes(it);
+        off += align256(bytes);
+        prof->rec = &B.chains[(size_t)i];
+        if (p.algo != MJ_ALGO_3WAY) {        // cascades, star and oriented plans run their own path
+            st = run_plan(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, p, wsi, bytes, s);
+        } else if (it.kind == MJ_LINEAR) {
+            st = [&]() -> int {
+                LinearLayout L = linear_layout(wsi, p);
+                unsigned long long* count = reinterpret_cast<unsigned long long*>(it.out);
+                if (it.a_domain)
+                    MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(it.a_domain, 256, 4096)), dim3(256), 0, s,
+                               count, (uint64_t)it.a_domain, 0ull);
+                if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
+                int e;
+                if ((e = launch_tables(prof, L.T, it.T, 0, p.log2_nc, seed_c(p), seed_slot(p), s))) return e;
+                PartLaunch P{};
+                P.njobs = 2;
+                P.job[0] = make_job(it.R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
+                P.job[0].out_pair = L.R.pairs;
+                P.job[1] = make_job(it.S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
+                P.job[1].out_pair = L.S.pairs;
+                if ((e = launch_partition(prof, "rs", P, s))) return e;
+                LinearCellArgs C;
+                C.R = L.R.pairs; C.rstarts = L.R.starts; C.S = L.S.pairs; C.sstarts = L.S.starts;
+                C.ddir = L.T.dir; C.dpool = L.T.pool;
+                C.c_seed = seed_c(p); C.c_bits = p.log2_nc; C.slot_seed = seed_slot(p); C.w_seed = seed_w(p);
+                C.count = count; C.a_domain = it.a_domain; C.err = L.T.err;
+                B.lin.push_back(C);
+                B.cell_base.push_back(B.cell_base.back() + (1u << p.log2_nb));
+                return MJ_OK;
+            }();
+        } else {
+            st = [&]() -> int {
+                TriLayout L = tri_layout(wsi, p);
+                unsigned long long* out = reinterpret_cast<unsigned long long*>(it.out);
+                MJ_LAUNCHM(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, s, out, (uint64_t)1, 0ull);
+                if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
+                int e;
+                if ((e = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, s))) return e;
+                B.tri.push_back(tri_join_args(L, p, out, 0));
+                B.tri.push_back(tri_join_args(L, p, out, 1));
+                return MJ_OK;
+            }();
+        }
+        prof->rec = nullptr;
+    }
+    prof->rec = nullptr;
+    B.join_bytes = off;
+    return st;
+}
+
+struct BatchStep {
+    std::vector<std::pair<uint32_t, uint32_t>> members;   // (chain, record)
+    uint32_t grid = 0, smem = 0;
+    size_t table = 0;                                     // its table in the tables' area (merged steps)
+};
+
+// The issue order.  Records with no merged form at the chains' heads go
+// first (they cannot wait for company); then the merged kernel at the heads
+// of the most remaining work (the chains' remaining lengths summed) runs for
+// every chain it heads, so that long chains move first and chains of the
+// same shape stay in step.
+static size_t schedule_batch(const std::vector<LaunchChain>& ch, std::vector<BatchStep>& steps) {
+    steps.clear();
+    const uint32_t n = (uint32_t)ch.size();
+    std::vector<size_t> head(n, 0);
+    size_t left = 0, tables = 0;
+    for (const LaunchChain& c : ch) left += c.recs.size();
+    std::map<std::pair<const void*, uint32_t>, std::pair<size_t, std::vector<uint32_t>>> heads;
+    while (left) {
+        heads.clear();
+        for (uint32_t i = 0; i < n; ++i) {
+            // records with no merged form, and merged launches with no blocks, leave at once
+            while (head[i] < ch[i].recs.size() &&
+                   (!ch[i].recs[head[i]].multi || ch[i].recs[head[i]].grid == 0)) {
+                const LaunchRec& r = ch[i].recs[head[i]];
+                if (!r.multi) {
+                    BatchStep a;
+                    a.members.push_back({i, (uint32_t)head[i]});
+                    steps.push_back(std::move(a));
+                }
+                ++head[i];
+                --left;
+            }
+            if (head[i] == ch[i].recs.size()) continue;
+            const LaunchRec& r = ch[i].recs[head[i]];
+            auto& h = heads[{r.multi, r.block}];
+            h.first += ch[i].recs.size() - head[i];
+            h.second.push_back(i);
+        }
+        if (heads.empty()) break;
+        auto best = heads.begin();
+        for (auto g = heads.begin(); g != heads.end(); ++g)
+            if (g->second.first > best->second.first) best = g;
+        BatchStep m;
+        for (uint32_t i : best->second.second) {
+            const LaunchRec& r = ch[i].recs[head[i]];
+            m.members.push_back({i, (uint32_t)head[i]});
+            m.grid += r.grid;
+            m.smem = std::max(m.smem, r.smem);
+            ++head[i];
+            --left;
+        }
+        if (m.members.size() > 1) {
+            const size_t k = m.members.size();
+            const LaunchRec& r0 = ch[m.members[0].first].recs[m.members[0].second];
+            m.table = tables;
+            tables += align256(k * r0.asz + (k + 1) * sizeof(uint32_t));
+        }
+        steps.push_back(std::move(m));
+    }
+    return tables;
+}
+
+// Bytes of the cell stage's tables (3-way plans) after the merged steps' ones.
+static size_t cell_table_bytes(size_t nl, size_t nt) {
+    return align256(nl * sizeof(LinearCellArgs)) + align256((nl + 1) * 4) + align256(nt * sizeof(TriJoinArgs));
+}
+
+uint64_t mj_batch_workspace(const mj_batch_item* items, int n) {
+    if (!items || n < 0) return 0;
+    // the joins' work recorded with a stand-in context and workspace, for
+    // the sizes of the merged steps' tables
+    mj_ctx sizing;
+    BatchRecord B;
+    char* stand_in = reinterpret_cast<char*>(uintptr_t(1) << 44);
+    (void)record_batch(&sizing, items, n, stand_in, nullptr, B);
+    std::vector<BatchStep> steps;
+    const size_t tables = schedule_batch(B.chains, steps);
+    const size_t nn = (size_t)n;
+    return B.join_bytes + align256(tables) + cell_table_bytes(nn, 2 * nn) + 2 * align256((2 * nn + 1) * 8) +
+           align256(16) + 256;
+}
 
 int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uint64_t ws_bytes,
                    void* stream) {
     if (!ctx || (!items && n) || n < 0) return MJ_ERR_INVALID_ARG;
     if (n == 0) return MJ_OK;
-    if (!ws || ws_bytes < mj_batch_workspace(items, n)) return MJ_ERR_WORKSPACE;
     // validation first: nothing is launched unless every item is valid
     for (int i = 0; i < n; ++i) {
         const mj_batch_item& it = items[i];
@@ -2388,88 +2583,26 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         if (p.log2_nb > PART_MAX_BITS || p.log2_nc > PART_MAX_BITS || p.log2_share > 16)
             return MJ_ERR_INVALID_ARG;
     }
+    if (!ws || ws_bytes < mj_batch_workspace(items, n)) return MJ_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Prof* prof = &ctx->prof;
     char* base = static_cast<char*>(ws);
-    size_t off = 0;
-    std::vector<LinearCellArgs> lin;
-    std::vector<uint32_t> cell_base(1, 0);
-    std::vector<TriJoinArgs> tri;
-    int st = batch_lanes(ctx);
+    BatchRecord B;
+    int st = record_batch(ctx, items, n, base, s, B);
     if (st) return st;
-    // The joins' preparations are independent short strings of small
-    // launches: they go to four lanes (the caller's stream and the
-    // context's three), each join to the lane with the least estimated work
-    // so far; the context's lanes start after everything queued on the
-    // caller's stream.
-    MJ_HIP(hipEventRecord(ctx->lane_fork, s));
-    for (int j = 0; j < BATCH_LANES; ++j) MJ_HIP(hipStreamWaitEvent(ctx->lanes[j], ctx->lane_fork, 0));
-    constexpr int NL = BATCH_LANES + 1;
-    double load[NL] = {};
-    auto prepare = [&](int i) -> int {
-        const mj_batch_item& it = items[i];
-        const mj_plan_t& p = it.plan;
-        void* wsi = base + off;
-        const size_t bytes = batch_item_bytes(it);
-        off += align256(bytes);
-        int lane = 0;
-        for (int j = 1; j < NL; ++j)
-            if (load[j] < load[lane]) lane = j;
-        load[lane] += 1.0 + double(it.R.n + it.S.n + it.T.n) / 65536.0;   // launches, then tuples
-        hipStream_t ls = lane ? ctx->lanes[lane - 1] : s;
-        int st;
-        if (p.algo != MJ_ALGO_3WAY)          // cascades, star and oriented plans run their own path
-            return run_plan(ctx, it.kind, &it.R, &it.S, &it.T, it.a_domain, it.out, p, wsi, bytes, ls);
-        if (it.kind == MJ_LINEAR) {
-            LinearLayout L = linear_layout(wsi, p);
-            unsigned long long* count = reinterpret_cast<unsigned long long*>(it.out);
-            if (it.a_domain)
-                MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(grid_for(it.a_domain, 256, 4096)), dim3(256), 0, ls,
-                          count, (uint64_t)it.a_domain, 0ull);
-            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
-            if ((st = launch_tables(prof, L.T, it.T, 0, p.log2_nc, seed_c(p), seed_slot(p), ls))) return st;
-            PartLaunch P{};
-            P.njobs = 2;
-            P.job[0] = make_job(it.R, L.R.hist, L.R.counts, L.R.starts, 1, seed_b(p), p.log2_nb, 0, 0, 0);
-            P.job[0].out_pair = L.R.pairs;
-            P.job[1] = make_job(it.S, L.S.hist, L.S.counts, L.S.starts, 0, seed_b(p), p.log2_nb, 0, 0, 0);
-            P.job[1].out_pair = L.S.pairs;
-            if ((st = launch_partition(prof, "rs", P, ls))) return st;
-            LinearCellArgs C;
-            C.R = L.R.pairs; C.rstarts = L.R.starts; C.S = L.S.pairs; C.sstarts = L.S.starts;
-            C.ddir = L.T.dir; C.dpool = L.T.pool;
-            C.c_seed = seed_c(p); C.c_bits = p.log2_nc; C.slot_seed = seed_slot(p); C.w_seed = seed_w(p);
-            C.count = count; C.a_domain = it.a_domain; C.err = L.T.err;
-            lin.push_back(C);
-            cell_base.push_back(cell_base.back() + (1u << p.log2_nb));
-        } else {
-            TriLayout L = tri_layout(wsi, p);
-            unsigned long long* out = reinterpret_cast<unsigned long long*>(it.out);
-            MJ_LAUNCH(prof, "k_fill_u64", k_fill_u64, dim3(1), dim3(64), 0, ls, out, (uint64_t)1, 0ull);
-            if (it.R.n == 0 || it.S.n == 0 || it.T.n == 0) return MJ_OK;
-            if ((st = tri_prepare(prof, ctx->num_cu, it.R, it.S, it.T, p, L, out, ls))) return st;
-            tri.push_back(tri_join_args(L, p, out, 0));
-            tri.push_back(tri_join_args(L, p, out, 1));
-        }
-        return MJ_OK;
-    };
-    for (int i = 0; i < n && st == MJ_OK; ++i) st = prepare(i);
-    // every lane joins back to the caller's stream, also after an error, so
-    // that no lane is left outside a capture of this call
-    for (int j = 0; j < BATCH_LANES; ++j) {
-        MJ_HIP(hipEventRecord(ctx->lane_done[j], ctx->lanes[j]));
-        MJ_HIP(hipStreamWaitEvent(s, ctx->lane_done[j], 0));
-    }
-    if (st) return st;
-    // device argument tables, staged through pinned memory.  An eager call
-    // reuses the context's buffer once the previous copy out of it has run;
-    // a captured copy is read again at every replay, so its buffer is its
-    // own and lives as long as the context.
-    const size_t nl = lin.size(), nt = tri.size();
+    std::vector<BatchStep> steps;
+    const size_t tables = schedule_batch(B.chains, steps);
+    // argument tables, staged through pinned memory: the merged steps', then
+    // the cell stage's.  An eager call reuses the context's buffer once the
+    // previous copy out of it has run; a captured copy is read again at every
+    // replay, so its buffer is its own and lives as long as the context.
+    const size_t nl = B.lin.size(), nt = B.tri.size();
     const size_t a_lin = align256(nl * sizeof(LinearCellArgs)), a_cb = align256((nl + 1) * 4);
-    const size_t a_tri = align256(nt * sizeof(TriJoinArgs));
-    const size_t stage = a_lin + a_cb + a_tri;
+    const size_t stage = align256(tables) + cell_table_bytes(nl, nt);
     const size_t want = std::max<size_t>(stage, 256);
+    char* dev = base + B.join_bytes;
+    if (uint64_t(B.join_bytes) + stage + 2 * align256((nt + 1) * 8) + align256(16) > ws_bytes)
+        return MJ_ERR_WORKSPACE;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     MJ_HIP(hipStreamIsCapturing(s, &cap));
     const bool captured = cap != hipStreamCaptureStatusNone;
@@ -2489,33 +2622,74 @@ int mj_batch_count(mj_ctx* ctx, const mj_batch_item* items, int n, void* ws, uin
         }
         host = ctx->stage;
     }
-    if (nl) std::memcpy(host, lin.data(), nl * sizeof(LinearCellArgs));
-    std::memcpy(host + a_lin, cell_base.data(), (nl + 1) * 4);
-    if (nt) std::memcpy(host + a_lin + a_cb, tri.data(), nt * sizeof(TriJoinArgs));
-    char* dev = base + off;
+    for (const BatchStep& m : steps) {
+        if (m.members.size() < 2) continue;
+        const size_t k = m.members.size();
+        const uint32_t asz = B.chains[m.members[0].first].recs[m.members[0].second].asz;
+        char* t = host + m.table;
+        uint32_t* bases = reinterpret_cast<uint32_t*>(t + k * asz);
+        uint32_t at = 0;
+        for (size_t q = 0; q < k; ++q) {
+            const LaunchChain& c = B.chains[m.members[q].first];
+            const LaunchRec& r = c.recs[m.members[q].second];
+            std::memcpy(t + q * asz, c.args.data() + r.aoff, asz);
+            bases[q] = at;
+            at += r.grid;
+        }
+        bases[k] = at;
+    }
+    char* cells = host + align256(tables);
+    if (nl) std::memcpy(cells, B.lin.data(), nl * sizeof(LinearCellArgs));
+    std::memcpy(cells + a_lin, B.cell_base.data(), (nl + 1) * 4);
+    if (nt) std::memcpy(cells + a_lin + a_cb, B.tri.data(), nt * sizeof(TriJoinArgs));
     MJ_HIP(hipMemcpyAsync(dev, host, stage, hipMemcpyHostToDevice, s));
     if (!captured) MJ_HIP(hipEventRecord(ctx->stage_read, s));
+    // the chains' work in the issue order
+    for (const BatchStep& m : steps) {
+        const LaunchRec& r0 = B.chains[m.members[0].first].recs[m.members[0].second];
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (prof->on) { ea = prof->ev(); eb = prof->ev(); (void)hipEventRecord(ea, s); }
+        if (m.members.size() == 1) {
+            if ((st = r0.alone(s))) {
+                std::fprintf(stderr, "libmj: batch step %s failed\n", r0.name.c_str());
+                return st;
+            }
+        } else {
+            MultiGrid M;
+            M.args = dev + m.table;
+            M.base = reinterpret_cast<const uint32_t*>(dev + m.table + m.members.size() * r0.asz);
+            M.njobs = (uint32_t)m.members.size();
+            void (*multi)(MultiGrid) = reinterpret_cast<void (*)(MultiGrid)>(const_cast<void*>(r0.multi));
+            hipLaunchKernelGGL(multi, dim3(m.grid), dim3(r0.block), m.smem, s, M);
+            const hipError_t le = hipGetLastError();
+            if (le != hipSuccess) {
+                std::fprintf(stderr, "libmj: merged launch of %s failed: %s\n", r0.name.c_str(), hipGetErrorString(le));
+                return MJ_ERR_HIP;
+            }
+        }
+        if (ea) { (void)hipEventRecord(eb, s); prof->pending.push_back({r0.name, ea, eb}); }
+    }
     if (nl) {
-        LinearBatchArgs B;
-        B.joins = reinterpret_cast<const LinearCellArgs*>(dev);
-        B.cell_base = reinterpret_cast<const uint32_t*>(dev + a_lin);
-        B.njoins = (uint32_t)nl;
-        MJ_LAUNCH(prof, "k_linear_cell_batch", k_linear_cell_batch, dim3(cell_base.back()),
-                  dim3(CELL_THREADS), 0, s, B);
+        LinearBatchArgs C;
+        C.joins = reinterpret_cast<const LinearCellArgs*>(cells - host + dev);
+        C.cell_base = reinterpret_cast<const uint32_t*>(cells - host + dev + a_lin);
+        C.njoins = (uint32_t)nl;
+        MJ_LAUNCH(prof, "k_linear_cell_batch", k_linear_cell_batch, dim3(B.cell_base.back()),
+                  dim3(CELL_THREADS), 0, s, C);
     }
     if (nt) {
         char* q = dev + stage;
-        TriBatchArgs B;
-        B.joins = reinterpret_cast<const TriJoinArgs*>(dev + a_lin + a_cb);
-        B.njoins = (uint32_t)nt;
-        B.light_base = reinterpret_cast<unsigned long long*>(q);
-        B.heavy_base = reinterpret_cast<unsigned long long*>(q + align256((nt + 1) * 8));
-        B.next = reinterpret_cast<unsigned long long*>(q + 2 * align256((nt + 1) * 8));
-        MJ_LAUNCH(prof, "k_tri_batch_prefix", k_tri_batch_prefix, dim3(1), dim3(64), 0, s, B);
+        TriBatchArgs T;
+        T.joins = reinterpret_cast<const TriJoinArgs*>(cells - host + dev + a_lin + a_cb);
+        T.njoins = (uint32_t)nt;
+        T.light_base = reinterpret_cast<unsigned long long*>(q);
+        T.heavy_base = reinterpret_cast<unsigned long long*>(q + align256((nt + 1) * 8));
+        T.next = reinterpret_cast<unsigned long long*>(q + 2 * align256((nt + 1) * 8));
+        MJ_LAUNCH(prof, "k_tri_batch_prefix", k_tri_batch_prefix, dim3(1), dim3(64), 0, s, T);
         MJ_LAUNCH(prof, "k_tri_light_batch", k_tri_light_batch, dim3((uint32_t)ctx->num_cu * 8),
-                  dim3(TRI_THREADS), 0, s, B);
+                  dim3(TRI_THREADS), 0, s, T);
         MJ_LAUNCH(prof, "k_tri_heavy_batch", k_tri_heavy_batch, dim3((uint32_t)ctx->num_cu * 2),
-                  dim3(TRI_HEAVY_THREADS), 0, s, B);
+                  dim3(TRI_HEAVY_THREADS), 0, s, T);
     }
     return MJ_OK;
 }

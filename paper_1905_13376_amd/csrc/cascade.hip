@@ -23,8 +23,7 @@ __device__ __forceinline__ uint32_t cas_pass_of(uint32_t b, uint32_t seed, uint3
     return top_bits(mix32(b, seed ^ 0x1B56C4E9u), level);
 }
 
-__global__ void __launch_bounds__(CAS_THREADS)
-k_cas_index(CasIndexArgs A) {
+MJ_KERNEL(k_cas_index, CAS_THREADS, CasIndexArgs) {
     __shared__ uint32_t tkeys[CAS_CAP];
     __shared__ uint32_t tcnt[CAS_CAP];
     __shared__ uint32_t toff[CAS_CAP];
@@ -33,7 +32,7 @@ k_cas_index(CasIndexArgs A) {
     __shared__ uint32_t st_level[64], st_pass[64];
     __shared__ int s_sp;
 
-    const uint32_t i = blockIdx.x;
+    const uint32_t i = vg.bid;
     const uint32_t r0 = A.rstarts[i], r1 = A.rstarts[i + 1];
     const uint32_t s0 = A.sstarts[i], s1 = A.sstarts[i + 1];
     const uint32_t mask = CAS_CAP - 1;
@@ -134,8 +133,8 @@ k_cas_index(CasIndexArgs A) {
 // ------------------------------------------------------------- u32/u64 -> u64 scan
 // out[i] = sum of in[0..i) for i in [0, n]; three launches.
 template <class In>
-__device__ __forceinline__ void scan_reduce(const In* in, uint64_t n, unsigned long long* partial) {
-    const uint64_t beg = uint64_t(blockIdx.x) * SCAN_TILE;
+__device__ __forceinline__ void scan_reduce(const In* in, uint64_t n, unsigned long long* partial, VGrid vg) {
+    const uint64_t beg = uint64_t(vg.bid) * SCAN_TILE;
     const uint64_t end = min<uint64_t>(beg + SCAN_TILE, n);
     unsigned long long s = 0;
     for (uint64_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += in[i];
@@ -146,21 +145,18 @@ __device__ __forceinline__ void scan_reduce(const In* in, uint64_t n, unsigned l
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < SCAN_THREADS / WAVE; ++w) t += ws[w];
-        partial[blockIdx.x] = t;
+        partial[vg.bid] = t;
     }
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial) { scan_reduce(in, n, partial); }
+MJ_KERNEL(k_scan_reduce, SCAN_THREADS, ScanArgs) { scan_reduce(A.in, A.n, A.partial, vg); }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_reduce64(const unsigned long long* in, uint64_t n, unsigned long long* partial) {
-    scan_reduce(in, n, partial);
-}
+MJ_KERNEL(k_scan_reduce64, SCAN_THREADS, Scan64Args) { scan_reduce(A.in, A.n, A.partial, vg); }
 
 // exclusive scan of the partials in place (one block); partial[nblk] = total
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_partials(unsigned long long* partial, uint32_t nblk) {
+MJ_KERNEL(k_scan_partials, SCAN_THREADS, ScanArgs) {
+    unsigned long long* partial = A.partial;
+    const uint32_t nblk = A.nblk;
     __shared__ unsigned long long carry;
     __shared__ unsigned long long ws[SCAN_THREADS / WAVE + 1];
     if (threadIdx.x == 0) carry = 0;
@@ -195,11 +191,11 @@ k_scan_partials(unsigned long long* partial, uint32_t nblk) {
 
 template <class In>
 __device__ __forceinline__ void scan_apply(const In* in, uint64_t n, const unsigned long long* partial,
-                                           unsigned long long* out) {
+                                           unsigned long long* out, VGrid vg) {
     __shared__ unsigned long long ws[SCAN_THREADS / WAVE + 1];
-    const uint64_t beg = uint64_t(blockIdx.x) * SCAN_TILE;
+    const uint64_t beg = uint64_t(vg.bid) * SCAN_TILE;
     const uint64_t end = min<uint64_t>(beg + SCAN_TILE, n);
-    unsigned long long carry = partial[blockIdx.x];
+    unsigned long long carry = partial[vg.bid];
     for (uint64_t c0 = beg; c0 < end; c0 += SCAN_THREADS) {
         const uint64_t i = c0 + threadIdx.x;
         const unsigned long long x = i < end ? in[i] : 0ull;
@@ -223,13 +219,10 @@ __device__ __forceinline__ void scan_apply(const In* in, uint64_t n, const unsig
         carry += ws[SCAN_THREADS / WAVE];
         __syncthreads();
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = partial[gridDim.x];
+    if (vg.bid == vg.nblk - 1 && threadIdx.x == 0) out[n] = partial[vg.nblk];
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial, unsigned long long* out) {
-    scan_apply(in, n, partial, out);
-}
+MJ_KERNEL(k_scan_apply, SCAN_THREADS, ScanArgs) { scan_apply(A.in, A.n, A.partial, A.out, vg); }
 
 // At most SCAN_TILE elements: the whole scan in one workgroup, one launch.
 template <class In>
@@ -262,24 +255,17 @@ __device__ __forceinline__ void scan_one(const In* in, uint64_t n, unsigned long
     if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_one(const uint32_t* in, uint64_t n, unsigned long long* out) { scan_one(in, n, out); }
+MJ_KERNEL(k_scan_one, SCAN_THREADS, ScanArgs) { scan_one(A.in, A.n, A.out); }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_one64(const unsigned long long* in, uint64_t n, unsigned long long* out) { scan_one(in, n, out); }
+MJ_KERNEL(k_scan_one64, SCAN_THREADS, Scan64Args) { scan_one(A.in, A.n, A.out); }
 
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_apply64(const unsigned long long* in, uint64_t n, const unsigned long long* partial,
-               unsigned long long* out) {
-    scan_apply(in, n, partial, out);
-}
+MJ_KERNEL(k_scan_apply64, SCAN_THREADS, Scan64Args) { scan_apply(A.in, A.n, A.partial, A.out, vg); }
 
 // ------------------------------------------------------------- expansion
 // Block b writes I positions [lo + b*EXP_TILE, ...) of the chunk [lo, hi).
-__global__ void __launch_bounds__(EXP_THREADS)
-k_cas_expand(CasExpandArgs A) {
+MJ_KERNEL(k_cas_expand, EXP_THREADS, CasExpandArgs) {
     __shared__ uint64_t s_first, s_last;
-    const unsigned long long p0 = A.lo + uint64_t(blockIdx.x) * EXP_TILE;
+    const unsigned long long p0 = A.lo + uint64_t(vg.bid) * EXP_TILE;
     if (p0 >= A.hi) return;
     const unsigned long long p1 = min<unsigned long long>(p0 + EXP_TILE, A.hi);
     if (threadIdx.x == 0) {
@@ -337,14 +323,13 @@ k_cas_expand(CasExpandArgs A) {
 }
 
 // ------------------------------------------------------------- second join
-__global__ void __launch_bounds__(256)
-k_cas_probe(CasProbeArgs A) {
+MJ_KERNEL(k_cas_probe, 256, CasProbeArgs) {
     const int lane = lane_id();
     const bool wide = A.deg && *A.use_wide != 0;           // uniform over the launch
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
+    const uint64_t stride = uint64_t(vg.nblk) * blockDim.x * 4;
     // the loop runs on the block's base so that every lane of a wave takes
     // part in the cross-lane steps of every round, the tail round included
-    for (uint64_t q0 = uint64_t(blockIdx.x) * blockDim.x * 4; q0 < A.n; q0 += stride) {
+    for (uint64_t q0 = uint64_t(vg.bid) * blockDim.x * 4; q0 < A.n; q0 += stride) {
         const uint64_t q = q0 + threadIdx.x;
         uint2 iv[4];
         uint32_t c[4], w[4];

@@ -21,16 +21,19 @@
 namespace mj {
 
 // ------------------------------------------------------------------ helpers
-__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+MJ_KERNEL(k_fill_u64, 256, FillU64Args) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)vg.nblk * blockDim.x)
+        A.p[i] = A.v;
 }
 
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+MJ_KERNEL(k_copy_u64, 256, CopyU64Args) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)vg.nblk * blockDim.x)
+        A.dst[i] = A.src[i];
+}
+
+MJ_KERNEL(k_fill_u32, 256, FillU32Args) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)vg.nblk * blockDim.x)
+        A.p[i] = A.v;
 }
 
 __global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out) {
@@ -113,16 +116,15 @@ __device__ __forceinline__ void db_count(const uint32_t* keys, uint32_t beg, uin
 // One workgroup per bucket: the (key, count) table in LDS, then one table
 // per bucket in the pool.  A bucket crowded by heavy keys runs as pieces,
 // one workgroup each, and the last piece to finish adds up their tables.
-__global__ void __launch_bounds__(DB_THREADS)
-k_dbuild(DBuildArgs A) {
+MJ_KERNEL(k_dbuild, DB_THREADS, DBuildArgs) {
     __shared__ uint32_t tkeys[DB_CAP];
     __shared__ uint32_t tvals[DB_CAP];
     __shared__ uint32_t s_special, s_distinct, s_over, s_log2, s_last;
     __shared__ unsigned long long s_base;
-    uint32_t j = blockIdx.x, piece = 0, pcs = 1;
+    uint32_t j = vg.bid, piece = 0, pcs = 1;
     if (A.split.items) {                                         // uniform over the block
-        if (blockIdx.x >= *A.split.nitems) return;
-        const uint32_t it = A.split.items[blockIdx.x];
+        if (vg.bid >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[vg.bid];
         j = it & 0xFFFu;
         piece = it >> 12;
         pcs = split_pieces(A.starts[j + 1] - A.starts[j], A.split.chunk);
@@ -768,11 +770,11 @@ k_count(CountArgs A) {
 // read of the previous array.
 // SAT_IN: table_narrow is a saturating copy; SAT_OUT: out_narrow is one.
 template <bool SAT_IN, bool SAT_OUT, class TW, class TWN, class TO, class TON>
-__device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO, TON>& A, TO* acc) {
-    uint32_t k = blockIdx.x, piece = 0;
+__device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO, TON>& A, TO* acc, VGrid vg) {
+    uint32_t k = vg.bid, piece = 0;
     if (A.split.items) {                                            // uniform over the block
-        if (blockIdx.x >= *A.split.nitems) return;
-        const uint32_t it = A.split.items[blockIdx.x];
+        if (vg.bid >= *A.split.nitems) return;
+        const uint32_t it = A.split.items[vg.bid];
         k = it & 0xFFFu;
         piece = it >> 12;
     }
@@ -849,26 +851,23 @@ __device__ __forceinline__ void range_accumulate(const RangeAccArgs<TW, TWN, TO,
     if (big) atomicOr(A.wide, 1u);
 }
 
-__global__ void __launch_bounds__(RANGE_THREADS)
-k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A) {
+MJ_KERNEL(k_range_deg, RANGE_THREADS, RangeDegArgs) {
     extern __shared__ uint32_t acc32[];
-    range_accumulate<false, false>(A, acc32);
+    range_accumulate<false, false>(A, acc32, vg);
 }
 
-__global__ void __launch_bounds__(RANGE_THREADS)
-k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> A) {
+MJ_KERNEL(k_range_w, RANGE_THREADS, RangeWArgs) {
     extern __shared__ unsigned long long acc64w[];
-    range_accumulate<false, true>(A, acc64w);
+    range_accumulate<false, true>(A, acc64w, vg);
 }
 
-__global__ void __launch_bounds__(RANGE_THREADS)
-k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> A) {
+MJ_KERNEL(k_range_count, RANGE_THREADS, RangeCountArgs) {
     extern __shared__ unsigned long long acc64c[];
-    range_accumulate<true, false>(A, acc64c);
+    range_accumulate<true, false>(A, acc64c, vg);
 }
 
-__global__ void k_check_size(const unsigned long long* got, unsigned long long want, uint32_t* err) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *got != want) atomicExch(err, 1u);
+MJ_KERNEL(k_check_size, 64, CheckSizeArgs) {
+    if (threadIdx.x == 0 && vg.bid == 0 && *A.got != A.want) atomicExch(A.err, 1u);
 }
 
 // ------------------------------------------------ S-largest linear join
@@ -968,10 +967,10 @@ __global__ void k_sl_wtables(const DirEntry* rdir, const uint2* rpool, const uns
     }
 }
 
-__global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err) {
-    if (*err == 0) return;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        out[i] = ~0ull;
+MJ_KERNEL(k_poison_u64, 256, PoisonArgs) {
+    if (*A.err == 0) return;
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n; i += (uint64_t)vg.nblk * blockDim.x)
+        A.out[i] = ~0ull;
 }
 
 }  // namespace mj

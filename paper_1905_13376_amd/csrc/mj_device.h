@@ -142,4 +142,70 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t* lds, uint32_t n, uint3
     return total;
 }
 
+// ----------------------------------------------------------- merged launches
+// Launches of one kernel, each with its own argument struct and grid, can
+// run as one grid: `base` holds each launch's first block, a workgroup finds
+// its launch by a search over it, and the kernel's body sees that launch's
+// block index and grid size in a VGrid.  Kernels written with MJ_KERNEL read
+// their block index and grid size only from there, so that they compute the
+// same alone and merged.
+struct VGrid { uint32_t bid, nblk; };
+struct MultiGrid {
+    const void* args;        // [njobs] argument structs of the kernel's type
+    const uint32_t* base;    // [njobs + 1] first block of each launch; base[njobs] = the grid
+    uint32_t njobs;
+};
+
+// The launch holding block b: the last j with base[j] <= b (every launch has
+// at least one block, so base increases).  Each round compares one entry per
+// lane and keeps the segment of the last lane whose entry is at most b: two
+// rounds for up to 4096 launches.  Every lane of the wave calls it, at the
+// kernel's start, with the same b; the result is the same in every lane.
+__device__ inline uint32_t multi_job(const MultiGrid& M, uint32_t b) {
+    const uint32_t nl = (uint32_t)__popcll(__ballot(1));   // the wave's lanes (the low ones)
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0, hi = M.njobs;
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + nl - 1) / nl;
+        const uint32_t k = lo + lane * step;
+        const unsigned long long bal = __ballot(k < hi && M.base[k] <= b);
+        lo += (uint32_t)(63 - __clzll((long long)bal)) * step;   // lane 0's entry always qualifies
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+// Launch j's argument struct.  The table is not written while the kernel
+// runs, so it is read as constant memory (like a kernel's own arguments):
+// uniform loads of its fields, also at indices known only at run time.
+#ifndef MJ_CONSTANT_AS
+#define MJ_CONSTANT_AS __attribute__((address_space(4)))
+#endif
+template <class Args>
+__device__ __forceinline__ const Args& merged_args(const void* table, uint32_t j) {
+    const MJ_CONSTANT_AS Args* t = (const MJ_CONSTANT_AS Args*)table;
+    return *(const Args*)(t + j);
+}
+
 }  // namespace mj
+
+// A kernel that runs alone (`name`, its grid is the launch's) or merged with
+// other launches of itself (`name##_multi`, one MultiGrid argument).  The
+// body follows the macro; it names its argument struct A and its grid vg.
+#define MJ_KERNEL(name, T, Args)                                                            \
+    __device__ __forceinline__ void name##_body(const Args& A, ::mj::VGrid vg);              \
+    __global__ void __launch_bounds__(T) name(Args A) {                                     \
+        name##_body(A, ::mj::VGrid{blockIdx.x, gridDim.x});                                 \
+    }                                                                                       \
+    __global__ void __launch_bounds__(T) name##_multi(::mj::MultiGrid M) {                  \
+        const uint32_t j_ = ::mj::multi_job(M, blockIdx.x);                                 \
+        name##_body(::mj::merged_args<Args>(M.args, j_),                                    \
+                    ::mj::VGrid{blockIdx.x - M.base[j_], M.base[j_ + 1] - M.base[j_]});     \
+    }                                                                                       \
+    __device__ __forceinline__ void name##_body(const Args& A, ::mj::VGrid vg)
+
+// Declarations of both forms, and the name of the argument struct.
+#define MJ_KERNEL_DECL(name, Args)    \
+    typedef Args name##_args;         \
+    __global__ void name(Args A);     \
+    __global__ void name##_multi(::mj::MultiGrid M)

@@ -85,10 +85,10 @@ struct PartLaunch {
     uint32_t nclear = 0;
 };
 
-__global__ void k_part_hist(PartLaunch L);
-__global__ void k_part_rowscan(PartLaunch L);
-__global__ void k_part_scan(PartLaunch L);
-__global__ void k_part_scatter(PartLaunch L);
+MJ_KERNEL_DECL(k_part_hist, PartLaunch);
+MJ_KERNEL_DECL(k_part_rowscan, PartLaunch);
+MJ_KERNEL_DECL(k_part_scan, PartLaunch);
+MJ_KERNEL_DECL(k_part_scatter, PartLaunch);
 size_t part_scatter_smem(uint32_t max_bits);
 
 // ------------------------------------------------- multiplicity tables (D)
@@ -127,7 +127,7 @@ struct DBuildArgs {
     uint2* rows = nullptr;
     uint32_t* row_special = nullptr;
 };
-__global__ void k_dbuild(DBuildArgs A);
+MJ_KERNEL_DECL(k_dbuild, DBuildArgs);
 
 // Lookup in a bucketed multiplicity table; 0 when absent.
 __device__ __forceinline__ uint32_t dtab_lookup(const DirEntry* __restrict__ dir,
@@ -328,16 +328,21 @@ struct RangeAccArgs {
     uint32_t row_len = 0;
 };
 // deg[c]: keys only, weight 1 (flagged 16-bit copy)
-__global__ void k_range_deg(RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> A);
+typedef RangeAccArgs<uint32_t, uint16_t, uint32_t, uint16_t> RangeDegArgs;
+MJ_KERNEL_DECL(k_range_deg, RangeDegArgs);
 // W[b] += deg[s.c] (reads deg's flagged copy; writes a saturating 16-bit copy)
-__global__ void k_range_w(RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> A);
+typedef RangeAccArgs<uint32_t, uint16_t, unsigned long long, uint16_t> RangeWArgs;
+MJ_KERNEL_DECL(k_range_w, RangeWArgs);
 // count[a] += W[r.b] (reads W's saturating copy)
-__global__ void k_range_count(RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> A);
+typedef RangeAccArgs<unsigned long long, uint16_t, unsigned long long, uint32_t> RangeCountArgs;
+MJ_KERNEL_DECL(k_range_count, RangeCountArgs);
 // every entry of out set to all ones when *err is set (a certified key bound broken)
-__global__ void k_poison_u64(unsigned long long* out, uint64_t n, const uint32_t* err);
+struct PoisonArgs { unsigned long long* out; uint64_t n; const uint32_t* err; };   // out[0..n) = ~0 when *err
+MJ_KERNEL_DECL(k_poison_u64, PoisonArgs);
 // *err set when a size found on the device (*got) is not the one the plan
 // was made with (a plan reused on data of the same sizes but other contents)
-__global__ void k_check_size(const unsigned long long* got, unsigned long long want, uint32_t* err);
+struct CheckSizeArgs { const unsigned long long* got; unsigned long long want; uint32_t* err; };   // err = 1 when *got != want
+MJ_KERNEL_DECL(k_check_size, CheckSizeArgs);
 
 struct CountArgs {
     const uint2* R;              // partitioned (a, b) by range of a
@@ -400,7 +405,7 @@ struct StarOccArgs {
     const unsigned long long* cursor;
     uint32_t* occ;                 // [pool_slots + 1]
 };
-__global__ void k_star_occ(StarOccArgs A);
+MJ_KERNEL_DECL(k_star_occ, StarOccArgs);
 
 // idtab[slot] = (key, id) for the occupied slots of R's table (same
 // positions, so a probe of idtab with the table's hash yields the id)
@@ -409,7 +414,7 @@ struct StarIdArgs {
     const unsigned long long* rid;
     uint2* idtab;                  // [pool_slots]
 };
-__global__ void k_star_ids(StarIdArgs A);
+MJ_KERNEL_DECL(k_star_ids, StarIdArgs);
 
 struct StarGroupArgs {
     const uint32_t* col0;          // (key, c) rows: S as (b, c) or I as (a, c)
@@ -426,9 +431,9 @@ struct StarGroupArgs {
     uint32_t* err;                 // set for an A value >= a_domain
 };
 // by B (the star three-way join's pass over S): sums per id of b
-__global__ void k_star_group_b(StarGroupArgs A);
+MJ_KERNEL_DECL(k_star_group_b, StarGroupArgs);
 // by A value (the star cascade's second join): sums per a
-__global__ void k_star_group_a(StarGroupArgs A);
+MJ_KERNEL_DECL(k_star_group_a, StarGroupArgs);
 
 struct StarReduceArgs {
     const unsigned long long* partial;
@@ -441,7 +446,7 @@ struct StarReduceArgs {
     uint32_t ngroups_max;          // by A: a_domain
     unsigned long long* out;       // overwritten (LDS modes) or left (global modes)
 };
-__global__ void k_star_reduce(StarReduceArgs A);
+MJ_KERNEL_DECL(k_star_reduce, StarReduceArgs);
 
 // count[a] += W[id(b)] over R's tuples
 struct StarCountArgs {
@@ -456,7 +461,7 @@ struct StarCountArgs {
     uint32_t a_domain;
     uint32_t* err;
 };
-__global__ void k_star_count(StarCountArgs A);
+MJ_KERNEL_DECL(k_star_count, StarCountArgs);
 
 // Star cascade (binary joins): R grouped by the id of B, I = R |x| S
 // materialised as (a, c) pairs, then I grouped by a with weights mult_T(c).
@@ -471,8 +476,9 @@ struct StarRIndexArgs {            // counting sort of R's A values by id(b)
     uint32_t* rcur;                  // [k] fill cursors (zeroed)
     uint32_t* ra;                    // [n] A values by id
 };
-__global__ void k_star_rmult(StarRIndexArgs A, uint32_t* mult);   // mult[id] = multiplicity
-__global__ void k_star_rfill(StarRIndexArgs A);
+struct StarRMultArgs { StarRIndexArgs x; uint32_t* mult; };   // mult[id] = multiplicity
+MJ_KERNEL_DECL(k_star_rmult, StarRMultArgs);
+MJ_KERNEL_DECL(k_star_rfill, StarRIndexArgs);
 
 struct StarExpandArgs {
     const uint32_t* col0;            // S as (b, c)
@@ -490,8 +496,8 @@ struct StarExpandArgs {
     uint64_t i_cap;                  // pairs I holds; positions beyond are reported
     uint32_t* err;
 };
-__global__ void k_star_icount(StarExpandArgs A);
-__global__ void k_star_expand(StarExpandArgs A);
+MJ_KERNEL_DECL(k_star_icount, StarExpandArgs);
+MJ_KERNEL_DECL(k_star_expand, StarExpandArgs);
 
 // ------------------------------------------------------------- cascade
 constexpr int CAS_THREADS = 512;
@@ -514,7 +520,7 @@ struct CasIndexArgs {
     uint32_t* elist;             // per S tuple: start of its list in Rgrp
     uint32_t seed;
 };
-__global__ void k_cas_index(CasIndexArgs A);
+MJ_KERNEL_DECL(k_cas_index, CasIndexArgs);
 
 struct CasExpandArgs {
     const unsigned long long* eoff;   // [ns + 1] exclusive scan of ecnt
@@ -526,7 +532,7 @@ struct CasExpandArgs {
     uint2* I;                         // [hi - lo]
     uint32_t swap;                    // write (S value, grouped value) instead of (grouped value, S value)
 };
-__global__ void k_cas_expand(CasExpandArgs A);
+MJ_KERNEL_DECL(k_cas_expand, CasExpandArgs);
 
 // I's pairs (a, c) come with the pairs of one A value consecutive (the
 // first join probes with R): each wave sums its runs of equal a before one
@@ -547,19 +553,31 @@ struct CasProbeArgs {
     uint32_t c_domain;
     const uint32_t* use_wide;
 };
-__global__ void k_cas_probe(CasProbeArgs A);
+MJ_KERNEL_DECL(k_cas_probe, CasProbeArgs);
 
 
-__global__ void k_scan_reduce(const uint32_t* in, uint64_t n, unsigned long long* partial);
-__global__ void k_scan_reduce64(const unsigned long long* in, uint64_t n, unsigned long long* partial);
-__global__ void k_scan_apply64(const unsigned long long* in, uint64_t n, const unsigned long long* partial,
-                               unsigned long long* out);
-__global__ void k_scan_partials(unsigned long long* partial, uint32_t nblk);
-__global__ void k_scan_apply(const uint32_t* in, uint64_t n, const unsigned long long* partial,
-                             unsigned long long* out);
-// at most SCAN_TILE elements: out[i] = sum of in[0..i) for i in [0, n], one workgroup
-__global__ void k_scan_one(const uint32_t* in, uint64_t n, unsigned long long* out);
-__global__ void k_scan_one64(const unsigned long long* in, uint64_t n, unsigned long long* out);
+// out[i] = sum of in[0..i) for i in [0, n]: per tile of SCAN_TILE a partial
+// sum (k_scan_reduce), the partials' exclusive prefix in place with
+// partial[nblk] = the total (k_scan_partials), then each tile's prefix
+// (k_scan_apply); or, for at most one tile, all of it in one workgroup
+// (k_scan_one)
+template <class In>
+struct ScanArgsT {
+    const In* in;
+    uint64_t n;
+    unsigned long long* partial;   // [nblk + 1]
+    unsigned long long* out;       // [n + 1]
+    uint32_t nblk;                 // tiles of SCAN_TILE
+};
+typedef ScanArgsT<uint32_t> ScanArgs;
+typedef ScanArgsT<unsigned long long> Scan64Args;
+MJ_KERNEL_DECL(k_scan_reduce, ScanArgs);
+MJ_KERNEL_DECL(k_scan_reduce64, Scan64Args);
+MJ_KERNEL_DECL(k_scan_partials, ScanArgs);
+MJ_KERNEL_DECL(k_scan_apply, ScanArgs);
+MJ_KERNEL_DECL(k_scan_apply64, Scan64Args);
+MJ_KERNEL_DECL(k_scan_one, ScanArgs);
+MJ_KERNEL_DECL(k_scan_one64, Scan64Args);
 
 // ------------------------------------------------------------- radix sort
 constexpr int RS_THREADS = 256;
@@ -573,16 +591,18 @@ struct RsArgs {
     uint32_t* hist;              // [256][ntiles]
     const uint32_t* starts;      // [257] digit starts
 };
-__global__ void k_rs_hist(RsArgs A);
-__global__ void k_rs_scatter(RsArgs A);
+MJ_KERNEL_DECL(k_rs_hist, RsArgs);
+MJ_KERNEL_DECL(k_rs_scatter, RsArgs);
 // small arrays: the whole sort in one workgroup, or one scan launch per pass
 constexpr uint32_t RS_SMALL_BITS = 14;
 constexpr uint32_t RS_SMALL = 1u << RS_SMALL_BITS;   // keys sorted whole in LDS
 constexpr int RS_SMALL_THREADS = 1024;
 constexpr uint32_t RS_SCAN1_TILES = 32;              // tiles scanned by one workgroup
 static_assert(size_t(RS_SMALL) * 8 <= LDS_BYTES && RS_SMALL_BITS <= 16, "small sort shape");
-__global__ void k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift);
-__global__ void k_rs_scan1(RsArgs A, uint32_t* starts);
+struct RsSmallArgs { unsigned long long* keys; uint32_t n; uint32_t shift; };
+struct RsScan1Args { RsArgs rs; uint32_t* starts; };
+MJ_KERNEL_DECL(k_rs_small, RsSmallArgs);
+MJ_KERNEL_DECL(k_rs_scan1, RsScan1Args);
 
 // --------------------------------------------------------------- triangle
 constexpr int TRI_THREADS = 256;           // light kernel: one table per wave
@@ -767,7 +787,7 @@ struct CasProbeTriArgs {
     uint32_t seed;
     unsigned long long* total;
 };
-__global__ void k_cas_probe_tri(CasProbeTriArgs A);
+MJ_KERNEL_DECL(k_cas_probe_tri, CasProbeTriArgs);
 struct TriBatchArgs {
     const TriJoinArgs* joins;            // [njoins] on the device
     uint32_t njoins;
@@ -786,16 +806,28 @@ struct LinearBatchArgs {
 };
 __global__ void k_linear_cell_batch(LinearBatchArgs B);
 
-__global__ void k_tri_keys(TriKeyArgs A);
-__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags, uint32_t* low);
-__global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,
-                              const unsigned long long* ridx, uint32_t* run_key,
-                              uint32_t* run_start, unsigned long long* nruns);
-__global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nruns_p,
-                          uint32_t bits, uint32_t* dir);
-__global__ void k_tri_classify(TriClassifyArgs A);
-__global__ void k_tri_light(TriJoinArgs A);
-__global__ void k_tri_heavy(TriJoinArgs A);
+MJ_KERNEL_DECL(k_tri_keys, TriKeyArgs);
+// runs of equal high words of sorted keys: flags of run heads (and the low
+// words, when `low` is set), then each head's run start and key, then a
+// directory of the runs by the top `bits` bits of their keys
+struct RunFlagsArgs { const unsigned long long* keys; uint64_t n; uint32_t* flags; uint32_t* low; };
+struct RunCompactArgs {
+    const unsigned long long* keys;
+    uint64_t n;
+    const uint32_t* flags;
+    const unsigned long long* ridx;   // [n + 1] exclusive scan of flags
+    uint32_t* run_key;
+    uint32_t* run_start;
+    unsigned long long* nruns;
+};
+// dir[p] = first run whose key prefix (top `bits` bits) is >= p, p in [0, 2^bits]
+struct RunDirArgs { const uint32_t* run_key; const unsigned long long* nruns; uint32_t bits; uint32_t* dir; };
+MJ_KERNEL_DECL(k_run_flags, RunFlagsArgs);
+MJ_KERNEL_DECL(k_run_compact, RunCompactArgs);
+MJ_KERNEL_DECL(k_run_dir, RunDirArgs);
+MJ_KERNEL_DECL(k_tri_classify, TriClassifyArgs);
+MJ_KERNEL_DECL(k_tri_light, TriJoinArgs);
+MJ_KERNEL_DECL(k_tri_heavy, TriJoinArgs);
 
 // ------------------------------------------------ materialised linear join
 // The result tuples (a, b, c, d) of R |x| S |x| T written out in nested-loop
@@ -866,10 +898,11 @@ struct OrientArgs {
     const uint32_t* deg;           // dense ids: [vdom] degree of each vertex (else unused)
     uint32_t vdom;
 };
-__global__ void k_orient_flags(OrientArgs A);
-__global__ void k_orient_flags_dense(OrientArgs A);
-__global__ void k_orient_compact(OrientArgs A);
-__global__ void k_orient_finish(OrientArgs A, uint64_t expect);
+MJ_KERNEL_DECL(k_orient_flags, OrientArgs);
+MJ_KERNEL_DECL(k_orient_flags_dense, OrientArgs);
+MJ_KERNEL_DECL(k_orient_compact, OrientArgs);
+struct OrientFinishArgs { OrientArgs o; uint64_t expect; };   // expect: the oriented edges' count
+MJ_KERNEL_DECL(k_orient_finish, OrientFinishArgs);
 __global__ void k_sym_check(const unsigned long long* K1, const unsigned long long* K2, uint64_t n, uint32_t* bad);
 
 // ------------------------------------------------------------ learned planner
@@ -931,7 +964,11 @@ __global__ void k_sketch_features(const uint32_t* hist3, uint64_t nr, uint64_t n
 
 // max of a column (key-range check)
 __global__ void k_col_max(const uint32_t* col, int64_t stride, uint64_t n, uint32_t* out);
-__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v);
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v);
+struct FillU64Args { unsigned long long* p; uint64_t n; unsigned long long v; };   // p[0..n) = v
+struct FillU32Args { uint32_t* p; uint64_t n; uint32_t v; };
+MJ_KERNEL_DECL(k_fill_u64, FillU64Args);
+MJ_KERNEL_DECL(k_fill_u32, FillU32Args);
+struct CopyU64Args { unsigned long long* dst; const unsigned long long* src; uint64_t n; };   // dst[0..n) = src[0..n)
+MJ_KERNEL_DECL(k_copy_u64, CopyU64Args);
 
 }  // namespace mj

@@ -15,10 +15,9 @@ namespace mj {
 // keep[i] = 1 when edge i = (u, v) points up in (degree, mixed id) order;
 // a loop, or a v that never appears as an edge's first end, means the
 // relation is not what the plan certified
-__global__ void __launch_bounds__(256)
-k_orient_flags(OrientArgs A) {
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 2;
-    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 2 + threadIdx.x; q < A.n; q += stride) {
+MJ_KERNEL(k_orient_flags, 256, OrientArgs) {
+    const uint64_t stride = uint64_t(vg.nblk) * blockDim.x * 2;
+    for (uint64_t q = uint64_t(vg.bid) * blockDim.x * 2 + threadIdx.x; q < A.n; q += stride) {
         uint32_t key[4], run[4];
         bool live[4];
 #pragma unroll
@@ -52,10 +51,9 @@ k_orient_flags(OrientArgs A) {
 // direct-indexed array.  An id at or above vdom, a loop, or a v of degree 0
 // (never an edge's first end) means the relation is not what the plan
 // certified.
-__global__ void __launch_bounds__(256)
-k_orient_flags_dense(OrientArgs A) {
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
-    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
+MJ_KERNEL(k_orient_flags_dense, 256, OrientArgs) {
+    const uint64_t stride = uint64_t(vg.nblk) * blockDim.x * 4;
+    for (uint64_t q = uint64_t(vg.bid) * blockDim.x * 4 + threadIdx.x; q < A.n; q += stride) {
         uint32_t u[4], v[4], du[4], dv[4];
         bool ok[4];
 #pragma unroll
@@ -86,10 +84,9 @@ k_orient_flags_dense(OrientArgs A) {
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_orient_compact(OrientArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+MJ_KERNEL(k_orient_compact, 256, OrientArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         if (!A.flags[i]) continue;
         A.E[A.ridx[i]] = make_uint2(ld_col(A.c0, i, A.stride), ld_col(A.c1, i, A.stride));
     }
@@ -97,9 +94,10 @@ k_orient_compact(OrientArgs A) {
 
 // total = 6 x triangles, or all ones when the relation was not symmetric
 // and simple after all (the oriented edges must be exactly half of them)
-__global__ void k_orient_finish(OrientArgs A, uint64_t expect) {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *A.total = (*A.err || A.ridx[A.n] != expect) ? ~0ull : *A.total * 6ull;
+MJ_KERNEL(k_orient_finish, 64, OrientFinishArgs) {
+    const OrientArgs& O = A.o;
+    if (vg.bid == 0 && threadIdx.x == 0)
+        *O.total = (*O.err || O.ridx[O.n] != A.expect) ? ~0ull : *O.total * 6ull;
 }
 
 // over the sorted (m(u), m(v)) and (m(v), m(u)) keys of one relation: equal

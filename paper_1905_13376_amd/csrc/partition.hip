@@ -52,8 +52,8 @@ __device__ __forceinline__ void part_store(T v, T* p) {
 // The tile a block works on: tiles of one XCD are contiguous, so the runs
 // adjacent tiles write into one bucket (adjacent in the output) meet in the
 // same L2.
-__device__ __forceinline__ uint32_t part_block() {
-    return MJ_PART_XCD_REMAP ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+__device__ __forceinline__ uint32_t part_block(VGrid vg) {
+    return MJ_PART_XCD_REMAP ? xcd_remap(vg.bid, vg.nblk) : vg.bid;
 }
 
 __device__ __forceinline__ int find_job(const PartLaunch& L, uint32_t blk) {
@@ -100,14 +100,14 @@ __device__ __forceinline__ void load_tile(const PartJob& J, uint64_t beg, uint32
     }
 }
 
-__global__ void __launch_bounds__(PART_THREADS)
-k_part_hist(PartLaunch L) {
+MJ_KERNEL(k_part_hist, PART_THREADS, PartLaunch) {
+    const PartLaunch& L = A;
     extern __shared__ uint32_t lhist[];
-    const uint32_t blk = part_block();
+    const uint32_t blk = part_block(vg);
     const int jid = find_job(L, blk);
     const PartJob& J = L.job[jid];
     const uint32_t nb = 1u << (J.bits0 + J.bits1);
-    if (blockIdx.x == 0) {                           // before the next launches of the group
+    if (vg.bid == 0) {                               // before the next launches of the group
         for (uint32_t w = threadIdx.x; w < L.nclear; w += blockDim.x) L.clear[w] = 0;
     }
     for (uint32_t d = threadIdx.x; d < nb; d += blockDim.x) lhist[d] = 0;
@@ -127,12 +127,12 @@ k_part_hist(PartLaunch L) {
 }
 
 // grid = sum over jobs of nb; block = one bucket row of one job.
-__global__ void __launch_bounds__(PART_THREADS)
-k_part_rowscan(PartLaunch L) {
+MJ_KERNEL(k_part_rowscan, PART_THREADS, PartLaunch) {
+    const PartLaunch& L = A;
     __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
     __shared__ uint32_t carry;
     int jid = 0;
-    uint32_t row = blockIdx.x;
+    uint32_t row = vg.bid;
     for (int q = 0; q < L.njobs; ++q) {
         const uint32_t nbq = 1u << (L.job[q].bits0 + L.job[q].bits1);
         if (row < nbq) { jid = q; break; }
@@ -196,18 +196,17 @@ __device__ void part_scan_job(const PartJob& J, uint32_t* lds, uint32_t* wave_tm
 }
 
 // One block per job.
-__global__ void __launch_bounds__(PART_THREADS)
-k_part_scan(PartLaunch L) {
+MJ_KERNEL(k_part_scan, PART_THREADS, PartLaunch) {
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wave_tmp[PART_THREADS / WAVE + 1];
-    part_scan_job(L.job[blockIdx.x], lds, wave_tmp);
+    part_scan_job(A.job[vg.bid], lds, wave_tmp);
 }
 
-__global__ void __launch_bounds__(PART_SCATTER_THREADS)
-k_part_scatter(PartLaunch L) {
+MJ_KERNEL(k_part_scatter, PART_SCATTER_THREADS, PartLaunch) {
+    const PartLaunch& L = A;
     extern __shared__ uint32_t smem[];
     __shared__ uint32_t wave_tmp[PART_SCATTER_THREADS / WAVE + 1];
-    const uint32_t blk = part_block();
+    const uint32_t blk = part_block(vg);
     const int jid = find_job(L, blk);
     const PartJob& J = L.job[jid];
     const uint32_t nb = 1u << (J.bits0 + J.bits1);

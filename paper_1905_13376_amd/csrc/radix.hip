@@ -16,10 +16,9 @@
 
 namespace mj {
 
-__global__ void __launch_bounds__(RS_THREADS)
-k_rs_hist(RsArgs A) {
+MJ_KERNEL(k_rs_hist, RS_THREADS, RsArgs) {
     __shared__ uint32_t lh[256];
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tile = xcd_remap(vg.bid, vg.nblk);
     for (uint32_t d = threadIdx.x; d < 256; d += blockDim.x) lh[d] = 0;
     __syncthreads();
     const uint64_t beg = uint64_t(tile) * RS_TILE;
@@ -31,12 +30,11 @@ k_rs_hist(RsArgs A) {
         A.hist[uint64_t(d) * A.ntiles + tile] = lh[d];
 }
 
-__global__ void __launch_bounds__(RS_THREADS)
-k_rs_scatter(RsArgs A) {
+MJ_KERNEL(k_rs_scatter, RS_THREADS, RsArgs) {
     __shared__ uint32_t running[256];
     __shared__ uint32_t wcnt[RS_THREADS / WAVE][256];
     // adjacent tiles write adjacent runs of every digit: keep them on one XCD
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tile = xcd_remap(vg.bid, vg.nblk);
     const int lane = lane_id();
     const int w = threadIdx.x / WAVE;
     constexpr int NW = RS_THREADS / WAVE;
@@ -90,13 +88,15 @@ k_rs_scatter(RsArgs A) {
 // histogram becomes its exclusive prefix over tiles (in place), and the
 // digits' totals their exclusive prefix (starts, with starts[256] = n):
 // what k_part_rowscan and k_part_scan write, in one launch.
-__global__ void __launch_bounds__(256)
-k_rs_scan1(RsArgs A, uint32_t* starts) {
+MJ_KERNEL(k_rs_scan1, 256, RsScan1Args) {
+    (void)vg;
+    const RsArgs& R = A.rs;
+    uint32_t* starts = A.starts;
     __shared__ uint32_t h[256 * RS_SCAN1_TILES];
     __shared__ uint32_t tot[256];
     __shared__ uint32_t wave_tmp[256 / WAVE + 1];
-    const uint32_t nt = A.ntiles, m = 256 * nt;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) h[i] = A.hist[i];
+    const uint32_t nt = R.ntiles, m = 256 * nt;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) h[i] = R.hist[i];
     __syncthreads();
     {
         const uint32_t d = threadIdx.x;          // one digit per thread
@@ -109,7 +109,7 @@ k_rs_scan1(RsArgs A, uint32_t* starts) {
         tot[d] = run;
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) A.hist[i] = h[i];
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) R.hist[i] = h[i];
     const uint32_t total = block_exclusive_scan(tot, 256, wave_tmp);
     starts[threadIdx.x] = tot[threadIdx.x];
     if (threadIdx.x == 0) starts[256] = total;
@@ -122,8 +122,10 @@ k_rs_scan1(RsArgs A, uint32_t* starts) {
 // the composites are sorted, and each position takes the key its index names
 // (kept in LDS beside them).  A bitonic network over the next power of two,
 // padded with the largest value; pads sort after every real entry.
-__global__ void __launch_bounds__(RS_SMALL_THREADS)
-k_rs_small(unsigned long long* keys, uint32_t n, uint32_t shift) {
+MJ_KERNEL(k_rs_small, RS_SMALL_THREADS, RsSmallArgs) {
+    (void)vg;
+    unsigned long long* keys = A.keys;
+    const uint32_t n = A.n, shift = A.shift;
     extern __shared__ unsigned long long rs_lds[];
     uint32_t P = 2;
     while (P < n) P <<= 1;

@@ -63,9 +63,9 @@ __device__ __forceinline__ uint2 star_row(const uint32_t* col0, const uint32_t* 
 }
 
 // rows [beg, end) of this workgroup's contiguous chunk
-__device__ __forceinline__ void star_chunk(uint64_t n, uint64_t& beg, uint64_t& end) {
-    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
-    beg = uint64_t(blockIdx.x) * per;
+__device__ __forceinline__ void star_chunk(uint64_t n, VGrid vg, uint64_t& beg, uint64_t& end) {
+    const uint64_t per = (n + vg.nblk - 1) / vg.nblk;
+    beg = uint64_t(vg.bid) * per;
     end = min<uint64_t>(n, beg + per);
 }
 
@@ -145,9 +145,9 @@ __device__ __forceinline__ void lds_get4(const uint2* tab, const uint32_t (&key)
 // next step's rows loaded before the current ones are processed.
 template <typename F>
 __device__ __forceinline__ void star_stream(const uint32_t* col0, const uint32_t* col1, int64_t stride,
-                                            uint64_t n, F&& body) {
+                                            uint64_t n, VGrid vg, F&& body) {
     uint64_t beg, end;
-    star_chunk(n, beg, end);
+    star_chunk(n, vg, beg, end);
     const uint64_t nthr = blockDim.x, step = STAR_U * nthr;
     uint2 cur[STAR_U], nxt[STAR_U];
 #pragma unroll
@@ -175,10 +175,10 @@ __device__ __forceinline__ void star_stream(const uint32_t* col0, const uint32_t
     }
 }
 
-__global__ void k_star_occ(StarOccArgs A) {
+MJ_KERNEL(k_star_occ, 256, StarOccArgs) {
     const uint64_t cursor = *A.cursor;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= A.R.pool_slots;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i <= A.R.pool_slots;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         uint32_t o;
         if (i == A.R.pool_slots) o = A.R.dir[0].special ? 1u : 0u;
         else o = (i < cursor && A.R.pool[i].x != EMPTY_KEY) ? 1u : 0u;
@@ -186,10 +186,10 @@ __global__ void k_star_occ(StarOccArgs A) {
     }
 }
 
-__global__ void k_star_ids(StarIdArgs A) {
+MJ_KERNEL(k_star_ids, 256, StarIdArgs) {
     const uint32_t ps = A.R.pool_slots;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ps;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < ps;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         const bool occ = A.rid[i + 1] != A.rid[i];
         A.idtab[i] = make_uint2(occ ? A.R.pool[i].x : EMPTY_KEY, occ ? (uint32_t)A.rid[i] : 0u);
     }
@@ -197,8 +197,7 @@ __global__ void k_star_ids(StarIdArgs A) {
 
 // Group-by of S = (b, c) rows by B, weight mult_T(c): the star three-way
 // join's one pass over the fact relation.
-__global__ void __launch_bounds__(STAR_THREADS)
-k_star_group_b(StarGroupArgs A) {
+MJ_KERNEL(k_star_group_b, STAR_THREADS, StarGroupArgs) {
     __shared__ uint2 ttab[STAR_LDS_SLOTS];
     __shared__ uint2 rtab[STAR_LDS_SLOTS];
     __shared__ unsigned long long acc[STAR_LDS_SLOTS / 2];
@@ -216,7 +215,7 @@ k_star_group_b(StarGroupArgs A) {
         for (uint32_t i = threadIdx.x; i < k; i += nthr) acc[i] = 0;
     }
     __syncthreads();
-    star_stream(A.col0, A.col1, A.stride, A.n,
+    star_stream(A.col0, A.col1, A.stride, A.n, vg,
                 [&](uint64_t, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
                     const bool (&live)[STAR_U]) {
         uint32_t w[STAR_U], id[STAR_U];
@@ -242,14 +241,13 @@ k_star_group_b(StarGroupArgs A) {
     __syncthreads();
     if (lds)
         for (uint32_t i = threadIdx.x; i < k; i += nthr)
-            A.partial[uint64_t(blockIdx.x) * STAR_STRIDE + i] = acc[i];
+            A.partial[uint64_t(vg.bid) * STAR_STRIDE + i] = acc[i];
 }
 
 // Group-by of (a, c) rows by A value, weight mult_T(c): the star cascade's
 // second join.  T's table in LDS when it fits, the sums in LDS while
 // a_domain <= STAR_GROUPS.
-__global__ void __launch_bounds__(STAR_THREADS)
-k_star_group_a(StarGroupArgs A) {
+MJ_KERNEL(k_star_group_a, STAR_THREADS, StarGroupArgs) {
     __shared__ uint2 ttab[STAR_LDS_SLOTS];
     __shared__ unsigned long long acc[STAR_GROUPS];
     const DirEntry te = A.T.dir[0];
@@ -262,7 +260,7 @@ k_star_group_a(StarGroupArgs A) {
     if (local)
         for (uint32_t i = threadIdx.x; i < ngroups; i += nthr) acc[i] = 0;
     __syncthreads();
-    star_stream(A.col0, A.col1, A.stride, A.n,
+    star_stream(A.col0, A.col1, A.stride, A.n, vg,
                 [&](uint64_t, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
                     const bool (&live)[STAR_U]) {
         uint32_t w[STAR_U];
@@ -279,14 +277,13 @@ k_star_group_a(StarGroupArgs A) {
     __syncthreads();
     if (local)
         for (uint32_t i = threadIdx.x; i < ngroups; i += nthr)
-            A.partial[uint64_t(blockIdx.x) * STAR_STRIDE + i] = acc[i];
+            A.partial[uint64_t(vg.bid) * STAR_STRIDE + i] = acc[i];
 }
 
 // out[g] = sum over blocks of partial[block][g] (LDS modes only): a block
 // takes 64 groups, its 16 rows of threads each sum every 16th block's
 // partials (64 consecutive groups per load), then the rows are added in LDS.
-__global__ void __launch_bounds__(STAR_REDUCE_THREADS)
-k_star_reduce(StarReduceArgs A) {
+MJ_KERNEL(k_star_reduce, STAR_REDUCE_THREADS, StarReduceArgs) {
     __shared__ unsigned long long part[STAR_REDUCE_THREADS / 64][64];
     uint32_t ngroups;
     if (A.by_b) {
@@ -298,7 +295,7 @@ k_star_reduce(StarReduceArgs A) {
     }
     constexpr uint32_t ROWS = STAR_REDUCE_THREADS / 64;
     const uint32_t col = threadIdx.x & 63u, row = threadIdx.x >> 6;
-    for (uint32_t g0 = blockIdx.x * 64; g0 < ngroups; g0 += gridDim.x * 64) {
+    for (uint32_t g0 = vg.bid * 64; g0 < ngroups; g0 += vg.nblk * 64) {
         const uint32_t g = g0 + col;
         unsigned long long s = 0;
         if (g < ngroups)
@@ -315,9 +312,9 @@ k_star_reduce(StarReduceArgs A) {
     }
 }
 
-__global__ void k_star_count(StarCountArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+MJ_KERNEL(k_star_count, 256, StarCountArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         const uint2 r = star_row(A.col0, A.col1, A.stride, i);
         const uint32_t sl = star_slot(A.R, r.y);
         if (sl == STAR_NONE) continue;
@@ -329,18 +326,19 @@ __global__ void k_star_count(StarCountArgs A) {
 }
 
 // --------------------------------------------------------------- cascade
-__global__ void k_star_rmult(StarRIndexArgs A, uint32_t* mult) {
-    const uint32_t ps = A.R.pool_slots;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i <= ps;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        if (A.rid[i + 1] == A.rid[i]) continue;        // not occupied
-        mult[A.rid[i]] = i == ps ? A.R.dir[0].special : A.R.pool[i].y;
+MJ_KERNEL(k_star_rmult, 256, StarRMultArgs) {
+    const StarRIndexArgs& X = A.x;
+    const uint32_t ps = X.R.pool_slots;
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i <= ps;
+         i += (uint64_t)vg.nblk * blockDim.x) {
+        if (X.rid[i + 1] == X.rid[i]) continue;        // not occupied
+        A.mult[X.rid[i]] = i == ps ? X.R.dir[0].special : X.R.pool[i].y;
     }
 }
 
-__global__ void k_star_rfill(StarRIndexArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+MJ_KERNEL(k_star_rfill, 256, StarRIndexArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         const uint2 r = star_row(A.col0, A.col1, A.stride, i);
         const uint32_t sl = star_slot(A.R, r.y);      // every b of R is in its table
         if (sl == STAR_NONE) continue;                // (unless its pool ran out: reported)
@@ -354,7 +352,7 @@ __global__ void k_star_rfill(StarRIndexArgs A) {
 // pairs themselves at prefix-sum positions), R's (key, id) table and the
 // group offsets in LDS when they fit.
 template <bool WRITE>
-__device__ void star_join1(const StarExpandArgs& A, uint2* rtab, unsigned long long* roffs) {
+__device__ void star_join1(const StarExpandArgs& A, VGrid vg, uint2* rtab, unsigned long long* roffs) {
     const DirEntry re = A.R.dir[0];
     const uint32_t rcap = 1u << re.log2cap;
     const uint32_t k = (uint32_t)A.rid[A.R.pool_slots + 1];
@@ -366,7 +364,7 @@ __device__ void star_join1(const StarExpandArgs& A, uint2* rtab, unsigned long l
     }
     __syncthreads();
     const uint64_t nthr = blockDim.x;
-    star_stream(A.col0, A.col1, A.stride, A.n,
+    star_stream(A.col0, A.col1, A.stride, A.n, vg,
                 [&](uint64_t q, const uint32_t (&key)[STAR_U], const uint32_t (&c)[STAR_U],
                     const bool (&live)[STAR_U]) {
         uint32_t id[STAR_U];
@@ -394,18 +392,16 @@ __device__ void star_join1(const StarExpandArgs& A, uint2* rtab, unsigned long l
     });
 }
 
-__global__ void __launch_bounds__(STAR_THREADS)
-k_star_icount(StarExpandArgs A) {
+MJ_KERNEL(k_star_icount, STAR_THREADS, StarExpandArgs) {
     __shared__ uint2 rtab[STAR_LDS_SLOTS];
     __shared__ unsigned long long roffs[STAR_STRIDE + 1];
-    star_join1<false>(A, rtab, roffs);
+    star_join1<false>(A, vg, rtab, roffs);
 }
 
-__global__ void __launch_bounds__(STAR_THREADS)
-k_star_expand(StarExpandArgs A) {
+MJ_KERNEL(k_star_expand, STAR_THREADS, StarExpandArgs) {
     __shared__ uint2 rtab[STAR_LDS_SLOTS];
     __shared__ unsigned long long roffs[STAR_STRIDE + 1];
-    star_join1<true>(A, rtab, roffs);
+    star_join1<true>(A, vg, rtab, roffs);
 }
 
 }  // namespace mj

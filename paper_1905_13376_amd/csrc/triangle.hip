@@ -30,9 +30,9 @@
 namespace mj {
 
 // --------------------------------------------------------------- key forms
-__global__ void k_tri_keys(TriKeyArgs A) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+MJ_KERNEL(k_tri_keys, 256, TriKeyArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
         const uint32_t hi = ld_col(A.key_col, i, A.stride);
         const uint32_t lo = ld_col(A.val_col, i, A.stride);
         A.out[i] = ((unsigned long long)mix32(hi, A.seed) << 32) | (A.raw_low ? lo : mix32(lo, A.seed));
@@ -42,43 +42,40 @@ __global__ void k_tri_keys(TriKeyArgs A) {
 // ------------------------------------------------------- runs of equal keys
 // (and, when `low` is given, the low words: the joins read only those once
 // the runs of the high words are indexed)
-__global__ void k_run_flags(const unsigned long long* keys, uint64_t n, uint32_t* flags, uint32_t* low) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const unsigned long long k = keys[i];
-        flags[i] = (i == 0 || (k >> 32) != (keys[i - 1] >> 32)) ? 1u : 0u;
-        if (low) low[i] = (uint32_t)k;
+MJ_KERNEL(k_run_flags, 256, RunFlagsArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
+        const unsigned long long k = A.keys[i];
+        A.flags[i] = (i == 0 || (k >> 32) != (A.keys[i - 1] >> 32)) ? 1u : 0u;
+        if (A.low) A.low[i] = (uint32_t)k;
     }
 }
 
 // run r starts at element i for every head i (ridx = exclusive scan of flags)
-__global__ void k_run_compact(const unsigned long long* keys, uint64_t n, const uint32_t* flags,
-                              const unsigned long long* ridx, uint32_t* run_key,
-                              uint32_t* run_start, unsigned long long* nruns) {
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        if (flags[i]) {
-            const uint64_t r = ridx[i];
-            run_key[r] = (uint32_t)(keys[i] >> 32);
-            run_start[r] = (uint32_t)i;
+MJ_KERNEL(k_run_compact, 256, RunCompactArgs) {
+    for (uint64_t i = vg.bid * (uint64_t)blockDim.x + threadIdx.x; i < A.n;
+         i += (uint64_t)vg.nblk * blockDim.x) {
+        if (A.flags[i]) {
+            const uint64_t r = A.ridx[i];
+            A.run_key[r] = (uint32_t)(A.keys[i] >> 32);
+            A.run_start[r] = (uint32_t)i;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        run_start[ridx[n]] = (uint32_t)n;
-        *nruns = ridx[n];
+    if (vg.bid == 0 && threadIdx.x == 0) {
+        A.run_start[A.ridx[A.n]] = (uint32_t)A.n;
+        *A.nruns = A.ridx[A.n];
     }
 }
 
 // dir[p] = first run whose key prefix (top `bits` bits) is >= p, p in [0, 2^bits]
-__global__ void k_run_dir(const uint32_t* run_key, const unsigned long long* nruns_p,
-                          uint32_t bits, uint32_t* dir) {
-    const uint64_t nruns = *nruns_p;
-    const uint64_t np = uint64_t(1) << bits;
-    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r <= nruns;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t lo = r == 0 ? 0 : uint64_t(top_bits(run_key[r - 1], bits)) + 1;
-        const uint64_t hi = r == nruns ? np : uint64_t(top_bits(run_key[r], bits));
-        for (uint64_t p = lo; p <= hi; ++p) dir[p] = (uint32_t)r;
+MJ_KERNEL(k_run_dir, 256, RunDirArgs) {
+    const uint64_t nruns = *A.nruns;
+    const uint64_t np = uint64_t(1) << A.bits;
+    for (uint64_t r = vg.bid * (uint64_t)blockDim.x + threadIdx.x; r <= nruns;
+         r += (uint64_t)vg.nblk * blockDim.x) {
+        const uint64_t lo = r == 0 ? 0 : uint64_t(top_bits(A.run_key[r - 1], A.bits)) + 1;
+        const uint64_t hi = r == nruns ? np : uint64_t(top_bits(A.run_key[r], A.bits));
+        for (uint64_t p = lo; p <= hi; ++p) A.dir[p] = (uint32_t)r;
     }
 }
 
@@ -93,10 +90,10 @@ __device__ __forceinline__ void heavy_shape(uint32_t x, uint32_t gn, uint32_t sh
     nsr = (gn + TRI_HEAVY_S - 1) / TRI_HEAVY_S;
 }
 
-__global__ void k_tri_classify(TriClassifyArgs A) {
+MJ_KERNEL(k_tri_classify, 256, TriClassifyArgs) {
     const uint64_t ng = *A.Grp.nruns;
-    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ng;
-         g += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t g = vg.bid * (uint64_t)blockDim.x + threadIdx.x; g < ng;
+         g += (uint64_t)vg.nblk * blockDim.x) {
         uint32_t rs, x;
         if (!run_lookup(A.Stg, A.Grp.run_key[g], rs, x)) continue;
         const uint32_t gn = A.Grp.run_start[g + 1] - A.Grp.run_start[g];
@@ -291,8 +288,8 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     if (lane == 0) { *W.spec = 0; *W.nused = 0; }                                    \
     wave_fence();
 
-__global__ void __launch_bounds__(TRI_THREADS)
-k_tri_light(TriJoinArgs A) {
+MJ_KERNEL(k_tri_light, TRI_THREADS, TriJoinArgs) {
+    (void)vg;                                         // work comes from the join's queue
     TRI_LIGHT_SETUP
     const uint32_t nitems = *A.nlight;
     unsigned long long acc = 0;
@@ -371,8 +368,8 @@ __device__ unsigned long long tri_heavy_item(const TriJoinArgs& A, uint32_t it, 
     BlockTable B{hkeys, hvals, &hspec, &hchunk};                          \
     const int lane = lane_id();
 
-__global__ void __launch_bounds__(TRI_HEAVY_THREADS)
-k_tri_heavy(TriJoinArgs A) {
+MJ_KERNEL(k_tri_heavy, TRI_HEAVY_THREADS, TriJoinArgs) {
+    (void)vg;
     TRI_HEAVY_SETUP
     const uint32_t nitems = (uint32_t)A.heavy_off[A.n_heavy_cap];
     unsigned long long acc = 0;
@@ -460,11 +457,10 @@ __global__ void k_tri_batch_prefix(TriBatchArgs Bt) {
 // ----------------------------------------------- cascade, cyclic second join
 // For every (a, c) of I = R |x| S: the multiplicity of (c, a) in T, found in
 // T's sorted list of m(c) by binary search on m(a).
-__global__ void __launch_bounds__(256)
-k_cas_probe_tri(CasProbeTriArgs A) {
+MJ_KERNEL(k_cas_probe_tri, 256, CasProbeTriArgs) {
     unsigned long long acc = 0;
-    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < A.n;
-         q += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t q = vg.bid * (uint64_t)blockDim.x + threadIdx.x; q < A.n;
+         q += (uint64_t)vg.nblk * blockDim.x) {
         const uint2 iv = A.I[q];
         uint32_t ts, y;
         if (!run_lookup(A.T, mix32(iv.y, A.seed), ts, y)) continue;

@@ -8,8 +8,9 @@ change -- a dynamic LDS declaration `extern __shared__ T name[];` becomes a
 pointer to the workgroup's dynamic LDS buffer -- and compiled as C++ for the
 CPU against the stand-in runtime of tests/hostsim (hip/hip_runtime.h,
 sim.cpp).  Output: _build/hostsim/replay (the benchmark's call sequence,
-replay.cpp) and _build/hostsim/abi_check (argument checks that need a
-context, abi_check.cpp).
+replay.cpp), _build/hostsim/abi_check (argument checks that need a
+context, abi_check.cpp) and _build/hostsim/multi_check (merged launches'
+block search, multi_check.cpp).
 """
 from __future__ import annotations
 
@@ -54,7 +55,8 @@ def build(sanitize: bool = True, jobs: int = 8, verbose: bool = False) -> str:
         if name.endswith((".hip", ".cpp")):
             units.append(dst)
     units += [os.path.join(HERE, "sim.cpp")]
-    mains = [os.path.join(HERE, "replay.cpp"), os.path.join(HERE, "abi_check.cpp")]
+    mains = [os.path.join(HERE, "replay.cpp"), os.path.join(HERE, "abi_check.cpp"),
+             os.path.join(HERE, "multi_check.cpp")]
     # uninitialised locals (kernel argument structs among them) hold a
     # non-zero pattern, so a field left unset reads as a wild value, not 0
     flags = ["-x", "c++", "-std=c++17", "-g", "-O1", "-fno-omit-frame-pointer", "-pthread",

@@ -36,6 +36,8 @@
 #define __shared__ static thread_local
 #define __restrict__ __restrict
 #define __align__(n) __attribute__((aligned(n)))
+// merged launches' argument tables are plain memory on the host
+#define MJ_CONSTANT_AS
 
 struct dim3 {
     uint32_t x, y, z;
@@ -102,7 +104,8 @@ inline void __syncthreads() { ::hipsim::syncthreads(); }
 inline void __threadfence() { __atomic_thread_fence(__ATOMIC_SEQ_CST); }
 // the device's scoped fence builtin: a fence of the given order on the host
 #define __builtin_amdgcn_fence(order, scope) __atomic_thread_fence(order)
-#define __builtin_amdgcn_wave_barrier() ((void)0)
+// the wave's lanes meet (a ballot is a rendezvous of the wave's live lanes)
+#define __builtin_amdgcn_wave_barrier() ((void)::hipsim::wave_exchange(0, ::hipsim::OP_BALLOT, 0, 64))
 #define __builtin_amdgcn_fence(...) __atomic_thread_fence(__ATOMIC_SEQ_CST)
 
 template <class T>

@@ -4,7 +4,8 @@ closed-form totals in meta.json.
 
     python tests/hostsim/make_inputs.py OUT_DIR [--full | --tiny]
 
-Without --full the power-law graph is scaled down (2^20 edges over 2^16
+The batch leg's eighty small joins are the same at every size.  Without
+--full the power-law graph is scaled down (2^20 edges over 2^16
 vertices, --tiny: 2^16 over 2^12) and the star schema's fact relation to
 2^22 tuples (--tiny: 2^18).
 """
@@ -19,6 +20,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+import oracle  # noqa: E402
 from workloads import generators as G  # noqa: E402
 
 
@@ -99,6 +101,18 @@ def main():
         g.shuffle(K2)
         put(name, K2, dom)
         meta[name]["closed_total"] = closed_total(K2, K2, K2)
+    # a batch: small joins of both kinds (the mixed batch's generator);
+    # a_domain 0 marks a cyclic join
+    # twelve joins of 10^2.7..10^4 edges, then 68 of 10^2.2..10^2.9 (merged
+    # launches of more than 64 joins)
+    batch = [("B", k, G.batch_instance(k, count=12, lo_exp=2.7, hi_exp=4.0)) for k in range(12)]
+    batch += [("B", 12 + k, G.batch_instance(k, count=68, base_seed=4600, lo_exp=2.2, hi_exp=2.9)) for k in range(68)]
+    for _, k, x in batch:
+        F = x["F"].view(np.uint32)
+        put(f"B{k}", F, x["n"] if x["kind"] == "linear" else 0)
+        # the linear join's total in closed form; the cyclic join's count from the oracle
+        meta[f"B{k}"]["closed_total"] = closed_total(F, F, F) if x["kind"] == "linear" else \
+            oracle.triangle3_count(F, F, F)
     with open(os.path.join(out, "meta.json"), "w") as f:
         json.dump(meta, f, indent=1)
     with open(os.path.join(out, "meta.txt"), "w") as f:          # name n a_domain closed_total

@@ -6,7 +6,7 @@
 // any access outside those buffers; the checks below report results that
 // differ from the closed forms or between algorithms.
 //
-//   replay DATA_DIR [legs...]     legs: main cascade skew small fm emit star slarge (default: all)
+//   replay DATA_DIR [legs...]     legs: main cascade skew small fm emit star slarge batch (default: all)
 //   environment: HIPSIM_STEPS (timed steps of the main leg, default 2)
 #include <algorithm>
 #include <cinttypes>
@@ -345,6 +345,93 @@ int main(int argc, char** argv) {
         expect(std::memcmp(c0, c1, na * 8) == 0, "slarge: equals the cascade");
         std::free(wst); std::free(c0); std::free(c1);
         std::free(const_cast<uint32_t*>(R)); std::free(const_cast<uint32_t*>(S)); std::free(const_cast<uint32_t*>(T));
+    }
+    if (want("batch")) {
+        // small joins of both kinds under every plan form, as one batch:
+        // each join's result equals its own call's, on two calls in a row
+        leg("batch");
+        const int algos_lin[3] = {MJ_ALGO_3WAY, MJ_ALGO_CASCADE, MJ_ALGO_STAR};
+        const int algos_tri[3] = {MJ_ALGO_3WAY, MJ_ALGO_CASCADE, MJ_ALGO_ORIENTED};
+        std::vector<const uint32_t*> data;
+        std::vector<mj_batch_item> items;
+        std::vector<std::vector<uint64_t>> want_out;
+        for (int k = 0; g_meta.count("B" + std::to_string(k)); ++k) {
+            const std::string nm = "B" + std::to_string(k);
+            const Meta& m = g_meta.at(nm);
+            const uint32_t* X = load(nm);
+            data.push_back(X);
+            const mj_rel r = rel_of(X, m.n);
+            const int kind = m.a_domain ? MJ_LINEAR : MJ_TRIANGLE;
+            mj_plan_t p;
+            std::memset(&p, 0, sizeof p);
+            check(make_plan(ctx, kind, &r, &r, &r, m.a_domain, &p), "mj_plan batch");
+            p.algo = kind == MJ_LINEAR ? algos_lin[k % 3] : algos_tri[k % 3];
+            if (p.algo == MJ_ALGO_STAR && (m.n > 4096)) p.algo = MJ_ALGO_3WAY;
+            if (p.algo == MJ_ALGO_ORIENTED && !(p.flags & MJ_PLAN_SYMMETRIC_SIMPLE)) p.algo = MJ_ALGO_3WAY;
+            if (p.algo == MJ_ALGO_STAR) { p.log2_nb = 0; p.log2_nc = 0; }
+            {
+                const uint64_t need = mj_plan_workspace(kind, r.n, r.n, r.n);
+                void* pws = alloc(need);
+                check(mj_plan(ctx, kind, &r, &r, &r, m.a_domain, MJ_PLANNER_FIXED, &p, pws, need, nullptr),
+                      "mj_plan batch fixed");
+                std::free(pws);
+            }
+            const uint64_t len = kind == MJ_LINEAR ? m.a_domain : 1;
+            std::vector<uint64_t> ref(len);
+            void* wsb = alloc(p.workspace_bytes);
+            if (p.algo == MJ_ALGO_CASCADE || p.algo == MJ_ALGO_STAR_CASCADE)
+                check(mj_cascade2_count(ctx, kind, &r, &r, &r, m.a_domain, ref.data(), &p, wsb, p.workspace_bytes,
+                                        nullptr), "batch: own call");
+            else if (kind == MJ_LINEAR)
+                check(mj_linear3_count(ctx, &r, &r, &r, m.a_domain, ref.data(), &p, wsb, p.workspace_bytes, nullptr),
+                      "batch: own call");
+            else
+                check(mj_triangle3_count(ctx, &r, &r, &r, ref.data(), &p, wsb, p.workspace_bytes, nullptr),
+                      "batch: own call");
+            std::free(wsb);
+            std::printf("[replay]   join %d: kind %d algo %d n %" PRIu64 " result sum %" PRIu64 "\n", k, kind, p.algo,
+                        m.n, sum(ref.data(), len));
+            expect(sum(ref.data(), len) == m.closed, "batch: the join's own call gives the expected total");
+            mj_batch_item it;
+            std::memset(&it, 0, sizeof it);
+            it.kind = kind; it.R = r; it.S = r; it.T = r; it.a_domain = m.a_domain; it.plan = p;
+            it.out = static_cast<uint64_t*>(alloc(len * 8));
+            items.push_back(it);
+            want_out.push_back(std::move(ref));
+        }
+        const int nb = (int)items.size();
+        const uint64_t need = mj_batch_workspace(items.data(), nb);
+        void* wsb = alloc(need);
+        for (int call = 0; call < 2; ++call) {
+            if (call == 1) check(mj_ctx_profile(ctx, 1), "profile on");
+            check(mj_batch_count(ctx, items.data(), nb, wsb, need, nullptr), "mj_batch_count");
+            bool same = true;
+            for (int k = 0; k < nb; ++k) {
+                const bool eq = std::memcmp(items[k].out, want_out[k].data(), want_out[k].size() * 8) == 0;
+                if (!eq)
+                    std::printf("[replay]   join %d differs: batch sum %" PRIu64 ", own call %" PRIu64 "\n", k,
+                                sum(items[k].out, want_out[k].size()), sum(want_out[k].data(), want_out[k].size()));
+                same = same && eq;
+            }
+            expect(same, call ? "batch: a second call gives the same results"
+                              : "batch: every join equals its own call");
+        }
+        char names[64 * 64];
+        double ms[64];
+        int64_t cnt[64];
+        const int nk = mj_ctx_profile_read(ctx, 64, names, ms, cnt);
+        check(mj_ctx_profile(ctx, 0), "profile off");
+        int64_t launches = 0;
+        for (int q = 0; q < nk && q < 64; ++q) launches += cnt[q];
+        std::printf("[replay]   batch of %d joins: %" PRId64 " launches:", nb, launches);
+        for (int q = 0; q < nk && q < 64; ++q) std::printf(" %.32s x%" PRId64, names + 32 * q, cnt[q]);
+        std::printf("\n");
+        // one byte short of the workspace is refused
+        expect(mj_batch_count(ctx, items.data(), nb, wsb, need - 1, nullptr) == MJ_ERR_WORKSPACE,
+               "batch: a workspace one byte short is refused");
+        std::free(wsb);
+        for (auto& it : items) std::free(it.out);
+        for (auto* X : data) std::free(const_cast<uint32_t*>(X));
     }
     check(mj_ctx_destroy(ctx), "mj_ctx_destroy");
     std::free(ws); std::free(out); std::free(const_cast<uint32_t*>(F));

@@ -5,11 +5,16 @@ buffer is an exact-size allocation pre-filled with a non-zero byte.
 - abi_check: argument checks that need a context (a planning workspace one
   byte short, a plan given other relations of the same sizes, a count
   workspace too small);
+- multi_check: merged launches (one grid for launches of one kernel from
+  several joins): every workgroup finds its own launch, block index and
+  grid size, for 1..6000 launches;
 - replay: the benchmark's sequence of calls on one context (the three-way
   join with per-kernel events, the cascade on the same plan, the small
   workload, the distinct count, windows of the materialised result, the
-  star schema under its four plans) on scaled-down inputs, each result
-  checked against a closed form or another algorithm, under two fill bytes.
+  star schema under its four plans, a batch of eighty small joins of both
+  kinds under every plan form) on scaled-down inputs, each result checked
+  against a closed form, the oracle or another algorithm, under two fill
+  bytes.
 Any access outside a buffer, undefined behaviour, a deadlock at a barrier
 or a differing result fails the test."""
 import os
@@ -38,6 +43,11 @@ def _run(cmd, env_extra=None, timeout=600):
 
 def test_abi_checks_under_sanitizers(built):
     rc, out = _run([os.path.join(built, "abi_check")])
+    assert rc == 0 and "all checks passed" in out, out[-3000:]
+
+
+def test_merged_launch_block_search(built):
+    rc, out = _run([os.path.join(built, "multi_check")])
     assert rc == 0 and "all checks passed" in out, out[-3000:]
 
 
