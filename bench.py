@@ -787,8 +787,8 @@ def planner_path(ctx, n=300):
 def batch_path(mj, ctx):
     """512 independent joins of uneven size (half linear, half cyclic; edge
     counts log-uniform in [10^3, 10^6]; uniform or Zipf(1.1) degrees): one
-    mj_batch_count call, its HIP-graph replay, and the same joins one call
-    each for comparison."""
+    mj_batch_count call (its kernel launches counted), its HIP-graph replay,
+    and the same joins one call each for comparison."""
     import numpy as np
     import torch
     from workloads import generators as G
@@ -808,6 +808,8 @@ def batch_path(mj, ctx):
     plan_ms = (time.perf_counter() - t0) * 1e3
     b = ctx.batch(joins, plans=plans)
     ms_batch = time_call(lambda: b.run(), 3)
+    _, kp = time_and_profile(ctx, lambda: b.run(), 1, 1)       # launches of one call
+    launches = int(round(sum(v[1] for v in kp.values())))
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
     b.run()
@@ -832,6 +834,7 @@ def batch_path(mj, ctx):
                for (k, _, _, _, a), o, ob in zip(joins, outs, outs_b))
     log(f"batch of 512: {ms_batch:.2f} ms (graph {ms_graph:.2f} ms), one call per join {ms_seq:.2f} ms")
     return {"joins": len(joins), "input_tuples": tuples, "ms_batch": round(ms_batch, 3),
+            "kernel_launches_per_call": launches,
             "ms_graph_replay": round(ms_graph, 3), "ms_one_call_per_join": round(ms_seq, 3),
             "tuples_per_s_batch": tuples / (ms_batch * 1e-3),
             "tuples_per_s_graph_replay": tuples / (ms_graph * 1e-3), "plan_ms_total": round(plan_ms, 1),

@@ -192,17 +192,23 @@ __device__ __forceinline__ const Args& merged_args(const void* table, uint32_t j
 // A kernel that runs alone (`name`, its grid is the launch's) or merged with
 // other launches of itself (`name##_multi`, one MultiGrid argument).  The
 // body follows the macro; it names its argument struct A and its grid vg.
+// Alone, the body takes the struct by value (the kernel's own argument, so
+// the code is that of a plain kernel); merged, by reference into the
+// constant table (a private copy would put an indexed array of the struct in
+// scratch memory).
 #define MJ_KERNEL(name, T, Args)                                                            \
-    __device__ __forceinline__ void name##_body(const Args& A, ::mj::VGrid vg);              \
+    template <class P_>                                                                     \
+    __device__ __forceinline__ void name##_body(P_ A, ::mj::VGrid vg);                      \
     __global__ void __launch_bounds__(T) name(Args A) {                                     \
-        name##_body(A, ::mj::VGrid{blockIdx.x, gridDim.x});                                 \
+        name##_body<const Args>(A, ::mj::VGrid{blockIdx.x, gridDim.x});                     \
     }                                                                                       \
     __global__ void __launch_bounds__(T) name##_multi(::mj::MultiGrid M) {                  \
         const uint32_t j_ = ::mj::multi_job(M, blockIdx.x);                                 \
-        name##_body(::mj::merged_args<Args>(M.args, j_),                                    \
-                    ::mj::VGrid{blockIdx.x - M.base[j_], M.base[j_ + 1] - M.base[j_]});     \
+        name##_body<const Args&>(::mj::merged_args<Args>(M.args, j_),                       \
+                                 ::mj::VGrid{blockIdx.x - M.base[j_], M.base[j_ + 1] - M.base[j_]}); \
     }                                                                                       \
-    __device__ __forceinline__ void name##_body(const Args& A, ::mj::VGrid vg)
+    template <class P_>                                                                     \
+    __device__ __forceinline__ void name##_body(P_ A, ::mj::VGrid vg)
 
 // Declarations of both forms, and the name of the argument struct.
 #define MJ_KERNEL_DECL(name, Args)    \
