@@ -609,6 +609,7 @@ constexpr int TRI_THREADS = 256;           // light kernel: one table per wave
 constexpr int TRI_HEAVY_THREADS = 1024;    // heavy kernel: one table per workgroup
 constexpr uint32_t TRI_LIGHT_X = 512;      // R list length handled by one wave
 constexpr uint32_t TRI_LIGHT_CAP = 1024;   // its LDS table (load <= 1/2)
+static_assert(TRI_LIGHT_CAP <= 65536, "used slots are kept as 16-bit numbers");
 constexpr uint32_t TRI_LIGHT_S = 4096;     // S group size handled by one wave
 constexpr uint32_t TRI_HEAVY_X = 4096;     // R slice handled by one workgroup
 constexpr uint32_t TRI_HEAVY_CAP = 8192;

@@ -199,8 +199,16 @@ __device__ __forceinline__ unsigned long long stream_chunk(const TriJoinArgs& A,
     if (!(valid && run_lookup(A.Itr, A.Grpl[si], ts, y)) ||
         (A.strict ? y >= x : y > x))                  // the other pass owns this s
         y = 0;
-    if (y <= TRI_SHORT_LIST) {
-        for (uint32_t t = ts; t < ts + y; ++t) acc += atab_get(keys, vals, mask, sp, A.Itrl[t]);
+    if (y <= TRI_SHORT_LIST) {                        // UNROLL loads in flight, then their probes
+        const uint32_t te = ts + y;
+        for (uint32_t t0 = ts; t0 < te; t0 += UNROLL) {
+            uint32_t key[UNROLL];
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) key[u] = t0 + u < te ? A.Itrl[t0 + u] : 0u;
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                if (t0 + u < te) acc += atab_get(keys, vals, mask, sp, key[u]);
+        }
     }
     unsigned long long longm = __ballot(y > TRI_SHORT_LIST);
     while (longm) {                                   // wave-uniform
@@ -234,7 +242,7 @@ __device__ __forceinline__ unsigned long long stream_chunk(const TriJoinArgs& A,
 struct WaveTable {
     uint32_t* keys;
     uint32_t* vals;
-    uint32_t* used;
+    uint16_t* used;                   // slots taken (< TRI_LIGHT_CAP), for the clean-up
     uint32_t* nused;
     uint32_t* spec;
 };
@@ -255,7 +263,7 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
             if (cur == a) { atomicAdd(&W.vals[s], 1u); break; }
             if (cur == EMPTY_KEY) {
                 const uint32_t old = atomicCAS(&W.keys[s], EMPTY_KEY, a);
-                if (old == EMPTY_KEY) { W.used[atomicAdd(W.nused, 1u)] = s; atomicAdd(&W.vals[s], 1u); break; }
+                if (old == EMPTY_KEY) { W.used[atomicAdd(W.nused, 1u)] = (uint16_t)s; atomicAdd(&W.vals[s], 1u); break; }
                 if (old == a) { atomicAdd(&W.vals[s], 1u); break; }
             }
             s = (s + 1u) & mask;
@@ -279,7 +287,7 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     constexpr int NW = TRI_THREADS / WAVE;                                           \
     __shared__ uint32_t tkeys[NW][TRI_LIGHT_CAP];                                    \
     __shared__ uint32_t tvals[NW][TRI_LIGHT_CAP];                                    \
-    __shared__ uint32_t tused[NW][TRI_LIGHT_X];                                      \
+    __shared__ uint16_t tused[NW][TRI_LIGHT_X];                                      \
     __shared__ uint32_t tnused[NW];                                                  \
     __shared__ uint32_t tspec[NW];                                                   \
     const int w = threadIdx.x / WAVE, lane = lane_id();                              \
