@@ -197,7 +197,7 @@ class Context:
         """{kernel name: (total ms, launches)} since the last read (waits for
         the recorded events)."""
         import numpy as np
-        cap = 64
+        cap = 256
         names = ctypes.create_string_buffer(32 * cap)
         ms = np.zeros(cap, dtype=np.float64)
         cnt = np.zeros(cap, dtype=np.int64)

@@ -164,7 +164,8 @@ def test_batch_512_full_golden(mj, ctx):
     """The full 512-join batch (seeds 4000 + k, 10^3..10^6 edges, half linear
     and half cyclic) under the planner's plans: every join's result equals
     the oracle's, stored by tests/golden/make_batch_golden.py, for the eager
-    call and for three replays of its HIP-graph capture."""
+    call (which launches at most 512 kernels: one per merged step) and for
+    three replays of its HIP-graph capture."""
     import json
     import os
     import torch
@@ -179,6 +180,14 @@ def test_batch_512_full_golden(mj, ctx):
     b = ctx.batch(joins)
     _check_golden(mj, b.run(), gold)
     torch.cuda.synchronize()
+    # one call issues merged steps: a few hundred launches, not each join's own
+    ctx.profile(True)
+    ctx.profile_read()
+    _check_golden(mj, b.run(), gold)
+    torch.cuda.synchronize()
+    launches = sum(v[1] for v in ctx.profile_read().values())
+    ctx.profile(False)
+    assert 0 < launches <= 512, launches
     s = torch.cuda.Stream()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s, capture_error_mode="relaxed"):
