@@ -23,8 +23,10 @@
  *     planning workspace of mj_plan_workspace() bytes.
  *   - Count calls are asynchronous on the given HIP stream (a hipStream_t
  *     passed as void*; NULL = the default stream); results are valid after
- *     the stream synchronises.  Calls on one context from one host thread
- *     per stream are safe; overlapping calls that share a workspace race.
+ *     the stream synchronises.  A context is used by one host thread at a
+ *     time (its profiling state, tuning cache and a batch's recording of
+ *     launches are not locked): threads that call concurrently need a
+ *     context each.  Overlapping calls that share a workspace race.
  *   - Every function returns an mj_status; on an error no kernel has been
  *     launched and outputs are untouched.  No C++ exception crosses the ABI.
  *   - n = 0 is valid and yields zero counts.
