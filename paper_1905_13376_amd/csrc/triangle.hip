@@ -296,17 +296,34 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     if (lane == 0) { *W.spec = 0; *W.nused = 0; }                                    \
     wave_fence();
 
+// Light items are taken a run at a time: the queue counter is one address,
+// whose atomics the L2 serves one after another (about 12 ns each), so one
+// atomic per item bounded the kernel once items numbered in the millions.
+// A run is at most TRI_LIGHT_GRAB items and at most a quarter of a wave's
+// fair share, so small queues still spread over all waves.
+constexpr uint32_t TRI_LIGHT_GRAB = 16;
+
+__device__ __forceinline__ uint32_t light_grab(unsigned long long nitems, unsigned long long waves) {
+    const unsigned long long g = nitems / (4ull * waves);
+    return (uint32_t)(g < 1 ? 1 : (g > TRI_LIGHT_GRAB ? TRI_LIGHT_GRAB : g));
+}
+
 MJ_KERNEL(k_tri_light, TRI_THREADS, TriJoinArgs) {
-    (void)vg;                                         // work comes from the join's queue
     TRI_LIGHT_SETUP
     const uint32_t nitems = *A.nlight;
+    const uint32_t grab = light_grab(nitems, (unsigned long long)vg.nblk * (TRI_THREADS / WAVE));
     unsigned long long acc = 0;
+    uint32_t it = 0, end = 0;
     while (true) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(A.light_next, 1u);
-        it = __shfl(it, 0, WAVE);
-        if (it >= nitems) break;
+        if (it >= end) {                              // wave-uniform
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(A.light_next, grab);
+            it = __shfl(t, 0, WAVE);
+            if (it >= nitems) break;
+            end = min(it + grab, nitems);
+        }
         acc += tri_light_group(A, A.light[it], W);
+        ++it;
     }
     acc = wave_sum_u64(acc);
     if (lane == 0 && acc) atomicAdd(A.total, acc);
@@ -409,17 +426,30 @@ __global__ void __launch_bounds__(TRI_THREADS)
 k_tri_light_batch(TriBatchArgs Bt) {
     TRI_LIGHT_SETUP
     const unsigned long long nitems = Bt.light_base[Bt.njoins];
+    const unsigned long long grab = light_grab(nitems, (unsigned long long)gridDim.x * (TRI_THREADS / WAVE));
+    unsigned long long it = 0, end = 0, acc = 0;
+    uint32_t cur = 0;                                 // the join whose count acc holds
     while (true) {
-        unsigned long long it = 0;
-        if (lane == 0) it = atomicAdd(Bt.next, 1ull);
-        it = __shfl(it, 0, WAVE);
-        if (it >= nitems) break;
+        if (it >= end) {                              // wave-uniform
+            unsigned long long t = 0;
+            if (lane == 0) t = atomicAdd(Bt.next, grab);
+            it = __shfl(t, 0, WAVE);
+            if (it >= nitems) break;
+            end = min(it + grab, nitems);
+        }
         const uint32_t j = batch_join_of(Bt.light_base, Bt.njoins, it);
+        if (j != cur) {                               // a run may span joins: add the last one's count
+            acc = wave_sum_u64(acc);
+            if (lane == 0 && acc) atomicAdd(Bt.joins[cur].total, acc);
+            acc = 0;
+            cur = j;
+        }
         const TriJoinArgs& A = Bt.joins[j];
-        unsigned long long acc = tri_light_group(A, A.light[it - Bt.light_base[j]], W);
-        acc = wave_sum_u64(acc);
-        if (lane == 0 && acc) atomicAdd(A.total, acc);
+        acc += tri_light_group(A, A.light[it - Bt.light_base[j]], W);
+        ++it;
     }
+    acc = wave_sum_u64(acc);
+    if (lane == 0 && acc) atomicAdd(Bt.joins[cur].total, acc);
 }
 
 __global__ void __launch_bounds__(TRI_HEAVY_THREADS)

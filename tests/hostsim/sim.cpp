@@ -424,7 +424,10 @@ hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
     std::memset(p, 0, sizeof *p);
     std::strcpy(p->name, "hipsim");
-    p->multiProcessorCount = 256;
+    // HIPSIM_CUS: a smaller device, so that persistent grids are few and
+    // each wave takes many work items
+    const char* cus = std::getenv("HIPSIM_CUS");
+    p->multiProcessorCount = cus ? std::max(1, std::atoi(cus)) : 256;
     p->sharedMemPerBlock = 160 * 1024;
     p->totalGlobalMem = size_t(288) << 30;
     return hipSuccess;

@@ -51,6 +51,17 @@ def test_merged_launch_block_search(built):
     assert rc == 0 and "all checks passed" in out, out[-3000:]
 
 
+def test_batch_on_a_small_device(built, tmp_path_factory):
+    """The batch leg with a one-CU device: persistent grids of a few waves,
+    each taking its work items in runs of several."""
+    data = tmp_path_factory.getbasetemp() / "hostsim_tiny"
+    if not (data / "meta.txt").exists():
+        subprocess.run([sys.executable, os.path.join(HOSTSIM, "make_inputs.py"), str(data), "--tiny"],
+                       check=True, capture_output=True)
+    rc, out = _run([os.path.join(built, "replay"), str(data), "batch"], {"HIPSIM_CUS": "1"})
+    assert rc == 0 and "all checks passed" in out, out[-3000:]
+
+
 @pytest.mark.parametrize("fill", ["0xA5", "0x00"])
 def test_replay_of_the_benchmark_sequence(built, tmp_path_factory, fill):
     data = tmp_path_factory.getbasetemp() / "hostsim_tiny"
