@@ -297,15 +297,16 @@ __device__ unsigned long long tri_light_group(const TriJoinArgs& A, uint32_t g, 
     wave_fence();
 
 // Light items are taken a run at a time: the queue counter is one address,
-// whose atomics the L2 serves one after another (about 12 ns each), so one
-// atomic per item bounded the kernel once items numbered in the millions.
-// A run is at most TRI_LIGHT_GRAB items and at most a quarter of a wave's
-// fair share, so small queues still spread over all waves.
-constexpr uint32_t TRI_LIGHT_GRAB = 16;
+// whose atomics are served one after another (about 12 ns each), so one
+// atomic per item bounded the kernel once items numbered in the millions,
+// and each atomic's round trip also stalls the wave that waits for it.  A
+// run is a quarter of a wave's fair share, at least TRI_LIGHT_GRAB_MIN and
+// at most TRI_LIGHT_GRAB items.
+constexpr uint32_t TRI_LIGHT_GRAB = 16, TRI_LIGHT_GRAB_MIN = 4;
 
 __device__ __forceinline__ uint32_t light_grab(unsigned long long nitems, unsigned long long waves) {
     const unsigned long long g = nitems / (4ull * waves);
-    return (uint32_t)(g < 1 ? 1 : (g > TRI_LIGHT_GRAB ? TRI_LIGHT_GRAB : g));
+    return (uint32_t)(g < TRI_LIGHT_GRAB_MIN ? TRI_LIGHT_GRAB_MIN : (g > TRI_LIGHT_GRAB ? TRI_LIGHT_GRAB : g));
 }
 
 MJ_KERNEL(k_tri_light, TRI_THREADS, TriJoinArgs) {
